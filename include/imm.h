@@ -1,0 +1,209 @@
+/*
+ * imm.h -- C ABI of libimm, the MI355X (gfx950) implementation of the hot
+ * path of IMM (Influence Maximization via Martingales) as studied in
+ * arXiv 2411.09473: random reverse-reachable (RRR) set sampling, occurrence
+ * counting, and greedy max-coverage seed selection, driven by IMM's
+ * martingale theta schedule.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns an imm_status; IMM_OK is 0. On error, out-parameters
+ *     are left untouched and imm_last_error() (thread-local) describes it.
+ *   - No C++ exception crosses this boundary.
+ *   - Handles (imm_graph, imm_result, imm_pool) are opaque and owned by the
+ *     library until the matching *_destroy call.
+ *   - Array arguments are host pointers unless the call's flags contain
+ *     IMM_DEVICE_PTRS, in which case they are device pointers on the current
+ *     HIP device that must stay valid for the duration of the call. Caller
+ *     arrays are only borrowed for the duration of the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that return host-side results synchronise that stream before
+ *     returning.
+ *   - Vertex ids are uint32 with n <= 2^32 - 2; edge ids are CSC positions
+ *     and m must be < 2^32.
+ *   - Randomness is Philox4x32-10 keyed by the 64-bit run seed; sample s,
+ *     edge e and vertex v map to fixed counters (root: (0, s_lo, s_hi, 0);
+ *     IC coin of edge e: word e&3 of (e>>2, s_lo, s_hi, 1); LT draw at v: word
+ *     v&3 of (v>>2, s_lo, s_hi, 2)), so every set is a pure function of
+ *     (graph, seed, sample id) and results do not depend on launch shapes.
+ */
+#ifndef IMM_H
+#define IMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IMM_OK = 0,
+    IMM_EINVAL = 1,     /* malformed argument or graph */
+    IMM_ENOMEM = 2,     /* device/host allocation failed or budget exceeded */
+    IMM_EOVERFLOW = 3,  /* theta (or a round target) >= 2^32, or m >= 2^32 */
+    IMM_EDEVICE = 4,    /* a HIP runtime call failed */
+    IMM_EBUSY = 5,      /* server: the query has not finished yet */
+    IMM_ECANCELLED = 6  /* server: the query was cancelled */
+} imm_status;
+
+/* Diffusion models (Section II-A). */
+typedef enum {
+    IMM_IC = 0, /* independent cascade: weight[e] is the live threshold thr,
+                   edge live iff draw < thr, i.e. p = thr / 2^32 */
+    IMM_LT = 1  /* linear threshold, live-edge form: weight[] is the per-column
+                   cumulative in-weight table cum (non-decreasing within a
+                   column); the live in-edge of v is the first e of v's column
+                   with draw < cum[e], none if there is no such e */
+} imm_model;
+
+/* flags */
+#define IMM_DEVICE_PTRS 0x1u /* array arguments are device pointers */
+#define IMM_KEEP_POOL 0x2u   /* imm_run: keep the final RRR pool for imm_result_pool */
+#define IMM_TIMING 0x4u      /* record per-phase kernel times with HIP events */
+
+typedef struct imm_graph imm_graph;
+typedef struct imm_result imm_result;
+typedef struct imm_pool imm_pool;
+
+/* Parameters of one IMM run (Algorithm 1's inputs k and epsilon, plus IMM's
+ * failure-probability exponent ell: the guarantee holds with probability at
+ * least 1 - n^-ell). max_device_bytes = 0 means no budget. */
+typedef struct {
+    uint32_t k;
+    uint32_t flags;
+    double epsilon;
+    double ell;
+    uint64_t seed;
+    uint64_t max_device_bytes;
+} imm_params;
+
+/* Work and time accounting of a run or of a sampling call. Times are in
+ * milliseconds, filled when IMM_TIMING was set (else 0). */
+typedef struct {
+    double ms_total;      /* host wall time of the call */
+    double ms_sample;     /* sampling kernels (fused counting included) */
+    double ms_compact;    /* size scan + pool compaction */
+    double ms_index;      /* inverted index: count scan + scatter */
+    double ms_select;     /* argmax + cover/decrement kernels */
+    double ms_sample_main;/* the wave-per-sample sampling kernel alone */
+    uint64_t main_launches;  /* launches of that kernel */
+    uint64_t sets;        /* RRR sets generated */
+    uint64_t entries;     /* total set size P */
+    uint64_t edges;       /* IC: coins evaluated (in-edges examined);
+                             LT: walk steps (draws evaluated) */
+    uint64_t live;        /* IC: live in-edges followed; LT: cum entries read */
+    uint64_t deferred;    /* sets finished by the large-set kernel */
+    uint64_t main_sets;   /* sets finished by the wave-per-sample kernel */
+    uint64_t main_entries;/* their total size */
+    uint64_t main_edges;  /* their edges (IC coins / LT steps) */
+    uint64_t main_live;   /* their live edges / cum entries */
+    uint32_t rounds;      /* sampling-phase rounds executed (imm_run) */
+    uint32_t pad;
+} imm_stats;
+
+/* Thread-local description of the last error of this thread. */
+const char* imm_last_error(void);
+
+/* ---------------------------------------------------------------- graph ---
+ * imm_graph_create: upload a directed graph given as CSC of in-edges (the
+ * graph is traversed by in-neighbours, Algorithm 3).
+ *   n        number of vertices, 2 <= n <= 2^32 - 2
+ *   m        number of edges, m < 2^32
+ *   col_off  uint64[n+1]: in-edges of v are [col_off[v], col_off[v+1]);
+ *            col_off[0] = 0, non-decreasing, col_off[n] = m
+ *   row_src  uint32[m]: source vertex of each in-edge (< n)
+ *   weight   uint32[m]: see imm_model
+ *   flags    IMM_DEVICE_PTRS or 0
+ * Errors: IMM_EINVAL on a malformed CSC (checked on the host; with
+ * IMM_DEVICE_PTRS the arrays are copied to the host for the check), an LT
+ * table that decreases within a column, or a bad model; IMM_EOVERFLOW if
+ * m >= 2^32; IMM_ENOMEM / IMM_EDEVICE from the runtime. The graph stays
+ * resident in device memory until imm_graph_destroy. */
+imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
+                            const uint32_t* row_src, const uint32_t* weight, imm_model model,
+                            uint32_t flags, void* stream, imm_graph** out);
+imm_status imm_graph_destroy(imm_graph* g);
+/* n, m, model and the device bytes held by the resident graph. */
+imm_status imm_graph_info(const imm_graph* g, uint32_t* n, uint64_t* m, imm_model* model,
+                          uint64_t* device_bytes);
+
+/* ---------------------------------------------------------------- theta ---
+ * IMM's theta constants (Tang, Shi, Xiao 2015, cited for Theta_Estimation,
+ * OPT_Lower_Bound and Set_Theta of Algorithm 1): lambda' (their Eq. 9) and
+ * lambda* (their Eq. 6), both with ell replaced by ell (1 + ln 2 / ln n),
+ * and the number of sampling rounds i_max = ceil(log2 n) - 1. FP64 on the
+ * host. Errors: IMM_EINVAL if n < 2, k = 0, k > n, eps <= 0 or ell <= 0. */
+imm_status imm_theta_plan(uint32_t n, uint32_t k, double eps, double ell,
+                          double* lambda_prime, double* lambda_star, uint32_t* i_max);
+
+/* ------------------------------------------------------------------ run ---
+ * imm_run: one full IMM run (Algorithm 1): sampling rounds i = 1..i_max
+ * with theta_i = ceil(lambda' 2^i / n) sets (generated while |R| < theta_i,
+ * reused across rounds), greedy selection and the lower-bound test
+ * n F_R(S_i) >= (1 + sqrt(2) eps) n / 2^i with early break; then
+ * theta = ceil(lambda* / LB), top-up, and the final greedy over all sets.
+ * Blocks until the seeds are on the host. Errors: IMM_EINVAL (k = 0, k > n,
+ * eps <= 0, ell <= 0), IMM_EOVERFLOW (a target >= 2^32), IMM_ENOMEM (budget
+ * exceeded or allocation failure; nothing leaks), IMM_EDEVICE. */
+imm_status imm_run(const imm_graph* g, const imm_params* p, void* stream, imm_result** out);
+
+/* theta (= |R| of the final selection), sampling rounds executed, LB, and
+ * the number of sets covered by the seeds (the sum of the gains). */
+imm_status imm_result_info(const imm_result* r, uint64_t* theta, uint32_t* rounds, double* lb,
+                           uint64_t* covered);
+/* seeds (uint32[k], in selection order) and their marginal gains
+ * (uint64[k], newly covered sets); either pointer may be NULL. Host memory. */
+imm_status imm_result_seeds(const imm_result* r, uint32_t* seeds, uint64_t* gains);
+/* The targets of the run: theta_1, theta_2, ... of the executed rounds, then
+ * the final theta (count entries, at most 64), and the coverage of each
+ * sampling-phase round (rounds entries, at most 64). Host memory; NULL ok. */
+imm_status imm_result_targets(const imm_result* r, uint32_t* count, uint64_t* targets,
+                              uint64_t* round_cov);
+/* The final RRR pool in canonical order (sets by sample id, vertices
+ * ascending within a set). Two-call protocol: n_sets/n_entries are always
+ * written; set_off (uint64[n_sets+1]) and set_vtx (uint32[n_entries]) are
+ * filled when non-NULL. Requires IMM_KEEP_POOL, else IMM_EINVAL. */
+imm_status imm_result_pool(const imm_result* r, uint64_t* n_sets, uint64_t* n_entries,
+                           uint64_t* set_off, uint32_t* set_vtx);
+imm_status imm_result_stats(const imm_result* r, imm_stats* stats);
+void imm_result_destroy(imm_result* r);
+
+/* --------------------------------------------------------- test-granular ---
+ * imm_sample: generate the RRR sets of sample ids [first_id, first_id+count)
+ * (Generate_RRRsets, Algorithm 3, with the occurrence counts fused) into a
+ * device-resident pool. flags: IMM_TIMING. Errors: IMM_EINVAL (count = 0 or
+ * first_id + count overflows), IMM_ENOMEM, IMM_EDEVICE. */
+imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint64_t count,
+                      uint32_t flags, void* stream, imm_pool** out);
+imm_status imm_pool_info(const imm_pool* p, uint64_t* n_sets, uint64_t* n_entries,
+                         imm_stats* stats);
+/* Copy the pool out in canonical order (host pointers, each may be NULL):
+ * set_off uint64[n_sets+1] (starting at 0), set_vtx uint32[n_entries],
+ * counts uint32[n] (occurrences of each vertex over these sets). */
+imm_status imm_pool_export(const imm_pool* p, uint64_t* set_off, uint32_t* set_vtx,
+                           uint32_t* counts);
+void imm_pool_destroy(imm_pool* p);
+
+/* imm_greedy: greedy max coverage (Find_Most_Influential_Set, Algorithm 2)
+ * over a caller-given pool: build the vertex->sets index, then k times pick
+ * the unselected vertex with the most uncovered sets (lowest id on ties),
+ * cover those sets and decrement their members' counts.
+ *   set_off uint64[n_sets+1] with set_off[0] = 0; set_vtx uint32[set_off[n_sets]],
+ *   members of a set distinct and < n. Host pointers unless IMM_DEVICE_PTRS.
+ *   seeds uint32[k], gains uint64[k], covered: host outputs.
+ * Errors: IMM_EINVAL (k = 0, k > n, n_sets >= 2^32, bad offsets or ids),
+ * IMM_ENOMEM, IMM_EDEVICE. */
+imm_status imm_greedy(uint32_t n, const uint64_t* set_off, const uint32_t* set_vtx,
+                      uint64_t n_sets, uint32_t k, uint32_t flags, void* stream,
+                      uint32_t* seeds, uint64_t* gains, uint64_t* covered);
+
+/* imm_philox4x32_10: evaluate the device Philox4x32-10 (Salmon et al.,
+ * SC'11) on `count` counters: ctr uint32[4*count] in, out uint32[4*count]
+ * out, key = (key_lo, key_hi). Host pointers unless IMM_DEVICE_PTRS. */
+imm_status imm_philox4x32_10(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t flags,
+                             void* stream, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMM_H */

@@ -1,0 +1,129 @@
+// device_common.hpp -- device helpers shared by the libimm kernels (gfx950):
+// the Philox4x32-10 stream that defines every random decision, and wave64
+// scan/reduction primitives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imm {
+
+constexpr uint32_t kWave = 64;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kSelected = 0xFFFFFFFFu;  // counts_work value of a chosen seed
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64 products by the published multipliers, an xor with the other two
+// counter words and the round key, a word permutation, and a Weyl key bump.
+// The key is wave-uniform (the run seed) so the key schedule stays scalar.
+struct Philox4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Philox4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t pick(const Philox4& r, uint32_t j) {
+    return j == 0 ? r.x : (j == 1 ? r.y : (j == 2 ? r.z : r.w));
+}
+
+// Root of sample s: floor(w * n / 2^64), w = word0 | word1 << 32.
+__device__ __forceinline__ uint32_t sample_root(uint64_t seed, uint64_t s, uint32_t n) {
+    const Philox4 r = philox10(0u, (uint32_t)s, (uint32_t)(s >> 32), 0u, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+    const uint64_t w = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    return (uint32_t)__umul64hi(w, (uint64_t)n);
+}
+
+// LT draw at vertex v in sample s: word v&3 of counter (v>>2, s_lo, s_hi, 2).
+__device__ __forceinline__ uint32_t lt_draw(uint64_t seed, uint64_t s, uint32_t v) {
+    const Philox4 r = philox10(v >> 2, (uint32_t)s, (uint32_t)(s >> 32), 2u, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+    return pick(r, v & 3u);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive wave64 prefix sum of a uint32.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint64_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
+#pragma unroll
+    for (uint32_t d = kWave / 2; d >= 1; d >>= 1) {
+        const uint64_t t = __shfl_xor(v, d, kWave);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (uint32_t d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Largest index o in [0, cnt) with base[o] <= t (base non-decreasing, base[0] = 0).
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* base, uint32_t cnt, uint32_t t) {
+    uint32_t lo = 0, hi = cnt;  // invariant: base[lo] <= t, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Enumerate the (segment, k) pairs of the 64 segments held one per lane;
+// f(owner_lane, a_owner, b_owner, k) runs once for every k < size_owner.
+// Requires blockDim.x == 64 (one wave per block).
+template <class F>
+__device__ __forceinline__ void wave_segments(uint32_t sz, uint64_t a, uint64_t b, F f) {
+    __shared__ uint32_t s_base[kWave];
+    __shared__ uint64_t s_a[kWave], s_b[kWave];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t incl = wave_incl_scan(sz);
+    const uint32_t T = __shfl(incl, kWave - 1, kWave);
+    s_base[lane] = incl - sz;
+    s_a[lane] = a;
+    s_b[lane] = b;
+    __syncthreads();
+    for (uint32_t t = lane; t < T; t += kWave) {
+        const uint32_t ow = owner_of(s_base, kWave, t);
+        f(ow, s_a[ow], s_b[ow], t - s_base[ow]);
+    }
+    __syncthreads();
+}
+
+}  // namespace imm

@@ -1,0 +1,938 @@
+// engine.cpp -- libimm host engine and C ABI (include/imm.h).
+//
+// Owns device memory, sequences the kernels of one IMM run on the caller's
+// stream and runs IMM's theta schedule (Algorithm 1 with the bounds of Tang
+// et al. 2015) in FP64 on the host. Per sampling round the host reads back a
+// handful of scalars (staging cursor, deferred/retried counts, pool size) and
+// one coverage figure; everything else stays on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/imm.h"
+#include "imm_internal.hpp"
+
+using namespace imm;
+
+// ---------------------------------------------------------------- errors --
+
+namespace {
+
+thread_local std::string g_err;
+
+imm_status fail(imm_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+struct Status {
+    imm_status st = IMM_OK;
+    bool ok() const { return st == IMM_OK; }
+};
+
+#define IMM_TRY(expr)                      \
+    do {                                   \
+        imm_status _s = (expr);            \
+        if (_s != IMM_OK) return _s;       \
+    } while (0)
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            return fail(_e == hipErrorOutOfMemory ? IMM_ENOMEM : IMM_EDEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));           \
+        }                                                                              \
+    } while (0)
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------ allocation --
+
+// Device allocations of one owner, with an optional byte budget.
+struct Arena {
+    uint64_t budget = 0;  // 0: none
+    uint64_t used = 0;
+    std::vector<std::pair<void*, uint64_t>> live;
+
+    imm_status alloc(void** p, uint64_t bytes, const char* what) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~uint64_t(255);
+        if (budget && used + bytes > budget)
+            return fail(IMM_ENOMEM, std::string("device budget exceeded allocating ") + what);
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return fail(IMM_ENOMEM, std::string("hipMalloc failed for ") + what);
+        }
+        used += bytes;
+        live.emplace_back(*p, bytes);
+        return IMM_OK;
+    }
+    void release(void* p) {
+        if (!p) return;
+        for (size_t i = 0; i < live.size(); ++i) {
+            if (live[i].first == p) {
+                used -= live[i].second;
+                (void)hipFree(p);
+                live[i] = live.back();
+                live.pop_back();
+                return;
+            }
+        }
+    }
+    void release_all() {
+        for (auto& x : live) (void)hipFree(x.first);
+        live.clear();
+        used = 0;
+    }
+    ~Arena() { release_all(); }
+};
+
+template <class T>
+imm_status grow(Arena& a, T** p, uint64_t* cap, uint64_t need, uint64_t keep, hipStream_t st,
+                const char* what) {
+    if (*p && *cap >= need) return IMM_OK;
+    uint64_t nc = std::max<uint64_t>(need, *cap + *cap / 2);
+    if (nc < 64) nc = 64;
+    T* q = nullptr;
+    imm_status s = a.alloc(reinterpret_cast<void**>(&q), nc * sizeof(T), what);
+    if (s != IMM_OK && nc > need) {
+        nc = need;
+        s = a.alloc(reinterpret_cast<void**>(&q), nc * sizeof(T), what);
+    }
+    IMM_TRY(s);
+    if (*p && keep) HIP_TRY(hipMemcpyAsync(q, *p, keep * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        a.release(*p);
+    }
+    *p = q;
+    *cap = nc;
+    return IMM_OK;
+}
+
+// Scalars the kernels update, in one device block.
+struct DevScalars {
+    unsigned long long cursor;
+    uint32_t ticket_small, ticket_big, defer_n, retry_n, argmax_ticket, big_flag;
+    uint32_t err, pad;
+    unsigned long long stats[kStCount];
+};
+
+// Phase timing with HIP events on the run's stream.
+struct Timer {
+    bool on = false;
+    hipStream_t st = nullptr;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    int open(int phase) {
+        if (!on) return -1;
+        Rec r{phase, get(), get()};
+        (void)hipEventRecord(r.a, st);
+        recs.push_back(r);
+        return (int)recs.size() - 1;
+    }
+    void close(int h) {
+        if (h < 0) return;
+        (void)hipEventRecord(recs[h].b, st);
+    }
+    // phases: 0 sample, 1 compact, 2 index, 3 select, 4 main sampling kernel
+    void collect(double* ms, uint64_t* main_launches) {
+        for (auto& r : recs) {
+            float t = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess)
+                ms[r.phase] += t;
+            if (r.phase == 4) ++*main_launches;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~Timer() {
+        for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- graph --
+
+struct imm_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    imm_model model = IMM_IC;
+    int device = 0;
+    Arena arena;
+    uint32_t* off = nullptr;
+    uint32_t* thr = nullptr;
+    uint32_t* src = nullptr;
+    uint2* cs = nullptr;
+    uint32_t* guide = nullptr;
+};
+
+namespace {
+
+IcGraphDev ic_view(const imm_graph* g) {
+    return IcGraphDev{g->off, g->thr, g->src, g->n, (uint32_t)g->m};
+}
+LtGraphDev lt_view(const imm_graph* g) {
+    return LtGraphDev{g->off, g->cs, g->guide, g->n, (uint32_t)g->m};
+}
+
+// ------------------------------------------------------------- workspace --
+
+struct Workspace {
+    int device = 0;
+    uint32_t n = 0;
+    hipStream_t st = nullptr;
+    Arena arena;
+    DevScalars* sc = nullptr;
+    DevScalars* hsc = nullptr;  // pinned mirror
+    uint32_t* counts_acc = nullptr;
+    uint32_t* counts_work = nullptr;
+    uint32_t* inv_cursor = nullptr;
+    uint64_t* inv_off = nullptr;
+    uint64_t* set_off = nullptr; uint64_t cap_sets = 0;     // cap_sets entries
+    uint32_t* set_vtx = nullptr; uint64_t cap_entries = 0;
+    uint32_t* inv_set = nullptr; uint64_t cap_inv = 0;
+    uint32_t* covered = nullptr; uint64_t cap_cov = 0;
+    uint32_t* stage = nullptr; uint64_t stage_cap = 0;
+    uint64_t* stage_off = nullptr; uint64_t cap_so = 0;
+    uint32_t* sizes = nullptr; uint64_t cap_sz = 0;
+    uint32_t* defer = nullptr; uint64_t cap_df = 0;
+    uint32_t* retry = nullptr; uint64_t cap_rt = 0;
+    uint64_t* scan_tmp = nullptr; uint64_t cap_scan = 0;
+    unsigned long long* partials = nullptr;
+    uint32_t* seeds_d = nullptr; uint32_t* gains_d = nullptr; uint64_t cap_k = 0;
+    uint32_t* gains_h = nullptr; uint64_t cap_kh = 0;
+    uint32_t* big = nullptr; uint64_t cap_big = 0; uint32_t big_slots = 0;
+    uint64_t n_sets = 0, n_entries = 0;
+    double ewma_size = 0.0;  // running mean set size (staging estimate)
+    Timer timer;
+
+    ~Workspace() {
+        if (hsc) (void)hipHostFree(hsc);
+        if (gains_h) (void)hipHostFree(gains_h);
+    }
+};
+
+imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget,
+                   bool timing) {
+    w.device = device;
+    w.n = n;
+    w.st = st;
+    w.arena.budget = budget;
+    w.timer.on = timing;
+    w.timer.st = st;
+    IMM_TRY(w.arena.alloc((void**)&w.sc, sizeof(DevScalars), "scalars"));
+    HIP_TRY(hipHostMalloc((void**)&w.hsc, sizeof(DevScalars), hipHostMallocDefault));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_acc, (uint64_t)n * 4, "counts"));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_work, (uint64_t)n * 4 + 16, "counts_work"));
+    IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
+    IMM_TRY(w.arena.alloc((void**)&w.inv_off, ((uint64_t)n + 1) * 8, "inv_off"));
+    IMM_TRY(w.arena.alloc((void**)&w.partials, 1024 * 8, "partials"));
+    HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
+    HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)n * 4, st));
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
+    HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
+    return IMM_OK;
+}
+
+imm_status ws_read_scalars(Workspace& w) {
+    HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    return IMM_OK;
+}
+
+imm_status ws_big_scratch(Workspace& w, uint32_t want_slots) {
+    const uint64_t words = ((uint64_t)w.n + 31) / 32;
+    const uint64_t per = words + w.n;
+    if (want_slots < 1) want_slots = 1;
+    if (w.big && w.big_slots >= want_slots) return IMM_OK;
+    if (w.big) {
+        HIP_TRY(hipStreamSynchronize(w.st));
+        w.arena.release(w.big);
+        w.big = nullptr;
+        w.big_slots = 0;
+    }
+    IMM_TRY(w.arena.alloc((void**)&w.big, per * want_slots * 4, "large-set scratch"));
+    HIP_TRY(hipMemsetAsync(w.big, 0, words * want_slots * 4, w.st));
+    w.big_slots = want_slots;
+    return IMM_OK;
+}
+
+BigScratch big_view(const Workspace& w, uint32_t slots) {
+    const uint32_t words = (uint32_t)(((uint64_t)w.n + 31) / 32);
+    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words, slots};
+}
+
+// Generate sample ids [id_lo, id_lo + count) into the pool at set index
+// w.n_sets (Generate_RRRsets with fused counting), then compact them.
+imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                     uint64_t count64) {
+    if (count64 == 0) return IMM_OK;
+    if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
+    const uint32_t count = (uint32_t)count64;
+    hipStream_t st = w.st;
+    IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
+    IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
+    IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
+    IMM_TRY(grow(w.arena, &w.retry, &w.cap_rt, count, 0, st, "retry list"));
+    {
+        // expected entries plus the unused tails of every wave's (IC) or
+        // lane's (LT) staging chunk
+        const double mean = w.ewma_size > 0 ? w.ewma_size : 16.0;
+        uint64_t tails;
+        if (g->model == IMM_IC) {
+            const uint64_t waves = std::min<uint64_t>(ic_small_grid(w.device),
+                                                      (count + kIcTicketChunk - 1) / kIcTicketChunk);
+            tails = waves * kIcStageChunk;
+        } else {
+            const uint64_t lanes = std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
+            tails = lanes * kLtChunk;
+        }
+        const uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
+        IMM_TRY(grow(w.arena, &w.stage, &w.stage_cap, want, 0, st, "staging"));
+    }
+    HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));
+
+    const SampleRange rg{seed, id_lo, count};
+    auto out = [&]() {
+        return SampleOut{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
+                         w.defer, &w.sc->defer_n, w.retry, &w.sc->retry_n, w.sc->stats};
+    };
+    int th = w.timer.open(0);
+    int tm = w.timer.open(4);
+    if (g->model == IMM_IC)
+        HIP_TRY(launch_ic_small(ic_view(g), rg, out(), &w.sc->ticket_small, ic_small_grid(w.device), st));
+    else
+        HIP_TRY(launch_lt_small(lt_view(g), rg, out(), &w.sc->ticket_small, lt_small_grid(w.device), st));
+    w.timer.close(tm);
+    w.timer.close(th);
+    IMM_TRY(ws_read_scalars(w));
+
+    // deferred sets (too large for the on-chip kernel), then retries after
+    // growing the staging buffer, until every set is stored
+    uint32_t* list = w.defer;
+    uint32_t* list_n = &w.sc->defer_n;
+    uint32_t* fl = w.retry;
+    uint32_t* fl_n = &w.sc->retry_n;
+    uint32_t pending = w.hsc->defer_n;
+    bool first_pass = true;
+    for (int guard = 0; guard < 64; ++guard) {
+        if (pending) {
+            const uint32_t cap_slots = g->model == IMM_IC ? 512u : 64u;
+            IMM_TRY(ws_big_scratch(w, std::min(pending, cap_slots)));
+            HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
+            int t2 = w.timer.open(0);
+            if (g->model == IMM_IC)
+                HIP_TRY(launch_ic_large(ic_view(g), rg, out(), list, list_n, fl, fl_n,
+                                        &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
+            else
+                HIP_TRY(launch_lt_large(lt_view(g), rg, out(), list, list_n, fl, fl_n,
+                                        &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
+            w.timer.close(t2);
+            IMM_TRY(ws_read_scalars(w));
+        }
+        // failures of this pass (plus, on the first pass, the main kernel's retries)
+        const uint32_t failed = (fl == w.retry) ? w.hsc->retry_n : w.hsc->defer_n;
+        (void)first_pass;
+        first_pass = false;
+        if (failed == 0) break;
+        // grow staging, keep what is stored, continue at the old capacity
+        const uint64_t used = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
+        const uint64_t old_cap = w.stage_cap;
+        const double mean = w.ewma_size > 0 ? w.ewma_size : 64.0;
+        uint64_t need = old_cap + (uint64_t)(mean * 2.0 * failed) + (uint64_t)failed * 64 + (1u << 20);
+        need = std::max<uint64_t>(need, old_cap * 2);
+        uint64_t cap = w.stage_cap;
+        IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
+        w.stage_cap = cap;
+        unsigned long long cur = old_cap;
+        HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
+        // the failed list becomes the input; the other list collects new failures
+        std::swap(list, fl);
+        std::swap(list_n, fl_n);
+        HIP_TRY(hipMemsetAsync(fl_n, 0, 4, st));
+        pending = failed;
+        if (guard == 63) return fail(IMM_ENOMEM, "staging could not be grown enough");
+    }
+
+    // compaction: set_off[n_sets .. n_sets+count] and the copy into the pool
+    const uint64_t stored_bound = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + count + 1, w.n_sets + 1, st, "set_off"));
+    IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, w.n_entries + stored_bound + 1, w.n_entries, st, "set_vtx"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(count), 0, st, "scan tmp"));
+    int tc = w.timer.open(1);
+    HIP_TRY(launch_scan_u32(w.sizes, w.set_off + w.n_sets, count, w.n_entries, w.scan_tmp, st));
+    HIP_TRY(launch_compact(w.stage, w.stage_off, w.set_off, w.n_sets, count, w.set_vtx, st));
+    w.timer.close(tc);
+    uint64_t p_new = 0;
+    HIP_TRY(hipMemcpyAsync(&p_new, w.set_off + w.n_sets + count, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double mean_round = (double)(p_new - w.n_entries) / (double)count;
+    w.ewma_size = w.ewma_size > 0 ? 0.5 * w.ewma_size + 0.5 * mean_round : mean_round;
+    w.n_sets += count;
+    w.n_entries = p_new;
+    return IMM_OK;
+}
+
+// Greedy selection over the whole pool: inverted index, then k argmax/cover
+// pairs. seeds_d/gains_d hold the result; the sum of the gains is returned.
+imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
+    hipStream_t st = w.st;
+    if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
+    IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, w.n_entries + 1, 0, st, "inv_set"));
+    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
+    if (w.cap_k < k) {
+        if (w.seeds_d) { HIP_TRY(hipStreamSynchronize(st)); w.arena.release(w.seeds_d); w.arena.release(w.gains_d); }
+        IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
+        IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
+        w.cap_k = k;
+    }
+    if (w.cap_kh < k) {
+        if (w.gains_h) (void)hipHostFree(w.gains_h);
+        w.gains_h = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
+        w.cap_kh = k;
+    }
+    int ti = w.timer.open(2);
+    HIP_TRY(launch_scan_u32(w.counts_acc, w.inv_off, w.n, 0, w.scan_tmp, st));
+    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, (uint32_t)w.n_sets, w.inv_off, w.inv_cursor,
+                               w.inv_set, &w.sc->err, st));
+    w.timer.close(ti);
+    int ts = w.timer.open(3);
+    HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
+    HIP_TRY(hipMemsetAsync(&w.sc->argmax_ticket, 0, 4, st));
+    const uint32_t ag = argmax_grid(w.n), cg = cover_grid(w.device);
+    for (uint32_t i = 0; i < k; ++i) {
+        HIP_TRY(launch_argmax(w.counts_work, w.n, w.partials, &w.sc->argmax_ticket, w.seeds_d,
+                              w.gains_d, i, ag, st));
+        HIP_TRY(launch_cover(w.inv_off, w.inv_set, w.set_off, w.set_vtx, w.covered, w.counts_work,
+                             w.seeds_d, i, cg, st));
+    }
+    w.timer.close(ts);
+    HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, &w.sc->err, 4, hipMemcpyDeviceToHost));
+    if (err) return fail(IMM_EDEVICE, "internal error: occurrence counts disagree with the pool");
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < k; ++i) c += w.gains_h[i];
+    *covered = c;
+    return IMM_OK;
+}
+
+// Canonical pool on the host: every set sorted ascending, sets by sample id.
+imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<uint32_t>* sv,
+                          std::vector<uint32_t>* counts) {
+    hipStream_t st = w.st;
+    if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
+    uint32_t* big_list = nullptr;
+    IMM_TRY(w.arena.alloc((void**)&big_list, (w.n_sets + 1) * 4, "sort list"));
+    HIP_TRY(hipMemsetAsync(&w.sc->big_flag, 0, 4, st));
+    HIP_TRY(launch_sort_small(w.set_off, (uint32_t)w.n_sets, w.set_vtx, big_list, &w.sc->big_flag, st));
+    IMM_TRY(ws_read_scalars(w));
+    const uint32_t nbig = w.hsc->big_flag;
+    if (nbig) {
+        std::vector<uint32_t> bl(nbig);
+        HIP_TRY(hipMemcpy(bl.data(), big_list, (uint64_t)nbig * 4, hipMemcpyDeviceToHost));
+        std::vector<uint64_t> o2(2);
+        uint64_t maxn = 0;
+        std::vector<uint32_t> np(nbig);
+        for (uint32_t b = 0; b < nbig; ++b) {
+            HIP_TRY(hipMemcpy(o2.data(), w.set_off + bl[b], 16, hipMemcpyDeviceToHost));
+            uint64_t sz = o2[1] - o2[0], p2 = 1;
+            while (p2 < sz) p2 <<= 1;
+            np[b] = (uint32_t)p2;
+            maxn = std::max(maxn, p2);
+        }
+        uint32_t* scratch = nullptr;
+        IMM_TRY(w.arena.alloc((void**)&scratch, maxn * 4, "sort scratch"));
+        for (uint32_t b = 0; b < nbig; ++b)
+            HIP_TRY(launch_sort_big(w.set_off, w.set_vtx, bl[b], np[b], scratch, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        w.arena.release(scratch);
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    w.arena.release(big_list);
+    if (so) {
+        so->resize(w.n_sets + 1);
+        HIP_TRY(hipMemcpy(so->data(), w.set_off, (w.n_sets + 1) * 8, hipMemcpyDeviceToHost));
+    }
+    if (sv) {
+        sv->resize(w.n_entries);
+        if (w.n_entries)
+            HIP_TRY(hipMemcpy(sv->data(), w.set_vtx, w.n_entries * 4, hipMemcpyDeviceToHost));
+    }
+    if (counts) {
+        counts->resize(w.n);
+        HIP_TRY(hipMemcpy(counts->data(), w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToHost));
+    }
+    return IMM_OK;
+}
+
+void fill_stats(Workspace& w, imm_stats* s) {
+    double ms[5] = {0, 0, 0, 0, 0};
+    uint64_t launches = 0;
+    w.timer.collect(ms, &launches);
+    s->ms_sample += ms[0];
+    s->ms_compact += ms[1];
+    s->ms_index += ms[2];
+    s->ms_select += ms[3];
+    s->ms_sample_main += ms[4];
+    s->main_launches += launches;
+    const unsigned long long* t = w.hsc->stats;
+    s->sets = t[kStMainSets] + t[kStBigSets];
+    s->entries = t[kStMainEntries] + t[kStBigEntries];
+    s->edges = t[kStMainEdges] + t[kStBigEdges];
+    s->live = t[kStMainLive] + t[kStBigLive];
+    s->deferred = t[kStBigSets];
+    s->main_sets = t[kStMainSets];
+    s->main_entries = t[kStMainEntries];
+    s->main_edges = t[kStMainEdges];
+    s->main_live = t[kStMainLive];
+}
+
+// ------------------------------------------------------------ theta math --
+// FP64, no contraction, this exact order (kept identical to the IMM theta
+// expressions of Tang et al. 2015: Eq. 9 lambda', Eq. 6 lambda*, with ell
+// replaced by ell (1 + ln 2 / ln n)).
+
+const double kLn2 = 0.69314718055994530942;
+const double kInvE = 0.36787944117144232160;
+
+double log_binom(uint32_t n, uint32_t k) {
+    double acc = 0.0;
+    for (uint32_t i = 1; i <= k; ++i) acc += std::log((double)(n - k + i) / (double)i);
+    return acc;
+}
+
+uint32_t bitlen(uint32_t x) {
+    uint32_t b = 0;
+    while (x) { ++b; x >>= 1; }
+    return b;
+}
+
+}  // namespace
+
+struct imm_result {
+    uint32_t k = 0;
+    std::vector<uint32_t> seeds;
+    std::vector<uint64_t> gains;
+    uint64_t theta = 0;
+    uint32_t rounds = 0;
+    double lb = 0.0;
+    uint64_t covered = 0;
+    std::vector<uint64_t> targets, round_cov;
+    bool has_pool = false;
+    std::vector<uint64_t> set_off;
+    std::vector<uint32_t> set_vtx;
+    imm_stats stats{};
+};
+
+struct imm_pool {
+    std::unique_ptr<Workspace> ws;
+    imm_stats stats{};
+};
+
+// =================================================================== ABI ===
+
+extern "C" {
+
+const char* imm_last_error(void) { return g_err.c_str(); }
+
+imm_status imm_theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* lambda_prime,
+                          double* lambda_star, uint32_t* i_max) {
+    if (n < 2 || k == 0 || k > n || !(eps > 0.0) || !(ell > 0.0))
+        return fail(IMM_EINVAL, "theta_plan: need n >= 2, 1 <= k <= n, eps > 0, ell > 0");
+    if (!lambda_prime || !lambda_star || !i_max) return fail(IMM_EINVAL, "theta_plan: null output");
+    const double ln_n = std::log((double)n);
+    const double ell_p = ell * (1.0 + kLn2 / ln_n);
+    const double logcnk = log_binom(n, k);
+    const double eps_p = std::sqrt(2.0) * eps;
+    const double lam_p = (2.0 + 2.0 / 3.0 * eps_p) *
+                         (logcnk + ell_p * ln_n + std::log(std::log2((double)n))) * (double)n /
+                         (eps_p * eps_p);
+    const double one_m = 1.0 - kInvE;
+    const double alpha = std::sqrt(ell_p * ln_n + kLn2);
+    const double beta = std::sqrt(one_m * (logcnk + ell_p * ln_n + kLn2));
+    const double t = one_m * alpha + beta;
+    const double lam_s = 2.0 * (double)n * t * t / (eps * eps);
+    *lambda_prime = lam_p;
+    *lambda_star = lam_s;
+    *i_max = bitlen(n - 1) - 1;
+    return IMM_OK;
+}
+
+imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
+                            const uint32_t* row_src, const uint32_t* weight, imm_model model,
+                            uint32_t flags, void* stream, imm_graph** out) {
+    try {
+        if (!out) return fail(IMM_EINVAL, "graph_create: null out");
+        if (n < 2 || n > 0xFFFFFFFEu) return fail(IMM_EINVAL, "graph_create: need 2 <= n <= 2^32-2");
+        if (m > 0xFFFFFFF0ull) return fail(IMM_EOVERFLOW, "graph_create: m must be < 2^32 - 16");
+        if (model != IMM_IC && model != IMM_LT) return fail(IMM_EINVAL, "graph_create: bad model");
+        if (!col_off || (m && (!row_src || !weight))) return fail(IMM_EINVAL, "graph_create: null array");
+        hipStream_t st = (hipStream_t)stream;
+        const bool dev = (flags & IMM_DEVICE_PTRS) != 0;
+        std::vector<uint64_t> h_off;
+        std::vector<uint32_t> h_src, h_w;
+        const uint64_t* co = col_off;
+        const uint32_t* rs = row_src;
+        const uint32_t* wt = weight;
+        if (dev) {
+            h_off.resize((size_t)n + 1);
+            h_src.resize(m);
+            h_w.resize(m);
+            HIP_TRY(hipMemcpyAsync(h_off.data(), col_off, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost, st));
+            if (m) {
+                HIP_TRY(hipMemcpyAsync(h_src.data(), row_src, m * 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipMemcpyAsync(h_w.data(), weight, m * 4, hipMemcpyDeviceToHost, st));
+            }
+            HIP_TRY(hipStreamSynchronize(st));
+            co = h_off.data();
+            rs = h_src.data();
+            wt = h_w.data();
+        }
+        if (co[0] != 0 || co[n] != m) return fail(IMM_EINVAL, "graph_create: col_off[0] must be 0 and col_off[n] = m");
+        for (uint32_t v = 0; v < n; ++v)
+            if (co[v] > co[v + 1]) return fail(IMM_EINVAL, "graph_create: col_off decreases");
+        for (uint64_t e = 0; e < m; ++e)
+            if (rs[e] >= n) return fail(IMM_EINVAL, "graph_create: row_src out of range");
+        if (model == IMM_LT) {
+            for (uint32_t v = 0; v < n; ++v)
+                for (uint64_t e = co[v] + 1; e < co[v + 1]; ++e)
+                    if (wt[e] < wt[e - 1]) return fail(IMM_EINVAL, "graph_create: LT cumulative table decreases within a column");
+        }
+        std::unique_ptr<imm_graph> g(new imm_graph());
+        g->n = n;
+        g->m = m;
+        g->model = model;
+        HIP_TRY(hipGetDevice(&g->device));
+        std::vector<uint32_t> off32((size_t)n + 1);
+        for (size_t v = 0; v <= n; ++v) off32[v] = (uint32_t)co[v];
+        IMM_TRY(g->arena.alloc((void**)&g->off, ((uint64_t)n + 1) * 4, "graph offsets"));
+        HIP_TRY(hipMemcpyAsync(g->off, off32.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice, st));
+        if (model == IMM_IC) {
+            const uint64_t mp = ((m + 3) & ~uint64_t(3)) + 4;
+            IMM_TRY(g->arena.alloc((void**)&g->thr, mp * 4, "thresholds"));
+            IMM_TRY(g->arena.alloc((void**)&g->src, (m ? m : 1) * 4, "sources"));
+            HIP_TRY(hipMemsetAsync(g->thr, 0, mp * 4, st));
+            if (m) {
+                HIP_TRY(hipMemcpyAsync(g->thr, wt, m * 4, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipMemcpyAsync(g->src, rs, m * 4, hipMemcpyHostToDevice, st));
+            }
+            HIP_TRY(hipStreamSynchronize(st));
+        } else {
+            std::vector<uint2> cs(m ? m : 1);
+            for (uint64_t e = 0; e < m; ++e) cs[e] = make_uint2(wt[e], rs[e]);
+            IMM_TRY(g->arena.alloc((void**)&g->cs, (m ? m : 1) * 8, "cum/src pairs"));
+            IMM_TRY(g->arena.alloc((void**)&g->guide, (m ? m : 1) * 4, "guide table"));
+            if (m) HIP_TRY(hipMemcpyAsync(g->cs, cs.data(), m * 8, hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_lt_guide(g->off, g->cs, g->guide, n, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        *out = g.release();
+        return IMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(IMM_ENOMEM, "graph_create: host allocation failed");
+    } catch (...) {
+        return fail(IMM_EDEVICE, "graph_create: unexpected exception");
+    }
+}
+
+imm_status imm_graph_destroy(imm_graph* g) {
+    if (!g) return fail(IMM_EINVAL, "graph_destroy: null graph");
+    (void)hipSetDevice(g->device);
+    delete g;
+    return IMM_OK;
+}
+
+imm_status imm_graph_info(const imm_graph* g, uint32_t* n, uint64_t* m, imm_model* model,
+                          uint64_t* device_bytes) {
+    if (!g) return fail(IMM_EINVAL, "graph_info: null graph");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (model) *model = g->model;
+    if (device_bytes) *device_bytes = g->arena.used;
+    return IMM_OK;
+}
+
+static imm_status run_impl(const imm_graph* g, const imm_params* p, hipStream_t st,
+                           imm_result** out) {
+    const double t0 = now_ms();
+    double lam_p, lam_s;
+    uint32_t i_max;
+    IMM_TRY(imm_theta_plan(g->n, p->k, p->epsilon, p->ell, &lam_p, &lam_s, &i_max));
+    HIP_TRY(hipSetDevice(g->device));
+    std::unique_ptr<Workspace> w(new Workspace());
+    IMM_TRY(ws_init(*w, g->n, g->device, st, p->max_device_bytes, (p->flags & IMM_TIMING) != 0));
+    std::unique_ptr<imm_result> r(new imm_result());
+    r->k = p->k;
+    const double eps_p = std::sqrt(2.0) * p->epsilon;
+    double lb = 1.0;
+    uint64_t cov = 0;
+    for (uint32_t i = 1; i <= i_max; ++i) {
+        const double x = std::ldexp((double)g->n, -(int)i);
+        const double tf = std::ceil(lam_p / x);
+        if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta_i >= 2^32");
+        const uint64_t target = (uint64_t)tf;
+        if (r->targets.size() < 63) r->targets.push_back(target);
+        if (w->n_sets < target) IMM_TRY(ws_extend(*w, g, p->seed, w->n_sets, target - w->n_sets));
+        IMM_TRY(ws_greedy(*w, p->k, &cov));
+        r->round_cov.push_back(cov);
+        r->rounds = i;
+        const double frac = (double)cov / (double)w->n_sets;
+        if ((double)g->n * frac >= (1.0 + eps_p) * x) {
+            lb = (double)g->n * frac / (1.0 + eps_p);
+            break;
+        }
+    }
+    const double tf = std::ceil(lam_s / lb);
+    if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta >= 2^32");
+    const uint64_t theta = (uint64_t)tf;
+    r->targets.push_back(theta);
+    if (w->n_sets < theta) IMM_TRY(ws_extend(*w, g, p->seed, w->n_sets, theta - w->n_sets));
+    IMM_TRY(ws_greedy(*w, p->k, &cov));
+    r->seeds.resize(p->k);
+    std::vector<uint32_t> g32(p->k);
+    HIP_TRY(hipMemcpy(r->seeds.data(), w->seeds_d, (uint64_t)p->k * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(g32.data(), w->gains_d, (uint64_t)p->k * 4, hipMemcpyDeviceToHost));
+    r->gains.assign(g32.begin(), g32.end());
+    r->theta = w->n_sets;
+    r->lb = lb;
+    r->covered = cov;
+    const double t1 = now_ms();
+    IMM_TRY(ws_read_scalars(*w));
+    fill_stats(*w, &r->stats);
+    r->stats.ms_total = t1 - t0;
+    r->stats.rounds = r->rounds;
+    if (p->flags & IMM_KEEP_POOL) {
+        IMM_TRY(ws_export_pool(*w, &r->set_off, &r->set_vtx, nullptr));
+        r->has_pool = true;
+    }
+    *out = r.release();
+    return IMM_OK;
+}
+
+imm_status imm_run(const imm_graph* g, const imm_params* p, void* stream, imm_result** out) {
+    if (!g || !p || !out) return fail(IMM_EINVAL, "run: null argument");
+    if (p->k == 0 || p->k > g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
+    if (!(p->epsilon > 0.0) || !(p->ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
+    try {
+        return run_impl(g, p, (hipStream_t)stream, out);
+    } catch (const std::bad_alloc&) {
+        return fail(IMM_ENOMEM, "run: host allocation failed");
+    } catch (...) {
+        return fail(IMM_EDEVICE, "run: unexpected exception");
+    }
+}
+
+imm_status imm_result_info(const imm_result* r, uint64_t* theta, uint32_t* rounds, double* lb,
+                           uint64_t* covered) {
+    if (!r) return fail(IMM_EINVAL, "result_info: null result");
+    if (theta) *theta = r->theta;
+    if (rounds) *rounds = r->rounds;
+    if (lb) *lb = r->lb;
+    if (covered) *covered = r->covered;
+    return IMM_OK;
+}
+
+imm_status imm_result_seeds(const imm_result* r, uint32_t* seeds, uint64_t* gains) {
+    if (!r) return fail(IMM_EINVAL, "result_seeds: null result");
+    if (seeds) std::memcpy(seeds, r->seeds.data(), r->seeds.size() * 4);
+    if (gains) std::memcpy(gains, r->gains.data(), r->gains.size() * 8);
+    return IMM_OK;
+}
+
+imm_status imm_result_targets(const imm_result* r, uint32_t* count, uint64_t* targets,
+                              uint64_t* round_cov) {
+    if (!r) return fail(IMM_EINVAL, "result_targets: null result");
+    const size_t nt = std::min<size_t>(r->targets.size(), 64);
+    if (count) *count = (uint32_t)nt;
+    if (targets) std::memcpy(targets, r->targets.data(), nt * 8);
+    if (round_cov) std::memcpy(round_cov, r->round_cov.data(), std::min<size_t>(r->round_cov.size(), 64) * 8);
+    return IMM_OK;
+}
+
+imm_status imm_result_pool(const imm_result* r, uint64_t* n_sets, uint64_t* n_entries,
+                           uint64_t* set_off, uint32_t* set_vtx) {
+    if (!r) return fail(IMM_EINVAL, "result_pool: null result");
+    if (!r->has_pool) return fail(IMM_EINVAL, "result_pool: run without IMM_KEEP_POOL");
+    if (n_sets) *n_sets = r->set_off.size() - 1;
+    if (n_entries) *n_entries = r->set_vtx.size();
+    if (set_off) std::memcpy(set_off, r->set_off.data(), r->set_off.size() * 8);
+    if (set_vtx && !r->set_vtx.empty()) std::memcpy(set_vtx, r->set_vtx.data(), r->set_vtx.size() * 4);
+    return IMM_OK;
+}
+
+imm_status imm_result_stats(const imm_result* r, imm_stats* stats) {
+    if (!r || !stats) return fail(IMM_EINVAL, "result_stats: null argument");
+    *stats = r->stats;
+    return IMM_OK;
+}
+
+void imm_result_destroy(imm_result* r) { delete r; }
+
+imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint64_t count,
+                      uint32_t flags, void* stream, imm_pool** out) {
+    if (!g || !out) return fail(IMM_EINVAL, "sample: null argument");
+    if (count == 0 || first_id + count < first_id) return fail(IMM_EINVAL, "sample: bad id range");
+    if (count > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sample: count >= 2^32");
+    try {
+        const double t0 = now_ms();
+        hipStream_t st = (hipStream_t)stream;
+        HIP_TRY(hipSetDevice(g->device));
+        std::unique_ptr<imm_pool> p(new imm_pool());
+        p->ws.reset(new Workspace());
+        IMM_TRY(ws_init(*p->ws, g->n, g->device, st, 0, (flags & IMM_TIMING) != 0));
+        IMM_TRY(ws_extend(*p->ws, g, seed, first_id, count));
+        IMM_TRY(ws_read_scalars(*p->ws));
+        p->stats.ms_total = now_ms() - t0;
+        fill_stats(*p->ws, &p->stats);
+        *out = p.release();
+        return IMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(IMM_ENOMEM, "sample: host allocation failed");
+    } catch (...) {
+        return fail(IMM_EDEVICE, "sample: unexpected exception");
+    }
+}
+
+imm_status imm_pool_info(const imm_pool* p, uint64_t* n_sets, uint64_t* n_entries,
+                         imm_stats* stats) {
+    if (!p) return fail(IMM_EINVAL, "pool_info: null pool");
+    if (n_sets) *n_sets = p->ws->n_sets;
+    if (n_entries) *n_entries = p->ws->n_entries;
+    if (stats) *stats = p->stats;
+    return IMM_OK;
+}
+
+imm_status imm_pool_export(const imm_pool* p, uint64_t* set_off, uint32_t* set_vtx,
+                           uint32_t* counts) {
+    if (!p) return fail(IMM_EINVAL, "pool_export: null pool");
+    try {
+        HIP_TRY(hipSetDevice(p->ws->device));
+        std::vector<uint64_t> so;
+        std::vector<uint32_t> sv, cn;
+        IMM_TRY(ws_export_pool(*p->ws, set_off ? &so : nullptr, set_vtx ? &sv : nullptr,
+                               counts ? &cn : nullptr));
+        if (set_off) std::memcpy(set_off, so.data(), so.size() * 8);
+        if (set_vtx && !sv.empty()) std::memcpy(set_vtx, sv.data(), sv.size() * 4);
+        if (counts) std::memcpy(counts, cn.data(), cn.size() * 4);
+        return IMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(IMM_ENOMEM, "pool_export: host allocation failed");
+    }
+}
+
+void imm_pool_destroy(imm_pool* p) { delete p; }
+
+imm_status imm_greedy(uint32_t n, const uint64_t* set_off, const uint32_t* set_vtx,
+                      uint64_t n_sets, uint32_t k, uint32_t flags, void* stream, uint32_t* seeds,
+                      uint64_t* gains, uint64_t* covered) {
+    if (n < 1 || n > 0xFFFFFFFEu || k == 0 || k > n) return fail(IMM_EINVAL, "greedy: need 1 <= k <= n");
+    if (n_sets >= 0xFFFFFFFFull) return fail(IMM_EINVAL, "greedy: n_sets must be < 2^32");
+    if (!set_off || !seeds) return fail(IMM_EINVAL, "greedy: null argument");
+    try {
+        hipStream_t st = (hipStream_t)stream;
+        const bool devp = (flags & IMM_DEVICE_PTRS) != 0;
+        std::vector<uint64_t> h_off;
+        const uint64_t* so = set_off;
+        if (devp) {
+            h_off.resize(n_sets + 1);
+            HIP_TRY(hipMemcpy(h_off.data(), set_off, (n_sets + 1) * 8, hipMemcpyDeviceToHost));
+            so = h_off.data();
+        }
+        if (so[0] != 0) return fail(IMM_EINVAL, "greedy: set_off[0] must be 0");
+        for (uint64_t j = 0; j < n_sets; ++j)
+            if (so[j] > so[j + 1]) return fail(IMM_EINVAL, "greedy: set_off decreases");
+        const uint64_t P = so[n_sets];
+        if (P && !set_vtx) return fail(IMM_EINVAL, "greedy: null set_vtx");
+        if (!devp) {
+            for (uint64_t t = 0; t < P; ++t)
+                if (set_vtx[t] >= n) return fail(IMM_EINVAL, "greedy: vertex id out of range");
+        }
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        Workspace w;
+        IMM_TRY(ws_init(w, n, dev, st, 0, false));
+        IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, n_sets + 1, 0, st, "set_off"));
+        IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, P + 1, 0, st, "set_vtx"));
+        const hipMemcpyKind kind = devp ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIP_TRY(hipMemcpyAsync(w.set_off, set_off, (n_sets + 1) * 8, kind, st));
+        if (P) HIP_TRY(hipMemcpyAsync(w.set_vtx, set_vtx, P * 4, kind, st));
+        if (devp) {
+            HIP_TRY(hipMemsetAsync(&w.sc->big_flag, 0, 4, st));
+            HIP_TRY(launch_validate_pool(w.set_off, n_sets, w.set_vtx, n, &w.sc->big_flag, st));
+            IMM_TRY(ws_read_scalars(w));
+            if (w.hsc->big_flag) return fail(IMM_EINVAL, "greedy: vertex id out of range");
+        }
+        HIP_TRY(launch_count_entries(w.set_vtx, P, w.counts_acc, st));
+        w.n_sets = n_sets;
+        w.n_entries = P;
+        uint64_t cov = 0;
+        IMM_TRY(ws_greedy(w, k, &cov));
+        std::vector<uint32_t> s32(k), g32(k);
+        HIP_TRY(hipMemcpy(s32.data(), w.seeds_d, (uint64_t)k * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(g32.data(), w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost));
+        std::memcpy(seeds, s32.data(), (size_t)k * 4);
+        if (gains)
+            for (uint32_t i = 0; i < k; ++i) gains[i] = g32[i];
+        if (covered) *covered = cov;
+        return IMM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(IMM_ENOMEM, "greedy: host allocation failed");
+    }
+}
+
+imm_status imm_philox4x32_10(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t flags,
+                             void* stream, uint32_t* out) {
+    if (!ctr || !out) return fail(IMM_EINVAL, "philox: null argument");
+    if (count == 0) return IMM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool devp = (flags & IMM_DEVICE_PTRS) != 0;
+    if (devp) {
+        HIP_TRY(launch_philox(ctr, count, key, out, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return IMM_OK;
+    }
+    Arena a;
+    uint32_t *dc = nullptr, *dout = nullptr;
+    IMM_TRY(a.alloc((void**)&dc, count * 16, "philox counters"));
+    IMM_TRY(a.alloc((void**)&dout, count * 16, "philox output"));
+    HIP_TRY(hipMemcpyAsync(dc, ctr, count * 16, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_philox(dc, count, key, dout, st));
+    HIP_TRY(hipMemcpyAsync(out, dout, count * 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// imm_internal.hpp -- host-side declarations shared by the libimm translation
+// units: device views of a resident graph, sampling outputs, and the kernel
+// launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace imm {
+
+// Resident IC graph: CSC offsets, live thresholds padded to a multiple of 4
+// (+4) entries so a 16-byte load of edge group e>>2 stays in bounds, sources.
+struct IcGraphDev {
+    const uint32_t* off;  // n+1
+    const uint32_t* thr;  // round_up(m,4)+4
+    const uint32_t* src;  // m
+    uint32_t n;
+    uint32_t m;
+};
+
+// Resident LT graph: offsets, (cum, src) pairs per in-edge, and the guide
+// table: for column v of in-degree d, guide[off[v]+j] is the first edge e of
+// the column with cum[e] > ceil(j 2^32 / d) - 1, i.e. the answer for the
+// smallest draw that falls in bucket j = floor(r d / 2^32).
+struct LtGraphDev {
+    const uint32_t* off;   // n+1
+    const uint2* cs;       // m (x = cum, y = src)
+    const uint32_t* guide; // m
+    uint32_t n;
+    uint32_t m;
+};
+
+// Work granules of the sampling kernels: sample ids claimed per ticket by a
+// wave of the IC kernel, staging entries it reserves at a time, and staging
+// entries an LT lane reserves at a time (also the longest walk it keeps).
+constexpr uint32_t kIcTicketChunk = 16;
+constexpr uint32_t kIcStageChunk = 4096;
+constexpr uint32_t kLtChunk = 1024;
+
+// Samples [id_lo, id_lo + count) of run seed `seed`.
+struct SampleRange {
+    uint64_t seed;
+    uint64_t id_lo;
+    uint32_t count;
+};
+
+// Stats slots (uint64 counters in device memory).
+enum StatSlot : int {
+    kStMainSets = 0, kStMainEntries, kStMainEdges, kStMainLive,
+    kStBigSets, kStBigEntries, kStBigEdges, kStBigLive, kStCount
+};
+
+// Where sampled sets go: a staging buffer with a bump cursor, per-sample
+// (stage offset, size), the accumulated occurrence counts, and the lists of
+// sample indices that must be redone by the large-set kernel (defer: the set
+// outgrew the on-chip structures; retry: the staging buffer was full).
+struct SampleOut {
+    uint32_t* stage;
+    uint64_t stage_cap;
+    unsigned long long* cursor;
+    uint64_t* stage_off;   // [count]
+    uint32_t* sizes;       // [count]
+    uint32_t* counts;      // [n]
+    uint32_t* defer;       // [count]
+    uint32_t* defer_n;
+    uint32_t* retry;       // [count]
+    uint32_t* retry_n;
+    unsigned long long* stats;  // [kStCount]
+};
+
+// Scratch of the large-set kernels: per slot a visited bitmap of `words`
+// uint32 (all zero between samples) and a queue of n uint32.
+struct BigScratch {
+    uint32_t* bitmaps;
+    uint32_t* queues;
+    uint32_t words;
+    uint32_t slots;
+};
+
+// ---- sampling (k_sample_ic.hip, k_sample_lt.hip)
+hipError_t launch_ic_small(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           uint32_t* ticket, uint32_t grid, hipStream_t st);
+hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
+                           uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
+                           hipStream_t st);
+hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           uint32_t* ticket, uint32_t grid, hipStream_t st);
+hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
+                           uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
+                           hipStream_t st);
+hipError_t launch_lt_guide(const uint32_t* off, const uint2* cs, uint32_t* guide, uint32_t n,
+                           hipStream_t st);
+uint32_t ic_small_grid(int device);
+uint32_t lt_small_grid(int device);
+
+// ---- pool, index, canonical order (k_pool.hip)
+// out[0] = base; out[i+1] = base + in[0] + ... + in[i]  (N entries in).
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t base,
+                           uint64_t* tile_tmp, hipStream_t st);
+uint64_t scan_tmp_entries(uint64_t N);
+// Copy staged sets [lo, lo+count) to set_vtx at set_off[lo..lo+count].
+hipError_t launch_compact(const uint32_t* stage, const uint64_t* stage_off,
+                          const uint64_t* set_off, uint64_t lo, uint32_t count,
+                          uint32_t* set_vtx, hipStream_t st);
+// inv_set[inv_off[v] + rank] = j for each member v of set j (rank by atomic
+// cursor); *err |= 1 if a vertex has more members than inv_off allows.
+hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint32_t n_sets,
+                              const uint64_t* inv_off, uint32_t* cursor, uint32_t* inv_set,
+                              uint32_t* err, hipStream_t st);
+// counts[v] += occurrences of v in set_vtx[0..P).
+hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
+                                hipStream_t st);
+// Check a caller pool: offsets non-decreasing, ids < n. flag[0] set on error.
+hipError_t launch_validate_pool(const uint64_t* set_off, uint64_t n_sets, const uint32_t* set_vtx,
+                                uint32_t n, uint32_t* flag, hipStream_t st);
+// Sort every set ascending in place; big_list/big_n get the sets too large
+// for the on-chip sort, which launch_sort_big then sorts one at a time.
+hipError_t launch_sort_small(const uint64_t* set_off, uint32_t n_sets, uint32_t* set_vtx,
+                             uint32_t* big_list, uint32_t* big_n, hipStream_t st);
+// Sort set j (size <= n_pow2, a power of two) using scratch[n_pow2].
+hipError_t launch_sort_big(const uint64_t* set_off, uint32_t* set_vtx, uint32_t j,
+                           uint32_t n_pow2, uint32_t* scratch, hipStream_t st);
+constexpr uint32_t kSortSmallMax = 4096;
+
+// ---- greedy selection (k_select.hip)
+uint32_t argmax_grid(uint32_t n);
+hipError_t launch_argmax(uint32_t* counts_work, uint32_t n, unsigned long long* partials,
+                         uint32_t* ticket, uint32_t* seeds, uint32_t* gains, uint32_t i,
+                         uint32_t grid, hipStream_t st);
+hipError_t launch_cover(const uint64_t* inv_off, const uint32_t* inv_set, const uint64_t* set_off,
+                        const uint32_t* set_vtx, uint32_t* covered, uint32_t* counts_work,
+                        const uint32_t* seeds, uint32_t i, uint32_t grid, hipStream_t st);
+uint32_t cover_grid(int device);
+
+// ---- misc
+hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,
+                         hipStream_t st);
+
+}  // namespace imm

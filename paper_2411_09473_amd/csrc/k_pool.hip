@@ -1,0 +1,332 @@
+// k_pool.hip -- RRR pool construction and the vertex->sets inverted index.
+//
+//  * scan: exclusive prefix sums of uint32 values into uint64 offsets
+//    (reduce tiles, scan the tile sums in one block, rescan tiles with carry).
+//  * compact: staged sets -> a CSR pool in sample-id order.
+//  * inverted index: inv_off = scan(counts); each member v of set j writes j
+//    into v's list, so covering the sets of a chosen seed (Algorithm 2,
+//    "if v in R") touches only those sets instead of testing every set.
+//  * canonical order for export: each set sorted ascending in place.
+// Segmented loops give the entries of 64 consecutive sets to the 64 lanes of
+// a wave, so the work stays balanced whatever the mix of set sizes.
+#include "device_common.hpp"
+#include "imm_internal.hpp"
+
+namespace imm {
+
+namespace {
+
+constexpr uint32_t kScanBS = 256;
+constexpr uint32_t kScanIPT = 8;
+constexpr uint32_t kScanTile = kScanBS * kScanIPT;
+
+__device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* s_w) {
+    const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    v = wave_sum64(v);
+    if (lane == 0) s_w[w] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) t += s_w[i];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan of one uint64 per thread across the block; returns the total.
+__device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* excl,
+                                                      uint64_t* s_w) {
+    const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint64_t incl = wave_incl_scan64(v);
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) {
+        const uint64_t x = s_w[i];
+        if (i < w) before += x;
+        total += x;
+    }
+    __syncthreads();
+    *excl = before + incl - v;
+    return total;
+}
+
+__global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in, uint64_t N,
+                                                             uint64_t* tile_sum) {
+    __shared__ uint64_t s_w[kScanBS / kWave];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t acc = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanIPT; ++k) {
+        const uint64_t i = base + (uint64_t)k * kScanBS + threadIdx.x;
+        if (i < N) acc += in[i];
+    }
+    const uint64_t t = block_sum64(acc, s_w);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t* tile_sum, uint64_t tiles) {
+    __shared__ uint64_t s_w[1024 / kWave];
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint64_t c = 0; c < tiles; c += 1024) {
+        const uint64_t i = c + threadIdx.x;
+        const uint64_t v = i < tiles ? tile_sum[i] : 0;
+        uint64_t excl;
+        const uint64_t total = block_excl_scan64(v, &excl, s_w);
+        const uint64_t carry = s_carry;
+        if (i < tiles) tile_sum[i] = carry + excl;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanBS) void scan_apply_kernel(const uint32_t* in, uint64_t N,
+                                                             const uint64_t* tile_off,
+                                                             uint64_t* out, uint64_t base) {
+    __shared__ uint64_t s_w[kScanBS / kWave];
+    const uint64_t tb = (uint64_t)blockIdx.x * kScanTile;
+    const uint64_t my = tb + (uint64_t)threadIdx.x * kScanIPT;  // kScanIPT consecutive
+    uint32_t v[kScanIPT];
+    uint64_t acc = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanIPT; ++k) {
+        v[k] = (my + k < N) ? in[my + k] : 0u;
+        acc += v[k];
+    }
+    uint64_t excl;
+    block_excl_scan64(acc, &excl, s_w);
+    uint64_t run = base + tile_off[blockIdx.x] + excl;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanIPT; ++k) {
+        run += v[k];
+        if (my + k < N) out[my + k + 1] = run;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = base;
+}
+
+__global__ __launch_bounds__(64) void compact_kernel(const uint32_t* stage,
+                                                     const uint64_t* stage_off,
+                                                     const uint64_t* set_off, uint64_t lo,
+                                                     uint32_t count, uint32_t* set_vtx) {
+    const uint64_t i = (uint64_t)blockIdx.x * kWave + threadIdx.x;
+    uint32_t sz = 0;
+    uint64_t src = 0, dst = 0;
+    if (i < count) {
+        dst = set_off[lo + i];
+        sz = (uint32_t)(set_off[lo + i + 1] - dst);
+        src = stage_off[i];
+    }
+    wave_segments(sz, src, dst, [&](uint32_t, uint64_t s0, uint64_t d0, uint32_t k) {
+        set_vtx[d0 + k] = stage[s0 + k];
+    });
+}
+
+// A member beyond its vertex's counted occurrences would mean the counts and
+// the pool disagree; it is not written and raises *err instead.
+__global__ __launch_bounds__(64) void inv_scatter_kernel(const uint64_t* set_off,
+                                                         const uint32_t* set_vtx,
+                                                         uint32_t n_sets, const uint64_t* inv_off,
+                                                         uint32_t* cursor, uint32_t* inv_set,
+                                                         uint32_t* err) {
+    const uint64_t j = (uint64_t)blockIdx.x * kWave + threadIdx.x;
+    uint32_t sz = 0;
+    uint64_t a = 0;
+    if (j < n_sets) {
+        a = set_off[j];
+        sz = (uint32_t)(set_off[j + 1] - a);
+    }
+    wave_segments(sz, a, j, [&](uint32_t, uint64_t a0, uint64_t jj, uint32_t k) {
+        const uint32_t u = set_vtx[a0 + k];
+        const uint32_t r = atomicAdd(&cursor[u], 1u);
+        const uint64_t lo = inv_off[u];
+        if (lo + r < inv_off[u + 1]) inv_set[lo + r] = (uint32_t)jj;
+        else atomicOr(err, 1u);
+    });
+}
+
+__global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_vtx, uint64_t P,
+                                                            uint32_t* counts) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride)
+        atomicAdd(&counts[set_vtx[t]], 1u);
+}
+
+__global__ __launch_bounds__(256) void validate_kernel(const uint64_t* set_off, uint64_t n_sets,
+                                                       const uint32_t* set_vtx, uint32_t n,
+                                                       uint32_t* flag) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t P = set_off[n_sets];
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_sets; j += stride)
+        if (set_off[j] > set_off[j + 1]) atomicOr(flag, 1u);
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride)
+        if (set_vtx[t] >= n) atomicOr(flag, 2u);
+}
+
+// Bitonic sort of buf[0..N) (N a power of two) by one wave; ascending.
+__device__ __forceinline__ void wave_bitonic(uint32_t* buf, uint32_t N) {
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = lane; i < N; i += kWave) {
+                const uint32_t p = i ^ j;
+                if (p > i) {
+                    const uint32_t a = buf[i], b = buf[p];
+                    const bool asc = (i & k) == 0;
+                    if ((a > b) == asc) {
+                        buf[i] = b;
+                        buf[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void sort_small_kernel(const uint64_t* set_off, uint32_t n_sets,
+                                                        uint32_t* set_vtx, uint32_t* big_list,
+                                                        uint32_t* big_n) {
+    __shared__ uint32_t buf[kSortSmallMax];
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t j = blockIdx.x; j < n_sets; j += gridDim.x) {
+        const uint64_t a = set_off[j];
+        const uint32_t sz = (uint32_t)(set_off[j + 1] - a);
+        if (sz <= 1) continue;
+        if (sz > kSortSmallMax) {
+            if (lane == 0) big_list[atomicAdd(big_n, 1u)] = j;
+            continue;
+        }
+        uint32_t N = 2;
+        while (N < sz) N <<= 1;
+        for (uint32_t i = lane; i < N; i += kWave) buf[i] = i < sz ? set_vtx[a + i] : kEmpty;
+        __syncthreads();
+        wave_bitonic(buf, N);
+        for (uint32_t i = lane; i < sz; i += kWave) set_vtx[a + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+// One block per big set, bitonic network over a padded copy in scratch.
+__global__ __launch_bounds__(1024) void sort_big_kernel(const uint64_t* set_off,
+                                                        uint32_t* set_vtx, uint32_t j,
+                                                        uint32_t* scratch, uint32_t N) {
+    const uint64_t a = set_off[j];
+    const uint32_t sz = (uint32_t)(set_off[j + 1] - a);
+    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) scratch[i] = i < sz ? set_vtx[a + i] : kEmpty;
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+                const uint32_t p = i ^ jj;
+                if (p > i) {
+                    const uint32_t x = scratch[i], y = scratch[p];
+                    const bool asc = (i & k) == 0;
+                    if ((x > y) == asc) {
+                        scratch[i] = y;
+                        scratch[p] = x;
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) set_vtx[a + i] = scratch[i];
+}
+
+__global__ __launch_bounds__(256) void philox_kernel(const uint32_t* ctr, uint64_t count,
+                                                     uint64_t key, uint32_t* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint4 c = reinterpret_cast<const uint4*>(ctr)[i];
+    const Philox4 r = philox10(c.x, c.y, c.z, c.w, (uint32_t)key, (uint32_t)(key >> 32));
+    reinterpret_cast<uint4*>(out)[i] = make_uint4(r.x, r.y, r.z, r.w);
+}
+
+uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g == 0) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+uint64_t scan_tmp_entries(uint64_t N) { return (N + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t base,
+                           uint64_t* tile_tmp, hipStream_t st) {
+    if (N == 0) {
+        return hipMemcpyAsync(out, &base, sizeof(uint64_t), hipMemcpyHostToDevice, st);
+    }
+    const uint64_t tiles = (N + kScanTile - 1) / kScanTile;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, N,
+                       tile_tmp);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, tile_tmp, tiles);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, N,
+                       tile_tmp, out, base);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const uint32_t* stage, const uint64_t* stage_off,
+                          const uint64_t* set_off, uint64_t lo, uint32_t count,
+                          uint32_t* set_vtx, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + kWave - 1) / kWave;
+    hipLaunchKernelGGL(compact_kernel, dim3(blocks), dim3(kWave), 0, st, stage, stage_off,
+                       set_off, lo, count, set_vtx);
+    return hipGetLastError();
+}
+
+hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint32_t n_sets,
+                              const uint64_t* inv_off, uint32_t* cursor, uint32_t* inv_set,
+                              uint32_t* err, hipStream_t st) {
+    if (n_sets == 0) return hipSuccess;
+    const uint32_t blocks = (n_sets + kWave - 1) / kWave;
+    hipLaunchKernelGGL(inv_scatter_kernel, dim3(blocks), dim3(kWave), 0, st, set_off, set_vtx,
+                       n_sets, inv_off, cursor, inv_set, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
+                                hipStream_t st) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(count_entries_kernel, dim3(grid_for(P, 256 * 8, 8192)), dim3(256), 0, st,
+                       set_vtx, P, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_pool(const uint64_t* set_off, uint64_t n_sets, const uint32_t* set_vtx,
+                                uint32_t n, uint32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(validate_kernel, dim3(2048), dim3(256), 0, st, set_off, n_sets, set_vtx, n,
+                       flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_small(const uint64_t* set_off, uint32_t n_sets, uint32_t* set_vtx,
+                             uint32_t* big_list, uint32_t* big_n, hipStream_t st) {
+    if (n_sets == 0) return hipSuccess;
+    hipLaunchKernelGGL(sort_small_kernel, dim3(grid_for(n_sets, 1, 16384)), dim3(kWave), 0, st,
+                       set_off, n_sets, set_vtx, big_list, big_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_big(const uint64_t* set_off, uint32_t* set_vtx, uint32_t j,
+                           uint32_t n_pow2, uint32_t* scratch, hipStream_t st) {
+    hipLaunchKernelGGL(sort_big_kernel, dim3(1), dim3(1024), 0, st, set_off, set_vtx, j, scratch,
+                       n_pow2);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,
+                         hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, st, ctr,
+                       count, key, out);
+    return hipGetLastError();
+}
+
+}  // namespace imm

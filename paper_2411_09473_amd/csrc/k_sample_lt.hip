@@ -1,0 +1,321 @@
+// k_sample_lt.hip -- LT RRR sampling as reverse live-edge walks, with fused
+// occurrence counts (Generate_RRRsets, Algorithm 3; LT model of Section II-A
+// in its live-edge form: every vertex keeps at most one live in-edge).
+//
+// A walk is a chain of dependent loads, so one lane runs one walk and a wave
+// keeps 64 walks in flight; a lane whose walk ends takes the next sample at
+// once (wave-aggregated tickets), which keeps the memory system busy.
+//  * The live in-edge of v is the first e of v's column with r < cum[e]. The
+//    guide table jumps to the first candidate of r's bucket j = floor(r d /
+//    2^32), from where a short forward scan over (cum, src) pairs finds the
+//    same edge the plain search would.
+//  * The path is written straight into the lane's staging chunk. A per-lane
+//    1024-bit map in LDS answers "not on the path" for most vertices; a hit
+//    is confirmed by rescanning the path, so the test is exact.
+//  * Counts are incremented as vertices join the path; a walk that has to
+//    move to the large-walk kernel (path longer than a chunk) or to a retry
+//    (staging full) gives its increments back first.
+#include "device_common.hpp"
+#include "imm_internal.hpp"
+
+namespace imm {
+
+namespace {
+
+constexpr uint32_t kBloomBits = 10;   // 1024-bit path filter per lane
+constexpr uint32_t kBloomWords = (1u << kBloomBits) / 32;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t bloom_hash(uint32_t v) {
+    return (v * 0x9E3779B1u) >> (32 - kBloomBits);
+}
+
+// The live in-edge source of `cur` for draw r, or kNone. *reads counts the
+// (cum, src) pairs inspected.
+__device__ __forceinline__ uint32_t lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
+                                            uint32_t r, uint32_t* reads) {
+    const uint32_t d = end - beg;
+    const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    uint32_t e = g.guide[beg + jb];
+    while (e < end) {
+        const uint2 p = g.cs[e];
+        ++*reads;
+        if (r < p.x) return p.y;
+        ++e;
+    }
+    return kNone;
+}
+
+__global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
+                                                      uint32_t* ticket) {
+    __shared__ uint32_t bloom[kBloomWords * kWave];
+    const uint32_t lane = threadIdx.x;
+    uint32_t* mb = bloom + lane;  // word w of this lane's filter is mb[w * 64]
+
+    bool has = false, done = false;
+    uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
+    uint64_t s = 0, chunk_base = 0;
+    uint32_t w_steps = 0, w_reads = 0;
+    uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
+
+    for (;;) {
+        const bool need = !has && !done;
+        const uint64_t mask = __ballot(need);
+        if (mask) {
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(ticket, (uint32_t)__popcll(mask));
+            base = __shfl(base, leader, kWave);
+            if (need) {
+                idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                if (idx >= rg.count) {
+                    done = true;
+                } else {
+                    s = rg.id_lo + idx;
+                    cur = sample_root(rg.seed, s, g.n);
+                    bool ok = true;
+                    if (chunk_used >= kLtChunk) {
+                        const uint64_t nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                        if (nb + kLtChunk > o.stage_cap) {
+                            o.retry[atomicAdd(o.retry_n, 1u)] = idx;
+                            ok = false;
+                        } else {
+                            chunk_base = nb;
+                            chunk_used = 0;
+                        }
+                    }
+                    if (ok) {
+#pragma unroll
+                        for (uint32_t wd = 0; wd < kBloomWords; ++wd) mb[wd * kWave] = 0u;
+                        wstart = chunk_used;
+                        o.stage[chunk_base + wstart] = cur;
+                        atomicAdd(&o.counts[cur], 1u);
+                        const uint32_t h = bloom_hash(cur);
+                        mb[(h >> 5) * kWave] |= 1u << (h & 31);
+                        len = 1;
+                        w_steps = 0;
+                        w_reads = 0;
+                        has = true;
+                    }
+                }
+            }
+        }
+        if (!__any(has)) break;
+        if (has) {
+            // one step of the walk
+            const uint32_t beg = g.off[cur], end = g.off[cur + 1];
+            uint32_t nxt = kNone;
+            if (beg < end) {
+                const uint32_t r = lt_draw(rg.seed, s, cur);
+                ++w_steps;
+                nxt = lt_pick(g, beg, end, r, &w_reads);
+            }
+            bool finish = nxt == kNone;
+            if (!finish) {
+                const uint32_t h = bloom_hash(nxt);
+                const uint32_t bit = 1u << (h & 31);
+                if (mb[(h >> 5) * kWave] & bit) {
+                    const uint32_t* path = o.stage + chunk_base + wstart;
+                    for (uint32_t t = 0; t < len; ++t) {
+                        if (path[t] == nxt) {
+                            finish = true;
+                            break;
+                        }
+                    }
+                }
+                if (!finish) {
+                    bool keep = true;
+                    if (wstart + len == kLtChunk) {
+                        bool moved = false;
+                        if (wstart != 0) {
+                            const uint64_t nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                            if (nb + kLtChunk <= o.stage_cap) {
+                                for (uint32_t t = 0; t < len; ++t)
+                                    o.stage[nb + t] = o.stage[chunk_base + wstart + t];
+                                chunk_base = nb;
+                                wstart = 0;
+                                moved = true;
+                            } else {
+                                o.retry[atomicAdd(o.retry_n, 1u)] = idx;
+                            }
+                        } else {
+                            o.defer[atomicAdd(o.defer_n, 1u)] = idx;
+                        }
+                        if (!moved) {
+                            for (uint32_t t = 0; t < len; ++t)
+                                atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
+                            chunk_used = wstart;
+                            has = false;
+                            keep = false;
+                        }
+                    }
+                    if (keep) {
+                        o.stage[chunk_base + wstart + len] = nxt;
+                        atomicAdd(&o.counts[nxt], 1u);
+                        mb[(h >> 5) * kWave] |= bit;
+                        ++len;
+                        cur = nxt;
+                    }
+                }
+            }
+            if (finish) {
+                o.stage_off[idx] = chunk_base + wstart;
+                o.sizes[idx] = len;
+                chunk_used = wstart + len;
+                st_sets += 1;
+                st_entries += len;
+                st_steps += w_steps;
+                st_reads += w_reads;
+                has = false;
+            }
+        }
+    }
+    st_sets = wave_sum64(st_sets);
+    st_entries = wave_sum64(st_entries);
+    st_steps = wave_sum64(st_steps);
+    st_reads = wave_sum64(st_reads);
+    if (lane == 0) {
+        atomicAdd(&o.stats[kStMainSets], (unsigned long long)st_sets);
+        atomicAdd(&o.stats[kStMainEntries], (unsigned long long)st_entries);
+        atomicAdd(&o.stats[kStMainEdges], (unsigned long long)st_steps);
+        atomicAdd(&o.stats[kStMainLive], (unsigned long long)st_reads);
+    }
+}
+
+// Walks handed over by lt_small_kernel: one walk per wave, lane 0 walks with
+// an exact visited bitmap in device memory (slot per workgroup), then the
+// wave stages the path and counts it.
+__global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
+                                                      const uint32_t* list, const uint32_t* list_n,
+                                                      uint32_t* fail, uint32_t* fail_n,
+                                                      uint32_t* ticket, BigScratch b) {
+    __shared__ uint32_t s_i, s_len;
+    __shared__ unsigned long long s_off, s_steps, s_reads;
+    const uint32_t lane = threadIdx.x;
+    uint32_t* bm = b.bitmaps + (size_t)blockIdx.x * b.words;
+    uint32_t* q = b.queues + (size_t)blockIdx.x * g.n;
+    const uint32_t cnt = *list_n;
+    uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
+    for (;;) {
+        if (lane == 0) s_i = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t li = s_i;
+        __syncthreads();
+        if (li >= cnt) break;
+        const uint32_t idx = list[li];
+        const uint64_t s = rg.id_lo + idx;
+        if (lane == 0) {
+            uint32_t cur = sample_root(rg.seed, s, g.n);
+            uint32_t len = 0, steps = 0, reads = 0;
+            q[len++] = cur;
+            atomicOr(&bm[cur >> 5], 1u << (cur & 31));
+            for (;;) {
+                const uint32_t beg = g.off[cur], end = g.off[cur + 1];
+                if (beg == end) break;
+                const uint32_t r = lt_draw(rg.seed, s, cur);
+                ++steps;
+                const uint32_t nxt = lt_pick(g, beg, end, r, &reads);
+                if (nxt == kNone) break;
+                const uint32_t bit = 1u << (nxt & 31);
+                if (atomicOr(&bm[nxt >> 5], bit) & bit) break;
+                q[len++] = nxt;
+                cur = nxt;
+            }
+            s_len = len;
+            s_steps = steps;
+            s_reads = reads;
+            s_off = atomicAdd(o.cursor, (unsigned long long)len);
+        }
+        __threadfence();
+        __syncthreads();
+        const uint32_t len = s_len;
+        const uint64_t off = s_off;
+        const bool fits = off + len <= o.stage_cap;
+        for (uint32_t i = lane; i < len; i += kWave) {
+            const uint32_t u = q[i];
+            if (fits) {
+                o.stage[off + i] = u;
+                atomicAdd(&o.counts[u], 1u);
+            }
+            __hip_atomic_store(&bm[u >> 5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) {
+            if (fits) {
+                o.stage_off[idx] = off;
+                o.sizes[idx] = len;
+                st_sets += 1;
+                st_entries += len;
+                st_steps += s_steps;
+                st_reads += s_reads;
+            } else {
+                fail[atomicAdd(fail_n, 1u)] = idx;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    if (lane == 0) {
+        atomicAdd(&o.stats[kStBigSets], (unsigned long long)st_sets);
+        atomicAdd(&o.stats[kStBigEntries], (unsigned long long)st_entries);
+        atomicAdd(&o.stats[kStBigEdges], (unsigned long long)st_steps);
+        atomicAdd(&o.stats[kStBigLive], (unsigned long long)st_reads);
+    }
+}
+
+// guide[beg + j] = first e in [beg, end) with cum[e] > ceil(j 2^32 / d) - 1,
+// or end if there is none, for every column (64 columns per wave).
+__global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const uint2* cs,
+                                                      uint32_t* guide, uint32_t n) {
+    const uint64_t v = (uint64_t)blockIdx.x * kWave + threadIdx.x;
+    uint32_t sz = 0;
+    uint64_t beg = 0;
+    if (v < n) {
+        beg = off[v];
+        sz = off[v + 1] - (uint32_t)beg;
+    }
+    wave_segments(sz, beg, sz, [&](uint32_t, uint64_t b0, uint64_t d, uint32_t j) {
+        const uint64_t lo = (((uint64_t)j << 32) + d - 1) / d;  // smallest r in bucket j
+        uint32_t a = (uint32_t)b0, z = (uint32_t)(b0 + d);      // first e with cum[e] > lo
+        while (a < z) {
+            const uint32_t mid = a + ((z - a) >> 1);
+            if ((uint64_t)cs[mid].x > lo) z = mid; else a = mid + 1;
+        }
+        guide[b0 + j] = a;
+    });
+}
+
+}  // namespace
+
+uint32_t lt_small_grid(int device) {
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    return (uint32_t)cus * 16u;
+}
+
+hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           uint32_t* ticket, uint32_t grid, hipStream_t st) {
+    const uint32_t need = (r.count + kWave - 1) / kWave;
+    if (grid > need) grid = need;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(lt_small_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
+                           uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
+                           hipStream_t st) {
+    if (b.slots == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lt_large_kernel, dim3(b.slots), dim3(kWave), 0, st, g, r, o, list, list_n,
+                       fail, fail_n, ticket, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_lt_guide(const uint32_t* off, const uint2* cs, uint32_t* guide, uint32_t n,
+                           hipStream_t st) {
+    const uint32_t blocks = (n + kWave - 1) / kWave;
+    hipLaunchKernelGGL(lt_guide_kernel, dim3(blocks), dim3(kWave), 0, st, off, cs, guide, n);
+    return hipGetLastError();
+}
+
+}  // namespace imm
