@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the IMM hot path on one MI355X.
+
+A step is one full IMM run (all sampling rounds with fused counting, pool
+compaction, inverted index, greedy selection, theta schedule; the graph is
+resident in HBM before timing starts) on the Youtube-shaped workload:
+directed Chung-Lu graph (degree exponent 2.1, n = 1,134,890, m = 2,987,624),
+IC model with p = 0.01 as 32-bit thresholds, k = 50, eps = 0.13, ell = 1,
+Philox seed 42. Inputs are synthetic (seeded generator), standing in for the
+paper's com-YouTube graph.
+
+Prints one JSON line: whole-run RRR sets/s as `value`, time-to-seeds as
+ms_per_step, the roofline figure of the dominant sampling kernel measured
+with HIP events on the stream it runs on, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(model: str, sets: int, entries: int, edges: int, live: int) -> int:
+    """Bytes the sampling method must move (split CSC layout).
+
+    IC, per set: 4 B size + 8 B staging offset; per member: 8 B in-edge
+    offsets, 4 B staging write, 8 B count read-modify-write; per coin
+    (in-edge examined): 4 B threshold; per live in-edge: 4 B source id.
+    LT, per set: 12 B; per member: 8 B offsets + 4 B staging + 8 B count;
+    per walk step: 4 B guide entry; per (cum, src) pair inspected: 8 B."""
+    if model == "ic":
+        return 12 * sets + 20 * entries + 4 * edges + 4 * live
+    return 12 * sets + 20 * entries + 4 * edges + 8 * live
+
+
+def cpu_baseline(g, spec, seconds: float):
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    p = oracle.Pool()
+    t0 = time.perf_counter()
+    target = 50_000
+    while True:
+        p.extend(g, spec["seed"], target, threads)
+        el = time.perf_counter() - t0
+        if el >= seconds or target >= 1 << 26:
+            break
+        rate = target / max(el, 1e-3)
+        target = int(min(target * 8, target + rate * (seconds - el) * 1.1 + 1))
+    el = time.perf_counter() - t0
+    return {"value": p.n_sets / el, "unit": "RRR sets/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Generate_RRRsets (counts included) over sample ids "
+                      f"[0, {p.n_sets}) of the same run (seed {spec['seed']}), "
+                      f"{el:.1f} s wall on {threads} threads; sampling phase only"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="youtube_ic")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the sampling path shards across GPUs only by design, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2411_09473_amd as imm
+    import synth
+
+    torch.cuda.set_device(0)
+    spec = synth.WORKLOADS[args.workload]
+    g = synth.make_graph(args.workload)
+    stream = torch.cuda.current_stream()
+    dg = imm.graph_from(g, stream=stream)
+    torch.cuda.synchronize()
+
+    def step():
+        return imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                           flags=imm.IMM_TIMING, stream=stream)
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"[bench] {args.steps} timed steps done", file=sys.stderr, flush=True)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    r = results[-1]
+    for x in results:
+        assert x.theta == r.theta and list(x.seeds) == list(r.seeds), "runs must be identical"
+    sets = r.stats["sets"]
+    value = sets / (ms_per_step / 1e3)
+
+    def tot(key):
+        return sum(x.stats[key] for x in results)
+
+    # per-kernel accounting over the timed steps
+    main_bytes = algorithmic_bytes(g.model, tot("main_sets"), tot("main_entries"),
+                                   tot("main_edges"), tot("main_live"))
+    big_bytes = algorithmic_bytes(g.model, tot("sets") - tot("main_sets"),
+                                  tot("entries") - tot("main_entries"),
+                                  tot("edges") - tot("main_edges"),
+                                  tot("live") - tot("main_live"))
+    kernels = {
+        "main": dict(name="ic_small_kernel" if g.model == "ic" else "lt_small_kernel",
+                     ms=tot("ms_sample_main"), launches=tot("main_launches"), bytes=main_bytes),
+        "large": dict(name="ic_large_kernel" if g.model == "ic" else "lt_large_kernel",
+                      ms=tot("ms_sample_big"), launches=tot("big_launches"), bytes=big_bytes),
+    }
+    dom = max(kernels.values(), key=lambda k: k["ms"])
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
+    per_launch = dom["bytes"] / max(dom["launches"], 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    samp_bytes = algorithmic_bytes(g.model, sets, r.stats["entries"], r.stats["edges"],
+                                   r.stats["live"])
+    ms_sample = r.stats["ms_sample"]
+
+    out = {
+        "metric": "RRR sets/s + edges traversed/s (HBM GB/s); IMM time-to-seeds, k=50",
+        "value": value,
+        "unit": "RRR sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: IMM, " + (
+                "IC p=0.01, directed Chung-Lu gamma=2.1" if args.workload == "youtube_ic"
+                else g.model.upper()) + f", n={g.n}, m={g.m}",
+            "k": spec["k"], "epsilon": spec["eps"], "ell": spec["ell"], "seed": spec["seed"],
+            "diffusion": g.model.upper(), "parallelism": "single GPU",
+        },
+        "time_to_seeds_ms": ms_per_step,
+        "theta": r.theta,
+        "rounds": r.rounds,
+        "edges_per_s": r.stats["edges"] / (ms_per_step / 1e3),
+        "phase_ms": {"sample": ms_sample, "compact": r.stats["ms_compact"],
+                     "index": r.stats["ms_index"], "select": r.stats["ms_select"],
+                     "host_wall": r.stats["ms_total"]},
+        "sampling_GBps": samp_bytes / (ms_sample * 1e-3) / 1e9 if ms_sample > 0 else None,
+        "sampling_sets_per_s": sets / (ms_sample * 1e-3) if ms_sample > 0 else None,
+        "kernels": {k: {"name": v["name"], "launches": v["launches"],
+                        "avg_ms": v["ms"] / max(v["launches"], 1),
+                        "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+                    for k, v in kernels.items()},
+        "roofline": {"kernel": dom["name"], "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": None, "avg_launch_ms": avg_ms,
+                     "bytes_per_launch": per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, spec, args.cpu_seconds)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,8 @@ typedef struct {
     uint64_t main_entries;/* their total size */
     uint64_t main_edges;  /* their edges (IC coins / LT steps) */
     uint64_t main_live;   /* their live edges / cum entries */
+    double ms_sample_big; /* the large-set sampling kernel alone */
+    uint64_t big_launches;/* launches of that kernel */
     uint32_t rounds;      /* sampling-phase rounds executed (imm_run) */
     uint32_t pad;
 } imm_stats;

@@ -158,13 +158,14 @@ struct Timer {
         if (h < 0) return;
         (void)hipEventRecord(recs[h].b, st);
     }
-    // phases: 0 sample, 1 compact, 2 index, 3 select, 4 main sampling kernel
-    void collect(double* ms, uint64_t* main_launches) {
+    // phases: 0 sample, 1 compact, 2 index, 3 select, 4 main sampling
+    // kernel, 5 large-set sampling kernel
+    void collect(double* ms, uint64_t* launches) {
         for (auto& r : recs) {
             float t = 0.f;
             if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess)
                 ms[r.phase] += t;
-            if (r.phase == 4) ++*main_launches;
+            if (r.phase >= 4) ++launches[r.phase - 4];
             pool.push_back(r.a);
             pool.push_back(r.b);
         }
@@ -348,12 +349,14 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
             IMM_TRY(ws_big_scratch(w, std::min(pending, cap_slots)));
             HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
             int t2 = w.timer.open(0);
+            int t3 = w.timer.open(5);
             if (g->model == IMM_IC)
                 HIP_TRY(launch_ic_large(ic_view(g), rg, out(), list, list_n, fl, fl_n,
                                         &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
             else
                 HIP_TRY(launch_lt_large(lt_view(g), rg, out(), list, list_n, fl, fl_n,
                                         &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
+            w.timer.close(t3);
             w.timer.close(t2);
             IMM_TRY(ws_read_scalars(w));
         }
@@ -499,15 +502,17 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
 }
 
 void fill_stats(Workspace& w, imm_stats* s) {
-    double ms[5] = {0, 0, 0, 0, 0};
-    uint64_t launches = 0;
-    w.timer.collect(ms, &launches);
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t launches[2] = {0, 0};
+    w.timer.collect(ms, launches);
     s->ms_sample += ms[0];
     s->ms_compact += ms[1];
     s->ms_index += ms[2];
     s->ms_select += ms[3];
     s->ms_sample_main += ms[4];
-    s->main_launches += launches;
+    s->ms_sample_big += ms[5];
+    s->main_launches += launches[0];
+    s->big_launches += launches[1];
     const unsigned long long* t = w.hsc->stats;
     s->sets = t[kStMainSets] + t[kStBigSets];
     s->entries = t[kStMainEntries] + t[kStBigEntries];
