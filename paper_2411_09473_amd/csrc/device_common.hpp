@@ -96,7 +96,8 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 }
 
 // Largest index o in [0, cnt) with base[o] <= t (base non-decreasing, base[0] = 0).
-__device__ __forceinline__ uint32_t owner_of(const uint32_t* base, uint32_t cnt, uint32_t t) {
+template <class T>
+__device__ __forceinline__ uint32_t owner_of(const T* base, uint32_t cnt, T t) {
     uint32_t lo = 0, hi = cnt;  // invariant: base[lo] <= t, answer in [lo, hi)
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -105,23 +106,41 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* base, uint32_t cnt,
     return lo;
 }
 
+// Like owner_of, for a thread whose t only grows: search forward from its
+// previous answer `ow` (base[ow] <= t must hold), galloping then bisecting.
+template <class T>
+__device__ __forceinline__ uint32_t owner_from(const T* base, uint32_t cnt, T t, uint32_t ow) {
+    uint32_t step = 1;
+    while (ow + step < cnt && base[ow + step] <= t) {
+        ow += step;
+        step <<= 1;
+    }
+    uint32_t hi = ow + step < cnt ? ow + step : cnt;
+    while (hi - ow > 1) {
+        const uint32_t mid = (ow + hi) >> 1;
+        if (base[mid] <= t) ow = mid; else hi = mid;
+    }
+    return ow;
+}
+
 // Enumerate the (segment, k) pairs of the 64 segments held one per lane;
 // f(owner_lane, a_owner, b_owner, k) runs once for every k < size_owner.
 // Requires blockDim.x == 64 (one wave per block).
 template <class F>
 __device__ __forceinline__ void wave_segments(uint32_t sz, uint64_t a, uint64_t b, F f) {
-    __shared__ uint32_t s_base[kWave];
+    __shared__ uint64_t s_base[kWave];
     __shared__ uint64_t s_a[kWave], s_b[kWave];
     const uint32_t lane = threadIdx.x;
-    const uint32_t incl = wave_incl_scan(sz);
-    const uint32_t T = __shfl(incl, kWave - 1, kWave);
+    const uint64_t incl = wave_incl_scan64(sz);
+    const uint64_t T = __shfl(incl, kWave - 1, kWave);
     s_base[lane] = incl - sz;
     s_a[lane] = a;
     s_b[lane] = b;
     __syncthreads();
-    for (uint32_t t = lane; t < T; t += kWave) {
-        const uint32_t ow = owner_of(s_base, kWave, t);
-        f(ow, s_a[ow], s_b[ow], t - s_base[ow]);
+    uint32_t ow = 0;
+    for (uint64_t t = lane; t < T; t += kWave) {
+        ow = owner_from(s_base, kWave, t, ow);
+        f(ow, s_a[ow], s_b[ow], (uint32_t)(t - s_base[ow]));
     }
     __syncthreads();
 }

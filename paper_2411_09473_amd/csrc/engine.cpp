@@ -126,6 +126,9 @@ imm_status grow(Arena& a, T** p, uint64_t* cap, uint64_t need, uint64_t keep, hi
     return IMM_OK;
 }
 
+// Upper bound on the device memory of the large-set kernels' scratch.
+constexpr uint64_t kBigScratchBytes = 16ull << 30;
+
 // Scalars the kernels update, in one device block.
 struct DevScalars {
     unsigned long long cursor;
@@ -226,7 +229,9 @@ struct Workspace {
     uint32_t* defer = nullptr; uint64_t cap_df = 0;
     uint32_t* retry = nullptr; uint64_t cap_rt = 0;
     uint64_t* scan_tmp = nullptr; uint64_t cap_scan = 0;
-    unsigned long long* partials = nullptr;
+    unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
+    uint32_t* chunk_n = nullptr;          // k queue lengths
+    Chunk* chunks = nullptr; uint64_t cap_chunks = 0;
     uint32_t* seeds_d = nullptr; uint32_t* gains_d = nullptr; uint64_t cap_k = 0;
     uint32_t* gains_h = nullptr; uint64_t cap_kh = 0;
     uint32_t* big = nullptr; uint64_t cap_big = 0; uint32_t big_slots = 0;
@@ -254,7 +259,6 @@ imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_
     IMM_TRY(w.arena.alloc((void**)&w.counts_work, (uint64_t)n * 4 + 16, "counts_work"));
     IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
     IMM_TRY(w.arena.alloc((void**)&w.inv_off, ((uint64_t)n + 1) * 8, "inv_off"));
-    IMM_TRY(w.arena.alloc((void**)&w.partials, 1024 * 8, "partials"));
     HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)n * 4, st));
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
@@ -345,8 +349,16 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
     bool first_pass = true;
     for (int guard = 0; guard < 64; ++guard) {
         if (pending) {
-            const uint32_t cap_slots = g->model == IMM_IC ? 512u : 64u;
-            IMM_TRY(ws_big_scratch(w, std::min(pending, cap_slots)));
+            // enough workgroups to fill the GPU, within a scratch cap
+            int cus = 256;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
+            const uint64_t per_slot = (((uint64_t)w.n + 31) / 32 + w.n) * 4;
+            uint64_t cap_slots = g->model == IMM_IC ? (uint64_t)cus * 8 : (uint64_t)cus;
+            cap_slots = std::min<uint64_t>(cap_slots, std::max<uint64_t>(1, kBigScratchBytes / per_slot));
+            // grow geometrically so rounds with more deferred sets reallocate rarely
+            const uint64_t want = std::min<uint64_t>(
+                cap_slots, std::max<uint64_t>(pending, 2ull * w.big_slots));
+            IMM_TRY(ws_big_scratch(w, (uint32_t)want));
             HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
             int t2 = w.timer.open(0);
             int t3 = w.timer.open(5);
@@ -412,11 +424,22 @@ imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
     IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
     IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
     if (w.cap_k < k) {
-        if (w.seeds_d) { HIP_TRY(hipStreamSynchronize(st)); w.arena.release(w.seeds_d); w.arena.release(w.gains_d); }
+        if (w.seeds_d) {
+            HIP_TRY(hipStreamSynchronize(st));
+            w.arena.release(w.seeds_d);
+            w.arena.release(w.gains_d);
+            w.arena.release(w.slots);
+            w.arena.release(w.chunk_n);
+        }
         IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
         IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
+        IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * kArgSlots * 8, "argmax slots"));
+        IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 4, "chunk counts"));
         w.cap_k = k;
     }
+    // a seed's chunks: at most one per started 64 members of every set
+    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.n_entries / 64 + 1, 0, st,
+                 "chunk queue"));
     if (w.cap_kh < k) {
         if (w.gains_h) (void)hipHostFree(w.gains_h);
         w.gains_h = nullptr;
@@ -432,13 +455,16 @@ imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
     int ts = w.timer.open(3);
     HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
-    HIP_TRY(hipMemsetAsync(&w.sc->argmax_ticket, 0, 4, st));
-    const uint32_t ag = argmax_grid(w.n), cg = cover_grid(w.device);
+    HIP_TRY(hipMemsetAsync(w.slots, 0, (uint64_t)k * kArgSlots * 8, st));
+    HIP_TRY(hipMemsetAsync(w.chunk_n, 0, (uint64_t)k * 4, st));
+    const uint32_t ag = argmax_grid(w.n), sg = select_grid(w.device);
     for (uint32_t i = 0; i < k; ++i) {
-        HIP_TRY(launch_argmax(w.counts_work, w.n, w.partials, &w.sc->argmax_ticket, w.seeds_d,
-                              w.gains_d, i, ag, st));
-        HIP_TRY(launch_cover(w.inv_off, w.inv_set, w.set_off, w.set_vtx, w.covered, w.counts_work,
-                             w.seeds_d, i, cg, st));
+        unsigned long long* sl = w.slots + (uint64_t)i * kArgSlots;
+        HIP_TRY(launch_argmax(w.counts_work, w.n, sl, ag, st));
+        HIP_TRY(launch_claim(w.inv_off, w.inv_set, w.set_off, w.covered, w.counts_work, sl,
+                             w.seeds_d, w.gains_d, i, w.chunks, w.chunk_n + i, sg, st));
+        HIP_TRY(launch_decrement(w.chunks, w.chunk_n + i, w.set_vtx, w.counts_work, w.seeds_d, i,
+                                 sg, st));
     }
     w.timer.close(ts);
     HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));

@@ -125,14 +125,28 @@ hipError_t launch_sort_big(const uint64_t* set_off, uint32_t* set_vtx, uint32_t 
 constexpr uint32_t kSortSmallMax = 4096;
 
 // ---- greedy selection (k_select.hip)
+// A run of at most 64 members of one covered set, queued for decrementing.
+struct Chunk {
+    uint64_t off;  // position of the first member in set_vtx
+    uint32_t len;  // 1..64
+    uint32_t pad;
+};
+// Partial maxima slots per seed (argmax spreads its atomics over these).
+constexpr uint32_t kArgSlots = 32;
 uint32_t argmax_grid(uint32_t n);
-hipError_t launch_argmax(uint32_t* counts_work, uint32_t n, unsigned long long* partials,
-                         uint32_t* ticket, uint32_t* seeds, uint32_t* gains, uint32_t i,
+uint32_t select_grid(int device);
+// slots[0..kArgSlots) must be zero before the launch for seed i.
+hipError_t launch_argmax(const uint32_t* counts_work, uint32_t n, unsigned long long* slots,
                          uint32_t grid, hipStream_t st);
-hipError_t launch_cover(const uint64_t* inv_off, const uint32_t* inv_set, const uint64_t* set_off,
-                        const uint32_t* set_vtx, uint32_t* covered, uint32_t* counts_work,
-                        const uint32_t* seeds, uint32_t i, uint32_t grid, hipStream_t st);
-uint32_t cover_grid(int device);
+// Records seed i and its gain, marks it selected, claims its uncovered sets
+// and queues their members in chunks (chunk_n zero before the launch).
+hipError_t launch_claim(const uint64_t* inv_off, const uint32_t* inv_set, const uint64_t* set_off,
+                        uint32_t* covered, uint32_t* counts_work, const unsigned long long* slots,
+                        uint32_t* seeds, uint32_t* gains, uint32_t i, Chunk* chunks,
+                        uint32_t* chunk_n, uint32_t grid, hipStream_t st);
+hipError_t launch_decrement(const Chunk* chunks, const uint32_t* chunk_n, const uint32_t* set_vtx,
+                            uint32_t* counts_work, const uint32_t* seeds, uint32_t i,
+                            uint32_t grid, hipStream_t st);
 
 // ---- misc
 hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,

@@ -11,7 +11,10 @@
 //    gathered only for live edges. A set that outgrows LDS is abandoned
 //    (no side effects) and its sample index deferred.
 //  * ic_large: one workgroup per deferred sample, with a visited bitmap and a
-//    queue in device memory (one slot per workgroup, reset sparsely).
+//    queue in device memory (one slot per workgroup, reset sparsely). A slot
+//    is only ever touched by its own workgroup, so workgroup barriers order
+//    every access; no device-scope fence is used (on this GPU such a fence
+//    writes back and invalidates the L2 of the whole XCD).
 // Finished sets are staged in chunks reserved from a bump cursor; their
 // members' counts are incremented right away. A set that finds the staging
 // buffer full is listed for a retry after the host grows it.
@@ -120,11 +123,12 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
             s_end[lane] = end;
             my_edges += end - beg;
             __syncthreads();
+            uint32_t ow = 0;
             for (uint32_t base = 0; base < G; base += kWave) {
                 if (lds_load(&s_over)) break;
                 const uint32_t t = base + lane;
                 if (t < G) {
-                    const uint32_t ow = owner_of(s_base, nb, t);
+                    ow = owner_from(s_base, nb, t, ow);
                     const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
                     const uint32_t eb = s_beg[ow], ee = s_end[ow];
                     const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
@@ -266,7 +270,6 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
             atomicOr(&bm[root >> 5], 1u << (root & 31));
             s_size = 1;
         }
-        __threadfence();
         __syncthreads();
 
         uint32_t head = 0, size = 1;
@@ -288,10 +291,11 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
             s_end[tid] = end;
             my_edges += end - beg;
             __syncthreads();
+            uint32_t ow = 0;
             for (uint32_t base = 0; base < G; base += kBigBlock) {
                 const uint32_t t = base + tid;
                 if (t < G) {
-                    const uint32_t ow = owner_of(s_base, nb, t);
+                    ow = owner_from(s_base, nb, t, ow);
                     const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
                     const uint32_t eb = s_beg[ow], ee = s_end[ow];
                     const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
@@ -312,7 +316,6 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
                     }
                 }
             }
-            __threadfence();
             __syncthreads();
             head += nb;
             size = s_size;
@@ -345,7 +348,6 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
             st_edges += my_edges;
             st_live += my_live;
         }
-        __threadfence();
         __syncthreads();
     }
     st_edges = wave_sum64(st_edges);
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
 
 uint32_t ic_small_grid(int device) {
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     return (uint32_t)cus * 24u;
 }
 

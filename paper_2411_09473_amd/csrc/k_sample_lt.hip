@@ -226,7 +226,6 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
             s_reads = reads;
             s_off = atomicAdd(o.cursor, (unsigned long long)len);
         }
-        __threadfence();
         __syncthreads();
         const uint32_t len = s_len;
         const uint64_t off = s_off;
@@ -251,7 +250,6 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
                 fail[atomicAdd(fail_n, 1u)] = idx;
             }
         }
-        __threadfence();
         __syncthreads();
     }
     if (lane == 0) {
@@ -288,7 +286,7 @@ __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const
 
 uint32_t lt_small_grid(int device) {
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     return (uint32_t)cus * 16u;
 }
 
