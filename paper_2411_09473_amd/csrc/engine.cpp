@@ -184,6 +184,10 @@ struct Timer {
 
 // ---------------------------------------------------------------- graph --
 
+namespace {
+struct Workspace;
+}
+
 struct imm_graph {
     uint32_t n = 0;
     uint64_t m = 0;
@@ -195,6 +199,9 @@ struct imm_graph {
     uint32_t* src = nullptr;
     uint2* cs = nullptr;
     uint32_t* guide = nullptr;
+    // workspace of the last run, reused by the next one
+    std::mutex ws_mu;
+    std::unique_ptr<Workspace> ws_cache;
 };
 
 namespace {
@@ -207,6 +214,15 @@ LtGraphDev lt_view(const imm_graph* g) {
 }
 
 // ------------------------------------------------------------- workspace --
+//
+// Device state of one IMM run (or of one imm_sample / imm_greedy call). A
+// graph keeps the workspace of its last run and hands it to the next run, so
+// repeated queries on a resident graph allocate nothing.
+//
+// The pool grows by whole sampling rounds. Its vertex->sets index is kept in
+// segments, one per round, each indexing only that round's sets (segment r
+// occupies inv_set positions [P_{r-1}, P_r), the same range its sets occupy
+// in set_vtx), so no set is indexed twice.
 
 struct Workspace {
     int device = 0;
@@ -215,11 +231,16 @@ struct Workspace {
     Arena arena;
     DevScalars* sc = nullptr;
     DevScalars* hsc = nullptr;  // pinned mirror
-    uint32_t* counts_acc = nullptr;
-    uint32_t* counts_work = nullptr;
+    uint64_t* hp = nullptr;     // pinned: pool size
+    uint32_t* herr = nullptr;   // pinned: error flag
+    uint32_t* counts_acc = nullptr;   // occurrences over all sets so far
+    uint32_t* counts_prev = nullptr;  // ... over the sets already indexed
+    uint32_t* counts_work = nullptr;  // the greedy's working copy
     uint32_t* inv_cursor = nullptr;
-    uint64_t* inv_off = nullptr;
-    uint64_t* set_off = nullptr; uint64_t cap_sets = 0;     // cap_sets entries
+    uint64_t* inv_offs = nullptr; uint64_t cap_offs = 0;  // nseg * (n+1)
+    uint32_t nseg = 0;
+    uint64_t indexed_sets = 0;
+    uint64_t* set_off = nullptr; uint64_t cap_sets = 0;
     uint32_t* set_vtx = nullptr; uint64_t cap_entries = 0;
     uint32_t* inv_set = nullptr; uint64_t cap_inv = 0;
     uint32_t* covered = nullptr; uint64_t cap_cov = 0;
@@ -233,35 +254,57 @@ struct Workspace {
     uint32_t* chunk_n = nullptr;          // k queue lengths
     Chunk* chunks = nullptr; uint64_t cap_chunks = 0;
     uint32_t* seeds_d = nullptr; uint32_t* gains_d = nullptr; uint64_t cap_k = 0;
-    uint32_t* gains_h = nullptr; uint64_t cap_kh = 0;
-    uint32_t* big = nullptr; uint64_t cap_big = 0; uint32_t big_slots = 0;
-    uint64_t n_sets = 0, n_entries = 0;
-    double ewma_size = 0.0;  // running mean set size (staging estimate)
+    uint32_t* gains_h = nullptr;
+    uint32_t* big = nullptr; uint32_t big_slots = 0;
+    uint64_t n_sets = 0;
+    uint64_t p_exact = 0;  // pool size, exact as of the last synchronisation
+    uint64_t p_ub = 0;     // upper bound on the pool size
+    double mean_size = 0.0;  // mean set size of the last round (staging estimate)
     Timer timer;
 
     ~Workspace() {
+        // kernels of a failed call may still be queued on the workspace's
+        // buffers; the caller's stream may already be gone, so wait for the
+        // whole device before the arena frees them
+        if (sc) (void)hipDeviceSynchronize();
         if (hsc) (void)hipHostFree(hsc);
+        if (hp) (void)hipHostFree(hp);
+        if (herr) (void)hipHostFree(herr);
         if (gains_h) (void)hipHostFree(gains_h);
     }
 };
 
-imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget,
-                   bool timing) {
+imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget) {
     w.device = device;
     w.n = n;
     w.st = st;
     w.arena.budget = budget;
-    w.timer.on = timing;
-    w.timer.st = st;
     IMM_TRY(w.arena.alloc((void**)&w.sc, sizeof(DevScalars), "scalars"));
     HIP_TRY(hipHostMalloc((void**)&w.hsc, sizeof(DevScalars), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w.hp, 8, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w.herr, 4, hipHostMallocDefault));
     IMM_TRY(w.arena.alloc((void**)&w.counts_acc, (uint64_t)n * 4, "counts"));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_prev, (uint64_t)n * 4, "counts (indexed)"));
     IMM_TRY(w.arena.alloc((void**)&w.counts_work, (uint64_t)n * 4 + 16, "counts_work"));
     IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
-    IMM_TRY(w.arena.alloc((void**)&w.inv_off, ((uint64_t)n + 1) * 8, "inv_off"));
-    HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
-    HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)n * 4, st));
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
+    return IMM_OK;
+}
+
+// Start a new run on an (initialised, possibly reused) workspace.
+imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
+    w.st = st;
+    w.timer.st = st;
+    w.timer.on = timing;
+    w.timer.recs.clear();
+    w.n_sets = 0;
+    w.p_exact = 0;
+    w.p_ub = 0;
+    w.nseg = 0;
+    w.indexed_sets = 0;
+    HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
+    HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
     return IMM_OK;
 }
@@ -272,36 +315,44 @@ imm_status ws_read_scalars(Workspace& w) {
     return IMM_OK;
 }
 
-imm_status ws_big_scratch(Workspace& w, uint32_t want_slots) {
+// Scratch of the large-set kernels: per slot a visited bitmap and a queue
+// of n entries; enough slots to fill the GPU (IC) or a few per CU (LT, whose
+// walks rarely outgrow a chunk), within kBigScratchBytes and the budget.
+imm_status ws_big_scratch(Workspace& w, imm_model model) {
+    if (w.big) return IMM_OK;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
     const uint64_t words = ((uint64_t)w.n + 31) / 32;
-    const uint64_t per = words + w.n;
-    if (want_slots < 1) want_slots = 1;
-    if (w.big && w.big_slots >= want_slots) return IMM_OK;
-    if (w.big) {
-        HIP_TRY(hipStreamSynchronize(w.st));
-        w.arena.release(w.big);
-        w.big = nullptr;
-        w.big_slots = 0;
+    const uint64_t per = (words + w.n) * 4;
+    uint64_t slots = model == IMM_IC ? (uint64_t)cus * 8 : (uint64_t)cus;
+    uint64_t limit = kBigScratchBytes;
+    if (w.arena.budget) {
+        const uint64_t left = w.arena.budget > w.arena.used ? w.arena.budget - w.arena.used : 0;
+        limit = std::min(limit, left / 4);
     }
-    IMM_TRY(w.arena.alloc((void**)&w.big, per * want_slots * 4, "large-set scratch"));
-    HIP_TRY(hipMemsetAsync(w.big, 0, words * want_slots * 4, w.st));
-    w.big_slots = want_slots;
+    slots = std::min<uint64_t>(slots, std::max<uint64_t>(1, limit / per));
+    IMM_TRY(w.arena.alloc((void**)&w.big, per * slots, "large-set scratch"));
+    HIP_TRY(hipMemsetAsync(w.big, 0, words * slots * 4, w.st));
+    w.big_slots = (uint32_t)slots;
     return IMM_OK;
 }
 
-BigScratch big_view(const Workspace& w, uint32_t slots) {
+BigScratch big_view(const Workspace& w) {
     const uint32_t words = (uint32_t)(((uint64_t)w.n + 31) / 32);
-    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words, slots};
+    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words, w.big_slots};
 }
 
 // Generate sample ids [id_lo, id_lo + count) into the pool at set index
-// w.n_sets (Generate_RRRsets with fused counting), then compact them.
+// w.n_sets (Generate_RRRsets with fused counting), then compact them. One
+// host synchronisation: after sampling, to learn whether any set is still
+// waiting for staging space and how much staging was used.
 imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
                      uint64_t count64) {
     if (count64 == 0) return IMM_OK;
     if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
     const uint32_t count = (uint32_t)count64;
     hipStream_t st = w.st;
+    IMM_TRY(ws_big_scratch(w, g->model));
     IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
     IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
     IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
@@ -309,14 +360,15 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
     {
         // expected entries plus the unused tails of every wave's (IC) or
         // lane's (LT) staging chunk
-        const double mean = w.ewma_size > 0 ? w.ewma_size : 16.0;
+        const double mean = w.mean_size > 0 ? w.mean_size : 16.0;
         uint64_t tails;
         if (g->model == IMM_IC) {
-            const uint64_t waves = std::min<uint64_t>(ic_small_grid(w.device),
-                                                      (count + kIcTicketChunk - 1) / kIcTicketChunk);
+            const uint64_t waves = std::min<uint64_t>(
+                ic_small_grid(w.device), (count + kIcTicketChunk - 1) / kIcTicketChunk);
             tails = waves * kIcStageChunk;
         } else {
-            const uint64_t lanes = std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
+            const uint64_t lanes =
+                std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
             tails = lanes * kLtChunk;
         }
         const uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
@@ -329,100 +381,129 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
         return SampleOut{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
                          w.defer, &w.sc->defer_n, w.retry, &w.sc->retry_n, w.sc->stats};
     };
-    int th = w.timer.open(0);
-    int tm = w.timer.open(4);
+    auto launch_large = [&](const uint32_t* list, const uint32_t* list_n, uint32_t* fl,
+                            uint32_t* fl_n) -> imm_status {
+        HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
+        const int t2 = w.timer.open(0);
+        const int t3 = w.timer.open(5);
+        if (g->model == IMM_IC)
+            HIP_TRY(launch_ic_large(ic_view(g), rg, out(), list, list_n, fl, fl_n,
+                                    &w.sc->ticket_big, big_view(w), st));
+        else
+            HIP_TRY(launch_lt_large(lt_view(g), rg, out(), list, list_n, fl, fl_n,
+                                    &w.sc->ticket_big, big_view(w), st));
+        w.timer.close(t3);
+        w.timer.close(t2);
+        return IMM_OK;
+    };
+    const int th = w.timer.open(0);
+    const int tm = w.timer.open(4);
     if (g->model == IMM_IC)
         HIP_TRY(launch_ic_small(ic_view(g), rg, out(), &w.sc->ticket_small, ic_small_grid(w.device), st));
     else
         HIP_TRY(launch_lt_small(lt_view(g), rg, out(), &w.sc->ticket_small, lt_small_grid(w.device), st));
     w.timer.close(tm);
     w.timer.close(th);
+    // sets that outgrew the on-chip structures (the count stays on the device)
+    IMM_TRY(launch_large(w.defer, &w.sc->defer_n, w.retry, &w.sc->retry_n));
     IMM_TRY(ws_read_scalars(w));
 
-    // deferred sets (too large for the on-chip kernel), then retries after
-    // growing the staging buffer, until every set is stored
-    uint32_t* list = w.defer;
-    uint32_t* list_n = &w.sc->defer_n;
-    uint32_t* fl = w.retry;
-    uint32_t* fl_n = &w.sc->retry_n;
-    uint32_t pending = w.hsc->defer_n;
-    bool first_pass = true;
-    for (int guard = 0; guard < 64; ++guard) {
-        if (pending) {
-            // enough workgroups to fill the GPU, within a scratch cap
-            int cus = 256;
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
-            const uint64_t per_slot = (((uint64_t)w.n + 31) / 32 + w.n) * 4;
-            uint64_t cap_slots = g->model == IMM_IC ? (uint64_t)cus * 8 : (uint64_t)cus;
-            cap_slots = std::min<uint64_t>(cap_slots, std::max<uint64_t>(1, kBigScratchBytes / per_slot));
-            // grow geometrically so rounds with more deferred sets reallocate rarely
-            const uint64_t want = std::min<uint64_t>(
-                cap_slots, std::max<uint64_t>(pending, 2ull * w.big_slots));
-            IMM_TRY(ws_big_scratch(w, (uint32_t)want));
-            HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
-            int t2 = w.timer.open(0);
-            int t3 = w.timer.open(5);
-            if (g->model == IMM_IC)
-                HIP_TRY(launch_ic_large(ic_view(g), rg, out(), list, list_n, fl, fl_n,
-                                        &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
-            else
-                HIP_TRY(launch_lt_large(lt_view(g), rg, out(), list, list_n, fl, fl_n,
-                                        &w.sc->ticket_big, big_view(w, std::min(pending, w.big_slots)), st));
-            w.timer.close(t3);
-            w.timer.close(t2);
-            IMM_TRY(ws_read_scalars(w));
-        }
-        // failures of this pass (plus, on the first pass, the main kernel's retries)
-        const uint32_t failed = (fl == w.retry) ? w.hsc->retry_n : w.hsc->defer_n;
-        (void)first_pass;
-        first_pass = false;
-        if (failed == 0) break;
-        // grow staging, keep what is stored, continue at the old capacity
+    // sets that found the staging buffer full: grow it (keeping what is
+    // stored), continue at the old capacity, redo them, until none is left
+    uint32_t failed = w.hsc->retry_n;
+    bool from_retry = true;
+    for (int guard = 0; failed; ++guard) {
+        if (guard == 32) return fail(IMM_ENOMEM, "staging could not be grown enough");
         const uint64_t used = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
         const uint64_t old_cap = w.stage_cap;
-        const double mean = w.ewma_size > 0 ? w.ewma_size : 64.0;
+        const double mean = w.mean_size > 0 ? w.mean_size : 64.0;
         uint64_t need = old_cap + (uint64_t)(mean * 2.0 * failed) + (uint64_t)failed * 64 + (1u << 20);
         need = std::max<uint64_t>(need, old_cap * 2);
         uint64_t cap = w.stage_cap;
         IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
         w.stage_cap = cap;
-        unsigned long long cur = old_cap;
+        const unsigned long long cur = old_cap;
         HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
-        // the failed list becomes the input; the other list collects new failures
-        std::swap(list, fl);
-        std::swap(list_n, fl_n);
+        uint32_t* list = from_retry ? w.retry : w.defer;
+        uint32_t* list_n = from_retry ? &w.sc->retry_n : &w.sc->defer_n;
+        uint32_t* fl = from_retry ? w.defer : w.retry;
+        uint32_t* fl_n = from_retry ? &w.sc->defer_n : &w.sc->retry_n;
         HIP_TRY(hipMemsetAsync(fl_n, 0, 4, st));
-        pending = failed;
-        if (guard == 63) return fail(IMM_ENOMEM, "staging could not be grown enough");
+        IMM_TRY(launch_large(list, list_n, fl, fl_n));
+        IMM_TRY(ws_read_scalars(w));
+        failed = from_retry ? w.hsc->defer_n : w.hsc->retry_n;
+        from_retry = !from_retry;
     }
 
-    // compaction: set_off[n_sets .. n_sets+count] and the copy into the pool
+    // compaction: set_off[n_sets .. n_sets+count] (based on the device copy of
+    // set_off[n_sets]) and the copy into the pool
     const uint64_t stored_bound = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + count + 1, w.n_sets + 1, st, "set_off"));
-    IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, w.n_entries + stored_bound + 1, w.n_entries, st, "set_vtx"));
+    IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, w.p_ub + stored_bound + 1,
+                 std::min(w.p_ub, w.cap_entries), st, "set_vtx"));
     IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(count), 0, st, "scan tmp"));
-    int tc = w.timer.open(1);
-    HIP_TRY(launch_scan_u32(w.sizes, w.set_off + w.n_sets, count, w.n_entries, w.scan_tmp, st));
+    const int tc = w.timer.open(1);
+    HIP_TRY(launch_scan_u32(w.sizes, nullptr, w.set_off + w.n_sets, count, 0, w.set_off + w.n_sets,
+                            w.scan_tmp, st));
     HIP_TRY(launch_compact(w.stage, w.stage_off, w.set_off, w.n_sets, count, w.set_vtx, st));
     w.timer.close(tc);
-    uint64_t p_new = 0;
-    HIP_TRY(hipMemcpyAsync(&p_new, w.set_off + w.n_sets + count, 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const double mean_round = (double)(p_new - w.n_entries) / (double)count;
-    w.ewma_size = w.ewma_size > 0 ? 0.5 * w.ewma_size + 0.5 * mean_round : mean_round;
     w.n_sets += count;
-    w.n_entries = p_new;
+    w.p_ub += stored_bound;
     return IMM_OK;
 }
 
-// Greedy selection over the whole pool: inverted index, then k argmax/cover
-// pairs. seeds_d/gains_d hold the result; the sum of the gains is returned.
-imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
+// Read the exact pool size (and the device error flag) at a synchronisation.
+imm_status ws_sync_pool(Workspace& w) {
+    HIP_TRY(hipMemcpyAsync(w.hp, w.set_off + w.n_sets, 8, hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipMemcpyAsync(w.herr, &w.sc->err, 4, hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    return IMM_OK;
+}
+
+void ws_note_pool(Workspace& w, uint64_t sets_before) {
+    const uint64_t p = *w.hp;
+    if (w.n_sets > sets_before)
+        w.mean_size = (double)(p - w.p_exact) / (double)(w.n_sets - sets_before);
+    w.p_exact = p;
+    w.p_ub = p;
+}
+
+// Index the sets added since the last call as a new segment: its offsets are
+// the scan of the count increase since then, based at the pool position of
+// its first set.
+imm_status ws_index_update(Workspace& w) {
     hipStream_t st = w.st;
+    if (w.indexed_sets == w.n_sets) return IMM_OK;
     if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
-    IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, w.n_entries + 1, 0, st, "inv_set"));
-    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
+    const uint64_t stride = (uint64_t)w.n + 1;
+    IMM_TRY(grow(w.arena, &w.inv_offs, &w.cap_offs, (w.nseg + 1) * stride, w.nseg * stride, st,
+                 "index offsets"));
+    IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, w.p_ub + 1, std::min(w.p_ub, w.cap_inv), st,
+                 "inv_set"));
     IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
+    uint64_t* io = w.inv_offs + w.nseg * stride;
+    const int ti = w.timer.open(2);
+    HIP_TRY(launch_scan_u32(w.counts_acc, w.counts_prev, io, w.n, 0, w.set_off + w.indexed_sets,
+                            w.scan_tmp, st));
+    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets,
+                               (uint32_t)(w.n_sets - w.indexed_sets), io, w.inv_cursor, w.inv_set,
+                               &w.sc->err, st));
+    HIP_TRY(hipMemcpyAsync(w.counts_prev, w.counts_acc, (uint64_t)w.n * 4,
+                           hipMemcpyDeviceToDevice, st));
+    w.timer.close(ti);
+    ++w.nseg;
+    w.indexed_sets = w.n_sets;
+    return IMM_OK;
+}
+
+// Greedy selection over the whole pool: bring the index up to date, then k
+// (argmax, claim, decrement) triples. Ends with the run's second
+// synchronisation per round, which also reads the exact pool size.
+imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
+    hipStream_t st = w.st;
+    IMM_TRY(ws_index_update(w));
+    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
     if (w.cap_k < k) {
         if (w.seeds_d) {
             HIP_TRY(hipStreamSynchronize(st));
@@ -430,29 +511,20 @@ imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
             w.arena.release(w.gains_d);
             w.arena.release(w.slots);
             w.arena.release(w.chunk_n);
+            (void)hipHostFree(w.gains_h);
+            w.gains_h = nullptr;
         }
         IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
         IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
         IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * kArgSlots * 8, "argmax slots"));
         IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 4, "chunk counts"));
+        HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
         w.cap_k = k;
     }
     // a seed's chunks: at most one per started 64 members of every set
-    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.n_entries / 64 + 1, 0, st,
+    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.p_ub / 64 + 1, 0, st,
                  "chunk queue"));
-    if (w.cap_kh < k) {
-        if (w.gains_h) (void)hipHostFree(w.gains_h);
-        w.gains_h = nullptr;
-        HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
-        w.cap_kh = k;
-    }
-    int ti = w.timer.open(2);
-    HIP_TRY(launch_scan_u32(w.counts_acc, w.inv_off, w.n, 0, w.scan_tmp, st));
-    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
-    HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, (uint32_t)w.n_sets, w.inv_off, w.inv_cursor,
-                               w.inv_set, &w.sc->err, st));
-    w.timer.close(ti);
-    int ts = w.timer.open(3);
+    const int ts = w.timer.open(3);
     HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
     HIP_TRY(hipMemsetAsync(w.slots, 0, (uint64_t)k * kArgSlots * 8, st));
@@ -461,17 +533,17 @@ imm_status ws_greedy(Workspace& w, uint32_t k, uint64_t* covered) {
     for (uint32_t i = 0; i < k; ++i) {
         unsigned long long* sl = w.slots + (uint64_t)i * kArgSlots;
         HIP_TRY(launch_argmax(w.counts_work, w.n, sl, ag, st));
-        HIP_TRY(launch_claim(w.inv_off, w.inv_set, w.set_off, w.covered, w.counts_work, sl,
-                             w.seeds_d, w.gains_d, i, w.chunks, w.chunk_n + i, sg, st));
+        HIP_TRY(launch_claim(w.inv_offs, w.nseg, w.n, w.inv_set, w.set_off, w.covered,
+                             w.counts_work, sl, w.seeds_d, w.gains_d, i, w.chunks, w.chunk_n + i,
+                             sg, st));
         HIP_TRY(launch_decrement(w.chunks, w.chunk_n + i, w.set_vtx, w.counts_work, w.seeds_d, i,
                                  sg, st));
     }
     w.timer.close(ts);
     HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    uint32_t err = 0;
-    HIP_TRY(hipMemcpy(&err, &w.sc->err, 4, hipMemcpyDeviceToHost));
-    if (err) return fail(IMM_EDEVICE, "internal error: occurrence counts disagree with the pool");
+    IMM_TRY(ws_sync_pool(w));
+    if (*w.herr) return fail(IMM_EDEVICE, "internal error: occurrence counts disagree with the pool");
+    ws_note_pool(w, sets_before);
     uint64_t c = 0;
     for (uint32_t i = 0; i < k; ++i) c += w.gains_h[i];
     *covered = c;
@@ -483,6 +555,8 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
                           std::vector<uint32_t>* counts) {
     hipStream_t st = w.st;
     if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
+    IMM_TRY(ws_sync_pool(w));
+    ws_note_pool(w, w.n_sets);
     uint32_t* big_list = nullptr;
     IMM_TRY(w.arena.alloc((void**)&big_list, (w.n_sets + 1) * 4, "sort list"));
     HIP_TRY(hipMemsetAsync(&w.sc->big_flag, 0, 4, st));
@@ -516,9 +590,9 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
         HIP_TRY(hipMemcpy(so->data(), w.set_off, (w.n_sets + 1) * 8, hipMemcpyDeviceToHost));
     }
     if (sv) {
-        sv->resize(w.n_entries);
-        if (w.n_entries)
-            HIP_TRY(hipMemcpy(sv->data(), w.set_vtx, w.n_entries * 4, hipMemcpyDeviceToHost));
+        sv->resize(w.p_exact);
+        if (w.p_exact)
+            HIP_TRY(hipMemcpy(sv->data(), w.set_vtx, w.p_exact * 4, hipMemcpyDeviceToHost));
     }
     if (counts) {
         counts->resize(w.n);
@@ -716,15 +790,25 @@ imm_status imm_graph_info(const imm_graph* g, uint32_t* n, uint64_t* m, imm_mode
     return IMM_OK;
 }
 
-static imm_status run_impl(const imm_graph* g, const imm_params* p, hipStream_t st,
+static imm_status run_impl(imm_graph* g, const imm_params* p, hipStream_t st,
                            imm_result** out) {
     const double t0 = now_ms();
     double lam_p, lam_s;
     uint32_t i_max;
     IMM_TRY(imm_theta_plan(g->n, p->k, p->epsilon, p->ell, &lam_p, &lam_s, &i_max));
     HIP_TRY(hipSetDevice(g->device));
-    std::unique_ptr<Workspace> w(new Workspace());
-    IMM_TRY(ws_init(*w, g->n, g->device, st, p->max_device_bytes, (p->flags & IMM_TIMING) != 0));
+    // take the graph's cached workspace when it fits the budget
+    std::unique_ptr<Workspace> w;
+    {
+        std::lock_guard<std::mutex> lk(g->ws_mu);
+        w = std::move(g->ws_cache);
+    }
+    if (w && (p->max_device_bytes != w->arena.budget)) w.reset();
+    if (!w) {
+        w.reset(new Workspace());
+        IMM_TRY(ws_init(*w, g->n, g->device, st, p->max_device_bytes));
+    }
+    IMM_TRY(ws_reset(*w, st, (p->flags & IMM_TIMING) != 0));
     std::unique_ptr<imm_result> r(new imm_result());
     r->k = p->k;
     const double eps_p = std::sqrt(2.0) * p->epsilon;
@@ -736,8 +820,9 @@ static imm_status run_impl(const imm_graph* g, const imm_params* p, hipStream_t 
         if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta_i >= 2^32");
         const uint64_t target = (uint64_t)tf;
         if (r->targets.size() < 63) r->targets.push_back(target);
+        const uint64_t before = w->n_sets;
         if (w->n_sets < target) IMM_TRY(ws_extend(*w, g, p->seed, w->n_sets, target - w->n_sets));
-        IMM_TRY(ws_greedy(*w, p->k, &cov));
+        IMM_TRY(ws_greedy(*w, p->k, before, &cov));
         r->round_cov.push_back(cov);
         r->rounds = i;
         const double frac = (double)cov / (double)w->n_sets;
@@ -750,13 +835,12 @@ static imm_status run_impl(const imm_graph* g, const imm_params* p, hipStream_t 
     if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta >= 2^32");
     const uint64_t theta = (uint64_t)tf;
     r->targets.push_back(theta);
+    const uint64_t before = w->n_sets;
     if (w->n_sets < theta) IMM_TRY(ws_extend(*w, g, p->seed, w->n_sets, theta - w->n_sets));
-    IMM_TRY(ws_greedy(*w, p->k, &cov));
+    IMM_TRY(ws_greedy(*w, p->k, before, &cov));
     r->seeds.resize(p->k);
-    std::vector<uint32_t> g32(p->k);
     HIP_TRY(hipMemcpy(r->seeds.data(), w->seeds_d, (uint64_t)p->k * 4, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(g32.data(), w->gains_d, (uint64_t)p->k * 4, hipMemcpyDeviceToHost));
-    r->gains.assign(g32.begin(), g32.end());
+    r->gains.assign(w->gains_h, w->gains_h + p->k);
     r->theta = w->n_sets;
     r->lb = lb;
     r->covered = cov;
@@ -769,6 +853,10 @@ static imm_status run_impl(const imm_graph* g, const imm_params* p, hipStream_t 
         IMM_TRY(ws_export_pool(*w, &r->set_off, &r->set_vtx, nullptr));
         r->has_pool = true;
     }
+    {
+        std::lock_guard<std::mutex> lk(g->ws_mu);
+        g->ws_cache = std::move(w);
+    }
     *out = r.release();
     return IMM_OK;
 }
@@ -778,7 +866,7 @@ imm_status imm_run(const imm_graph* g, const imm_params* p, void* stream, imm_re
     if (p->k == 0 || p->k > g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
     if (!(p->epsilon > 0.0) || !(p->ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
     try {
-        return run_impl(g, p, (hipStream_t)stream, out);
+        return run_impl(const_cast<imm_graph*>(g), p, (hipStream_t)stream, out);
     } catch (const std::bad_alloc&) {
         return fail(IMM_ENOMEM, "run: host allocation failed");
     } catch (...) {
@@ -843,8 +931,11 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         HIP_TRY(hipSetDevice(g->device));
         std::unique_ptr<imm_pool> p(new imm_pool());
         p->ws.reset(new Workspace());
-        IMM_TRY(ws_init(*p->ws, g->n, g->device, st, 0, (flags & IMM_TIMING) != 0));
+        IMM_TRY(ws_init(*p->ws, g->n, g->device, st, 0));
+        IMM_TRY(ws_reset(*p->ws, st, (flags & IMM_TIMING) != 0));
         IMM_TRY(ws_extend(*p->ws, g, seed, first_id, count));
+        IMM_TRY(ws_sync_pool(*p->ws));
+        ws_note_pool(*p->ws, 0);
         IMM_TRY(ws_read_scalars(*p->ws));
         p->stats.ms_total = now_ms() - t0;
         fill_stats(*p->ws, &p->stats);
@@ -861,7 +952,7 @@ imm_status imm_pool_info(const imm_pool* p, uint64_t* n_sets, uint64_t* n_entrie
                          imm_stats* stats) {
     if (!p) return fail(IMM_EINVAL, "pool_info: null pool");
     if (n_sets) *n_sets = p->ws->n_sets;
-    if (n_entries) *n_entries = p->ws->n_entries;
+    if (n_entries) *n_entries = p->ws->p_exact;
     if (stats) *stats = p->stats;
     return IMM_OK;
 }
@@ -914,7 +1005,8 @@ imm_status imm_greedy(uint32_t n, const uint64_t* set_off, const uint32_t* set_v
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         Workspace w;
-        IMM_TRY(ws_init(w, n, dev, st, 0, false));
+        IMM_TRY(ws_init(w, n, dev, st, 0));
+        IMM_TRY(ws_reset(w, st, false));
         IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, n_sets + 1, 0, st, "set_off"));
         IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, P + 1, 0, st, "set_vtx"));
         const hipMemcpyKind kind = devp ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -928,15 +1020,14 @@ imm_status imm_greedy(uint32_t n, const uint64_t* set_off, const uint32_t* set_v
         }
         HIP_TRY(launch_count_entries(w.set_vtx, P, w.counts_acc, st));
         w.n_sets = n_sets;
-        w.n_entries = P;
+        w.p_ub = P;
         uint64_t cov = 0;
-        IMM_TRY(ws_greedy(w, k, &cov));
-        std::vector<uint32_t> s32(k), g32(k);
+        IMM_TRY(ws_greedy(w, k, n_sets, &cov));
+        std::vector<uint32_t> s32(k);
         HIP_TRY(hipMemcpy(s32.data(), w.seeds_d, (uint64_t)k * 4, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(g32.data(), w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost));
         std::memcpy(seeds, s32.data(), (size_t)k * 4);
         if (gains)
-            for (uint32_t i = 0; i < k; ++i) gains[i] = g32[i];
+            for (uint32_t i = 0; i < k; ++i) gains[i] = w.gains_h[i];
         if (covered) *covered = cov;
         return IMM_OK;
     } catch (const std::bad_alloc&) {

@@ -33,7 +33,7 @@ struct LtGraphDev {
 // Work granules of the sampling kernels: sample ids claimed per ticket by a
 // wave of the IC kernel, staging entries it reserves at a time, and staging
 // entries an LT lane reserves at a time (also the longest walk it keeps).
-constexpr uint32_t kIcTicketChunk = 16;
+constexpr uint32_t kIcTicketChunk = 64;
 constexpr uint32_t kIcStageChunk = 4096;
 constexpr uint32_t kLtChunk = 1024;
 
@@ -96,19 +96,22 @@ uint32_t ic_small_grid(int device);
 uint32_t lt_small_grid(int device);
 
 // ---- pool, index, canonical order (k_pool.hip)
-// out[0] = base; out[i+1] = base + in[0] + ... + in[i]  (N entries in).
-hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t base,
-                           uint64_t* tile_tmp, hipStream_t st);
+// out[0] = B; out[i+1] = B + x[0] + ... + x[i] for N >= 1 entries, where
+// x[i] = in[i] - (sub ? sub[i] : 0) and B = base_dev ? *base_dev : base.
+hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* sub, uint64_t* out, uint64_t N,
+                           uint64_t base, const uint64_t* base_dev, uint64_t* tile_tmp,
+                           hipStream_t st);
 uint64_t scan_tmp_entries(uint64_t N);
 // Copy staged sets [lo, lo+count) to set_vtx at set_off[lo..lo+count].
 hipError_t launch_compact(const uint32_t* stage, const uint64_t* stage_off,
                           const uint64_t* set_off, uint64_t lo, uint32_t count,
                           uint32_t* set_vtx, hipStream_t st);
-// inv_set[inv_off[v] + rank] = j for each member v of set j (rank by atomic
-// cursor); *err |= 1 if a vertex has more members than inv_off allows.
-hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint32_t n_sets,
-                              const uint64_t* inv_off, uint32_t* cursor, uint32_t* inv_set,
-                              uint32_t* err, hipStream_t st);
+// For the sets j in [lo, lo+count): inv_set[inv_off[v] + rank] = j for each
+// member v of set j (rank by atomic cursor); *err |= 1 if a vertex has more
+// members than inv_off allows.
+hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                              uint32_t count, const uint64_t* inv_off, uint32_t* cursor,
+                              uint32_t* inv_set, uint32_t* err, hipStream_t st);
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);
@@ -140,10 +143,13 @@ hipError_t launch_argmax(const uint32_t* counts_work, uint32_t n, unsigned long 
                          uint32_t grid, hipStream_t st);
 // Records seed i and its gain, marks it selected, claims its uncovered sets
 // and queues their members in chunks (chunk_n zero before the launch).
-hipError_t launch_claim(const uint64_t* inv_off, const uint32_t* inv_set, const uint64_t* set_off,
-                        uint32_t* covered, uint32_t* counts_work, const unsigned long long* slots,
-                        uint32_t* seeds, uint32_t* gains, uint32_t i, Chunk* chunks,
-                        uint32_t* chunk_n, uint32_t grid, hipStream_t st);
+// The index is kept in nseg segments (one per sampling round); segment r's
+// offsets are inv_off[r * (n + 1) .. r * (n + 1) + n], absolute in inv_set.
+hipError_t launch_claim(const uint64_t* inv_off, uint32_t nseg, uint32_t n,
+                        const uint32_t* inv_set, const uint64_t* set_off, uint32_t* covered,
+                        uint32_t* counts_work, const unsigned long long* slots, uint32_t* seeds,
+                        uint32_t* gains, uint32_t i, Chunk* chunks, uint32_t* chunk_n,
+                        uint32_t grid, hipStream_t st);
 hipError_t launch_decrement(const Chunk* chunks, const uint32_t* chunk_n, const uint32_t* set_vtx,
                             uint32_t* counts_work, const uint32_t* seeds, uint32_t i,
                             uint32_t grid, hipStream_t st);

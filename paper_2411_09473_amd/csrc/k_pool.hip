@@ -49,7 +49,13 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* excl
     return total;
 }
 
-__global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in, uint64_t N,
+// Scanned value of element i: in[i], or in[i] - sub[i] when sub is given.
+__device__ __forceinline__ uint32_t scan_val(const uint32_t* in, const uint32_t* sub, uint64_t i) {
+    return sub ? in[i] - sub[i] : in[i];
+}
+
+__global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in,
+                                                             const uint32_t* sub, uint64_t N,
                                                              uint64_t* tile_sum) {
     __shared__ uint64_t s_w[kScanBS / kWave];
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in,
 #pragma unroll
     for (uint32_t k = 0; k < kScanIPT; ++k) {
         const uint64_t i = base + (uint64_t)k * kScanBS + threadIdx.x;
-        if (i < N) acc += in[i];
+        if (i < N) acc += scan_val(in, sub, i);
     }
     const uint64_t t = block_sum64(acc, s_w);
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
@@ -81,17 +87,22 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t* tile_sum, uin
     }
 }
 
-__global__ __launch_bounds__(kScanBS) void scan_apply_kernel(const uint32_t* in, uint64_t N,
+// base_dev, when given, supplies the base from device memory (it may alias
+// out[0], which is rewritten with the same value).
+__global__ __launch_bounds__(kScanBS) void scan_apply_kernel(const uint32_t* in,
+                                                             const uint32_t* sub, uint64_t N,
                                                              const uint64_t* tile_off,
-                                                             uint64_t* out, uint64_t base) {
+                                                             uint64_t* out, uint64_t base,
+                                                             const uint64_t* base_dev) {
     __shared__ uint64_t s_w[kScanBS / kWave];
+    if (base_dev) base = *base_dev;
     const uint64_t tb = (uint64_t)blockIdx.x * kScanTile;
     const uint64_t my = tb + (uint64_t)threadIdx.x * kScanIPT;  // kScanIPT consecutive
     uint32_t v[kScanIPT];
     uint64_t acc = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kScanIPT; ++k) {
-        v[k] = (my + k < N) ? in[my + k] : 0u;
+        v[k] = (my + k < N) ? scan_val(in, sub, my + k) : 0u;
         acc += v[k];
     }
     uint64_t excl;
@@ -125,14 +136,14 @@ __global__ __launch_bounds__(64) void compact_kernel(const uint32_t* stage,
 // A member beyond its vertex's counted occurrences would mean the counts and
 // the pool disagree; it is not written and raises *err instead.
 __global__ __launch_bounds__(64) void inv_scatter_kernel(const uint64_t* set_off,
-                                                         const uint32_t* set_vtx,
-                                                         uint32_t n_sets, const uint64_t* inv_off,
+                                                         const uint32_t* set_vtx, uint64_t lo,
+                                                         uint32_t count, const uint64_t* inv_off,
                                                          uint32_t* cursor, uint32_t* inv_set,
                                                          uint32_t* err) {
-    const uint64_t j = (uint64_t)blockIdx.x * kWave + threadIdx.x;
+    const uint64_t j = lo + (uint64_t)blockIdx.x * kWave + threadIdx.x;
     uint32_t sz = 0;
     uint64_t a = 0;
-    if (j < n_sets) {
+    if (j < lo + count) {
         a = set_off[j];
         sz = (uint32_t)(set_off[j + 1] - a);
     }
@@ -256,18 +267,17 @@ uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap) {
 
 uint64_t scan_tmp_entries(uint64_t N) { return (N + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t launch_scan_u32(const uint32_t* in, uint64_t* out, uint64_t N, uint64_t base,
-                           uint64_t* tile_tmp, hipStream_t st) {
-    if (N == 0) {
-        return hipMemcpyAsync(out, &base, sizeof(uint64_t), hipMemcpyHostToDevice, st);
-    }
+hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* sub, uint64_t* out, uint64_t N,
+                           uint64_t base, const uint64_t* base_dev, uint64_t* tile_tmp,
+                           hipStream_t st) {
+    if (N == 0) return hipErrorInvalidValue;
     const uint64_t tiles = (N + kScanTile - 1) / kScanTile;
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, N,
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, sub, N,
                        tile_tmp);
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, tile_tmp, tiles);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, N,
-                       tile_tmp, out, base);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, sub, N,
+                       tile_tmp, out, base, base_dev);
     return hipGetLastError();
 }
 
@@ -281,13 +291,13 @@ hipError_t launch_compact(const uint32_t* stage, const uint64_t* stage_off,
     return hipGetLastError();
 }
 
-hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint32_t n_sets,
-                              const uint64_t* inv_off, uint32_t* cursor, uint32_t* inv_set,
-                              uint32_t* err, hipStream_t st) {
-    if (n_sets == 0) return hipSuccess;
-    const uint32_t blocks = (n_sets + kWave - 1) / kWave;
-    hipLaunchKernelGGL(inv_scatter_kernel, dim3(blocks), dim3(kWave), 0, st, set_off, set_vtx,
-                       n_sets, inv_off, cursor, inv_set, err);
+hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                              uint32_t count, const uint64_t* inv_off, uint32_t* cursor,
+                              uint32_t* inv_set, uint32_t* err, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + kWave - 1) / kWave;
+    hipLaunchKernelGGL(inv_scatter_kernel, dim3(blocks), dim3(kWave), 0, st, set_off, set_vtx, lo,
+                       count, inv_off, cursor, inv_set, err);
     return hipGetLastError();
 }
 

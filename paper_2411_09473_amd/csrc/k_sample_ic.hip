@@ -3,8 +3,13 @@
 // Section II-A).
 //
 // Two kernels share the work of one sampling round:
-//  * ic_small: one wave64 per sample. The set doubles as the BFS queue and
-//    lives in LDS together with an open-addressing hash of visited vertices.
+//  * ic_small: a wave takes 64 sample ids at a time. First each lane draws
+//    the root of its own sample and flips the coins of the root's in-edges
+//    (roots of in-degree <= kLaneDegCap); a root with no live in-edge is a
+//    complete set {root}, stored at once (at low edge probabilities that is
+//    most samples). The other samples of the batch then run one at a time,
+//    one wave per sample: the set doubles as the BFS queue and lives in LDS
+//    together with an open-addressing hash of visited vertices.
 //    Each BFS level takes up to 64 queued vertices, and the wave walks their
 //    in-edges in aligned groups of four: one Philox call yields the four
 //    coins of a group and one 16-byte load its four thresholds; sources are
@@ -28,7 +33,8 @@ namespace {
 constexpr uint32_t kSmallCap = 256;     // members kept in LDS
 constexpr uint32_t kHashBits = 10;      // 1024-slot LDS hash (load < 0.32)
 constexpr uint32_t kHashSize = 1u << kHashBits;
-constexpr uint32_t kTicketChunk = kIcTicketChunk;
+constexpr uint32_t kTicketChunk = kIcTicketChunk;  // one sample id per lane
+constexpr uint32_t kLaneDegCap = 32;  // roots tried one per lane up to this in-degree
 constexpr uint32_t kStageChunk = kIcStageChunk;
 constexpr uint32_t kBigBlock = 256;
 
@@ -68,6 +74,7 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
     __shared__ uint32_t hash[kHashSize];
     __shared__ uint32_t members[kSmallCap];
     __shared__ uint32_t s_base[kWave], s_g0[kWave], s_beg[kWave], s_end[kWave];
+    __shared__ uint32_t s_pend[kWave];
     __shared__ uint32_t s_size, s_over, s_tk;
     __shared__ unsigned long long s_chunk;
 
@@ -75,137 +82,190 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
     const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     for (uint32_t i = lane; i < kHashSize; i += kWave) hash[i] = kEmpty;
 
-    uint32_t tk_next = 0, tk_left = 0;
     uint64_t chunk_base = 0;
-    uint32_t chunk_left = 0;
+    uint32_t chunk_left = 0;  // uniform across the wave
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;  // lane-partial
 
-    for (;;) {
-        if (tk_left == 0) {
-            if (lane == 0) s_tk = atomicAdd(ticket, kTicketChunk);
+    // Reserve `need` staging entries from the wave's chunk (a new chunk when
+    // the current one is too short); false when the staging buffer is full.
+    auto reserve = [&](uint32_t need, uint64_t* off) -> bool {
+        if (need > chunk_left) {
+            if (lane == 0) s_chunk = atomicAdd(o.cursor, (unsigned long long)kStageChunk);
             __syncthreads();
-            tk_next = s_tk;
-            tk_left = kTicketChunk;
+            chunk_base = s_chunk;
+            chunk_left = kStageChunk;
             __syncthreads();
+            if (chunk_base + kStageChunk > o.stage_cap) {
+                chunk_left = 0;
+                return false;
+            }
         }
-        const uint32_t idx = tk_next;
-        if (idx >= rg.count) break;
-        ++tk_next;
-        --tk_left;
+        *off = chunk_base + (kStageChunk - chunk_left);
+        chunk_left -= need;
+        return true;
+    };
 
-        const uint64_t s = rg.id_lo + idx;
-        const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
-        if (lane == 0) {
-            const uint32_t root = sample_root(rg.seed, s, g.n);
-            members[0] = root;
-            hash[hslot(root)] = root;
-            s_size = 1;
-            s_over = 0;
+    for (;;) {
+        if (lane == 0) s_tk = atomicAdd(ticket, kTicketChunk);
+        __syncthreads();
+        const uint32_t base_idx = s_tk;
+        __syncthreads();
+        if (base_idx >= rg.count) break;
+
+        // ---- one sample per lane: a root without a live in-edge is a
+        // complete set {root}; the others go to the wave-per-sample BFS
+        const uint32_t my_idx = base_idx + lane;
+        const bool valid = my_idx < rg.count;
+        const uint64_t ms = rg.id_lo + my_idx;
+        uint32_t root = 0, rbeg = 0, rend = 0;
+        bool single = false;
+        if (valid) {
+            root = sample_root(rg.seed, ms, g.n);
+            rbeg = g.off[root];
+            rend = g.off[root + 1];
+            single = rend - rbeg <= kLaneDegCap;
+            for (uint32_t grp = rbeg >> 2; single && (grp << 2) < rend; ++grp) {
+                const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
+                const Philox4 r = philox10(grp, (uint32_t)ms, (uint32_t)(ms >> 32), 1u, k0, k1);
+                const uint32_t e0 = grp << 2;
+                const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+                const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t e = e0 + j;
+                    if (e >= rbeg && e < rend && rr[j] < tt[j]) single = false;
+                }
+            }
         }
+        const uint64_t smask = __ballot(single);
+        const uint32_t nsingle = (uint32_t)__popcll(smask);
+        if (nsingle) {
+            uint64_t off = 0;
+            const bool ok = reserve(nsingle, &off);
+            const uint32_t rank = (uint32_t)__popcll(smask & ((1ull << lane) - 1ull));
+            if (single) {
+                if (ok) {
+                    o.stage[off + rank] = root;
+                    atomicAdd(&o.counts[root], 1u);
+                    o.stage_off[my_idx] = off + rank;
+                    o.sizes[my_idx] = 1;
+                    st_sets += 1;
+                    st_entries += 1;
+                    st_edges += rend - rbeg;
+                } else {
+                    o.retry[atomicAdd(o.retry_n, 1u)] = my_idx;
+                }
+            }
+        }
+        const uint64_t pmask = __ballot(valid && !single);
+        const uint32_t npend = (uint32_t)__popcll(pmask);
+        if (valid && !single) s_pend[__popcll(pmask & ((1ull << lane) - 1ull))] = my_idx;
         __syncthreads();
 
-        uint32_t head = 0, size = 1;
-        uint32_t my_edges = 0, my_live = 0;
-        while (head < size) {
-            const uint32_t nb = min(kWave, size - head);
-            uint32_t beg = 0, end = 0;
-            if (lane < nb) {
-                const uint32_t v = members[head + lane];
-                beg = g.off[v];
-                end = g.off[v + 1];
+        // ---- wave-per-sample BFS for the remaining samples of this batch
+        for (uint32_t pi = 0; pi < npend; ++pi) {
+            const uint32_t idx = s_pend[pi];
+            const uint64_t s = rg.id_lo + idx;
+            const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
+            if (lane == 0) {
+                const uint32_t r0 = sample_root(rg.seed, s, g.n);
+                members[0] = r0;
+                hash[hslot(r0)] = r0;
+                s_size = 1;
+                s_over = 0;
             }
-            const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
-            const uint32_t incl = wave_incl_scan(ng);
-            const uint32_t G = __shfl(incl, kWave - 1, kWave);
-            s_base[lane] = incl - ng;
-            s_g0[lane] = beg >> 2;
-            s_beg[lane] = beg;
-            s_end[lane] = end;
-            my_edges += end - beg;
             __syncthreads();
-            uint32_t ow = 0;
-            for (uint32_t base = 0; base < G; base += kWave) {
-                if (lds_load(&s_over)) break;
-                const uint32_t t = base + lane;
-                if (t < G) {
-                    ow = owner_from(s_base, nb, t, ow);
-                    const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
-                    const uint32_t eb = s_beg[ow], ee = s_end[ow];
-                    const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
-                    const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
-                    const uint32_t e0 = grp << 2;
-                    const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-                    const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
+
+            uint32_t head = 0, size = 1;
+            uint32_t my_edges = 0, my_live = 0;
+            while (head < size) {
+                const uint32_t nb = min(kWave, size - head);
+                uint32_t beg = 0, end = 0;
+                if (lane < nb) {
+                    const uint32_t v = members[head + lane];
+                    beg = g.off[v];
+                    end = g.off[v + 1];
+                }
+                const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
+                const uint32_t incl = wave_incl_scan(ng);
+                const uint32_t G = __shfl(incl, kWave - 1, kWave);
+                s_base[lane] = incl - ng;
+                s_g0[lane] = beg >> 2;
+                s_beg[lane] = beg;
+                s_end[lane] = end;
+                my_edges += end - beg;
+                __syncthreads();
+                uint32_t ow = 0;
+                for (uint32_t base = 0; base < G; base += kWave) {
+                    if (lds_load(&s_over)) break;
+                    const uint32_t t = base + lane;
+                    if (t < G) {
+                        ow = owner_from(s_base, nb, t, ow);
+                        const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
+                        const uint32_t eb = s_beg[ow], ee = s_end[ow];
+                        const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
+                        const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
+                        const uint32_t e0 = grp << 2;
+                        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
+                        const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
 #pragma unroll
-                    for (uint32_t j = 0; j < 4; ++j) {
-                        const uint32_t e = e0 + j;
-                        if (e >= eb && e < ee && rr[j] < tt[j]) {
-                            ++my_live;
-                            small_insert(g.src[e], hash, members, &s_size, &s_over);
+                        for (uint32_t j = 0; j < 4; ++j) {
+                            const uint32_t e = e0 + j;
+                            if (e >= eb && e < ee && rr[j] < tt[j]) {
+                                ++my_live;
+                                small_insert(g.src[e], hash, members, &s_size, &s_over);
+                            }
                         }
                     }
                 }
+                __syncthreads();
+                head += nb;
+                size = s_size;
+                const uint32_t over = s_over;
+                __syncthreads();
+                if (over) break;
             }
-            __syncthreads();
-            head += nb;
-            size = s_size;
-            const uint32_t over = s_over;
-            __syncthreads();
-            if (over) break;
-        }
 
-        const bool over = s_over != 0u;
-        if (over) {
-            if (lane == 0) o.defer[atomicAdd(o.defer_n, 1u)] = idx;
-        } else {
-            bool stored = true;
-            if (size > chunk_left) {
-                if (lane == 0) s_chunk = atomicAdd(o.cursor, (unsigned long long)kStageChunk);
-                __syncthreads();
-                chunk_base = s_chunk;
-                chunk_left = kStageChunk;
-                __syncthreads();
-                if (chunk_base + kStageChunk > o.stage_cap) {
-                    chunk_left = 0;
-                    stored = false;
+            const bool over = s_over != 0u;
+            if (over) {
+                if (lane == 0) o.defer[atomicAdd(o.defer_n, 1u)] = idx;
+            } else {
+                uint64_t off = 0;
+                if (reserve(size, &off)) {
+                    for (uint32_t i = lane; i < size; i += kWave) {
+                        const uint32_t u = members[i];
+                        o.stage[off + i] = u;
+                        atomicAdd(&o.counts[u], 1u);
+                    }
+                    if (lane == 0) {
+                        o.stage_off[idx] = off;
+                        o.sizes[idx] = size;
+                        st_sets += 1;
+                        st_entries += size;
+                    }
+                    st_edges += my_edges;
+                    st_live += my_live;
+                } else if (lane == 0) {
+                    o.retry[atomicAdd(o.retry_n, 1u)] = idx;
                 }
             }
-            if (stored) {
-                const uint64_t off = chunk_base + (kStageChunk - chunk_left);
-                for (uint32_t i = lane; i < size; i += kWave) {
-                    const uint32_t u = members[i];
-                    o.stage[off + i] = u;
-                    atomicAdd(&o.counts[u], 1u);
+            // reset the hash slots this sample used (all members are present)
+            const uint32_t used = min(size, kSmallCap);
+            __syncthreads();
+            for (uint32_t i = lane; i < used; i += kWave) {
+                const uint32_t u = members[i];
+                uint32_t slot = hslot(u);
+                for (uint32_t probe = 0; probe < kHashSize; ++probe) {
+                    if (hash[slot] == u) { hash[slot] = kEmpty; break; }
+                    slot = (slot + 1) & (kHashSize - 1);
                 }
-                if (lane == 0) {
-                    o.stage_off[idx] = off;
-                    o.sizes[idx] = size;
-                    st_sets += 1;
-                    st_entries += size;
-                }
-                chunk_left -= size;
-                st_edges += my_edges;
-                st_live += my_live;
-            } else if (lane == 0) {
-                o.retry[atomicAdd(o.retry_n, 1u)] = idx;
             }
-        }
-        // reset the hash slots this sample used (all members are present)
-        const uint32_t used = min(size, kSmallCap);
-        __syncthreads();
-        for (uint32_t i = lane; i < used; i += kWave) {
-            const uint32_t u = members[i];
-            uint32_t slot = hslot(u);
-            for (uint32_t probe = 0; probe < kHashSize; ++probe) {
-                if (hash[slot] == u) { hash[slot] = kEmpty; break; }
-                slot = (slot + 1) & (kHashSize - 1);
+            if (over) {
+                // an abandoned set may have hashed vertices beyond the list
+                for (uint32_t i = lane; i < kHashSize; i += kWave) hash[i] = kEmpty;
             }
+            __syncthreads();
         }
-        if (over) {
-            // an abandoned set may have hashed vertices beyond the list
-            for (uint32_t i = lane; i < kHashSize; i += kWave) hash[i] = kEmpty;
-        }
-        __syncthreads();
     }
     st_sets = wave_sum64(st_sets);
     st_entries = wave_sum64(st_entries);

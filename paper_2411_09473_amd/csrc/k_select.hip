@@ -70,8 +70,8 @@ __device__ __forceinline__ uint64_t slots_max(const unsigned long long* slots) {
     return m;
 }
 
-__global__ __launch_bounds__(kClaimBS) void claim_kernel(const uint64_t* inv_off,
-                                                         const uint32_t* inv_set,
+__global__ __launch_bounds__(kClaimBS) void claim_kernel(const uint64_t* inv_off, uint32_t nseg,
+                                                         uint32_t n, const uint32_t* inv_set,
                                                          const uint64_t* set_off,
                                                          uint32_t* covered, uint32_t* cw,
                                                          const unsigned long long* slots,
@@ -85,51 +85,97 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const uint64_t* inv_off
         gains[i] = (uint32_t)(m >> 32);
         cw[v] = kSelected;
     }
-    const uint64_t lb = inv_off[v], len = inv_off[v + 1] - lb;
     const uint64_t step = (uint64_t)gridDim.x * kClaimBS;
     const uint32_t lane = threadIdx.x % kWave;
-    for (uint64_t base = (uint64_t)blockIdx.x * kClaimBS; base < len; base += step) {
-        const uint64_t t = base + threadIdx.x;
-        uint32_t nch = 0;
-        uint64_t a = 0, sz = 0;
-        if (t < len) {
-            const uint32_t j = inv_set[lb + t];
-            const uint32_t bit = 1u << (j & 31);
-            const uint32_t old = atomicOr(&covered[j >> 5], bit);
-            if (!(old & bit)) {
-                a = set_off[j];
-                sz = set_off[j + 1] - a;
-                nch = (uint32_t)((sz + kWave - 1) / kWave);
+    for (uint32_t seg = 0; seg < nseg; ++seg) {
+        const uint64_t* io = inv_off + (uint64_t)seg * ((uint64_t)n + 1);
+        const uint64_t lb = io[v], len = io[v + 1] - lb;
+        for (uint64_t base = (uint64_t)blockIdx.x * kClaimBS; base < len; base += step) {
+            const uint64_t t = base + threadIdx.x;
+            uint32_t nch = 0;
+            uint64_t a = 0, sz = 0;
+            if (t < len) {
+                const uint32_t j = inv_set[lb + t];
+                const uint32_t bit = 1u << (j & 31);
+                const uint32_t old = atomicOr(&covered[j >> 5], bit);
+                if (!(old & bit)) {
+                    a = set_off[j];
+                    sz = set_off[j + 1] - a;
+                    nch = (uint32_t)((sz + kWave - 1) / kWave);
+                }
             }
-        }
-        // one queue reservation per wave
-        const uint32_t incl = wave_incl_scan(nch);
-        const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-        uint32_t wbase = 0;
-        if (lane == kWave - 1 && tot) wbase = atomicAdd(chunk_n, tot);
-        wbase = __shfl(wbase, kWave - 1, kWave);
-        const uint32_t pos = wbase + incl - nch;
-        for (uint32_t c = 0; c < nch; ++c) {
-            const uint64_t o = (uint64_t)c * kWave;
-            chunks[pos + c] = Chunk{a + o, (uint32_t)(sz - o < kWave ? sz - o : kWave), 0u};
+            // one queue reservation per wave
+            const uint32_t incl = wave_incl_scan(nch);
+            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+            uint32_t wbase = 0;
+            if (lane == kWave - 1 && tot) wbase = atomicAdd(chunk_n, tot);
+            wbase = __shfl(wbase, kWave - 1, kWave);
+            const uint32_t pos = wbase + incl - nch;
+            for (uint32_t c = 0; c < nch; ++c) {
+                const uint64_t o = (uint64_t)c * kWave;
+                chunks[pos + c] = Chunk{a + o, (uint32_t)(sz - o < kWave ? sz - o : kWave), 0u};
+            }
         }
     }
 }
+
+// When the queue is long (a seed covering many sets), decrements are first
+// summed per workgroup in an LDS table (vertex -> count) and applied with one
+// atomic per distinct vertex: covered sets share their high-degree vertices,
+// which would otherwise take one global atomic per covering set. A vertex
+// that finds no slot within a few probes is decremented directly.
+constexpr uint32_t kAggBits = 12;
+constexpr uint32_t kAggSize = 1u << kAggBits;
+constexpr uint32_t kAggProbes = 8;
 
 __global__ __launch_bounds__(kDecBS) void decrement_kernel(const Chunk* chunks,
                                                            const uint32_t* chunk_n,
                                                            const uint32_t* set_vtx, uint32_t* cw,
                                                            const uint32_t* seeds, uint32_t i) {
+    __shared__ uint32_t h_key[kAggSize], h_cnt[kAggSize];
     const uint32_t nchunks = *chunk_n;
+    const uint32_t wpb = kDecBS / kWave;
+    if (blockIdx.x * wpb >= nchunks) return;
     const uint32_t v = seeds[i];
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t wid = (blockIdx.x * kDecBS + threadIdx.x) / kWave;
-    const uint32_t nw = gridDim.x * kDecBS / kWave;
+    const uint32_t wid = blockIdx.x * wpb + threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * wpb;
+    const bool agg = nchunks >= 4 * nw;
+    if (agg) {
+        for (uint32_t x = threadIdx.x; x < kAggSize; x += kDecBS) {
+            h_key[x] = kEmpty;
+            h_cnt[x] = 0;
+        }
+        __syncthreads();
+    }
     for (uint32_t c = wid; c < nchunks; c += nw) {
         const Chunk ch = chunks[c];
         if (lane < ch.len) {
             const uint32_t u = set_vtx[ch.off + lane];
-            if (u != v) atomicSub(&cw[u], 1u);
+            if (u != v) {
+                bool done = false;
+                if (agg) {
+                    uint32_t slot = (u * 0x9E3779B1u) >> (32 - kAggBits);
+                    for (uint32_t p = 0; p < kAggProbes; ++p) {
+                        uint32_t cur = h_key[slot];
+                        if (cur == kEmpty) cur = atomicCAS(&h_key[slot], kEmpty, u);
+                        if (cur == kEmpty || cur == u) {
+                            atomicAdd(&h_cnt[slot], 1u);
+                            done = true;
+                            break;
+                        }
+                        slot = (slot + 1) & (kAggSize - 1);
+                    }
+                }
+                if (!done) atomicSub(&cw[u], 1u);
+            }
+        }
+    }
+    if (agg) {
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < kAggSize; x += kDecBS) {
+            const uint32_t c = h_cnt[x];
+            if (c) atomicSub(&cw[h_key[x]], c);
         }
     }
 }
@@ -155,12 +201,13 @@ hipError_t launch_argmax(const uint32_t* counts_work, uint32_t n, unsigned long 
     return hipGetLastError();
 }
 
-hipError_t launch_claim(const uint64_t* inv_off, const uint32_t* inv_set, const uint64_t* set_off,
-                        uint32_t* covered, uint32_t* counts_work, const unsigned long long* slots,
-                        uint32_t* seeds, uint32_t* gains, uint32_t i, Chunk* chunks,
-                        uint32_t* chunk_n, uint32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL(claim_kernel, dim3(grid), dim3(kClaimBS), 0, st, inv_off, inv_set, set_off,
-                       covered, counts_work, slots, seeds, gains, i, chunks, chunk_n);
+hipError_t launch_claim(const uint64_t* inv_off, uint32_t nseg, uint32_t n,
+                        const uint32_t* inv_set, const uint64_t* set_off, uint32_t* covered,
+                        uint32_t* counts_work, const unsigned long long* slots, uint32_t* seeds,
+                        uint32_t* gains, uint32_t i, Chunk* chunks, uint32_t* chunk_n,
+                        uint32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(claim_kernel, dim3(grid), dim3(kClaimBS), 0, st, inv_off, nseg, n, inv_set,
+                       set_off, covered, counts_work, slots, seeds, gains, i, chunks, chunk_n);
     return hipGetLastError();
 }
 
