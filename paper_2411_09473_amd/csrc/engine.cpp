@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -371,7 +372,13 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
                 std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
             tails = lanes * kLtChunk;
         }
-        const uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
+        uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
+        // IMM_STAGE_SCALE (a factor, default 1) scales this first guess; small
+        // values exercise the staging-growth path
+        if (const char* e = std::getenv("IMM_STAGE_SCALE")) {
+            const double f = std::atof(e);
+            if (f > 0.0) want = std::max<uint64_t>(64, (uint64_t)((double)want * f));
+        }
         IMM_TRY(grow(w.arena, &w.stage, &w.stage_cap, want, 0, st, "staging"));
     }
     HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));

@@ -29,7 +29,7 @@ import numpy as np
 
 TWO32 = 1 << 32
 U32_MAX = TWO32 - 1
-_CACHE_VERSION = "v1"
+_CACHE_VERSION = "v2"
 
 
 @dataclasses.dataclass
@@ -59,30 +59,31 @@ class Graph:
 
 
 # ---------------------------------------------------------------------------
-# Edge-list generators: directed, self-loops and duplicate edges removed, draws
-# continue until exactly m distinct edges exist (first occurrences in draw
-# order are kept), then vertex ids are relabelled by a seeded random
-# permutation.
+# Edge-list generators: directed, self-loops and duplicate edges removed.
+# Candidate edges are drawn independently; among the distinct non-loop
+# candidates exactly m are kept (a seeded uniform choice), and vertex ids are
+# relabelled by a seeded random permutation (the Graph500 practice).
 # ---------------------------------------------------------------------------
 
 
-def _first_distinct(n: int, draw, m: int, rng: np.random.Generator):
-    """Collect the first m distinct non-loop (src, dst) pairs in draw order."""
+def _keep_m_distinct(n: int, draw, m: int, rng: np.random.Generator):
+    """Draw candidate (src, dst) batches until at least m distinct non-loop
+    pairs exist, keep a uniform random m of them, permute vertex ids."""
     keys = np.empty(0, dtype=np.int64)
-    batch = int(m * 1.08) + 1024
+    batch = int(m * 1.06) + 1024
     while True:
         s, d = draw(batch)
         ok = s != d
-        k = s[ok].astype(np.int64) * n + d[ok].astype(np.int64)
-        keys = np.concatenate([keys, k])
-        _, first = np.unique(keys, return_index=True)
-        if first.size >= m:
-            first.sort()
-            keys = keys[first[:m]]
+        keys = np.unique(np.concatenate([keys, s[ok].astype(np.int64) * n + d[ok]]))
+        if keys.size >= m:
             break
-        batch = max(1024, int((m - first.size) * 1.5) + 1024)
-    src = (keys // n).astype(np.int64)
-    dst = (keys % n).astype(np.int64)
+        batch = max(1024, int((m - keys.size) * 1.5) + 1024)
+    if keys.size > m:
+        keep = rng.choice(keys.size, size=m, replace=False)
+        keep.sort()
+        keys = keys[keep]
+    src = keys // n
+    dst = keys % n
     perm = rng.permutation(n).astype(np.int64)
     return perm[src], perm[dst]
 
@@ -104,7 +105,7 @@ def rmat_edges(scale: int, m: int, a=0.57, b=0.19, c=0.19, seed: int = 1):
             d = (d << 1) | db
         return s, d
 
-    src, dst = _first_distinct(n, draw, m, rng)
+    src, dst = _keep_m_distinct(n, draw, m, rng)
     return n, src, dst, rng
 
 
@@ -118,7 +119,7 @@ def _chung_lu_weights(n: int, m: int, gamma: float) -> np.ndarray:
         return np.sum((i0 / (idx + i0)) ** alpha) - target
 
     lo, hi = 1e-9, float(n) * 1e6
-    for _ in range(200):
+    for _ in range(80):
         mid = np.sqrt(lo * hi)
         if f(mid) > 0:
             hi = mid
@@ -130,29 +131,31 @@ def _chung_lu_weights(n: int, m: int, gamma: float) -> np.ndarray:
 
 
 def chung_lu_edges(n: int, m: int, gamma: float, seed: int = 1):
-    """Directed Chung-Lu edges; the same expected-degree sequence is used for
-    the out-endpoint and the in-endpoint (correlated in/out degrees)."""
+    """Directed Chung-Lu edges: both endpoints of a candidate edge are drawn
+    with probability proportional to the same expected-degree sequence
+    (correlated in/out degrees). A batch of B candidates is drawn as
+    multinomial endpoint counts, with the sources randomly paired to the
+    targets, which is the same distribution as B independent draws."""
     rng = np.random.Generator(np.random.PCG64(seed))
     w = _chung_lu_weights(n, m, gamma)
-    cdf = np.cumsum(w)
-    cdf /= cdf[-1]
+    p = w / w.sum()
+    ids = np.arange(n, dtype=np.int64)
 
     def draw(bsz):
-        s = np.searchsorted(cdf, rng.random(bsz), side="right")
-        d = np.searchsorted(cdf, rng.random(bsz), side="right")
-        np.minimum(s, n - 1, out=s)
-        np.minimum(d, n - 1, out=d)
-        return s.astype(np.int64), d.astype(np.int64)
+        s = np.repeat(ids, rng.multinomial(bsz, p))
+        d = np.repeat(ids, rng.multinomial(bsz, p))
+        rng.shuffle(s)
+        return s, d
 
-    src, dst = _first_distinct(n, draw, m, rng)
+    src, dst = _keep_m_distinct(n, draw, m, rng)
     return n, src, dst, rng
 
 
 def to_csc(n: int, src: np.ndarray, dst: np.ndarray):
     """CSC of in-edges: columns by destination, sources ascending in a column."""
-    order = np.lexsort((src, dst))
-    row_src = src[order].astype(np.uint32)
-    cnt = np.bincount(dst, minlength=n).astype(np.uint64)
+    key = np.sort(dst.astype(np.int64) * n + src.astype(np.int64))
+    row_src = (key % n).astype(np.uint32)
+    cnt = np.bincount(key // n, minlength=n).astype(np.uint64)
     col_off = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(cnt, out=col_off[1:])
     return col_off, row_src

@@ -1,0 +1,151 @@
+"""Edge cases of the GPU path, each checked against the oracle: graphs without
+edges, every vertex selected, certain and impossible edges, sample ids that
+cross 2^32, the staging-growth path, device-memory budgets, device-pointer
+inputs, and repeated runs on a resident graph."""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import canonical, say
+
+pytestmark = pytest.mark.gpu
+
+T32 = 1 << 32
+
+
+def _parity(imm, orc, g, k, eps, seed, stream, pool=True):
+    dg = imm.graph_from(g, stream=stream)
+    r = imm.imm_run(dg, k, eps, 1.0, seed, flags=imm.IMM_KEEP_POOL if pool else 0,
+                    stream=stream)
+    o = orc.imm(g, k, eps, 1.0, seed, keep_pool=pool)
+    assert r.targets == o["targets"] and r.round_cov == o["round_cov"]
+    assert (r.theta, r.rounds, r.covered, r.lb) == (o["theta"], o["rounds"], o["covered"], o["lb"])
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    np.testing.assert_array_equal(r.gains, o["gains"])
+    if pool:
+        so, sv = r.pool()
+        cso, csv = canonical(o["set_off"], o["set_vtx"], g.n)
+        np.testing.assert_array_equal(so, cso)
+        np.testing.assert_array_equal(sv, csv)
+    return r
+
+
+@pytest.mark.parametrize("model", ["ic", "lt"])
+def test_no_edges(imm, orc, stream, model):
+    g = synth.tiny_graph(2, [], model, [])
+    say(f"no edges {model}")
+    for k in (1, 2):
+        _parity(imm, orc, g, k, 0.5, 3, stream)
+
+
+def test_select_every_vertex(imm, orc, stream):
+    g = synth.tiny_graph(6, [(0, 1), (1, 2), (2, 0), (3, 4)], "ic", [1 << 31] * 4)
+    _parity(imm, orc, g, 6, 0.5, 11, stream)
+
+
+def test_certain_and_impossible_edges(imm, orc, stream):
+    n = 300
+    edges = [(v, v + 1) for v in range(n - 1)] + [(v + 2, v) for v in range(0, n - 2, 7)]
+    thr = [T32 - 1] * (n - 1) + [0] * len(range(0, n - 2, 7))
+    g = synth.tiny_graph(n, edges, "ic", thr)
+    r = _parity(imm, orc, g, 3, 0.3, 5, stream)
+    assert r.stats["deferred"] > 0  # chains longer than the on-chip set limit
+
+
+def test_lt_with_no_live_edge_mass(imm, orc, stream):
+    # every column keeps 1/4 probability of no live in-edge
+    rng = np.random.default_rng(3)
+    n = 400
+    edges = sorted({(int(u), int(v)) for u, v in rng.integers(0, n, size=(3000, 2)) if u != v})
+    deg = np.bincount([v for _, v in edges], minlength=n)
+    q = [(3 << 30) // int(deg[v]) for _, v in edges]
+    g = synth.tiny_graph(n, edges, "lt", q)
+    _parity(imm, orc, g, 5, 0.3, 9, stream)
+
+
+def test_zero_thresholds(imm, orc, stream):
+    base = synth.make_graph("rmat12_wc")
+    g = synth.Graph("rmat12_zero", base.n, base.m, base.col_off, base.row_src,
+                    np.zeros(base.m, np.uint32), "ic")
+    _parity(imm, orc, g, 10, 0.5, 42, stream)
+
+
+def test_sample_ids_across_2_32(imm, orc, stream):
+    for name in ("rmat12_p10", "rmat12_lt"):
+        g = synth.make_graph(name)
+        dg = imm.graph_from(g, stream=stream)
+        first = (1 << 32) - 300
+        pool = imm.imm_sample(dg, 77, first, 600, stream=stream)
+        so, sv, cn = pool.export()
+        oso, osv = orc.sample(g, 77, first, 600)
+        cso, csv = canonical(oso, osv, g.n)
+        np.testing.assert_array_equal(so, cso)
+        np.testing.assert_array_equal(sv, csv)
+        np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
+
+
+@pytest.mark.parametrize("name", ["rmat12_p10", "cl_lt_xs"])
+def test_staging_growth_path(imm, orc, stream, name):
+    """A first staging guess far too small: sets are retried after growth
+    and the result is unchanged."""
+    spec = synth.WORKLOADS[name]
+    os.environ["IMM_STAGE_SCALE"] = "0.001"
+    try:
+        _parity(imm, orc, synth.make_graph(name), spec["k"], spec["eps"], 42, stream)
+    finally:
+        del os.environ["IMM_STAGE_SCALE"]
+
+
+def test_budget_enomem_then_retry(imm, orc, stream):
+    g = synth.make_graph("rmat12_wc")
+    dg = imm.graph_from(g, stream=stream)
+    with pytest.raises(imm.ImmError) as e:
+        imm.imm_run(dg, 10, 0.5, 1.0, 42, max_device_bytes=1 << 16, stream=stream)
+    assert e.value.status == imm.IMM_ENOMEM
+    r = imm.imm_run(dg, 10, 0.5, 1.0, 42, max_device_bytes=1 << 30, stream=stream)
+    o = orc.imm(g, 10, 0.5, 1.0, 42)
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    assert r.theta == o["theta"]
+
+
+def test_overflow_is_reported(imm, stream):
+    g = synth.make_graph("rmat12_wc")
+    dg = imm.graph_from(g, stream=stream)
+    with pytest.raises(imm.ImmError) as e:
+        imm.imm_run(dg, 10, 1e-4, 1.0, 42, stream=stream)
+    assert e.value.status == imm.IMM_EOVERFLOW
+
+
+def test_device_pointer_inputs(imm, orc, stream):
+    import torch
+    g = synth.make_graph("rmat12_wc")
+    t = lambda a, dt: torch.from_numpy(a.astype(dt).view(np.int64 if dt == np.uint64 else np.int32)).cuda()
+    dg = imm.imm_graph_create(g.n, g.m, t(g.col_off, np.uint64), t(g.row_src, np.uint32),
+                              t(g.weight, np.uint32), "ic", stream=stream)
+    torch.cuda.synchronize()
+    r = imm.imm_run(dg, 10, 0.5, 1.0, 42, stream=stream)
+    o = orc.imm(g, 10, 0.5, 1.0, 42)
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    so, sv = orc.sample(g, 42, 0, 3000)
+    s, ga, cov = imm.imm_greedy(g.n, t(so, np.uint64), t(sv, np.uint32), 10, stream=stream)
+    os_, og, ocov = orc.greedy(g.n, so, sv, 10)
+    np.testing.assert_array_equal(s, os_)
+    assert cov == ocov
+
+
+def test_repeated_runs_reuse_workspace(imm, orc, stream):
+    """The resident graph's cached workspace gives identical results run
+    after run, across models and different k on the same graph."""
+    g = synth.make_graph("rmat12_wc")
+    dg = imm.graph_from(g, stream=stream)
+    o10 = orc.imm(g, 10, 0.5, 1.0, 42)
+    o3 = orc.imm(g, 3, 0.3, 1.0, 7)
+    for _ in range(3):
+        r = imm.imm_run(dg, 10, 0.5, 1.0, 42, stream=stream)
+        np.testing.assert_array_equal(r.seeds, o10["seeds"])
+        r = imm.imm_run(dg, 3, 0.3, 1.0, 7, stream=stream)
+        np.testing.assert_array_equal(r.seeds, o3["seeds"])
+        assert r.theta == o3["theta"]

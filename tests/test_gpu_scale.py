@@ -1,0 +1,94 @@
+"""GPU vs oracle at the workload sizes the benchmark uses.
+
+* LiveJournal-shaped LT (n = 4.8M, m = 69M, k = 50, eps = 0.13): the whole
+  IMM run, bit-exact (theta trajectory, LB, seeds, gains, canonical pool).
+* Youtube-shaped IC (n = 1,134,890, m = 2,987,624, p = 0.01, k = 50,
+  eps = 0.13), the benchmark's configuration: the oracle cannot redo the
+  21M-set run inside a test, so the run is checked on sampled outputs the
+  oracle computes one by one (2000 random sets of the returned pool), and
+  the selection is checked by running the oracle's greedy (Algorithm 2) on
+  the returned pool; the theta schedule is checked against the host-side
+  theta plan.
+* One-tenth-size versions of both, bit-exact on the whole run.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import oracle_threads
+from gpu_util import canonical, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(imm, name, stream, flags=0):
+    spec = synth.WORKLOADS[name]
+    g = synth.make_graph(name)
+    dg = imm.graph_from(g, stream=stream)
+    r = imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"], flags=flags,
+                    stream=stream)
+    return g, spec, r
+
+
+def _full_parity(imm, orc, name, stream, pool):
+    say(f"full-run parity {name}")
+    g, spec, r = _run(imm, name, stream, imm.IMM_KEEP_POOL if pool else 0)
+    o = orc.imm(g, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                threads=oracle_threads(), keep_pool=pool)
+    assert r.targets == o["targets"]
+    assert r.round_cov == o["round_cov"]
+    assert (r.theta, r.rounds, r.covered, r.lb) == (o["theta"], o["rounds"], o["covered"], o["lb"])
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    np.testing.assert_array_equal(r.gains, o["gains"])
+    if pool:
+        so, sv = r.pool()
+        cso, csv = canonical(o["set_off"], o["set_vtx"], g.n)
+        np.testing.assert_array_equal(so, cso)
+        np.testing.assert_array_equal(sv, csv)
+
+
+@pytest.mark.timeout(300)
+def test_lj_lt_full_size_bit_exact(imm, orc, stream):
+    _full_parity(imm, orc, "lj_lt", stream, pool=True)
+
+
+def test_lj_lt_small_bit_exact(imm, orc, stream):
+    _full_parity(imm, orc, "lj_lt_s", stream, pool=True)
+
+
+@pytest.mark.timeout(300)
+def test_youtube_small_bit_exact(imm, orc, stream):
+    _full_parity(imm, orc, "youtube_ic_s", stream, pool=False)
+
+
+@pytest.mark.timeout(600)
+def test_youtube_full_size_sampled(imm, orc, stream):
+    say("full-size Youtube-shaped IC run (benchmark configuration)")
+    g, spec, r = _run(imm, "youtube_ic", stream, imm.IMM_KEEP_POOL)
+    so, sv = r.pool()
+    assert so.size - 1 == r.theta
+    # sampled sets, recomputed one by one by the oracle
+    rng = np.random.default_rng(2024)
+    ids = np.concatenate([[0, 1, r.theta - 1], rng.integers(0, r.theta, 2000)])
+    for s in ids:
+        want = np.sort(orc.rrr_set(g, spec["seed"], int(s)))
+        np.testing.assert_array_equal(sv[so[s]:so[s + 1]], want, err_msg=f"set {s}")
+    # the theta schedule (Algorithm 1 with the host-side constants)
+    lp, ls, _ = imm.imm_theta_plan(g.n, spec["k"], spec["eps"], spec["ell"])
+    for i, t in enumerate(r.targets[:-1], start=1):
+        assert t == math.ceil(lp / math.ldexp(g.n, -i))
+    epsp = math.sqrt(2.0) * spec["eps"]
+    x = math.ldexp(g.n, -r.rounds)
+    frac = r.round_cov[-1] / r.targets[r.rounds - 1]
+    if g.n * frac >= (1.0 + epsp) * x:
+        assert r.lb == g.n * frac / (1.0 + epsp)
+    assert r.targets[-1] == math.ceil(ls / r.lb) and r.theta == max(r.targets)
+    # selection: the oracle's greedy over the returned pool
+    say(f"oracle greedy over {so.size - 1} sets / {sv.size} entries")
+    os_, og, ocov = orc.greedy(g.n, so, sv, spec["k"])
+    np.testing.assert_array_equal(r.seeds, os_)
+    np.testing.assert_array_equal(r.gains, og)
+    assert r.covered == ocov
