@@ -64,6 +64,46 @@ def cpu_baseline(g, spec, seconds: float):
                       f"{el:.1f} s wall on {threads} threads; sampling phase only"}
 
 
+def sample_mode(args, imm, g, dg, spec, stream, torch):
+    """Steady-state Generate_RRRsets throughput: one imm_sample call of
+    args.sample_count ids per step (kernel times from HIP events)."""
+    for _ in range(args.warmup):
+        imm.imm_sample(dg, spec["seed"], 0, args.sample_count, flags=imm.IMM_TIMING,
+                       stream=stream).close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pools = []
+    for _ in range(args.steps):
+        p = imm.imm_sample(dg, spec["seed"], 0, args.sample_count, flags=imm.IMM_TIMING,
+                           stream=stream)
+        pools.append(p.stats)
+        p.close()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    st = pools[-1]
+    samp_ms = sum(x["ms_sample"] for x in pools) / len(pools)
+    main_ms = sum(x["ms_sample_main"] for x in pools) / len(pools)
+    nbytes = algorithmic_bytes(g.model, st["sets"], st["entries"], st["edges"], st["live"])
+    mbytes = algorithmic_bytes(g.model, st["main_sets"], st["main_entries"], st["main_edges"],
+                               st["main_live"])
+    ach = mbytes / (main_ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "RRR sets/s (steady-state sampling)", "value": st["sets"] / (samp_ms * 1e-3),
+        "unit": "RRR sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: imm_sample of {args.sample_count} ids",
+                   "seed": spec["seed"]},
+        "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
+        "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
+        "deferred": st["deferred"],
+        "roofline": {"kernel": "ic_small_kernel" if g.model == "ic" else "lt_small_kernel",
+                     "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBPS, "traffic": None, "avg_launch_ms": main_ms,
+                     "bytes_per_launch": mbytes},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +112,9 @@ def main():
     ap.add_argument("--workload", default="youtube_ic")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample-count", type=int, default=0,
+                    help="steady-state sampling mode: each step generates this many "
+                         "RRR sets with imm_sample (no selection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -90,6 +133,9 @@ def main():
     stream = torch.cuda.current_stream()
     dg = imm.graph_from(g, stream=stream)
     torch.cuda.synchronize()
+
+    if args.sample_count:
+        return sample_mode(args, imm, g, dg, spec, stream, torch)
 
     def step():
         return imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"],

@@ -133,7 +133,7 @@ constexpr uint64_t kBigScratchBytes = 16ull << 30;
 // Scalars the kernels update, in one device block.
 struct DevScalars {
     unsigned long long cursor;
-    uint32_t ticket_small, ticket_big, defer_n, retry_n, argmax_ticket, big_flag;
+    uint32_t ticket_small, ticket_big, defer_n, retry_n, spare_n, big_flag;
     uint32_t err, pad;
     unsigned long long stats[kStCount];
 };
@@ -250,6 +250,7 @@ struct Workspace {
     uint32_t* sizes = nullptr; uint64_t cap_sz = 0;
     uint32_t* defer = nullptr; uint64_t cap_df = 0;
     uint32_t* retry = nullptr; uint64_t cap_rt = 0;
+    uint32_t* spare = nullptr; uint64_t cap_sp = 0;  // third list for retry passes
     uint64_t* scan_tmp = nullptr; uint64_t cap_scan = 0;
     unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
     uint32_t* chunk_n = nullptr;          // k queue lengths
@@ -347,17 +348,15 @@ BigScratch big_view(const Workspace& w) {
 // w.n_sets (Generate_RRRsets with fused counting), then compact them. One
 // host synchronisation: after sampling, to learn whether any set is still
 // waiting for staging space and how much staging was used.
-imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                     uint64_t count64) {
-    if (count64 == 0) return IMM_OK;
-    if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
-    const uint32_t count = (uint32_t)count64;
+imm_status ws_extend_once(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                          uint32_t count) {
     hipStream_t st = w.st;
     IMM_TRY(ws_big_scratch(w, g->model));
     IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
     IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
     IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
     IMM_TRY(grow(w.arena, &w.retry, &w.cap_rt, count, 0, st, "retry list"));
+    IMM_TRY(grow(w.arena, &w.spare, &w.cap_sp, count, 0, st, "retry list"));
     {
         // expected entries plus the unused tails of every wave's (IC) or
         // lane's (LT) staging chunk
@@ -383,42 +382,44 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
     }
     HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));
 
-    const SampleRange rg{seed, id_lo, count};
-    auto out = [&]() {
-        return SampleOut{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
-                         w.defer, &w.sc->defer_n, w.retry, &w.sc->retry_n, w.sc->stats};
-    };
-    auto launch_large = [&](const uint32_t* list, const uint32_t* list_n, uint32_t* fl,
-                            uint32_t* fl_n) -> imm_status {
-        HIP_TRY(hipMemsetAsync(&w.sc->ticket_big, 0, 4, st));
-        const int t2 = w.timer.open(0);
+    // A pass runs the fast kernel over the range (list = nullptr) or over a
+    // list of indices, then the large-set kernel over what it deferred.
+    // Failures for lack of staging land in *fl; deferred sets in w.defer.
+    auto pass = [&](const uint32_t* list, const uint32_t* list_n, uint32_t nitems, uint32_t* fl,
+                    uint32_t* fl_n) -> imm_status {
+        const SampleRange rg{seed, id_lo, nitems, list, list_n};
+        const SampleRange rgl{seed, id_lo, count, nullptr, nullptr};
+        const SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
+                          w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
+        HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 8, st));  // ticket_small, ticket_big
+        HIP_TRY(hipMemsetAsync(&w.sc->defer_n, 0, 4, st));
+        const int th = w.timer.open(0);
+        const int tm = w.timer.open(4);
+        if (g->model == IMM_IC)
+            HIP_TRY(launch_ic_small(ic_view(g), rg, o, &w.sc->ticket_small, ic_small_grid(w.device), st));
+        else
+            HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, lt_small_grid(w.device), st));
+        w.timer.close(tm);
         const int t3 = w.timer.open(5);
         if (g->model == IMM_IC)
-            HIP_TRY(launch_ic_large(ic_view(g), rg, out(), list, list_n, fl, fl_n,
+            HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
                                     &w.sc->ticket_big, big_view(w), st));
         else
-            HIP_TRY(launch_lt_large(lt_view(g), rg, out(), list, list_n, fl, fl_n,
+            HIP_TRY(launch_lt_large(lt_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
                                     &w.sc->ticket_big, big_view(w), st));
         w.timer.close(t3);
-        w.timer.close(t2);
-        return IMM_OK;
+        w.timer.close(th);
+        return ws_read_scalars(w);
     };
-    const int th = w.timer.open(0);
-    const int tm = w.timer.open(4);
-    if (g->model == IMM_IC)
-        HIP_TRY(launch_ic_small(ic_view(g), rg, out(), &w.sc->ticket_small, ic_small_grid(w.device), st));
-    else
-        HIP_TRY(launch_lt_small(lt_view(g), rg, out(), &w.sc->ticket_small, lt_small_grid(w.device), st));
-    w.timer.close(tm);
-    w.timer.close(th);
-    // sets that outgrew the on-chip structures (the count stays on the device)
-    IMM_TRY(launch_large(w.defer, &w.sc->defer_n, w.retry, &w.sc->retry_n));
-    IMM_TRY(ws_read_scalars(w));
+    IMM_TRY(pass(nullptr, nullptr, count, w.retry, &w.sc->retry_n));
 
     // sets that found the staging buffer full: grow it (keeping what is
-    // stored), continue at the old capacity, redo them, until none is left
+    // stored), continue at the old capacity, and redo just those sets
+    uint32_t* in = w.retry;
+    uint32_t* in_n = &w.sc->retry_n;
+    uint32_t* out_l = w.spare;
+    uint32_t* out_n = &w.sc->spare_n;
     uint32_t failed = w.hsc->retry_n;
-    bool from_retry = true;
     for (int guard = 0; failed; ++guard) {
         if (guard == 32) return fail(IMM_ENOMEM, "staging could not be grown enough");
         const uint64_t used = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
@@ -431,15 +432,11 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
         w.stage_cap = cap;
         const unsigned long long cur = old_cap;
         HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
-        uint32_t* list = from_retry ? w.retry : w.defer;
-        uint32_t* list_n = from_retry ? &w.sc->retry_n : &w.sc->defer_n;
-        uint32_t* fl = from_retry ? w.defer : w.retry;
-        uint32_t* fl_n = from_retry ? &w.sc->defer_n : &w.sc->retry_n;
-        HIP_TRY(hipMemsetAsync(fl_n, 0, 4, st));
-        IMM_TRY(launch_large(list, list_n, fl, fl_n));
-        IMM_TRY(ws_read_scalars(w));
-        failed = from_retry ? w.hsc->defer_n : w.hsc->retry_n;
-        from_retry = !from_retry;
+        HIP_TRY(hipMemsetAsync(out_n, 0, 4, st));
+        IMM_TRY(pass(in, in_n, failed, out_l, out_n));
+        std::swap(in, out_l);
+        std::swap(in_n, out_n);
+        failed = (in == w.retry) ? w.hsc->retry_n : w.hsc->spare_n;
     }
 
     // compaction: set_off[n_sets .. n_sets+count] (based on the device copy of
@@ -457,6 +454,28 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
     w.n_sets += count;
     w.p_ub += stored_bound;
     return IMM_OK;
+}
+
+imm_status ws_sync_pool(Workspace& w);
+void ws_note_pool(Workspace& w, uint64_t sets_before);
+
+// ws_extend_once for [id_lo, id_lo + count); when the workspace has no set
+// size estimate yet, a pilot batch measures one before the rest is sized.
+imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                     uint64_t count64) {
+    if (count64 == 0) return IMM_OK;
+    if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
+    uint32_t count = (uint32_t)count64;
+    constexpr uint32_t kPilot = 1u << 16;
+    if (w.mean_size <= 0.0 && count > 2 * kPilot) {
+        const uint64_t before = w.n_sets;
+        IMM_TRY(ws_extend_once(w, g, seed, id_lo, kPilot));
+        IMM_TRY(ws_sync_pool(w));
+        ws_note_pool(w, before);
+        id_lo += kPilot;
+        count -= kPilot;
+    }
+    return ws_extend_once(w, g, seed, id_lo, count);
 }
 
 // Read the exact pool size (and the device error flag) at a synchronisation.

@@ -37,11 +37,14 @@ constexpr uint32_t kIcTicketChunk = 64;
 constexpr uint32_t kIcStageChunk = 4096;
 constexpr uint32_t kLtChunk = 1024;
 
-// Samples [id_lo, id_lo + count) of run seed `seed`.
+// Samples of run seed `seed`: sample id = id_lo + index, for the indices
+// [0, count), or, when `list` is given, for list[0 .. *list_n) (a retry pass).
 struct SampleRange {
     uint64_t seed;
     uint64_t id_lo;
     uint32_t count;
+    const uint32_t* list;
+    const uint32_t* list_n;
 };
 
 // Stats slots (uint64 counters in device memory).

@@ -105,17 +105,19 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
         return true;
     };
 
+    const uint32_t total = rg.list ? *rg.list_n : rg.count;
     for (;;) {
         if (lane == 0) s_tk = atomicAdd(ticket, kTicketChunk);
         __syncthreads();
-        const uint32_t base_idx = s_tk;
+        const uint32_t base_pos = s_tk;
         __syncthreads();
-        if (base_idx >= rg.count) break;
+        if (base_pos >= total) break;
 
         // ---- one sample per lane: a root without a live in-edge is a
         // complete set {root}; the others go to the wave-per-sample BFS
-        const uint32_t my_idx = base_idx + lane;
-        const bool valid = my_idx < rg.count;
+        const uint32_t my_pos = base_pos + lane;
+        const bool valid = my_pos < total;
+        const uint32_t my_idx = valid ? (rg.list ? rg.list[my_pos] : my_pos) : 0u;
         const uint64_t ms = rg.id_lo + my_idx;
         uint32_t root = 0, rbeg = 0, rend = 0;
         bool single = false;

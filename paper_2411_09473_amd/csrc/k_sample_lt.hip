@@ -10,8 +10,9 @@
 //    2^32), from where a short forward scan over (cum, src) pairs finds the
 //    same edge the plain search would.
 //  * The path is written straight into the lane's staging chunk. A per-lane
-//    1024-bit map in LDS answers "not on the path" for most vertices; a hit
-//    is confirmed by rescanning the path, so the test is exact.
+//    4096-bit Bloom filter (three hashes) in LDS answers "not on the path"
+//    for most vertices; a hit is confirmed by rescanning the path
+//    (vectorised), so the test is exact.
 //  * Counts are incremented as vertices join the path; a walk that has to
 //    move to the large-walk kernel (path longer than a chunk) or to a retry
 //    (staging full) gives its increments back first.
@@ -22,19 +23,53 @@ namespace imm {
 
 namespace {
 
-constexpr uint32_t kBloomBits = 10;   // 1024-bit path filter per lane
+constexpr uint32_t kBloomBits = 12;   // 4096-bit path filter per lane, 3 hashes
 constexpr uint32_t kBloomWords = (1u << kBloomBits) / 32;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kDirectDeg = 8;    // columns read whole, without the guide
 
-__device__ __forceinline__ uint32_t bloom_hash(uint32_t v) {
-    return (v * 0x9E3779B1u) >> (32 - kBloomBits);
+// The three filter positions of v (multiplicative hashes).
+__device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t h[3]) {
+    h[0] = (v * 0x9E3779B1u) >> (32 - kBloomBits);
+    h[1] = (v * 0x85EBCA77u) >> (32 - kBloomBits);
+    h[2] = (v * 0xC2B2AE3Du) >> (32 - kBloomBits);
+}
+
+// mb points at word 0 of this lane's filter; word w is mb[w * 64].
+__device__ __forceinline__ void bloom_set(uint32_t* mb, uint32_t v) {
+    uint32_t h[3];
+    bloom_pos(v, h);
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) mb[(h[j] >> 5) * kWave] |= 1u << (h[j] & 31);
+}
+
+__device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
+    uint32_t h[3];
+    bloom_pos(v, h);
+    bool all = true;
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) all &= ((mb[(h[j] >> 5) * kWave] >> (h[j] & 31)) & 1u) != 0;
+    return all;
 }
 
 // The live in-edge source of `cur` for draw r, or kNone. *reads counts the
-// (cum, src) pairs inspected.
+// (cum, src) pairs inspected. A short column is loaded whole in one round of
+// independent loads; a longer one starts at its guide entry.
 __device__ __forceinline__ uint32_t lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
                                             uint32_t r, uint32_t* reads) {
     const uint32_t d = end - beg;
+    if (d <= kDirectDeg) {
+        uint32_t res = kNone;
+#pragma unroll
+        for (uint32_t j = 0; j < kDirectDeg; ++j) {
+            if (j < d) {
+                const uint2 p = g.cs[beg + j];
+                if (res == kNone && r < p.x) res = p.y;
+            }
+        }
+        *reads += d;
+        return res;
+    }
     const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
     uint32_t e = g.guide[beg + jb];
     while (e < end) {
@@ -44,6 +79,31 @@ __device__ __forceinline__ uint32_t lt_pick(const LtGraphDev& g, uint32_t beg, u
         ++e;
     }
     return kNone;
+}
+
+// Is w among the len entries of path (which starts at stage[pos])? Entries
+// are read as aligned 16-byte groups, sixteen independent loads per round;
+// words of the groups outside [pos, pos + len) are ignored. The groups never
+// cross the end of the lane's chunk, whose bounds are multiples of four.
+__device__ __forceinline__ bool on_path(const uint32_t* stage, uint64_t pos, uint32_t len,
+                                        uint32_t w) {
+    const uint64_t end = pos + len;
+    for (uint64_t q = pos & ~3ull; q < end; q += 64) {
+        bool hit = false;
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+            const uint64_t b = q + 4 * j;
+            if (b < end) {
+                const uint4 v = *reinterpret_cast<const uint4*>(stage + b);
+                hit |= (v.x == w) & (b >= pos);
+                hit |= (v.y == w) & (b + 1 >= pos) & (b + 1 < end);
+                hit |= (v.z == w) & (b + 2 >= pos) & (b + 2 < end);
+                hit |= (v.w == w) & (b + 3 >= pos) & (b + 3 < end);
+            }
+        }
+        if (hit) return true;
+    }
+    return false;
 }
 
 __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
@@ -58,6 +118,7 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
     uint32_t w_steps = 0, w_reads = 0;
     uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
 
+    const uint32_t total = rg.list ? *rg.list_n : rg.count;
     for (;;) {
         const bool need = !has && !done;
         const uint64_t mask = __ballot(need);
@@ -67,10 +128,11 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
             if (lane == leader) base = atomicAdd(ticket, (uint32_t)__popcll(mask));
             base = __shfl(base, leader, kWave);
             if (need) {
-                idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-                if (idx >= rg.count) {
+                const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                if (pos >= total) {
                     done = true;
                 } else {
+                    idx = rg.list ? rg.list[pos] : pos;
                     s = rg.id_lo + idx;
                     cur = sample_root(rg.seed, s, g.n);
                     bool ok = true;
@@ -85,13 +147,11 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                         }
                     }
                     if (ok) {
-#pragma unroll
                         for (uint32_t wd = 0; wd < kBloomWords; ++wd) mb[wd * kWave] = 0u;
                         wstart = chunk_used;
                         o.stage[chunk_base + wstart] = cur;
                         atomicAdd(&o.counts[cur], 1u);
-                        const uint32_t h = bloom_hash(cur);
-                        mb[(h >> 5) * kWave] |= 1u << (h & 31);
+                        bloom_set(mb, cur);
                         len = 1;
                         w_steps = 0;
                         w_reads = 0;
@@ -112,17 +172,8 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
             }
             bool finish = nxt == kNone;
             if (!finish) {
-                const uint32_t h = bloom_hash(nxt);
-                const uint32_t bit = 1u << (h & 31);
-                if (mb[(h >> 5) * kWave] & bit) {
-                    const uint32_t* path = o.stage + chunk_base + wstart;
-                    for (uint32_t t = 0; t < len; ++t) {
-                        if (path[t] == nxt) {
-                            finish = true;
-                            break;
-                        }
-                    }
-                }
+                if (bloom_test(mb, nxt) && on_path(o.stage, chunk_base + wstart, len, nxt))
+                    finish = true;
                 if (!finish) {
                     bool keep = true;
                     if (wstart + len == kLtChunk) {
@@ -152,7 +203,7 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     if (keep) {
                         o.stage[chunk_base + wstart + len] = nxt;
                         atomicAdd(&o.counts[nxt], 1u);
-                        mb[(h >> 5) * kWave] |= bit;
+                        bloom_set(mb, nxt);
                         ++len;
                         cur = nxt;
                     }
