@@ -104,6 +104,81 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
     }))
 
 
+def _gen_instance(arg):
+    import synth
+    i, s = arg
+    return synth.make_graph(f"batch{i}", gen=s["gen"], model=s["model"], enc=s["enc"],
+                            gseed=s["gseed"])
+
+
+def make_batch_graphs(count: int):
+    """The multi-instance workload's graphs, generated in worker processes
+    (before this process touches the GPU)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    insts = synth.batch_instances(count)
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        graphs = list(ex.map(_gen_instance, enumerate(insts)))
+    return insts, graphs
+
+
+def batch_mode(args, imm, insts, graphs, stream, torch):
+    """Aggregate IMM queries/s of the multi-instance workload: all instances
+    in one imm_run_batch call per step, against the same instances run one
+    at a time with imm_run on the same GPU."""
+    dgs = [imm.graph_from(g, stream=stream) for g in graphs]
+    torch.cuda.synchronize()
+    qs = [(d, dict(k=s["k"], epsilon=s["eps"], ell=s["ell"], seed=s["seed"]))
+          for d, s in zip(dgs, insts)]
+
+    def batched():
+        return imm.imm_run_batch(qs, stream=stream)
+
+    def one_by_one():
+        return [imm.imm_run(d, q["k"], q["epsilon"], q["ell"], q["seed"], stream=stream)
+                for d, q in qs]
+
+    for _ in range(args.warmup):
+        batched()
+        one_by_one()
+    print("[bench] batch warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rb = batched()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print("[bench] batched steps done", file=sys.stderr, flush=True)
+    for _ in range(args.steps):
+        rs = one_by_one()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print("[bench] one-at-a-time steps done", file=sys.stderr, flush=True)
+    for a, b in zip(rb, rs):
+        assert a.theta == b.theta and list(a.seeds) == list(b.seeds), "batched != alone"
+    nq = len(qs)
+    ms_b = (t1 - t0) * 1e3 / args.steps
+    ms_s = (t2 - t1) * 1e3 / args.steps
+    sets = sum(r.stats["sets"] for r in rb)
+    print(json.dumps({
+        "metric": "IMM queries/s (batched)", "value": nq / (ms_b * 1e-3), "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{nq} IC instances: weighted-cascade R-MAT, scale U{{12..20}}, "
+                               f"degree U{{4..32}}, k in {{5,10,25,50}}, eps in {{0.5,0.3,0.13}}",
+                   "parallelism": "single GPU"},
+        "one_at_a_time_queries_per_s": nq / (ms_s * 1e-3),
+        "one_at_a_time_ms": ms_s,
+        "speedup": ms_s / ms_b,
+        "sets_per_s": sets / (ms_b * 1e-3),
+        "theta_range": [min(r.theta for r in rb), max(r.theta for r in rb)],
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +190,9 @@ def main():
     ap.add_argument("--sample-count", type=int, default=0,
                     help="steady-state sampling mode: each step generates this many "
                          "RRR sets with imm_sample (no selection)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="multi-instance mode: this many IMM instances per step, "
+                         "batched, against the same run one at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -122,12 +200,19 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    batch = None
+    if args.batch:
+        batch = make_batch_graphs(args.batch)
+        print(f"[bench] {args.batch} batch graphs ready", file=sys.stderr, flush=True)
+
     import torch
 
     import paper_2411_09473_amd as imm
     import synth
 
     torch.cuda.set_device(0)
+    if batch is not None:
+        return batch_mode(args, imm, batch[0], batch[1], torch.cuda.current_stream(), torch)
     spec = synth.WORKLOADS[args.workload]
     g = synth.make_graph(args.workload)
     stream = torch.cuda.current_stream()

@@ -148,6 +148,24 @@ imm_status imm_theta_plan(uint32_t n, uint32_t k, double eps, double ell,
  * exceeded or allocation failure; nothing leaks), IMM_EDEVICE. */
 imm_status imm_run(const imm_graph* g, const imm_params* p, void* stream, imm_result** out);
 
+/* imm_run_batch: `count` independent IMM runs (graphs[j], params[j]) advanced
+ * together, round by round, on one device: each round's sampling of every
+ * unfinished run is in flight at once (on up to 8 internal streams of default
+ * priority, ordered after the work already queued on `stream`), and each
+ * seed step of the greedy selection is one set of launches for all of them
+ * (on `stream`). Runs may share a graph. The results equal those of count
+ * imm_run calls with the same arguments, bit for bit: every set is a pure
+ * function of (graph, seed, sample id), and each run's selection reads only
+ * its own pool. Blocks until every run has finished.
+ *   graphs  const imm_graph*[count], all on the current device
+ *   params  imm_params[count]
+ *   out     imm_result*[count]: receives one result per run
+ * Errors: IMM_EINVAL (count = 0, a null or mixed-device graph, bad params),
+ * otherwise the first failing run's status; then every out[j] is NULL and
+ * nothing leaks. */
+imm_status imm_run_batch(const imm_graph* const* graphs, const imm_params* params,
+                         uint32_t count, void* stream, imm_result** out);
+
 /* theta (= |R| of the final selection), sampling rounds executed, LB, and
  * the number of sets covered by the seeds (the sum of the gains). */
 imm_status imm_result_info(const imm_result* r, uint64_t* theta, uint32_t* rounds, double* lb,

@@ -73,6 +73,7 @@ _sig = {
     "imm_graph_info": [_vp, _P(_u32), _P(_u64), _P(_int), _P(_u64)],
     "imm_theta_plan": [_u32, _u32, _dbl, _dbl, _P(_dbl), _P(_dbl), _P(_u32)],
     "imm_run": [_vp, _P(imm_params), _vp, _P(_vp)],
+    "imm_run_batch": [_vp, _vp, _u32, _vp, _vp],
     "imm_result_info": [_vp, _P(_u64), _P(_u32), _P(_dbl), _P(_u64)],
     "imm_result_seeds": [_vp, _vp, _vp],
     "imm_result_targets": [_vp, _P(_u32), _vp, _vp],
@@ -234,6 +235,27 @@ def imm_run(g: Graph, k, epsilon, ell=1.0, seed=0, flags=0, max_device_bytes=0,
     out = C.c_void_p()
     _check(_lib.imm_run(g.handle, C.byref(p), _stream(stream), C.byref(out)))
     return Result(out.value, k)
+
+
+def imm_run_batch(queries, stream=None) -> list:
+    """Run several IMM queries together (imm_run_batch).
+
+    queries: sequence of (Graph, dict) where the dict holds imm_run's keyword
+    arguments k, epsilon and optionally ell, seed, flags, max_device_bytes.
+    Returns one Result per query, in order."""
+    cnt = len(queries)
+    if cnt == 0:
+        return []
+    hs = (C.c_void_p * cnt)(*[g.handle.value for g, _ in queries])
+    ps = (imm_params * cnt)()
+    for j, (_, q) in enumerate(queries):
+        ps[j] = imm_params(k=q["k"], flags=q.get("flags", 0), epsilon=q["epsilon"],
+                           ell=q.get("ell", 1.0), seed=q.get("seed", 0),
+                           max_device_bytes=q.get("max_device_bytes", 0))
+    outs = (C.c_void_p * cnt)()
+    _check(_lib.imm_run_batch(C.cast(hs, _vp), C.cast(ps, _vp), cnt, _stream(stream),
+                              C.cast(outs, _vp)))
+    return [Result(outs[j], queries[j][1]["k"]) for j in range(cnt)]
 
 
 class Pool:

@@ -1,0 +1,257 @@
+// engine.hpp -- host-side structures of libimm shared by workspace.cpp,
+// runner.cpp and api.cpp: error reporting, device allocation with a byte
+// budget, the per-query device workspace, and the resident graph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/imm.h"
+#include "imm_internal.hpp"
+
+namespace imm {
+
+// ---------------------------------------------------------------- errors --
+
+imm_status fail(imm_status st, const std::string& msg);
+const char* last_error();  // this thread's last message
+double now_ms();
+
+#define IMM_TRY(expr)                \
+    do {                             \
+        imm_status _s = (expr);      \
+        if (_s != IMM_OK) return _s; \
+    } while (0)
+
+#define HIP_TRY(expr)                                                                \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess) {                                                      \
+            return ::imm::fail(_e == hipErrorOutOfMemory ? IMM_ENOMEM : IMM_EDEVICE, \
+                               std::string(#expr) + ": " + hipGetErrorString(_e));  \
+        }                                                                            \
+    } while (0)
+
+// ------------------------------------------------------------ allocation --
+
+// Device allocations of one owner, with an optional byte budget (0: none).
+struct Arena {
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    std::vector<std::pair<void*, uint64_t>> live;
+
+    imm_status alloc(void** p, uint64_t bytes, const char* what);
+    void release(void* p);
+    void release_all();
+    ~Arena() { release_all(); }
+};
+
+// Make *p hold at least `need` elements (growing by half or more), keeping
+// its first `keep` elements; waits for `st` before freeing the old buffer.
+template <class T>
+imm_status grow(Arena& a, T** p, uint64_t* cap, uint64_t need, uint64_t keep, hipStream_t st,
+                const char* what) {
+    if (*p && *cap >= need) return IMM_OK;
+    uint64_t nc = *cap + *cap / 2 > need ? *cap + *cap / 2 : need;
+    if (nc < 64) nc = 64;
+    T* q = nullptr;
+    imm_status s = a.alloc(reinterpret_cast<void**>(&q), nc * sizeof(T), what);
+    if (s != IMM_OK && nc > need) {
+        nc = need;
+        s = a.alloc(reinterpret_cast<void**>(&q), nc * sizeof(T), what);
+    }
+    IMM_TRY(s);
+    if (*p && keep) HIP_TRY(hipMemcpyAsync(q, *p, keep * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        a.release(*p);
+    }
+    *p = q;
+    *cap = nc;
+    return IMM_OK;
+}
+
+// Upper bound on the device memory of one workspace's large-set scratch.
+constexpr uint64_t kBigScratchBytes = 16ull << 30;
+
+// Scalars the kernels update, in one device block.
+struct DevScalars {
+    unsigned long long cursor;
+    uint32_t ticket_small, ticket_big, defer_n, retry_n, spare_n, big_flag;
+    uint32_t err, pad;
+    unsigned long long stats[kStCount];
+};
+
+// Phase timing with HIP events (phases: 0 sample, 1 compact, 2 index,
+// 3 select, 4 main sampling kernel, 5 large-set sampling kernel).
+struct Timer {
+    bool on = false;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    int open(int phase, hipStream_t st);
+    void close(int h, hipStream_t st);
+    void collect(double* ms, uint64_t* launches);
+    ~Timer();
+};
+
+// ------------------------------------------------------------- workspace --
+//
+// Device state of one IMM query (or of one imm_sample / imm_greedy call).
+// The pool grows by whole sampling rounds; its vertex->sets index is kept in
+// segments, one per round, each indexing only that round's sets (segment r
+// occupies inv_set positions [P_{r-1}, P_r), the range its sets occupy in
+// set_vtx), so no set is indexed twice.
+struct Workspace {
+    int device = 0;
+    uint32_t n = 0;
+    hipStream_t st = nullptr;  // the stream of the query using it
+    uint32_t big_cap = 0;      // large-set scratch slots wanted (0: fill the GPU)
+    Arena arena;
+    DevScalars* sc = nullptr;
+    DevScalars* hsc = nullptr;  // pinned mirror
+    uint64_t* hp = nullptr;     // pinned: pool size
+    uint32_t* herr = nullptr;   // pinned: error flag
+    uint32_t* counts_acc = nullptr;   // occurrences over all sets so far
+    uint32_t* counts_prev = nullptr;  // ... over the sets already indexed
+    uint32_t* counts_work = nullptr;  // the greedy's working copy
+    uint32_t* inv_cursor = nullptr;
+    uint64_t* inv_offs = nullptr;
+    uint64_t cap_offs = 0;
+    uint32_t nseg = 0;
+    uint64_t indexed_sets = 0;
+    uint64_t* set_off = nullptr;
+    uint64_t cap_sets = 0;
+    uint32_t* set_vtx = nullptr;
+    uint64_t cap_entries = 0;
+    uint32_t* inv_set = nullptr;
+    uint64_t cap_inv = 0;
+    uint32_t* covered = nullptr;
+    uint64_t cap_cov = 0;
+    uint32_t* stage = nullptr;
+    uint64_t stage_cap = 0;
+    uint64_t* stage_off = nullptr;
+    uint64_t cap_so = 0;
+    uint32_t* sizes = nullptr;
+    uint64_t cap_sz = 0;
+    uint32_t* defer = nullptr;
+    uint64_t cap_df = 0;
+    uint32_t* retry = nullptr;
+    uint64_t cap_rt = 0;
+    uint32_t* spare = nullptr;
+    uint64_t cap_sp = 0;
+    uint64_t* scan_tmp = nullptr;
+    uint64_t cap_scan = 0;
+    unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
+    uint32_t* chunk_n = nullptr;          // k queue lengths
+    Chunk* chunks = nullptr;
+    uint64_t cap_chunks = 0;
+    uint32_t* seeds_d = nullptr;
+    uint32_t* gains_d = nullptr;
+    uint64_t cap_k = 0;
+    uint32_t* gains_h = nullptr;  // pinned
+    SelectDesc* desc_d = nullptr; // one descriptor, for selection run alone
+    uint32_t* big = nullptr;
+    uint32_t big_slots = 0;
+    uint64_t n_sets = 0;
+    uint64_t p_exact = 0;    // pool size, exact as of the last synchronisation
+    uint64_t p_ub = 0;       // upper bound on the pool size
+    double mean_size = 0.0;  // mean set size of the last round (staging estimate)
+    uint64_t pending_count = 0;  // sets of the sampling pass in flight
+    uint64_t pending_lo = 0;
+    Timer timer;
+
+    ~Workspace();
+};
+
+}  // namespace imm
+
+// ---------------------------------------------------------------- graph --
+
+struct imm_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    imm_model model = IMM_IC;
+    int device = 0;
+    imm::Arena arena;
+    uint32_t* off = nullptr;
+    uint32_t* thr = nullptr;
+    uint32_t* src = nullptr;
+    uint2* cs = nullptr;
+    uint32_t* guide = nullptr;
+    // workspaces of finished queries, reused by later ones
+    std::mutex ws_mu;
+    std::vector<std::unique_ptr<imm::Workspace>> ws_cache;
+};
+
+struct imm_result {
+    uint32_t k = 0;
+    std::vector<uint32_t> seeds;
+    std::vector<uint64_t> gains;
+    uint64_t theta = 0;
+    uint32_t rounds = 0;
+    double lb = 0.0;
+    uint64_t covered = 0;
+    std::vector<uint64_t> targets, round_cov;
+    bool has_pool = false;
+    std::vector<uint64_t> set_off;
+    std::vector<uint32_t> set_vtx;
+    imm_stats stats{};
+};
+
+namespace imm {
+
+IcGraphDev ic_view(const imm_graph* g);
+LtGraphDev lt_view(const imm_graph* g);
+
+// ---- workspace.cpp
+imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget);
+imm_status ws_reset(Workspace& w, hipStream_t st, bool timing);
+imm_status ws_read_scalars(Workspace& w);
+// Sampling of [id_lo, id_lo + count): the pass is launched without waiting
+// (ws_extend_launch), then, after the stream is synchronised and the
+// scalars read, completed (retries, compaction: ws_extend_finish).
+imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                            uint64_t count);
+imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);
+// Both halves and the synchronisation in between.
+imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                     uint64_t count);
+// Selection: index update and per-instance state for k seeds (on w.st);
+// returns the descriptor with its block ranges left for the caller.
+imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d);
+// Queue the copy-out of gains, pool size and error flag on stream st.
+imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st);
+// After st is synchronised: error check, exact pool size, coverage.
+imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
+// Prepare, run and finish the selection of this workspace alone.
+imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
+imm_status ws_sync_pool(Workspace& w);
+void ws_note_pool(Workspace& w, uint64_t sets_before);
+imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<uint32_t>* sv,
+                          std::vector<uint32_t>* counts);
+void fill_stats(Workspace& w, imm_stats* s);
+
+// ---- runner.cpp
+// Theta constants (Tang et al. 2015, Eq. 9 and Eq. 6 with ell adjusted).
+imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* lambda_prime,
+                      double* lambda_star, uint32_t* i_max);
+// Run queries to completion, advancing them together round by round.
+// streams[q] (may repeat) is the stream query q samples on; `main` carries
+// the batched selection. out[q] receives a result or stays null with
+// status[q] set.
+void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t count,
+                 hipStream_t main, const hipStream_t* streams, imm_result** out,
+                 imm_status* status, std::string* errors);
+
+}  // namespace imm

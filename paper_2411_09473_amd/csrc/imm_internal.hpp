@@ -137,25 +137,37 @@ struct Chunk {
     uint32_t len;  // 1..64
     uint32_t pad;
 };
-// Partial maxima slots per seed (argmax spreads its atomics over these).
+// Partial maxima slots per seed step (argmax spreads its atomics over these).
 constexpr uint32_t kArgSlots = 32;
-uint32_t argmax_grid(uint32_t n);
-uint32_t select_grid(int device);
-// slots[0..kArgSlots) must be zero before the launch for seed i.
-hipError_t launch_argmax(const uint32_t* counts_work, uint32_t n, unsigned long long* slots,
-                         uint32_t grid, hipStream_t st);
-// Records seed i and its gain, marks it selected, claims its uncovered sets
-// and queues their members in chunks (chunk_n zero before the launch).
-// The index is kept in nseg segments (one per sampling round); segment r's
-// offsets are inv_off[r * (n + 1) .. r * (n + 1) + n], absolute in inv_set.
-hipError_t launch_claim(const uint64_t* inv_off, uint32_t nseg, uint32_t n,
-                        const uint32_t* inv_set, const uint64_t* set_off, uint32_t* covered,
-                        uint32_t* counts_work, const unsigned long long* slots, uint32_t* seeds,
-                        uint32_t* gains, uint32_t i, Chunk* chunks, uint32_t* chunk_n,
-                        uint32_t grid, hipStream_t st);
-hipError_t launch_decrement(const Chunk* chunks, const uint32_t* chunk_n, const uint32_t* set_vtx,
-                            uint32_t* counts_work, const uint32_t* seeds, uint32_t i,
-                            uint32_t grid, hipStream_t st);
+
+// One instance's greedy state, as the batched selection kernels see it.
+// Its index has nseg segments; segment r's offsets are
+// inv_offs[r * (n + 1) .. r * (n + 1) + n], absolute in inv_set. slots holds
+// k * kArgSlots zeroed entries, chunk_n k zeroed counters. Workgroups
+// [arg_lo, arg_lo + arg_cnt) of the argmax launch and [sel_lo, sel_lo +
+// sel_cnt) of the claim and decrement launches belong to this instance;
+// ranges ascend with the instance index.
+struct SelectDesc {
+    uint32_t* cw;
+    const uint64_t* inv_offs;
+    const uint32_t* inv_set;
+    const uint64_t* set_off;
+    const uint32_t* set_vtx;
+    uint32_t* covered;
+    unsigned long long* slots;
+    uint32_t* seeds;
+    uint32_t* gains;
+    Chunk* chunks;
+    uint32_t* chunk_n;
+    uint32_t n, k, nseg;
+    uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
+    uint32_t pad;
+};
+uint32_t argmax_blocks(uint32_t n);
+uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch);
+// Seed step t (argmax, claim, decrement) of every instance with t < k.
+hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,
+                              uint32_t arg_blocks, uint32_t sel_blocks, hipStream_t st);
 
 // ---- misc
 hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,

@@ -1,0 +1,341 @@
+// runner.cpp -- IMM's sampling/selection driver (Algorithm 1) with the theta
+// schedule of Tang et al. 2015, for one query or a batch of them.
+//
+// Each query is a state machine over iterations: sampling round i targets
+// theta_i = ceil(lambda' 2^i / n) sets and ends with a greedy selection and
+// the lower-bound test; after the break (or the last round) one final
+// iteration targets theta = ceil(lambda* / LB) and its selection is the
+// answer. A batch advances all its queries one iteration at a time: every
+// query launches its sampling on its own stream, one synchronisation, then
+// the selections of all queries run together (each launch of the selection
+// kernels covers every query) and one more synchronisation; the FP64 theta
+// decisions are taken on the host in between.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace imm {
+
+namespace {
+
+// FP64, no contraction, this exact order (kept identical to IMM's theta
+// expressions: Tang et al. 2015 Eq. 9 lambda', Eq. 6 lambda*, with ell
+// replaced by ell (1 + ln 2 / ln n)).
+const double kLn2 = 0.69314718055994530942;
+const double kInvE = 0.36787944117144232160;
+
+double log_binom(uint32_t n, uint32_t k) {
+    double acc = 0.0;
+    for (uint32_t i = 1; i <= k; ++i) acc += std::log((double)(n - k + i) / (double)i);
+    return acc;
+}
+
+uint32_t bitlen(uint32_t x) {
+    uint32_t b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+constexpr size_t kMaxCachedWorkspaces = 8;
+
+}  // namespace
+
+imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* lambda_prime,
+                      double* lambda_star, uint32_t* i_max) {
+    if (n < 2 || k == 0 || k > n || !(eps > 0.0) || !(ell > 0.0))
+        return fail(IMM_EINVAL, "theta_plan: need n >= 2, 1 <= k <= n, eps > 0, ell > 0");
+    const double ln_n = std::log((double)n);
+    const double ell_p = ell * (1.0 + kLn2 / ln_n);
+    const double logcnk = log_binom(n, k);
+    const double eps_p = std::sqrt(2.0) * eps;
+    const double lam_p = (2.0 + 2.0 / 3.0 * eps_p) *
+                         (logcnk + ell_p * ln_n + std::log(std::log2((double)n))) * (double)n /
+                         (eps_p * eps_p);
+    const double one_m = 1.0 - kInvE;
+    const double alpha = std::sqrt(ell_p * ln_n + kLn2);
+    const double beta = std::sqrt(one_m * (logcnk + ell_p * ln_n + kLn2));
+    const double t = one_m * alpha + beta;
+    const double lam_s = 2.0 * (double)n * t * t / (eps * eps);
+    *lambda_prime = lam_p;
+    *lambda_star = lam_s;
+    *i_max = bitlen(n - 1) - 1;
+    return IMM_OK;
+}
+
+namespace {
+
+struct Query {
+    imm_graph* g = nullptr;
+    imm_params p{};
+    hipStream_t st = nullptr;
+    std::unique_ptr<Workspace> w;
+    double lam_p = 0, lam_s = 0, eps_p = 0, lb = 1.0;
+    uint32_t i_max = 0, i = 0;
+    bool final = false, done = false;
+    uint64_t before = 0, cov = 0;
+    std::unique_ptr<imm_result> r;
+    imm_status status = IMM_OK;
+    std::string err;
+    double t0 = 0, ms_select = 0;
+    SelectDesc desc{};
+};
+
+imm_status acquire_workspace(Query& q, uint32_t big_cap) {
+    {
+        std::lock_guard<std::mutex> lk(q.g->ws_mu);
+        auto& c = q.g->ws_cache;
+        for (size_t j = 0; j < c.size(); ++j) {
+            if (c[j]->arena.budget == q.p.max_device_bytes) {
+                q.w = std::move(c[j]);
+                c.erase(c.begin() + (long)j);
+                break;
+            }
+        }
+    }
+    if (!q.w) {
+        q.w.reset(new Workspace());
+        q.w->big_cap = big_cap;
+        IMM_TRY(ws_init(*q.w, q.g->n, q.g->device, q.st, q.p.max_device_bytes));
+    } else if (q.w->big_cap != big_cap) {
+        // large-set scratch sized for another batch width: reallocated on use
+        if (q.w->big) q.w->arena.release(q.w->big);
+        q.w->big = nullptr;
+        q.w->big_slots = 0;
+        q.w->big_cap = big_cap;
+    }
+    return ws_reset(*q.w, q.st, (q.p.flags & IMM_TIMING) != 0);
+}
+
+void release_workspace(Query& q) {
+    if (!q.w) return;
+    std::lock_guard<std::mutex> lk(q.g->ws_mu);
+    if (q.g->ws_cache.size() < kMaxCachedWorkspaces) q.g->ws_cache.push_back(std::move(q.w));
+    q.w.reset();
+}
+
+imm_status start(Query& q, uint32_t big_cap) {
+    q.t0 = now_ms();
+    if (q.p.k == 0 || q.p.k > q.g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
+    if (!(q.p.epsilon > 0.0) || !(q.p.ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
+    IMM_TRY(theta_plan(q.g->n, q.p.k, q.p.epsilon, q.p.ell, &q.lam_p, &q.lam_s, &q.i_max));
+    IMM_TRY(acquire_workspace(q, big_cap));
+    q.r.reset(new imm_result());
+    q.r->k = q.p.k;
+    q.eps_p = std::sqrt(2.0) * q.p.epsilon;
+    q.lb = 1.0;
+    q.i = 0;
+    q.final = q.i_max == 0;
+    return IMM_OK;
+}
+
+// This iteration's target, and its sampling launched on the query's stream.
+imm_status begin_iteration(Query& q) {
+    double tf;
+    if (!q.final) {
+        ++q.i;
+        tf = std::ceil(q.lam_p / std::ldexp((double)q.g->n, -(int)q.i));
+        if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta_i >= 2^32");
+        if (q.r->targets.size() < 63) q.r->targets.push_back((uint64_t)tf);
+    } else {
+        tf = std::ceil(q.lam_s / q.lb);
+        if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta >= 2^32");
+        q.r->targets.push_back((uint64_t)tf);
+    }
+    const uint64_t target = (uint64_t)tf;
+    Workspace& w = *q.w;
+    q.before = w.n_sets;
+    return ws_extend_launch(w, q.g, q.p.seed, w.n_sets,
+                            w.n_sets < target ? target - w.n_sets : 0);
+}
+
+// After the theta decision of this iteration's coverage.
+imm_status end_iteration(Query& q) {
+    Workspace& w = *q.w;
+    IMM_TRY(ws_select_finish(w, q.p.k, q.before, &q.cov));
+    imm_result& r = *q.r;
+    if (!q.final) {
+        r.round_cov.push_back(q.cov);
+        r.rounds = q.i;
+        const double x = std::ldexp((double)q.g->n, -(int)q.i);
+        const double frac = (double)q.cov / (double)w.n_sets;
+        if ((double)q.g->n * frac >= (1.0 + q.eps_p) * x) {
+            q.lb = (double)q.g->n * frac / (1.0 + q.eps_p);
+            q.final = true;
+        } else if (q.i == q.i_max) {
+            q.final = true;
+        }
+        return IMM_OK;
+    }
+    r.seeds.resize(q.p.k);
+    HIP_TRY(hipMemcpyAsync(r.seeds.data(), w.seeds_d, (uint64_t)q.p.k * 4, hipMemcpyDeviceToHost,
+                           w.st));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    r.gains.assign(w.gains_h, w.gains_h + q.p.k);
+    r.theta = w.n_sets;
+    r.lb = q.lb;
+    r.covered = q.cov;
+    const double t1 = now_ms();
+    IMM_TRY(ws_read_scalars(w));
+    fill_stats(w, &r.stats);
+    r.stats.ms_select += q.ms_select;
+    r.stats.ms_total = t1 - q.t0;
+    r.stats.rounds = r.rounds;
+    if (q.p.flags & IMM_KEEP_POOL) {
+        IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
+        r.has_pool = true;
+    }
+    q.done = true;
+    return IMM_OK;
+}
+
+}  // namespace
+
+void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t count,
+                 hipStream_t main, const hipStream_t* streams, imm_result** out,
+                 imm_status* status, std::string* errors) {
+    std::vector<Query> qs(count);
+    std::vector<Query*> active;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, graphs[0]->device);
+    const uint32_t big_cap = count > 1 ? std::max<uint32_t>(32u, (uint32_t)cus * 8u / count) : 0u;
+    auto finish_err = [&](Query& q, imm_status s) {
+        q.status = s;
+        q.err = last_error();
+        q.done = true;
+        q.w.reset();  // a failed workspace is not reused
+    };
+    for (uint32_t j = 0; j < count; ++j) {
+        Query& q = qs[j];
+        q.g = graphs[j];
+        q.p = params[j];
+        q.st = streams[j];
+        const imm_status s = start(q, big_cap);
+        if (s != IMM_OK) finish_err(q, s);
+        else active.push_back(&q);
+    }
+
+    std::vector<SelectDesc> descs;
+    SelectDesc* descs_h = nullptr;
+    SelectDesc* descs_d = nullptr;
+    size_t cap_descs = 0;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    std::vector<hipEvent_t> joins;
+    bool timing = false;
+    for (auto* q : active) timing |= (q->p.flags & IMM_TIMING) != 0;
+    if (timing) {
+        (void)hipEventCreate(&ev_a);
+        (void)hipEventCreate(&ev_b);
+    }
+
+    while (!active.empty()) {
+        // sampling, each query on its stream
+        std::vector<Query*> live;
+        for (auto* q : active) {
+            const imm_status s = begin_iteration(*q);
+            if (s != IMM_OK) finish_err(*q, s);
+            else live.push_back(q);
+        }
+        // one wait per stream, then retries, compaction, index, selection state
+        std::vector<hipStream_t> synced;
+        std::vector<Query*> ready;
+        for (auto* q : live) {
+            if (std::find(synced.begin(), synced.end(), q->st) == synced.end()) {
+                (void)hipStreamSynchronize(q->st);
+                synced.push_back(q->st);
+            }
+        }
+        for (auto* q : live) {
+            imm_status s = ws_extend_finish(*q->w, q->g, q->p.seed);
+            if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
+            if (s != IMM_OK) finish_err(*q, s);
+            else ready.push_back(q);
+        }
+        // the selections of all queries together, on the main stream
+        if (!ready.empty()) {
+            descs.clear();
+            uint32_t arg_total = 0, sel_total = 0, kmax = 0;
+            for (auto* q : ready) {
+                SelectDesc d = q->desc;
+                d.arg_lo = arg_total;
+                d.arg_cnt = argmax_blocks(d.n);
+                d.sel_lo = sel_total;
+                d.sel_cnt = select_blocks(q->g->device, q->w->n_sets, (uint32_t)ready.size());
+                arg_total += d.arg_cnt;
+                sel_total += d.sel_cnt;
+                kmax = std::max(kmax, d.k);
+                descs.push_back(d);
+            }
+            bool ok = true;
+            if (cap_descs < descs.size()) {
+                if (descs_h) (void)hipHostFree(descs_h);
+                if (descs_d) (void)hipFree(descs_d);
+                descs_h = nullptr;
+                descs_d = nullptr;
+                cap_descs = descs.size() * 2;
+                ok = hipHostMalloc((void**)&descs_h, cap_descs * sizeof(SelectDesc),
+                                   hipHostMallocDefault) == hipSuccess &&
+                     hipMalloc((void**)&descs_d, cap_descs * sizeof(SelectDesc)) == hipSuccess;
+                if (!ok) cap_descs = 0;
+            }
+            if (ok) {
+                std::memcpy(descs_h, descs.data(), descs.size() * sizeof(SelectDesc));
+                for (auto* q : ready) {
+                    if (q->st == main) continue;
+                    hipEvent_t e = nullptr;
+                    (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                    (void)hipEventRecord(e, q->st);
+                    (void)hipStreamWaitEvent(main, e, 0);
+                    joins.push_back(e);
+                }
+                ok = hipMemcpyAsync(descs_d, descs_h, descs.size() * sizeof(SelectDesc),
+                                    hipMemcpyHostToDevice, main) == hipSuccess;
+                if (timing) (void)hipEventRecord(ev_a, main);
+                for (uint32_t t = 0; ok && t < kmax; ++t)
+                    ok = launch_select_step(descs_d, (uint32_t)descs.size(), t, arg_total,
+                                            sel_total, main) == hipSuccess;
+                if (timing) (void)hipEventRecord(ev_b, main);
+                for (auto* q : ready)
+                    if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main) == IMM_OK;
+                if (ok) ok = hipStreamSynchronize(main) == hipSuccess;
+                for (auto e : joins) (void)hipEventDestroy(e);
+                joins.clear();
+                if (ok && timing) {
+                    float msf = 0.f;
+                    (void)hipEventElapsedTime(&msf, ev_a, ev_b);
+                    for (auto* q : ready) q->ms_select += msf;
+                }
+            }
+            for (auto* q : ready) {
+                const imm_status s = ok ? end_iteration(*q)
+                                        : fail(IMM_EDEVICE, "batched selection failed");
+                if (s != IMM_OK) finish_err(*q, s);
+            }
+        }
+        std::vector<Query*> next;
+        for (auto* q : active)
+            if (!q->done) next.push_back(q);
+        active.swap(next);
+    }
+    if (descs_h) (void)hipHostFree(descs_h);
+    if (descs_d) (void)hipFree(descs_d);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    for (uint32_t j = 0; j < count; ++j) {
+        Query& q = qs[j];
+        status[j] = q.status;
+        if (errors) errors[j] = q.err;
+        if (q.status == IMM_OK && q.r) {
+            out[j] = q.r.release();
+            release_workspace(q);
+        } else {
+            out[j] = nullptr;
+        }
+    }
+}
+
+}  // namespace imm

@@ -1,0 +1,546 @@
+// workspace.cpp -- the device workspace of one IMM query: allocation with a
+// budget, the sampling pass with its retry loop and compaction (steps of
+// Generate_RRRsets), the per-round index segment, and the per-instance half
+// of the greedy selection (Find_Most_Influential_Set).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace imm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+imm_status fail(imm_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------ allocation --
+
+imm_status Arena::alloc(void** p, uint64_t bytes, const char* what) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~uint64_t(255);
+    if (budget && used + bytes > budget)
+        return fail(IMM_ENOMEM, std::string("device budget exceeded allocating ") + what);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(IMM_ENOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    used += bytes;
+    live.emplace_back(*p, bytes);
+    return IMM_OK;
+}
+
+void Arena::release(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < live.size(); ++i) {
+        if (live[i].first == p) {
+            used -= live[i].second;
+            (void)hipFree(p);
+            live[i] = live.back();
+            live.pop_back();
+            return;
+        }
+    }
+}
+
+void Arena::release_all() {
+    for (auto& x : live) (void)hipFree(x.first);
+    live.clear();
+    used = 0;
+}
+
+// ---------------------------------------------------------------- timing --
+
+hipEvent_t Timer::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+int Timer::open(int phase, hipStream_t st) {
+    if (!on) return -1;
+    Rec r{phase, get(), get()};
+    (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+}
+
+void Timer::close(int h, hipStream_t st) {
+    if (h < 0) return;
+    (void)hipEventRecord(recs[h].b, st);
+}
+
+void Timer::collect(double* ms, uint64_t* launches) {
+    for (auto& r : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess)
+            ms[r.phase] += t;
+        if (r.phase >= 4) ++launches[r.phase - 4];
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    recs.clear();
+}
+
+Timer::~Timer() {
+    for (auto& r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------- workspace --
+
+Workspace::~Workspace() {
+    // kernels of a failed call may still be queued on these buffers and the
+    // caller's stream may already be gone: wait for the whole device
+    if (sc) (void)hipDeviceSynchronize();
+    if (hsc) (void)hipHostFree(hsc);
+    if (hp) (void)hipHostFree(hp);
+    if (herr) (void)hipHostFree(herr);
+    if (gains_h) (void)hipHostFree(gains_h);
+}
+
+IcGraphDev ic_view(const imm_graph* g) {
+    return IcGraphDev{g->off, g->thr, g->src, g->n, (uint32_t)g->m};
+}
+
+LtGraphDev lt_view(const imm_graph* g) {
+    return LtGraphDev{g->off, g->cs, g->guide, g->n, (uint32_t)g->m};
+}
+
+imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget) {
+    w.device = device;
+    w.n = n;
+    w.st = st;
+    w.arena.budget = budget;
+    IMM_TRY(w.arena.alloc((void**)&w.sc, sizeof(DevScalars), "scalars"));
+    HIP_TRY(hipHostMalloc((void**)&w.hsc, sizeof(DevScalars), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w.hp, 8, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&w.herr, 4, hipHostMallocDefault));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_acc, (uint64_t)n * 4, "counts"));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_prev, (uint64_t)n * 4, "counts (indexed)"));
+    IMM_TRY(w.arena.alloc((void**)&w.counts_work, (uint64_t)n * 4 + 16, "counts_work"));
+    IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
+    IMM_TRY(w.arena.alloc((void**)&w.desc_d, sizeof(SelectDesc), "select descriptor"));
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
+    return IMM_OK;
+}
+
+imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
+    w.st = st;
+    w.timer.on = timing;
+    w.timer.recs.clear();
+    w.n_sets = 0;
+    w.p_exact = 0;
+    w.p_ub = 0;
+    w.nseg = 0;
+    w.indexed_sets = 0;
+    HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
+    HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
+    return IMM_OK;
+}
+
+imm_status ws_read_scalars(Workspace& w) {
+    HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    return IMM_OK;
+}
+
+namespace {
+
+// Scratch of the large-set kernels: per slot a visited bitmap and a queue
+// of n entries; enough slots to fill the GPU (IC) or a few per CU (LT, whose
+// walks rarely outgrow a chunk), within kBigScratchBytes and the budget.
+imm_status ws_big_scratch(Workspace& w, imm_model model) {
+    if (w.big) return IMM_OK;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
+    const uint64_t words = ((uint64_t)w.n + 31) / 32;
+    const uint64_t per = (words + w.n) * 4;
+    uint64_t slots = model == IMM_IC ? (uint64_t)cus * 8 : (uint64_t)cus;
+    if (w.big_cap) slots = std::min<uint64_t>(slots, w.big_cap);
+    uint64_t limit = kBigScratchBytes;
+    if (w.arena.budget) {
+        const uint64_t left = w.arena.budget > w.arena.used ? w.arena.budget - w.arena.used : 0;
+        limit = std::min(limit, left / 4);
+    }
+    slots = std::min<uint64_t>(slots, std::max<uint64_t>(1, limit / per));
+    IMM_TRY(w.arena.alloc((void**)&w.big, per * slots, "large-set scratch"));
+    HIP_TRY(hipMemsetAsync(w.big, 0, words * slots * 4, w.st));
+    w.big_slots = (uint32_t)slots;
+    return IMM_OK;
+}
+
+BigScratch big_view(const Workspace& w) {
+    const uint32_t words = (uint32_t)(((uint64_t)w.n + 31) / 32);
+    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words, w.big_slots};
+}
+
+// One sampling pass: the fast kernel over the range (list = nullptr) or over
+// a list of indices, then the large-set kernel over what it deferred.
+// Failures for lack of staging land in fl; deferred sets in w.defer. The
+// scalars are copied to the pinned mirror; nothing waits.
+imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                       uint32_t count, const uint32_t* list, const uint32_t* list_n,
+                       uint32_t nitems, uint32_t* fl, uint32_t* fl_n) {
+    hipStream_t st = w.st;
+    const SampleRange rg{seed, id_lo, nitems, list, list_n};
+    const SampleRange rgl{seed, id_lo, count, nullptr, nullptr};
+    const SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
+                      w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
+    HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 8, st));  // ticket_small, ticket_big
+    HIP_TRY(hipMemsetAsync(&w.sc->defer_n, 0, 4, st));
+    const int th = w.timer.open(0, st);
+    const int tm = w.timer.open(4, st);
+    if (g->model == IMM_IC)
+        HIP_TRY(launch_ic_small(ic_view(g), rg, o, &w.sc->ticket_small, ic_small_grid(w.device), st));
+    else
+        HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, lt_small_grid(w.device), st));
+    w.timer.close(tm, st);
+    const int t3 = w.timer.open(5, st);
+    if (g->model == IMM_IC)
+        HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
+                                &w.sc->ticket_big, big_view(w), st));
+    else
+        HIP_TRY(launch_lt_large(lt_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
+                                &w.sc->ticket_big, big_view(w), st));
+    w.timer.close(t3, st);
+    w.timer.close(th, st);
+    HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    return IMM_OK;
+}
+
+}  // namespace
+
+imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                            uint64_t count64) {
+    w.pending_count = 0;
+    if (count64 == 0) return IMM_OK;
+    if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
+    uint32_t count = (uint32_t)count64;
+    // with no set-size estimate yet, a pilot batch measures one first
+    constexpr uint32_t kPilot = 1u << 16;
+    if (w.mean_size <= 0.0 && count > 2 * kPilot) {
+        const uint64_t before = w.n_sets;
+        IMM_TRY(ws_extend_launch(w, g, seed, id_lo, kPilot));
+        HIP_TRY(hipStreamSynchronize(w.st));
+        IMM_TRY(ws_extend_finish(w, g, seed));
+        IMM_TRY(ws_sync_pool(w));
+        ws_note_pool(w, before);
+        id_lo += kPilot;
+        count -= kPilot;
+    }
+    hipStream_t st = w.st;
+    IMM_TRY(ws_big_scratch(w, g->model));
+    IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
+    IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
+    IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
+    IMM_TRY(grow(w.arena, &w.retry, &w.cap_rt, count, 0, st, "retry list"));
+    IMM_TRY(grow(w.arena, &w.spare, &w.cap_sp, count, 0, st, "retry list"));
+    {
+        // expected entries plus the unused tails of every wave's (IC) or
+        // lane's (LT) staging chunk
+        const double mean = w.mean_size > 0 ? w.mean_size : 16.0;
+        uint64_t tails;
+        if (g->model == IMM_IC) {
+            const uint64_t waves = std::min<uint64_t>(
+                ic_small_grid(w.device), (count + kIcTicketChunk - 1) / kIcTicketChunk);
+            tails = waves * kIcStageChunk;
+        } else {
+            const uint64_t lanes =
+                std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
+            tails = lanes * kLtChunk;
+        }
+        uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
+        // IMM_STAGE_SCALE (a factor, default 1) scales this first guess; small
+        // values exercise the staging-growth path
+        if (const char* e = std::getenv("IMM_STAGE_SCALE")) {
+            const double f = std::atof(e);
+            if (f > 0.0) want = std::max<uint64_t>(64, (uint64_t)((double)want * f));
+        }
+        IMM_TRY(grow(w.arena, &w.stage, &w.stage_cap, want, 0, st, "staging"));
+    }
+    HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));
+    w.pending_count = count;
+    w.pending_lo = id_lo;
+    return sample_pass(w, g, seed, id_lo, count, nullptr, nullptr, count, w.retry,
+                       &w.sc->retry_n);
+}
+
+imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
+    if (w.pending_count == 0) return IMM_OK;
+    const uint32_t count = (uint32_t)w.pending_count;
+    const uint64_t id_lo = w.pending_lo;
+    w.pending_count = 0;
+    hipStream_t st = w.st;
+    // sets that found the staging buffer full: grow it (keeping what is
+    // stored), continue at the old capacity, and redo just those sets
+    uint32_t* in = w.retry;
+    uint32_t* in_n = &w.sc->retry_n;
+    uint32_t* out_l = w.spare;
+    uint32_t* out_n = &w.sc->spare_n;
+    uint32_t failed = w.hsc->retry_n;
+    for (int guard = 0; failed; ++guard) {
+        if (guard == 32) return fail(IMM_ENOMEM, "staging could not be grown enough");
+        const uint64_t used = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
+        const uint64_t old_cap = w.stage_cap;
+        const double mean = w.mean_size > 0 ? w.mean_size : 64.0;
+        uint64_t need =
+            old_cap + (uint64_t)(mean * 2.0 * failed) + (uint64_t)failed * 64 + (1u << 20);
+        need = std::max<uint64_t>(need, old_cap * 2);
+        uint64_t cap = w.stage_cap;
+        IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
+        w.stage_cap = cap;
+        const unsigned long long cur = old_cap;
+        HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(out_n, 0, 4, st));
+        IMM_TRY(sample_pass(w, g, seed, id_lo, count, in, in_n, failed, out_l, out_n));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::swap(in, out_l);
+        std::swap(in_n, out_n);
+        failed = (in == w.retry) ? w.hsc->retry_n : w.hsc->spare_n;
+    }
+
+    // compaction: set_off[n_sets .. n_sets+count] (based on the device copy of
+    // set_off[n_sets]) and the copy into the pool
+    const uint64_t stored_bound = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + count + 1, w.n_sets + 1, st,
+                 "set_off"));
+    IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, w.p_ub + stored_bound + 1,
+                 std::min(w.p_ub, w.cap_entries), st, "set_vtx"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(count), 0, st, "scan tmp"));
+    const int tc = w.timer.open(1, st);
+    HIP_TRY(launch_scan_u32(w.sizes, nullptr, w.set_off + w.n_sets, count, 0,
+                            w.set_off + w.n_sets, w.scan_tmp, st));
+    HIP_TRY(launch_compact(w.stage, w.stage_off, w.set_off, w.n_sets, count, w.set_vtx, st));
+    w.timer.close(tc, st);
+    w.n_sets += count;
+    w.p_ub += stored_bound;
+    return IMM_OK;
+}
+
+imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
+                     uint64_t count) {
+    IMM_TRY(ws_extend_launch(w, g, seed, id_lo, count));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    return ws_extend_finish(w, g, seed);
+}
+
+// Read the exact pool size (and the device error flag) at a synchronisation.
+imm_status ws_sync_pool(Workspace& w) {
+    HIP_TRY(hipMemcpyAsync(w.hp, w.set_off + w.n_sets, 8, hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipMemcpyAsync(w.herr, &w.sc->err, 4, hipMemcpyDeviceToHost, w.st));
+    HIP_TRY(hipStreamSynchronize(w.st));
+    return IMM_OK;
+}
+
+void ws_note_pool(Workspace& w, uint64_t sets_before) {
+    const uint64_t p = *w.hp;
+    if (w.n_sets > sets_before)
+        w.mean_size = (double)(p - w.p_exact) / (double)(w.n_sets - sets_before);
+    w.p_exact = p;
+    w.p_ub = p;
+}
+
+namespace {
+
+// Index the sets added since the last call as a new segment: its offsets are
+// the scan of the count increase since then, based at the pool position of
+// its first set.
+imm_status ws_index_update(Workspace& w) {
+    hipStream_t st = w.st;
+    if (w.indexed_sets == w.n_sets) return IMM_OK;
+    if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
+    const uint64_t stride = (uint64_t)w.n + 1;
+    IMM_TRY(grow(w.arena, &w.inv_offs, &w.cap_offs, (w.nseg + 1) * stride, w.nseg * stride, st,
+                 "index offsets"));
+    IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, w.p_ub + 1, std::min(w.p_ub, w.cap_inv), st,
+                 "inv_set"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
+    uint64_t* io = w.inv_offs + w.nseg * stride;
+    const int ti = w.timer.open(2, st);
+    HIP_TRY(launch_scan_u32(w.counts_acc, w.counts_prev, io, w.n, 0, w.set_off + w.indexed_sets,
+                            w.scan_tmp, st));
+    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets,
+                               (uint32_t)(w.n_sets - w.indexed_sets), io, w.inv_cursor, w.inv_set,
+                               &w.sc->err, st));
+    HIP_TRY(hipMemcpyAsync(w.counts_prev, w.counts_acc, (uint64_t)w.n * 4,
+                           hipMemcpyDeviceToDevice, st));
+    w.timer.close(ti, st);
+    ++w.nseg;
+    w.indexed_sets = w.n_sets;
+    return IMM_OK;
+}
+
+}  // namespace
+
+imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
+    hipStream_t st = w.st;
+    IMM_TRY(ws_index_update(w));
+    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
+    if (w.cap_k < k) {
+        if (w.seeds_d) {
+            HIP_TRY(hipStreamSynchronize(st));
+            w.arena.release(w.seeds_d);
+            w.arena.release(w.gains_d);
+            w.arena.release(w.slots);
+            w.arena.release(w.chunk_n);
+            (void)hipHostFree(w.gains_h);
+            w.gains_h = nullptr;
+        }
+        IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
+        IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
+        IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * kArgSlots * 8, "argmax slots"));
+        IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 4, "chunk counts"));
+        HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
+        w.cap_k = k;
+    }
+    // a seed's chunks: at most one per started 64 members of every set
+    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.p_ub / 64 + 1, 0, st,
+                 "chunk queue"));
+    HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
+    HIP_TRY(hipMemsetAsync(w.slots, 0, (uint64_t)k * kArgSlots * 8, st));
+    HIP_TRY(hipMemsetAsync(w.chunk_n, 0, (uint64_t)k * 4, st));
+    *d = SelectDesc{w.counts_work, w.inv_offs, w.inv_set, w.set_off, w.set_vtx, w.covered,
+                    w.slots, w.seeds_d, w.gains_d, w.chunks, w.chunk_n, w.n, k, w.nseg,
+                    0, 0, 0, 0, 0};
+    return IMM_OK;
+}
+
+imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(w.hp, w.set_off + w.n_sets, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(w.herr, &w.sc->err, 4, hipMemcpyDeviceToHost, st));
+    return IMM_OK;
+}
+
+imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
+    if (*w.herr) return fail(IMM_EDEVICE, "internal error: occurrence counts disagree with the pool");
+    ws_note_pool(w, sets_before);
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < k; ++i) c += w.gains_h[i];
+    *covered = c;
+    return IMM_OK;
+}
+
+imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
+    hipStream_t st = w.st;
+    SelectDesc d;
+    IMM_TRY(ws_select_prepare(w, k, &d));
+    d.arg_cnt = argmax_blocks(w.n);
+    d.sel_cnt = select_blocks(w.device, w.n_sets, 1);
+    HIP_TRY(hipMemcpyAsync(w.desc_d, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    const int ts = w.timer.open(3, st);
+    for (uint32_t t = 0; t < k; ++t)
+        HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, st));
+    w.timer.close(ts, st);
+    IMM_TRY(ws_select_copy_out(w, k, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ws_select_finish(w, k, sets_before, covered);
+}
+
+// Canonical pool on the host: every set sorted ascending, sets by sample id.
+imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<uint32_t>* sv,
+                          std::vector<uint32_t>* counts) {
+    hipStream_t st = w.st;
+    if (w.n_sets > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "more than 2^32 sets");
+    IMM_TRY(ws_sync_pool(w));
+    ws_note_pool(w, w.n_sets);
+    uint32_t* big_list = nullptr;
+    IMM_TRY(w.arena.alloc((void**)&big_list, (w.n_sets + 1) * 4, "sort list"));
+    HIP_TRY(hipMemsetAsync(&w.sc->big_flag, 0, 4, st));
+    HIP_TRY(launch_sort_small(w.set_off, (uint32_t)w.n_sets, w.set_vtx, big_list, &w.sc->big_flag,
+                              st));
+    IMM_TRY(ws_read_scalars(w));
+    const uint32_t nbig = w.hsc->big_flag;
+    if (nbig) {
+        std::vector<uint32_t> bl(nbig);
+        HIP_TRY(hipMemcpy(bl.data(), big_list, (uint64_t)nbig * 4, hipMemcpyDeviceToHost));
+        std::vector<uint64_t> o2(2);
+        uint64_t maxn = 0;
+        std::vector<uint32_t> np(nbig);
+        for (uint32_t b = 0; b < nbig; ++b) {
+            HIP_TRY(hipMemcpy(o2.data(), w.set_off + bl[b], 16, hipMemcpyDeviceToHost));
+            uint64_t sz = o2[1] - o2[0], p2 = 1;
+            while (p2 < sz) p2 <<= 1;
+            np[b] = (uint32_t)p2;
+            maxn = std::max(maxn, p2);
+        }
+        uint32_t* scratch = nullptr;
+        IMM_TRY(w.arena.alloc((void**)&scratch, maxn * 4, "sort scratch"));
+        for (uint32_t b = 0; b < nbig; ++b)
+            HIP_TRY(launch_sort_big(w.set_off, w.set_vtx, bl[b], np[b], scratch, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        w.arena.release(scratch);
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    w.arena.release(big_list);
+    if (so) {
+        so->resize(w.n_sets + 1);
+        HIP_TRY(hipMemcpy(so->data(), w.set_off, (w.n_sets + 1) * 8, hipMemcpyDeviceToHost));
+    }
+    if (sv) {
+        sv->resize(w.p_exact);
+        if (w.p_exact)
+            HIP_TRY(hipMemcpy(sv->data(), w.set_vtx, w.p_exact * 4, hipMemcpyDeviceToHost));
+    }
+    if (counts) {
+        counts->resize(w.n);
+        HIP_TRY(hipMemcpy(counts->data(), w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToHost));
+    }
+    return IMM_OK;
+}
+
+void fill_stats(Workspace& w, imm_stats* s) {
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t launches[2] = {0, 0};
+    w.timer.collect(ms, launches);
+    s->ms_sample += ms[0];
+    s->ms_compact += ms[1];
+    s->ms_index += ms[2];
+    s->ms_select += ms[3];
+    s->ms_sample_main += ms[4];
+    s->ms_sample_big += ms[5];
+    s->main_launches += launches[0];
+    s->big_launches += launches[1];
+    const unsigned long long* t = w.hsc->stats;
+    s->sets = t[kStMainSets] + t[kStBigSets];
+    s->entries = t[kStMainEntries] + t[kStBigEntries];
+    s->edges = t[kStMainEdges] + t[kStBigEdges];
+    s->live = t[kStMainLive] + t[kStBigLive];
+    s->deferred = t[kStBigSets];
+    s->main_sets = t[kStMainSets];
+    s->main_entries = t[kStMainEntries];
+    s->main_edges = t[kStMainEdges];
+    s->main_live = t[kStMainLive];
+}
+
+}  // namespace imm

@@ -29,7 +29,7 @@ import numpy as np
 
 TWO32 = 1 << 32
 U32_MAX = TWO32 - 1
-_CACHE_VERSION = "v2"
+_CACHE_VERSION = "v3"
 
 
 @dataclasses.dataclass
@@ -88,22 +88,50 @@ def _keep_m_distinct(n: int, draw, m: int, rng: np.random.Generator):
     return perm[src], perm[dst]
 
 
+def _rmat_code_table(levels: int, quanta) -> np.ndarray:
+    """Joint quadrant codes of `levels` R-MAT levels for every integer in
+    [0, 100**levels): base-100 digit i picks level i's quadrant (a, b, c, d
+    cover quanta[0..3] of the 100 values); the code holds the source bits
+    in bits [levels, 2*levels) and the destination bits in [0, levels)."""
+    per = np.repeat(np.arange(4, dtype=np.uint8), quanta)  # 100 entries
+    x = np.arange(100 ** levels, dtype=np.int64)
+    sbits = np.zeros(x.size, dtype=np.uint8)
+    dbits = np.zeros(x.size, dtype=np.uint8)
+    for _ in range(levels):
+        qd = per[x % 100]
+        x //= 100
+        sbits = (sbits << 1) | (qd >> 1)
+        dbits = (dbits << 1) | (qd & 1)
+    return (sbits << levels) | dbits
+
+
 def rmat_edges(scale: int, m: int, a=0.57, b=0.19, c=0.19, seed: int = 1):
     """R-MAT edges (Chakrabarti et al.) on 2**scale vertices; quadrant
-    probabilities a (src bit 0, dst bit 0), b (0,1), c (1,0), d = 1-a-b-c."""
+    probabilities a (src bit 0, dst bit 0), b (0,1), c (1,0), d = 1-a-b-c.
+    The probabilities are whole percentages, so up to three levels are drawn
+    at once, exactly, from one uniform integer in [0, 10**6)."""
     n = 1 << scale
     rng = np.random.Generator(np.random.PCG64(seed))
+    quanta = [int(round(100 * x)) for x in (a, b, c)]
+    quanta.append(100 - sum(quanta))
+    assert all(abs(q / 100 - x) < 1e-12 for q, x in zip(quanta, (a, b, c, 1 - a - b - c)))
+    tables = {}
 
     def draw(bsz):
-        s = np.zeros(bsz, dtype=np.int64)
-        d = np.zeros(bsz, dtype=np.int64)
-        for _ in range(scale):
-            u = rng.random(bsz)
-            sb = (u >= a + b).astype(np.int64)
-            db = (((u >= a) & (u < a + b)) | (u >= a + b + c)).astype(np.int64)
-            s = (s << 1) | sb
-            d = (d << 1) | db
-        return s, d
+        s = np.zeros(bsz, dtype=np.uint32)
+        d = np.zeros(bsz, dtype=np.uint32)
+        left = scale
+        while left:
+            lv = min(3, left)
+            left -= lv
+            if lv not in tables:
+                tables[lv] = _rmat_code_table(lv, quanta)
+            code = tables[lv][rng.integers(0, 100 ** lv, size=bsz, dtype=np.uint32)]
+            np.left_shift(s, lv, out=s)
+            np.bitwise_or(s, code >> lv, out=s)
+            np.left_shift(d, lv, out=d)
+            np.bitwise_or(d, code & ((1 << lv) - 1), out=d)
+        return s.astype(np.int64), d.astype(np.int64)
 
     src, dst = _keep_m_distinct(n, draw, m, rng)
     return n, src, dst, rng
@@ -324,14 +352,15 @@ def tiny_graph(n: int, edges, model: str, params) -> Graph:
     return Graph("tiny", n, int(row_src.size), col_off, row_src, w, model)
 
 
-def batch_instances(count: int = 64, master_seed: int = 2024):
+def batch_instances(count: int = 64, master_seed: int = 2024, max_scale: int = 20):
     """The multi-instance workload: per instance a weighted-cascade R-MAT graph
     with scale ~ U{12..20} and average degree ~ U{4..32}, k ~ {5,10,25,50},
-    eps ~ {0.5,0.3,0.13}, ell = 1 and Philox seed 42 + i."""
+    eps ~ {0.5,0.3,0.13}, ell = 1 and Philox seed 42 + i. ``max_scale`` caps
+    the scale (the other draws are unchanged) for test-sized batches."""
     rng = np.random.Generator(np.random.PCG64(master_seed))
     out = []
     for i in range(count):
-        scale = int(rng.integers(12, 21))
+        scale = min(int(rng.integers(12, 21)), max_scale)
         deg = int(rng.integers(4, 33))
         k = int(rng.choice([5, 10, 25, 50]))
         eps = float(rng.choice([0.5, 0.3, 0.13]))

@@ -1,0 +1,106 @@
+"""Batched IMM (imm_run_batch): many independent queries advanced together
+on one GPU. Every query's result must equal the CPU oracle's IMM run with
+the same arguments, bit for bit, and equal imm_run of that query alone."""
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import oracle_threads
+from gpu_util import canonical, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(r, o, g=None):
+    assert r.targets == o["targets"]
+    assert r.round_cov == o["round_cov"]
+    assert (r.theta, r.rounds, r.covered) == (o["theta"], o["rounds"], o["covered"])
+    assert r.lb == o["lb"]
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    np.testing.assert_array_equal(r.gains, o["gains"])
+    if g is not None:
+        so, sv = r.pool()
+        cso, csv = canonical(o["set_off"], o["set_vtx"], g.n)
+        np.testing.assert_array_equal(so, cso)
+        np.testing.assert_array_equal(sv, csv)
+
+
+def test_batch_mixed_models(imm, orc, stream):
+    """IC and LT queries, giant sets, a graph shared by several queries, and
+    kept pools, in one batch."""
+    names = ["rmat12_wc", "rmat12_lt", "cl_lt_xs", "rmat12_p10"]
+    graphs = {nm: synth.make_graph(nm) for nm in names}
+    dev = {nm: imm.graph_from(g, stream=stream) for nm, g in graphs.items()}
+    qs = []
+    for nm in names:
+        sp = synth.WORKLOADS[nm]
+        qs.append((nm, dict(k=sp["k"], epsilon=sp["eps"], ell=sp["ell"], seed=sp["seed"],
+                            flags=imm.IMM_KEEP_POOL)))
+    qs.append(("rmat12_wc", dict(k=25, epsilon=0.3, seed=7)))
+    qs.append(("rmat12_wc", dict(k=1, epsilon=0.5, seed=8, ell=2.0)))
+    qs.append(("rmat12_lt", dict(k=40, epsilon=0.25, seed=9)))
+    say(f"batch of {len(qs)}: " + ", ".join(f"{nm} k={q['k']}" for nm, q in qs))
+    res = imm.imm_run_batch([(dev[nm], q) for nm, q in qs], stream=stream)
+    for (nm, q), r in zip(qs, res):
+        say(f"  check {nm} k={q['k']} seed={q['seed']}")
+        keep = bool(q.get("flags", 0) & imm.IMM_KEEP_POOL)
+        o = orc.imm(graphs[nm], q["k"], q["epsilon"], q.get("ell", 1.0), q["seed"],
+                    threads=oracle_threads(), keep_pool=keep)
+        _check(r, o, graphs[nm] if keep else None)
+        one = imm.imm_run(dev[nm], q["k"], q["epsilon"], q.get("ell", 1.0), q["seed"],
+                          stream=stream)
+        np.testing.assert_array_equal(one.seeds, r.seeds)
+        assert one.theta == r.theta
+
+
+def test_batch_of_64_instances(imm, orc, stream):
+    """The multi-instance workload's draws (k, eps, degree, seeds) at graph
+    scale <= 13: 64 queries on 64 graphs in one call."""
+    insts = synth.batch_instances(64, max_scale=13)
+    graphs = [synth.make_graph(f"batch{i}", gen=s["gen"], model=s["model"], enc=s["enc"],
+                               gseed=s["gseed"]) for i, s in enumerate(insts)]
+    dev = [imm.graph_from(g, stream=stream) for g in graphs]
+    say("batch of 64 (scale <= 13)")
+    res = imm.imm_run_batch([(d, dict(k=s["k"], epsilon=s["eps"], ell=s["ell"], seed=s["seed"]))
+                             for d, s in zip(dev, insts)], stream=stream)
+    for i, (g, s, r) in enumerate(zip(graphs, insts, res)):
+        say(f"  check {i}: n={g.n} m={g.m} k={s['k']} eps={s['eps']} theta={r.theta}")
+        o = orc.imm(g, s["k"], s["eps"], s["ell"], s["seed"], threads=oracle_threads())
+        _check(r, o)
+
+
+def test_batch_repeat_and_single_after(imm, orc, stream):
+    """Workspaces cached by a batch are reused by later batches and by a
+    lone imm_run with identical results."""
+    g = synth.make_graph("rmat12_wc")
+    dg = imm.graph_from(g, stream=stream)
+    q = [(dg, dict(k=10, epsilon=0.5, seed=s)) for s in (1, 2, 3, 4, 5, 6, 7, 8, 9)]
+    a = imm.imm_run_batch(q, stream=stream)
+    b = imm.imm_run_batch(q[::-1], stream=stream)[::-1]
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.seeds, y.seeds)
+        assert (x.theta, x.covered) == (y.theta, y.covered)
+    for s, x in zip((1, 2, 3, 4, 5, 6, 7, 8, 9), a):
+        one = imm.imm_run(dg, 10, 0.5, 1.0, s, stream=stream)
+        o = orc.imm(g, 10, 0.5, 1.0, s, threads=oracle_threads())
+        _check(one, o)
+        _check(x, o)
+
+
+def test_batch_errors(imm, stream):
+    g = synth.make_graph("rmat12_wc")
+    dg = imm.graph_from(g, stream=stream)
+    with pytest.raises(imm.ImmError) as e:
+        imm.imm_run_batch([(dg, dict(k=5, epsilon=0.5, seed=1)),
+                           (dg, dict(k=g.n + 1, epsilon=0.5, seed=2))], stream=stream)
+    assert e.value.status == imm.IMM_EINVAL
+    with pytest.raises(imm.ImmError) as e:
+        imm.imm_run_batch([(dg, dict(k=5, epsilon=0.5, seed=1)),
+                           (dg, dict(k=5, epsilon=0.5, seed=2, max_device_bytes=1 << 16))],
+                          stream=stream)
+    assert e.value.status == imm.IMM_ENOMEM
+    # the library is still usable
+    r = imm.imm_run_batch([(dg, dict(k=5, epsilon=0.5, seed=1))], stream=stream)
+    one = imm.imm_run(dg, 5, 0.5, 1.0, 1, stream=stream)
+    np.testing.assert_array_equal(r[0].seeds, one.seeds)
