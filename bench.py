@@ -43,6 +43,49 @@ def algorithmic_bytes(model: str, sets: int, entries: int, edges: int, live: int
     return 12 * sets + 20 * entries + 4 * edges + 8 * live
 
 
+def kernel_table(model: str, stats: list) -> dict:
+    """Per sampling kernel: name, launches, summed HIP-event time and the
+    algorithmic bytes of the sets it finished, over a list of stats dicts."""
+    def tot(key):
+        return sum(x[key] for x in stats)
+
+    main = (tot("main_sets"), tot("main_entries"), tot("main_edges"), tot("main_live"))
+    lane = (tot("lane_sets"), tot("lane_sets"), tot("lane_edges"), 0)
+    big = (tot("sets") - main[0] - lane[0], tot("entries") - main[1] - lane[1],
+           tot("edges") - main[2] - lane[2], tot("live") - main[3])
+    ic = model == "ic"
+    out = {
+        "main": dict(name="ic_bfs_kernel" if ic else "lt_small_kernel", ms=tot("ms_sample_main"),
+                     launches=tot("main_launches"), bytes=algorithmic_bytes(model, *main)),
+        "large": dict(name="ic_large_kernel" if ic else "lt_large_kernel",
+                      ms=tot("ms_sample_big"), launches=tot("big_launches"),
+                      bytes=algorithmic_bytes(model, *big)),
+    }
+    if ic:
+        out["lane"] = dict(name="ic_lane_kernel", ms=tot("ms_sample_lane"),
+                           launches=tot("lane_launches"), bytes=algorithmic_bytes(model, *lane))
+    return out
+
+
+def roofline_of(kernels: dict) -> dict:
+    """Roofline entry of the kernel with the most time: algorithmic bytes
+    per launch over its mean launch duration."""
+    dom = max(kernels.values(), key=lambda k: k["ms"])
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
+    per_launch = dom["bytes"] / max(dom["launches"], 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"kernel": dom["name"], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+            "avg_launch_ms": avg_ms, "bytes_per_launch": per_launch}
+
+
+def kernel_summary(kernels: dict) -> dict:
+    return {k: {"name": v["name"], "launches": v["launches"],
+                "avg_ms": v["ms"] / max(v["launches"], 1),
+                "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+            for k, v in kernels.items()}
+
+
 def cpu_baseline(g, spec, seconds: float):
     import oracle
 
@@ -82,11 +125,8 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     st = pools[-1]
     samp_ms = sum(x["ms_sample"] for x in pools) / len(pools)
-    main_ms = sum(x["ms_sample_main"] for x in pools) / len(pools)
     nbytes = algorithmic_bytes(g.model, st["sets"], st["entries"], st["edges"], st["live"])
-    mbytes = algorithmic_bytes(g.model, st["main_sets"], st["main_entries"], st["main_edges"],
-                               st["main_live"])
-    ach = mbytes / (main_ms * 1e-3) / 1e9
+    kernels = kernel_table(g.model, pools)
     print(json.dumps({
         "metric": "RRR sets/s (steady-state sampling)", "value": st["sets"] / (samp_ms * 1e-3),
         "unit": "RRR sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -96,11 +136,8 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
                    "seed": spec["seed"]},
         "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
         "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
-        "deferred": st["deferred"],
-        "roofline": {"kernel": "ic_small_kernel" if g.model == "ic" else "lt_small_kernel",
-                     "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBPS, "traffic": None, "avg_launch_ms": main_ms,
-                     "bytes_per_launch": mbytes},
+        "deferred": st["deferred"], "ic_team": st["team"], "ic_big_block": st["big_block"], "kernels": kernel_summary(kernels),
+        "roofline": roofline_of(kernels),
     }))
 
 
@@ -195,9 +232,9 @@ def main():
                          "batched, against the same run one at a time")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the sampling path shards across GPUs only by design, see DESIGN.md)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the "
+              "library has no multi-GPU path (sampling would shard by sample-id range, "
+              "with one reduction of the counts per round)", file=sys.stderr)
         sys.exit(2)
 
     batch = None
@@ -245,26 +282,7 @@ def main():
     sets = r.stats["sets"]
     value = sets / (ms_per_step / 1e3)
 
-    def tot(key):
-        return sum(x.stats[key] for x in results)
-
-    # per-kernel accounting over the timed steps
-    main_bytes = algorithmic_bytes(g.model, tot("main_sets"), tot("main_entries"),
-                                   tot("main_edges"), tot("main_live"))
-    big_bytes = algorithmic_bytes(g.model, tot("sets") - tot("main_sets"),
-                                  tot("entries") - tot("main_entries"),
-                                  tot("edges") - tot("main_edges"),
-                                  tot("live") - tot("main_live"))
-    kernels = {
-        "main": dict(name="ic_small_kernel" if g.model == "ic" else "lt_small_kernel",
-                     ms=tot("ms_sample_main"), launches=tot("main_launches"), bytes=main_bytes),
-        "large": dict(name="ic_large_kernel" if g.model == "ic" else "lt_large_kernel",
-                      ms=tot("ms_sample_big"), launches=tot("big_launches"), bytes=big_bytes),
-    }
-    dom = max(kernels.values(), key=lambda k: k["ms"])
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
-    per_launch = dom["bytes"] / max(dom["launches"], 1)
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    kernels = kernel_table(g.model, [x.stats for x in results])
     samp_bytes = algorithmic_bytes(g.model, sets, r.stats["entries"], r.stats["edges"],
                                    r.stats["live"])
     ms_sample = r.stats["ms_sample"]
@@ -292,20 +310,16 @@ def main():
         "time_to_seeds_ms": ms_per_step,
         "theta": r.theta,
         "rounds": r.rounds,
+        "ic_team": r.stats["team"],
+        "ic_big_block": r.stats["big_block"],
         "edges_per_s": r.stats["edges"] / (ms_per_step / 1e3),
         "phase_ms": {"sample": ms_sample, "compact": r.stats["ms_compact"],
                      "index": r.stats["ms_index"], "select": r.stats["ms_select"],
                      "host_wall": r.stats["ms_total"]},
         "sampling_GBps": samp_bytes / (ms_sample * 1e-3) / 1e9 if ms_sample > 0 else None,
         "sampling_sets_per_s": sets / (ms_sample * 1e-3) if ms_sample > 0 else None,
-        "kernels": {k: {"name": v["name"], "launches": v["launches"],
-                        "avg_ms": v["ms"] / max(v["launches"], 1),
-                        "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
-                    for k, v in kernels.items()},
-        "roofline": {"kernel": dom["name"], "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None, "avg_launch_ms": avg_ms,
-                     "bytes_per_launch": per_launch},
+        "kernels": kernel_summary(kernels),
+        "roofline": roofline_of(kernels),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, spec, args.cpu_seconds)

@@ -92,13 +92,19 @@ typedef struct {
                              LT: walk steps (draws evaluated) */
     uint64_t live;        /* IC: live in-edges followed; LT: cum entries read */
     uint64_t deferred;    /* sets finished by the large-set kernel */
-    uint64_t main_sets;   /* sets finished by the wave-per-sample kernel */
+    uint64_t main_sets;   /* sets finished by the wave/team-per-sample kernel */
     uint64_t main_entries;/* their total size */
     uint64_t main_edges;  /* their edges (IC coins / LT steps) */
     uint64_t main_live;   /* their live edges / cum entries */
     double ms_sample_big; /* the large-set sampling kernel alone */
     uint64_t big_launches;/* launches of that kernel */
     uint32_t rounds;      /* sampling-phase rounds executed (imm_run) */
+    uint32_t team;        /* IC: waves per sample of the BFS kernel (autotuned) */
+    double ms_sample_lane;   /* IC: the lane-per-root kernel alone */
+    uint64_t lane_launches;  /* launches of that kernel */
+    uint64_t lane_sets;      /* IC: single-vertex sets it finished */
+    uint64_t lane_edges;     /* IC: coins it evaluated for them */
+    uint32_t big_block;      /* IC: threads per giant set (autotuned) */
     uint32_t pad;
 } imm_stats;
 

@@ -56,7 +56,10 @@ class imm_stats(C.Structure):
                 ("live", C.c_uint64), ("deferred", C.c_uint64), ("main_sets", C.c_uint64),
                 ("main_entries", C.c_uint64), ("main_edges", C.c_uint64),
                 ("main_live", C.c_uint64), ("ms_sample_big", C.c_double),
-                ("big_launches", C.c_uint64), ("rounds", C.c_uint32), ("pad", C.c_uint32)]
+                ("big_launches", C.c_uint64), ("rounds", C.c_uint32), ("team", C.c_uint32),
+                ("ms_sample_lane", C.c_double), ("lane_launches", C.c_uint64),
+                ("lane_sets", C.c_uint64), ("lane_edges", C.c_uint64),
+                ("big_block", C.c_uint32), ("pad", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

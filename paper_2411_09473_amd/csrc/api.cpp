@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -74,6 +75,16 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
         g->n = n;
         g->m = m;
         g->model = model;
+        // launch shapes forced from the environment (else autotuned)
+        const char* et = std::getenv("IMM_IC_TEAM");
+        const char* eb = std::getenv("IMM_IC_BIG");
+        const int team = et ? std::atoi(et) : 0;
+        const int big = eb ? std::atoi(eb) : 0;
+        if (team == 1 || team == 2 || team == 4) g->ic_team = (uint32_t)team;
+        if (big == 256 || big == 1024) g->ic_big_block = (uint32_t)big;
+        g->team_forced = team == 1 || team == 2 || team == 4;
+        g->big_forced = big == 256 || big == 1024;
+        g->tuned = g->team_forced && g->big_forced;
         HIP_TRY(hipGetDevice(&g->device));
         std::vector<uint32_t> off32((size_t)n + 1);
         for (size_t v = 0; v <= n; ++v) off32[v] = (uint32_t)co[v];
@@ -260,6 +271,7 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         const double t0 = now_ms();
         hipStream_t st = (hipStream_t)stream;
         HIP_TRY(hipSetDevice(g->device));
+        IMM_TRY(tune_graph(const_cast<imm_graph*>(g), st));
         std::unique_ptr<imm_pool> p(new imm_pool());
         p->ws.reset(new Workspace());
         IMM_TRY(ws_init(*p->ws, g->n, g->device, st, 0));
@@ -270,6 +282,8 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         IMM_TRY(ws_read_scalars(*p->ws));
         p->stats.ms_total = now_ms() - t0;
         fill_stats(*p->ws, &p->stats);
+        p->stats.team = g->model == IMM_IC ? g->ic_team : 0;
+        p->stats.big_block = g->model == IMM_IC ? g->ic_big_block : 0;
         *out = p.release();
         return IMM_OK;
     } catch (const std::bad_alloc&) {

@@ -77,19 +77,25 @@ imm_status grow(Arena& a, T** p, uint64_t* cap, uint64_t need, uint64_t keep, hi
     return IMM_OK;
 }
 
-// Upper bound on the device memory of one workspace's large-set scratch.
+// Upper bound on the device memory of one workspace's large-set scratch,
+// the queue entries of an IC giant-set slot, and the IC slots whose queues
+// hold n entries (for the sets that outgrow the bounded ones).
 constexpr uint64_t kBigScratchBytes = 16ull << 30;
+constexpr uint32_t kGiantQueue = 1u << 16;
+constexpr uint32_t kHugeSlots = 16;
 
 // Scalars the kernels update, in one device block.
 struct DevScalars {
     unsigned long long cursor;
-    uint32_t ticket_small, ticket_big, defer_n, retry_n, spare_n, big_flag;
-    uint32_t err, pad;
+    // reset per pass: the seven words from ticket_small to defer_n
+    uint32_t ticket_small, ticket_big, ticket_bfs, ticket_huge, pend_n, over_n, defer_n;
+    uint32_t retry_n, spare_n, big_flag, err;
     unsigned long long stats[kStCount];
 };
 
 // Phase timing with HIP events (phases: 0 sample, 1 compact, 2 index,
-// 3 select, 4 main sampling kernel, 5 large-set sampling kernel).
+// 3 select, 4 main sampling kernel, 5 large-set sampling kernel, 6 IC
+// lane-per-root kernel).
 struct Timer {
     bool on = false;
     struct Rec {
@@ -150,6 +156,8 @@ struct Workspace {
     uint64_t cap_rt = 0;
     uint32_t* spare = nullptr;
     uint64_t cap_sp = 0;
+    uint32_t* pend = nullptr;  // IC: samples left for the BFS pass
+    uint64_t cap_pd = 0;
     uint64_t* scan_tmp = nullptr;
     uint64_t cap_scan = 0;
     unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
@@ -161,8 +169,13 @@ struct Workspace {
     uint64_t cap_k = 0;
     uint32_t* gains_h = nullptr;  // pinned
     SelectDesc* desc_d = nullptr; // one descriptor, for selection run alone
-    uint32_t* big = nullptr;
+    uint32_t* big = nullptr;   // giant-set slots: bitmap + bounded queue each
     uint32_t big_slots = 0;
+    uint32_t big_qcap = 0;
+    uint32_t* huge = nullptr;  // IC: a few slots with queues of n
+    uint32_t huge_slots = 0;
+    uint32_t* over = nullptr;  // IC: giant sets that outgrew a bounded queue
+    uint64_t cap_ov = 0;
     uint64_t n_sets = 0;
     uint64_t p_exact = 0;    // pool size, exact as of the last synchronisation
     uint64_t p_ub = 0;       // upper bound on the pool size
@@ -183,6 +196,15 @@ struct imm_graph {
     uint64_t m = 0;
     imm_model model = IMM_IC;
     int device = 0;
+    // IC launch shapes picked by tune_graph on first use: waves per sample of
+    // the BFS pass (IMM_IC_TEAM = 1, 2 or 4 forces it) and the giant-set
+    // workgroup size (IMM_IC_BIG = 256 or 1024 forces it)
+    uint32_t ic_team = 1;
+    uint32_t ic_big_block = 256;  // threads per giant set (256 or 1024)
+    bool team_forced = false, big_forced = false;
+    double defer_rate = 0.0;  // giant sets per sample seen while tuning
+    bool tuned = false;
+    std::mutex tune_mu;
     imm::Arena arena;
     uint32_t* off = nullptr;
     uint32_t* thr = nullptr;
@@ -241,6 +263,11 @@ void ws_note_pool(Workspace& w, uint64_t sets_before);
 imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<uint32_t>* sv,
                           std::vector<uint32_t>* counts);
 void fill_stats(Workspace& w, imm_stats* s);
+
+// ---- tune.cpp
+// Pick g's IC team size by timing one fixed sampling batch per candidate
+// (sets do not depend on the choice). Once per graph; thread-safe.
+imm_status tune_graph(imm_graph* g, hipStream_t st);
 
 // ---- runner.cpp
 // Theta constants (Tang et al. 2015, Eq. 9 and Eq. 6 with ell adjusted).

@@ -48,9 +48,12 @@ struct SampleRange {
 };
 
 // Stats slots (uint64 counters in device memory).
+// Main: the wave/team-per-sample kernels; Big: the large-set kernels; Lane:
+// the IC lane-per-root kernel (its sets are single vertices).
 enum StatSlot : int {
     kStMainSets = 0, kStMainEntries, kStMainEdges, kStMainLive,
-    kStBigSets, kStBigEntries, kStBigEdges, kStBigLive, kStCount
+    kStBigSets, kStBigEntries, kStBigEdges, kStBigLive,
+    kStLaneSets, kStLaneEdges, kStCount
 };
 
 // Where sampled sets go: a staging buffer with a bump cursor, per-sample
@@ -72,21 +75,37 @@ struct SampleOut {
 };
 
 // Scratch of the large-set kernels: per slot a visited bitmap of `words`
-// uint32 (all zero between samples) and a queue of n uint32.
+// uint32 (all zero between samples) and a queue of qcap (<= n) uint32.
 struct BigScratch {
     uint32_t* bitmaps;
     uint32_t* queues;
     uint32_t words;
     uint32_t slots;
+    uint32_t qcap;
 };
 
 // ---- sampling (k_sample_ic.hip, k_sample_lt.hip)
-hipError_t launch_ic_small(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t grid, hipStream_t st);
+// IC, first pass: lane-per-root tries over the range (or list); samples that
+// are not a single vertex are appended to pend (*pend_n entries).
+hipError_t launch_ic_lane(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                          uint32_t* pend, uint32_t* pend_n, uint32_t* ticket, uint32_t grid,
+                          hipStream_t st);
+// IC, second pass: BFS of the pending samples, one team of `team` (1, 2 or
+// 4) waves per sample; r.count bounds *pend_n.
+hipError_t launch_ic_bfs(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                         const uint32_t* pend, const uint32_t* pend_n, uint32_t* ticket,
+                         uint32_t team, uint32_t grid, hipStream_t st);
+uint32_t ic_bfs_grid(int device, uint32_t team);
+// IC, giant sets: one workgroup of `block` (256 or 1024) threads per listed
+// sample, b.slots workgroups (each owns one scratch slot). A set with more
+// than b.qcap members is abandoned and its index appended to over (which may
+// be null only when b.qcap = n).
 hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
-                           uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
+                           uint32_t* fail_n, uint32_t* over, uint32_t* over_n,
+                           uint32_t* ticket, const BigScratch& b, uint32_t block,
                            hipStream_t st);
+uint32_t ic_large_slots(int device, uint32_t block);
 hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
                            uint32_t* ticket, uint32_t grid, hipStream_t st);
 hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,

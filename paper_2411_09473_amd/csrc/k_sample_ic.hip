@@ -2,21 +2,26 @@
 // (Generate_RRRsets with in-place counter updates, Algorithm 3; IC model,
 // Section II-A).
 //
-// Two kernels share the work of one sampling round:
-//  * ic_small: a wave takes 64 sample ids at a time. First each lane draws
-//    the root of its own sample and flips the coins of the root's in-edges
-//    (roots of in-degree <= kLaneDegCap); a root with no live in-edge is a
-//    complete set {root}, stored at once (at low edge probabilities that is
-//    most samples). The other samples of the batch then run one at a time,
-//    one wave per sample: the set doubles as the BFS queue and lives in LDS
-//    together with an open-addressing hash of visited vertices.
-//    Each BFS level takes up to 64 queued vertices, and the wave walks their
-//    in-edges in aligned groups of four: one Philox call yields the four
-//    coins of a group and one 16-byte load its four thresholds; sources are
-//    gathered only for live edges. A set that outgrows LDS is abandoned
-//    (no side effects) and its sample index deferred.
-//  * ic_large: one workgroup per deferred sample, with a visited bitmap and a
-//    queue in device memory (one slot per workgroup, reset sparsely). A slot
+// Three kernels share the work of one sampling round:
+//  * ic_lane: a wave takes 64 sample ids at a time. Each lane draws the root
+//    of its own sample and flips the coins of the root's in-edges (roots of
+//    in-degree <= kLaneDegCap); a root with no live in-edge is a complete set
+//    {root}, stored at once (at low edge probabilities that is most samples).
+//    Every other sample index goes to a pending list.
+//  * ic_bfs<TEAM>: a team of TEAM waves (one workgroup) takes one pending
+//    sample at a time, so samples of very different cost spread evenly over
+//    the GPU. The set doubles as the BFS queue and lives in LDS together with
+//    an open-addressing hash of visited vertices. Each BFS level takes up to
+//    64*TEAM queued vertices and the team sweeps their in-edges in aligned
+//    groups of four: one Philox call yields the four coins of a group and one
+//    16-byte load its four thresholds; sources are read only for live edges.
+//    A set that outgrows LDS is abandoned (no side effects) and its sample
+//    index deferred.
+//  * ic_large<BS>: one workgroup of BS (256 or 1024) threads per deferred
+//    sample (a giant set, whose BFS levels are wide), with a visited bitmap and a
+//    queue in device memory (one slot per workgroup, reset sparsely). Queues
+//    hold a bounded number of members; the rare set that outgrows one is
+//    redone by a second launch over a few slots with queues of n. A slot
 //    is only ever touched by its own workgroup, so workgroup barriers order
 //    every access; no device-scope fence is used (on this GPU such a fence
 //    writes back and invalidates the L2 of the whole XCD).
@@ -30,91 +35,167 @@ namespace imm {
 
 namespace {
 
-constexpr uint32_t kSmallCap = 256;     // members kept in LDS
-constexpr uint32_t kHashBits = 10;      // 1024-slot LDS hash (load < 0.32)
-constexpr uint32_t kHashSize = 1u << kHashBits;
-constexpr uint32_t kTicketChunk = kIcTicketChunk;  // one sample id per lane
 constexpr uint32_t kLaneDegCap = 32;  // roots tried one per lane up to this in-degree
 constexpr uint32_t kStageChunk = kIcStageChunk;
-constexpr uint32_t kBigBlock = 256;
 
-__device__ __forceinline__ uint32_t hslot(uint32_t v) { return (v * 0x9E3779B1u) >> (32 - kHashBits); }
+// LDS shape of a BFS team of TEAM waves: members kept on chip and a visited
+// hash of twice that many slots (load factor <= 1/2).
+template <uint32_t TEAM>
+struct Team {
+    static constexpr uint32_t BS = kWave * TEAM;
+    static constexpr uint32_t CAP = 256 * TEAM;
+    static constexpr uint32_t HBITS = TEAM == 1 ? 9 : (TEAM == 2 ? 10 : 11);
+    static constexpr uint32_t HSIZE = 1u << HBITS;
+    static_assert(2 * CAP == HSIZE, "hash holds twice the member capacity");
+    static_assert(CAP <= kStageChunk, "a set fits one staging chunk");
+};
 
 __device__ __forceinline__ uint32_t lds_load(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Insert u into the LDS visited hash; append it to the member list when new.
-__device__ __forceinline__ void small_insert(uint32_t u, uint32_t* hash, uint32_t* members,
-                                             uint32_t* s_size, uint32_t* s_over) {
-    uint32_t slot = hslot(u);
-    for (uint32_t probe = 0; probe < kHashSize; ++probe) {
-        const uint32_t cur = lds_load(&hash[slot]);
-        if (cur == u) return;
-        if (cur == kEmpty) {
-            if (lds_load(s_size) >= kSmallCap) {
-                *s_over = 1u;
-                return;
-            }
-            const uint32_t old = atomicCAS(&hash[slot], kEmpty, u);
-            if (old == kEmpty) {
-                const uint32_t pos = atomicAdd(s_size, 1u);
-                if (pos < kSmallCap) members[pos] = u; else *s_over = 1u;
-                return;
-            }
-            if (old == u) return;
+// Staging space of one workgroup: the rest of its current chunk.
+struct Stager {
+    uint64_t base = 0;
+    uint32_t left = 0;
+};
+
+// Reserve `need` (<= kStageChunk) staging entries; called by the whole
+// workgroup alike. False when the staging buffer is full.
+__device__ __forceinline__ bool stage_reserve(Stager& c, uint32_t need, uint64_t* off,
+                                              unsigned long long* s_chunk, const SampleOut& o) {
+    if (need > c.left) {
+        if (threadIdx.x == 0) *s_chunk = atomicAdd(o.cursor, (unsigned long long)kStageChunk);
+        __syncthreads();
+        c.base = *s_chunk;
+        c.left = kStageChunk;
+        __syncthreads();
+        if (c.base + kStageChunk > o.stage_cap) {
+            c.left = 0;
+            return false;
         }
-        slot = (slot + 1) & (kHashSize - 1);
     }
-    *s_over = 1u;
+    *off = c.base + (kStageChunk - c.left);
+    c.left -= need;
+    return true;
 }
 
-__global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange rg, SampleOut o,
-                                                      uint32_t* ticket) {
-    __shared__ uint32_t hash[kHashSize];
-    __shared__ uint32_t members[kSmallCap];
-    __shared__ uint32_t s_base[kWave], s_g0[kWave], s_beg[kWave], s_end[kWave];
-    __shared__ uint32_t s_pend[kWave];
-    __shared__ uint32_t s_size, s_over, s_tk;
-    __shared__ unsigned long long s_chunk;
+// Block-wide exclusive scan of one uint32 per thread; returns the total.
+template <uint32_t BS>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* excl_out,
+                                                    uint32_t* s_wsum) {
+    const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const uint32_t incl = wave_incl_scan(v);
+    if (BS == kWave) {
+        *excl_out = incl - v;
+        return __shfl(incl, kWave - 1, kWave);
+    }
+    if (lane == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < BS / kWave; ++i) {
+        const uint32_t x = s_wsum[i];
+        if (i < w) before += x;
+        total += x;
+    }
+    *excl_out = before + incl - v;
+    return total;
+}
 
+// Lay out the in-edge groups of queue entries [head, head + nb) (nb <= BS):
+// entry i owns groups [s_base[i], s_base[i+1]) of the level, which are edge
+// groups s_g0[i] + 0, 1, ... of its column [s_beg[i], s_end[i]). Returns the
+// level's group count; adds the entries' in-degrees to *edges.
+template <uint32_t BS>
+__device__ __forceinline__ uint32_t level_layout(const IcGraphDev& g, const uint32_t* queue,
+                                                 uint32_t head, uint32_t nb, uint32_t* s_base,
+                                                 uint32_t* s_g0, uint32_t* s_beg,
+                                                 uint32_t* s_end, uint32_t* s_wsum,
+                                                 uint32_t* edges) {
+    const uint32_t tid = threadIdx.x;
+    uint32_t beg = 0, end = 0;
+    if (tid < nb) {
+        const uint32_t v = queue[head + tid];
+        beg = g.off[v];
+        end = g.off[v + 1];
+    }
+    const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
+    uint32_t excl;
+    const uint32_t G = block_excl_scan<BS>(ng, &excl, s_wsum);
+    s_base[tid] = excl;
+    s_g0[tid] = beg >> 2;
+    s_beg[tid] = beg;
+    s_end[tid] = end;
+    *edges += end - beg;
+    return G;
+}
+
+// Flip the coins of one level's G groups (layout from level_layout), BS
+// threads, each taking groups tid, tid + BS, ...; on_live(u) runs for the
+// source u of every live in-edge. After a wave has seen a live edge it asks
+// stop() (uniform across the wave) whether to abandon the level.
+template <uint32_t BS, class OnLive, class Stop>
+__device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, uint32_t shi,
+                                            uint32_t k0, uint32_t k1, const uint32_t* s_base,
+                                            const uint32_t* s_g0, const uint32_t* s_beg,
+                                            const uint32_t* s_end, uint32_t nb, uint32_t G,
+                                            uint32_t* live_n, OnLive on_live, Stop stop) {
+    // the owner of the thread's current group and its group range [lo, hi),
+    // kept in registers until the thread's groups move past it
+    uint32_t ow = 0, lo = 0;
+    uint32_t hi = nb > 1 ? s_base[1] : G;
+    uint32_t g0 = s_g0[0], eb = s_beg[0], ee = s_end[0];
+    for (uint32_t t = threadIdx.x; t < G; t += BS) {
+        if (t >= hi) {
+            ow = owner_from(s_base, nb, t, ow);
+            lo = s_base[ow];
+            hi = ow + 1 < nb ? s_base[ow + 1] : G;
+            g0 = s_g0[ow];
+            eb = s_beg[ow];
+            ee = s_end[ow];
+        }
+        const uint32_t grp = g0 + (t - lo);
+        const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
+        const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
+        const uint32_t e0 = grp << 2;
+        uint32_t live = 0;
+        live |= (r.x < th.x && e0 >= eb && e0 < ee) ? 1u : 0u;
+        live |= (r.y < th.y && e0 + 1 >= eb && e0 + 1 < ee) ? 2u : 0u;
+        live |= (r.z < th.z && e0 + 2 >= eb && e0 + 2 < ee) ? 4u : 0u;
+        live |= (r.w < th.w && e0 + 3 >= eb && e0 + 3 < ee) ? 8u : 0u;
+        const bool any = live != 0u;
+        if (any) {
+            *live_n += (uint32_t)__popc(live);
+            do {
+                const uint32_t j = (uint32_t)__ffs(live) - 1u;
+                live &= live - 1u;
+                on_live(g.src[e0 + j]);
+            } while (live);
+        }
+        if (__ballot(any) && stop()) break;
+    }
+}
+
+// ----------------------------------------------------------------- ic_lane
+
+__global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRange rg,
+                                                        SampleOut o, uint32_t* pend,
+                                                        uint32_t* pend_n, uint32_t* ticket) {
+    __shared__ uint32_t s_tk;
+    __shared__ unsigned long long s_chunk;
     const uint32_t lane = threadIdx.x;
     const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
-    for (uint32_t i = lane; i < kHashSize; i += kWave) hash[i] = kEmpty;
-
-    uint64_t chunk_base = 0;
-    uint32_t chunk_left = 0;  // uniform across the wave
-    uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;  // lane-partial
-
-    // Reserve `need` staging entries from the wave's chunk (a new chunk when
-    // the current one is too short); false when the staging buffer is full.
-    auto reserve = [&](uint32_t need, uint64_t* off) -> bool {
-        if (need > chunk_left) {
-            if (lane == 0) s_chunk = atomicAdd(o.cursor, (unsigned long long)kStageChunk);
-            __syncthreads();
-            chunk_base = s_chunk;
-            chunk_left = kStageChunk;
-            __syncthreads();
-            if (chunk_base + kStageChunk > o.stage_cap) {
-                chunk_left = 0;
-                return false;
-            }
-        }
-        *off = chunk_base + (kStageChunk - chunk_left);
-        chunk_left -= need;
-        return true;
-    };
-
+    Stager sg;
+    uint64_t st_sets = 0, st_edges = 0;  // lane-partial
     const uint32_t total = rg.list ? *rg.list_n : rg.count;
     for (;;) {
-        if (lane == 0) s_tk = atomicAdd(ticket, kTicketChunk);
+        if (lane == 0) s_tk = atomicAdd(ticket, kIcTicketChunk);
         __syncthreads();
         const uint32_t base_pos = s_tk;
         __syncthreads();
         if (base_pos >= total) break;
 
-        // ---- one sample per lane: a root without a live in-edge is a
-        // complete set {root}; the others go to the wave-per-sample BFS
         const uint32_t my_pos = base_pos + lane;
         const bool valid = my_pos < total;
         const uint32_t my_idx = valid ? (rg.list ? rg.list[my_pos] : my_pos) : 0u;
@@ -130,20 +211,18 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
                 const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
                 const Philox4 r = philox10(grp, (uint32_t)ms, (uint32_t)(ms >> 32), 1u, k0, k1);
                 const uint32_t e0 = grp << 2;
-                const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-                const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    const uint32_t e = e0 + j;
-                    if (e >= rbeg && e < rend && rr[j] < tt[j]) single = false;
-                }
+                if ((r.x < th.x && e0 >= rbeg && e0 < rend) ||
+                    (r.y < th.y && e0 + 1 >= rbeg && e0 + 1 < rend) ||
+                    (r.z < th.z && e0 + 2 >= rbeg && e0 + 2 < rend) ||
+                    (r.w < th.w && e0 + 3 >= rbeg && e0 + 3 < rend))
+                    single = false;
             }
         }
         const uint64_t smask = __ballot(single);
         const uint32_t nsingle = (uint32_t)__popcll(smask);
         if (nsingle) {
             uint64_t off = 0;
-            const bool ok = reserve(nsingle, &off);
+            const bool ok = stage_reserve(sg, nsingle, &off, &s_chunk, o);
             const uint32_t rank = (uint32_t)__popcll(smask & ((1ull << lane) - 1ull));
             if (single) {
                 if (ok) {
@@ -152,128 +231,164 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
                     o.stage_off[my_idx] = off + rank;
                     o.sizes[my_idx] = 1;
                     st_sets += 1;
-                    st_entries += 1;
                     st_edges += rend - rbeg;
                 } else {
                     o.retry[atomicAdd(o.retry_n, 1u)] = my_idx;
                 }
             }
         }
-        const uint64_t pmask = __ballot(valid && !single);
-        const uint32_t npend = (uint32_t)__popcll(pmask);
-        if (valid && !single) s_pend[__popcll(pmask & ((1ull << lane) - 1ull))] = my_idx;
+        const bool pending = valid && !single;
+        const uint64_t pmask = __ballot(pending);
+        if (pmask) {
+            uint32_t pbase = 0;
+            if (lane == 0) pbase = atomicAdd(pend_n, (uint32_t)__popcll(pmask));
+            pbase = __shfl(pbase, 0, kWave);
+            if (pending) pend[pbase + (uint32_t)__popcll(pmask & ((1ull << lane) - 1ull))] = my_idx;
+        }
+    }
+    st_sets = wave_sum64(st_sets);
+    st_edges = wave_sum64(st_edges);
+    if (lane == 0) {
+        atomicAdd(&o.stats[kStLaneSets], (unsigned long long)st_sets);
+        atomicAdd(&o.stats[kStLaneEdges], (unsigned long long)st_edges);
+    }
+}
+
+// ------------------------------------------------------------------ ic_bfs
+
+// Insert u into the LDS visited hash; append it to the member list when new.
+template <uint32_t TEAM>
+__device__ __forceinline__ void team_insert(uint32_t u, uint32_t* hash, uint32_t* members,
+                                            uint32_t* s_size, uint32_t* s_over) {
+    using T = Team<TEAM>;
+    uint32_t slot = (u * 0x9E3779B1u) >> (32 - T::HBITS);
+    for (uint32_t probe = 0; probe < T::HSIZE; ++probe) {
+        const uint32_t cur = lds_load(&hash[slot]);
+        if (cur == u) return;
+        if (cur == kEmpty) {
+            if (lds_load(s_size) >= T::CAP) {
+                *s_over = 1u;
+                return;
+            }
+            const uint32_t old = atomicCAS(&hash[slot], kEmpty, u);
+            if (old == kEmpty) {
+                const uint32_t pos = atomicAdd(s_size, 1u);
+                if (pos < T::CAP) members[pos] = u; else *s_over = 1u;
+                return;
+            }
+            if (old == u) return;
+        }
+        slot = (slot + 1) & (T::HSIZE - 1);
+    }
+    *s_over = 1u;
+}
+
+template <uint32_t TEAM>
+__global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, SampleRange rg,
+                                                              SampleOut o, const uint32_t* pend,
+                                                              const uint32_t* pend_n,
+                                                              uint32_t* ticket) {
+    using T = Team<TEAM>;
+    constexpr uint32_t BS = T::BS;
+    __shared__ uint32_t hash[T::HSIZE];
+    __shared__ uint32_t members[T::CAP];
+    __shared__ uint32_t s_base[BS], s_g0[BS], s_beg[BS], s_end[BS];
+    __shared__ uint32_t s_wsum[TEAM];
+    __shared__ uint32_t s_size, s_over, s_tk;
+    __shared__ unsigned long long s_chunk;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
+    for (uint32_t i = tid; i < T::HSIZE; i += BS) hash[i] = kEmpty;
+    Stager sg;
+    uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;  // thread-partial
+    const uint32_t total = *pend_n;
+
+    for (;;) {
+        if (tid == 0) s_tk = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t pos = s_tk;
+        __syncthreads();
+        if (pos >= total) break;
+        const uint32_t idx = pend[pos];
+        const uint64_t s = rg.id_lo + idx;
+        const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
+        if (tid == 0) {
+            const uint32_t r0 = sample_root(rg.seed, s, g.n);
+            members[0] = r0;
+            hash[(r0 * 0x9E3779B1u) >> (32 - T::HBITS)] = r0;
+            s_size = 1;
+            s_over = 0;
+        }
         __syncthreads();
 
-        // ---- wave-per-sample BFS for the remaining samples of this batch
-        for (uint32_t pi = 0; pi < npend; ++pi) {
-            const uint32_t idx = s_pend[pi];
-            const uint64_t s = rg.id_lo + idx;
-            const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
-            if (lane == 0) {
-                const uint32_t r0 = sample_root(rg.seed, s, g.n);
-                members[0] = r0;
-                hash[hslot(r0)] = r0;
-                s_size = 1;
-                s_over = 0;
-            }
+        uint32_t head = 0, size = 1, my_edges = 0, my_live = 0;
+        bool over = false;
+        while (head < size) {
+            const uint32_t nb = min(BS, size - head);
+            const uint32_t G = level_layout<BS>(g, members, head, nb, s_base, s_g0, s_beg, s_end,
+                                                s_wsum, &my_edges);
             __syncthreads();
-
-            uint32_t head = 0, size = 1;
-            uint32_t my_edges = 0, my_live = 0;
-            while (head < size) {
-                const uint32_t nb = min(kWave, size - head);
-                uint32_t beg = 0, end = 0;
-                if (lane < nb) {
-                    const uint32_t v = members[head + lane];
-                    beg = g.off[v];
-                    end = g.off[v + 1];
-                }
-                const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
-                const uint32_t incl = wave_incl_scan(ng);
-                const uint32_t G = __shfl(incl, kWave - 1, kWave);
-                s_base[lane] = incl - ng;
-                s_g0[lane] = beg >> 2;
-                s_beg[lane] = beg;
-                s_end[lane] = end;
-                my_edges += end - beg;
-                __syncthreads();
-                uint32_t ow = 0;
-                for (uint32_t base = 0; base < G; base += kWave) {
-                    if (lds_load(&s_over)) break;
-                    const uint32_t t = base + lane;
-                    if (t < G) {
-                        ow = owner_from(s_base, nb, t, ow);
-                        const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
-                        const uint32_t eb = s_beg[ow], ee = s_end[ow];
-                        const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
-                        const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
-                        const uint32_t e0 = grp << 2;
-                        const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-                        const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
-#pragma unroll
-                        for (uint32_t j = 0; j < 4; ++j) {
-                            const uint32_t e = e0 + j;
-                            if (e >= eb && e < ee && rr[j] < tt[j]) {
-                                ++my_live;
-                                small_insert(g.src[e], hash, members, &s_size, &s_over);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-                head += nb;
-                size = s_size;
-                const uint32_t over = s_over;
-                __syncthreads();
-                if (over) break;
-            }
-
-            const bool over = s_over != 0u;
-            if (over) {
-                if (lane == 0) o.defer[atomicAdd(o.defer_n, 1u)] = idx;
-            } else {
-                uint64_t off = 0;
-                if (reserve(size, &off)) {
-                    for (uint32_t i = lane; i < size; i += kWave) {
-                        const uint32_t u = members[i];
-                        o.stage[off + i] = u;
-                        atomicAdd(&o.counts[u], 1u);
-                    }
-                    if (lane == 0) {
-                        o.stage_off[idx] = off;
-                        o.sizes[idx] = size;
-                        st_sets += 1;
-                        st_entries += size;
-                    }
-                    st_edges += my_edges;
-                    st_live += my_live;
-                } else if (lane == 0) {
-                    o.retry[atomicAdd(o.retry_n, 1u)] = idx;
-                }
-            }
-            // reset the hash slots this sample used (all members are present)
-            const uint32_t used = min(size, kSmallCap);
+            level_sweep<BS>(
+                g, slo, shi, k0, k1, s_base, s_g0, s_beg, s_end, nb, G, &my_live,
+                [&](uint32_t u) { team_insert<TEAM>(u, hash, members, &s_size, &s_over); },
+                [&]() { return lds_load(&s_over) != 0u; });
             __syncthreads();
-            for (uint32_t i = lane; i < used; i += kWave) {
-                const uint32_t u = members[i];
-                uint32_t slot = hslot(u);
-                for (uint32_t probe = 0; probe < kHashSize; ++probe) {
-                    if (hash[slot] == u) { hash[slot] = kEmpty; break; }
-                    slot = (slot + 1) & (kHashSize - 1);
-                }
-            }
-            if (over) {
-                // an abandoned set may have hashed vertices beyond the list
-                for (uint32_t i = lane; i < kHashSize; i += kWave) hash[i] = kEmpty;
-            }
+            head += nb;
+            size = s_size;
+            over = s_over != 0u;
             __syncthreads();
+            if (over) break;
         }
+
+        if (over) {
+            if (tid == 0) o.defer[atomicAdd(o.defer_n, 1u)] = idx;
+        } else {
+            uint64_t off = 0;
+            if (stage_reserve(sg, size, &off, &s_chunk, o)) {
+                for (uint32_t i = tid; i < size; i += BS) {
+                    const uint32_t u = members[i];
+                    o.stage[off + i] = u;
+                    atomicAdd(&o.counts[u], 1u);
+                }
+                if (tid == 0) {
+                    o.stage_off[idx] = off;
+                    o.sizes[idx] = size;
+                    st_sets += 1;
+                    st_entries += size;
+                }
+                st_edges += my_edges;
+                st_live += my_live;
+            } else if (tid == 0) {
+                o.retry[atomicAdd(o.retry_n, 1u)] = idx;
+            }
+        }
+        // reset the hash slots this sample used (all members are listed)
+        const uint32_t used = min(size, T::CAP);
+        __syncthreads();
+        if (over) {
+            // an abandoned set may have hashed vertices beyond the list
+            for (uint32_t i = tid; i < T::HSIZE; i += BS) hash[i] = kEmpty;
+        } else {
+            for (uint32_t i = tid; i < used; i += BS) {
+                const uint32_t u = members[i];
+                uint32_t slot = (u * 0x9E3779B1u) >> (32 - T::HBITS);
+                for (uint32_t probe = 0; probe < T::HSIZE; ++probe) {
+                    if (hash[slot] == u) {
+                        hash[slot] = kEmpty;
+                        break;
+                    }
+                    slot = (slot + 1) & (T::HSIZE - 1);
+                }
+            }
+        }
+        __syncthreads();
     }
     st_sets = wave_sum64(st_sets);
     st_entries = wave_sum64(st_entries);
     st_edges = wave_sum64(st_edges);
     st_live = wave_sum64(st_live);
-    if (lane == 0) {
+    if (tid % kWave == 0) {
         atomicAdd(&o.stats[kStMainSets], (unsigned long long)st_sets);
         atomicAdd(&o.stats[kStMainEntries], (unsigned long long)st_entries);
         atomicAdd(&o.stats[kStMainEdges], (unsigned long long)st_edges);
@@ -281,29 +396,14 @@ __global__ __launch_bounds__(64) void ic_small_kernel(IcGraphDev g, SampleRange 
     }
 }
 
-// Block-wide exclusive scan of one uint32 per thread; returns the total.
-template <uint32_t BS>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* excl_out,
-                                                    uint32_t* s_wsum) {
-    const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    const uint32_t incl = wave_incl_scan(v);
-    if (lane == kWave - 1) s_wsum[w] = incl;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < BS / kWave; ++i) {
-        const uint32_t x = s_wsum[i];
-        if (i < w) before += x;
-        total += x;
-    }
-    *excl_out = before + incl - v;
-    return total;
-}
+// ---------------------------------------------------------------- ic_large
 
+template <uint32_t kBigBlock>
 __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, SampleRange rg,
                                                              SampleOut o, const uint32_t* list,
                                                              const uint32_t* list_n,
                                                              uint32_t* fail, uint32_t* fail_n,
+                                                             uint32_t* over, uint32_t* over_n,
                                                              uint32_t* ticket, BigScratch b) {
     __shared__ uint32_t s_base[kBigBlock], s_g0[kBigBlock], s_beg[kBigBlock], s_end[kBigBlock];
     __shared__ uint32_t s_wsum[kBigBlock / kWave];
@@ -313,7 +413,7 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
     const uint32_t tid = threadIdx.x;
     const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     uint32_t* bm = b.bitmaps + (size_t)blockIdx.x * b.words;
-    uint32_t* q = b.queues + (size_t)blockIdx.x * g.n;
+    uint32_t* q = b.queues + (size_t)blockIdx.x * b.qcap;
     const uint32_t cnt = *list_n;
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;
 
@@ -334,54 +434,40 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
         }
         __syncthreads();
 
-        uint32_t head = 0, size = 1;
-        uint32_t my_edges = 0, my_live = 0;
+        uint32_t head = 0, size = 1, my_edges = 0, my_live = 0;
+        bool overflow = false;
         while (head < size) {
             const uint32_t nb = min(kBigBlock, size - head);
-            uint32_t beg = 0, end = 0;
-            if (tid < nb) {
-                const uint32_t v = q[head + tid];
-                beg = g.off[v];
-                end = g.off[v + 1];
-            }
-            const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
-            uint32_t excl;
-            const uint32_t G = block_excl_scan<kBigBlock>(ng, &excl, s_wsum);
-            s_base[tid] = excl;
-            s_g0[tid] = beg >> 2;
-            s_beg[tid] = beg;
-            s_end[tid] = end;
-            my_edges += end - beg;
+            const uint32_t G = level_layout<kBigBlock>(g, q, head, nb, s_base, s_g0, s_beg,
+                                                       s_end, s_wsum, &my_edges);
             __syncthreads();
-            uint32_t ow = 0;
-            for (uint32_t base = 0; base < G; base += kBigBlock) {
-                const uint32_t t = base + tid;
-                if (t < G) {
-                    ow = owner_from(s_base, nb, t, ow);
-                    const uint32_t grp = s_g0[ow] + (t - s_base[ow]);
-                    const uint32_t eb = s_beg[ow], ee = s_end[ow];
-                    const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
-                    const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
-                    const uint32_t e0 = grp << 2;
-                    const uint32_t rr[4] = {r.x, r.y, r.z, r.w};
-                    const uint32_t tt[4] = {th.x, th.y, th.z, th.w};
-#pragma unroll
-                    for (uint32_t j = 0; j < 4; ++j) {
-                        const uint32_t e = e0 + j;
-                        if (e >= eb && e < ee && rr[j] < tt[j]) {
-                            ++my_live;
-                            const uint32_t u = g.src[e];
-                            const uint32_t bit = 1u << (u & 31);
-                            const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                            if (!(old & bit)) q[atomicAdd(&s_size, 1u)] = u;
-                        }
+            level_sweep<kBigBlock>(
+                g, slo, shi, k0, k1, s_base, s_g0, s_beg, s_end, nb, G, &my_live,
+                [&](uint32_t u) {
+                    const uint32_t bit = 1u << (u & 31);
+                    const uint32_t old = atomicOr(&bm[u >> 5], bit);
+                    if (!(old & bit)) {
+                        const uint32_t pos = atomicAdd(&s_size, 1u);
+                        if (pos < b.qcap) q[pos] = u;
                     }
-                }
-            }
+                },
+                []() { return false; });
             __syncthreads();
             head += nb;
             size = s_size;
+            overflow = size > b.qcap;
             __syncthreads();
+            if (overflow) break;
+        }
+
+        if (overflow) {
+            // the queue no longer lists every visited vertex: clear the whole
+            // bitmap, and leave the sample to the pass with full-size queues
+            for (uint32_t i = tid; i < b.words; i += kBigBlock)
+                __hip_atomic_store(&bm[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) over[atomicAdd(over_n, 1u)] = idx;
+            __syncthreads();
+            continue;
         }
 
         if (tid == 0) s_off = atomicAdd(o.cursor, (unsigned long long)size);
@@ -424,30 +510,78 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
     }
 }
 
-}  // namespace
-
-uint32_t ic_small_grid(int device) {
+int cu_count(int device) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    return (uint32_t)cus * 24u;
+    return cus;
 }
 
-hipError_t launch_ic_small(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t grid, hipStream_t st) {
-    const uint32_t need = (r.count + kTicketChunk - 1) / kTicketChunk;
+}  // namespace
+
+uint32_t ic_small_grid(int device) { return (uint32_t)cu_count(device) * 24u; }
+
+uint32_t ic_bfs_grid(int device, uint32_t team) {
+    // enough workgroups for 8 waves per SIMD
+    return (uint32_t)cu_count(device) * 32u / team;
+}
+
+hipError_t launch_ic_lane(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                          uint32_t* pend, uint32_t* pend_n, uint32_t* ticket, uint32_t grid,
+                          hipStream_t st) {
+    const uint32_t need = (r.count + kIcTicketChunk - 1) / kIcTicketChunk;
     if (grid > need) grid = need;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(ic_small_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+    hipLaunchKernelGGL(ic_lane_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, pend, pend_n,
+                       ticket);
     return hipGetLastError();
+}
+
+hipError_t launch_ic_bfs(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
+                         const uint32_t* pend, const uint32_t* pend_n, uint32_t* ticket,
+                         uint32_t team, uint32_t grid, hipStream_t st) {
+    // r.count bounds the pending list (its length is read on the device)
+    if (grid > r.count) grid = r.count;
+    if (grid == 0) return hipSuccess;
+    switch (team) {
+        case 1:
+            hipLaunchKernelGGL(ic_bfs_kernel<1>, dim3(grid), dim3(kWave), 0, st, g, r, o, pend,
+                               pend_n, ticket);
+            break;
+        case 2:
+            hipLaunchKernelGGL(ic_bfs_kernel<2>, dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
+                               pend, pend_n, ticket);
+            break;
+        case 4:
+            hipLaunchKernelGGL(ic_bfs_kernel<4>, dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
+                               pend, pend_n, ticket);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+uint32_t ic_large_slots(int device, uint32_t block) {
+    // the same 512 threads per CU either way: many mid-sized giant sets in
+    // flight (256) or fewer, wider ones (1024)
+    return (uint32_t)cu_count(device) * (block == 256 ? 8u : 2u);
 }
 
 hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
-                           uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
+                           uint32_t* fail_n, uint32_t* over, uint32_t* over_n,
+                           uint32_t* ticket, const BigScratch& b, uint32_t block,
                            hipStream_t st) {
-    if (b.slots == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(ic_large_kernel, dim3(b.slots), dim3(kBigBlock), 0, st, g, r, o, list,
-                       list_n, fail, fail_n, ticket, b);
+    if (b.slots == 0 || b.qcap == 0 || b.qcap > g.n) return hipErrorInvalidValue;
+    if (b.qcap < g.n && (over == nullptr || over_n == nullptr)) return hipErrorInvalidValue;
+    if (block == 256)
+        hipLaunchKernelGGL(ic_large_kernel<256>, dim3(b.slots), dim3(256), 0, st, g, r, o, list,
+                           list_n, fail, fail_n, over, over_n, ticket, b);
+    else if (block == 1024)
+        hipLaunchKernelGGL(ic_large_kernel<1024>, dim3(b.slots), dim3(1024), 0, st, g, r, o,
+                           list, list_n, fail, fail_n, over, over_n, ticket, b);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

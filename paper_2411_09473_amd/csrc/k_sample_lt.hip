@@ -244,7 +244,7 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
     __shared__ unsigned long long s_off, s_steps, s_reads;
     const uint32_t lane = threadIdx.x;
     uint32_t* bm = b.bitmaps + (size_t)blockIdx.x * b.words;
-    uint32_t* q = b.queues + (size_t)blockIdx.x * g.n;
+    uint32_t* q = b.queues + (size_t)blockIdx.x * b.qcap;
     const uint32_t cnt = *list_n;
     uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
     for (;;) {
@@ -354,7 +354,7 @@ hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const Samp
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
                            uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
                            hipStream_t st) {
-    if (b.slots == 0) return hipErrorInvalidValue;
+    if (b.slots == 0 || b.qcap != g.n) return hipErrorInvalidValue;
     hipLaunchKernelGGL(lt_large_kernel, dim3(b.slots), dim3(kWave), 0, st, g, r, o, list, list_n,
                        fail, fail_n, ticket, b);
     return hipGetLastError();

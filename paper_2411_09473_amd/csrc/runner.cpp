@@ -101,12 +101,20 @@ imm_status acquire_workspace(Query& q, uint32_t big_cap) {
         q.w.reset(new Workspace());
         q.w->big_cap = big_cap;
         IMM_TRY(ws_init(*q.w, q.g->n, q.g->device, q.st, q.p.max_device_bytes));
-    } else if (q.w->big_cap != big_cap) {
-        // large-set scratch sized for another batch width: reallocated on use
-        if (q.w->big) q.w->arena.release(q.w->big);
-        q.w->big = nullptr;
-        q.w->big_slots = 0;
-        q.w->big_cap = big_cap;
+    } else {
+        // giant-set scratch narrower than this batch width wants (0: all the
+        // GPU can use) is reallocated on use; wider scratch is kept
+        Workspace& w = *q.w;
+        const uint32_t want = big_cap ? big_cap : 0xFFFFFFFFu;
+        if (w.big && w.big_cap != big_cap && w.big_slots < want) {
+            w.arena.release(w.big);
+            w.arena.release(w.huge);
+            w.big = nullptr;
+            w.huge = nullptr;
+            w.big_slots = 0;
+            w.huge_slots = 0;
+        }
+        w.big_cap = big_cap;
     }
     return ws_reset(*q.w, q.st, (q.p.flags & IMM_TIMING) != 0);
 }
@@ -123,6 +131,7 @@ imm_status start(Query& q, uint32_t big_cap) {
     if (q.p.k == 0 || q.p.k > q.g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
     if (!(q.p.epsilon > 0.0) || !(q.p.ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
     IMM_TRY(theta_plan(q.g->n, q.p.k, q.p.epsilon, q.p.ell, &q.lam_p, &q.lam_s, &q.i_max));
+    IMM_TRY(tune_graph(q.g, q.st));
     IMM_TRY(acquire_workspace(q, big_cap));
     q.r.reset(new imm_result());
     q.r->k = q.p.k;
@@ -185,6 +194,8 @@ imm_status end_iteration(Query& q) {
     r.stats.ms_select += q.ms_select;
     r.stats.ms_total = t1 - q.t0;
     r.stats.rounds = r.rounds;
+    r.stats.team = q.g->model == IMM_IC ? q.g->ic_team : 0;
+    r.stats.big_block = q.g->model == IMM_IC ? q.g->ic_big_block : 0;
     if (q.p.flags & IMM_KEEP_POOL) {
         IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
         r.has_pool = true;
@@ -202,7 +213,7 @@ void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t co
     std::vector<Query*> active;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, graphs[0]->device);
-    const uint32_t big_cap = count > 1 ? std::max<uint32_t>(32u, (uint32_t)cus * 8u / count) : 0u;
+    const uint32_t big_cap = count > 1 ? std::max<uint32_t>(64u, (uint32_t)cus * 8u / count) : 0u;
     auto finish_err = [&](Query& q, imm_status s) {
         q.status = s;
         q.err = last_error();

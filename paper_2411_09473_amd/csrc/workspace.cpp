@@ -173,32 +173,53 @@ imm_status ws_read_scalars(Workspace& w) {
 
 namespace {
 
-// Scratch of the large-set kernels: per slot a visited bitmap and a queue
-// of n entries; enough slots to fill the GPU (IC) or a few per CU (LT, whose
-// walks rarely outgrow a chunk), within kBigScratchBytes and the budget.
-imm_status ws_big_scratch(Workspace& w, imm_model model) {
+// Scratch of the large-set kernels: per slot a visited bitmap and a queue.
+// IC: enough slots for the 256-thread shape with queues of kGiantQueue
+// entries, plus kHugeSlots slots with queues of n for the sets that outgrow
+// those; LT: one slot per CU with queues of n (its walks rarely outgrow a
+// chunk). All within kBigScratchBytes and the budget.
+imm_status ws_big_scratch(Workspace& w, const imm_graph* g) {
     if (w.big) return IMM_OK;
+    const bool ic = g->model == IMM_IC;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
     const uint64_t words = ((uint64_t)w.n + 31) / 32;
-    const uint64_t per = (words + w.n) * 4;
-    uint64_t slots = model == IMM_IC ? (uint64_t)cus * 8 : (uint64_t)cus;
+    const uint32_t qcap = ic ? std::min<uint32_t>(w.n, kGiantQueue) : w.n;
+    const uint64_t per = (words + qcap) * 4;
+    const uint64_t per_huge = (words + w.n) * 4;
+    uint64_t slots = ic ? ic_large_slots(w.device, 256) : (uint64_t)cus;
     if (w.big_cap) slots = std::min<uint64_t>(slots, w.big_cap);
+    const uint64_t huge = ic && qcap < w.n ? kHugeSlots : 0;
     uint64_t limit = kBigScratchBytes;
     if (w.arena.budget) {
         const uint64_t left = w.arena.budget > w.arena.used ? w.arena.budget - w.arena.used : 0;
         limit = std::min(limit, left / 4);
     }
-    slots = std::min<uint64_t>(slots, std::max<uint64_t>(1, limit / per));
+    const uint64_t huge_bytes = huge * per_huge;
+    const uint64_t room = limit > huge_bytes ? limit - huge_bytes : 0;
+    slots = std::min<uint64_t>(slots, std::max<uint64_t>(1, room / per));
     IMM_TRY(w.arena.alloc((void**)&w.big, per * slots, "large-set scratch"));
     HIP_TRY(hipMemsetAsync(w.big, 0, words * slots * 4, w.st));
     w.big_slots = (uint32_t)slots;
+    w.big_qcap = qcap;
+    if (huge) {
+        IMM_TRY(w.arena.alloc((void**)&w.huge, huge_bytes, "huge-set scratch"));
+        HIP_TRY(hipMemsetAsync(w.huge, 0, words * huge * 4, w.st));
+        w.huge_slots = (uint32_t)huge;
+    }
     return IMM_OK;
 }
 
-BigScratch big_view(const Workspace& w) {
+// The scratch slots, at most `want` of them.
+BigScratch big_view(const Workspace& w, uint32_t want) {
     const uint32_t words = (uint32_t)(((uint64_t)w.n + 31) / 32);
-    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words, w.big_slots};
+    return BigScratch{w.big, w.big + (uint64_t)words * w.big_slots, words,
+                      std::min(w.big_slots, want), w.big_qcap};
+}
+
+BigScratch huge_view(const Workspace& w) {
+    const uint32_t words = (uint32_t)(((uint64_t)w.n + 31) / 32);
+    return BigScratch{w.huge, w.huge + (uint64_t)words * w.huge_slots, words, w.huge_slots, w.n};
 }
 
 // One sampling pass: the fast kernel over the range (list = nullptr) or over
@@ -213,22 +234,41 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
     const SampleRange rgl{seed, id_lo, count, nullptr, nullptr};
     const SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
                       w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
-    HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 8, st));  // ticket_small, ticket_big
-    HIP_TRY(hipMemsetAsync(&w.sc->defer_n, 0, 4, st));
+    HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 7 * sizeof(uint32_t), st));
     const int th = w.timer.open(0, st);
-    const int tm = w.timer.open(4, st);
-    if (g->model == IMM_IC)
-        HIP_TRY(launch_ic_small(ic_view(g), rg, o, &w.sc->ticket_small, ic_small_grid(w.device), st));
-    else
+    if (g->model == IMM_IC) {
+        const int tl = w.timer.open(6, st);
+        HIP_TRY(launch_ic_lane(ic_view(g), rg, o, w.pend, &w.sc->pend_n, &w.sc->ticket_small,
+                               ic_small_grid(w.device), st));
+        w.timer.close(tl, st);
+        const int tm = w.timer.open(4, st);
+        const SampleRange rgp{seed, id_lo, nitems, nullptr, nullptr};
+        HIP_TRY(launch_ic_bfs(ic_view(g), rgp, o, w.pend, &w.sc->pend_n, &w.sc->ticket_bfs,
+                              g->ic_team, ic_bfs_grid(w.device, g->ic_team), st));
+        w.timer.close(tm, st);
+    } else {
+        const int tm = w.timer.open(4, st);
         HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, lt_small_grid(w.device), st));
-    w.timer.close(tm, st);
+        w.timer.close(tm, st);
+    }
     const int t3 = w.timer.open(5, st);
-    if (g->model == IMM_IC)
-        HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
-                                &w.sc->ticket_big, big_view(w), st));
-    else
+    if (g->model == IMM_IC) {
+        // the tuned giant-set shape, unless the pass is expected to defer
+        // far more sets than the wide shape has workgroups
+        uint32_t block = g->ic_big_block;
+        if (!g->big_forced &&
+            g->defer_rate * (double)nitems > 2.0 * ic_large_slots(w.device, 1024))
+            block = 256;
+        HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n, w.over,
+                                &w.sc->over_n, &w.sc->ticket_big,
+                                big_view(w, ic_large_slots(w.device, block)), block, st));
+        if (w.huge_slots)
+            HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.over, &w.sc->over_n, fl, fl_n, nullptr,
+                                    nullptr, &w.sc->ticket_huge, huge_view(w), 1024, st));
+    } else {
         HIP_TRY(launch_lt_large(lt_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
-                                &w.sc->ticket_big, big_view(w), st));
+                                &w.sc->ticket_big, big_view(w, w.big_slots), st));
+    }
     w.timer.close(t3, st);
     w.timer.close(th, st);
     HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
@@ -256,16 +296,22 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
         count -= kPilot;
     }
     hipStream_t st = w.st;
-    IMM_TRY(ws_big_scratch(w, g->model));
+    IMM_TRY(ws_big_scratch(w, g));
     IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
     IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
     IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
     IMM_TRY(grow(w.arena, &w.retry, &w.cap_rt, count, 0, st, "retry list"));
     IMM_TRY(grow(w.arena, &w.spare, &w.cap_sp, count, 0, st, "retry list"));
+    if (g->model == IMM_IC) {
+        IMM_TRY(grow(w.arena, &w.pend, &w.cap_pd, count, 0, st, "pending list"));
+        IMM_TRY(grow(w.arena, &w.over, &w.cap_ov, count, 0, st, "huge-set list"));
+    }
     {
         // expected entries plus the unused tails of every wave's (IC) or
         // lane's (LT) staging chunk
-        const double mean = w.mean_size > 0 ? w.mean_size : 16.0;
+        // with no measured mean yet, a generous guess (a shortfall costs a
+        // retry pass, an excess only memory)
+        const double mean = w.mean_size > 0 ? w.mean_size : 64.0;
         uint64_t tails;
         if (g->model == IMM_IC) {
             const uint64_t waves = std::min<uint64_t>(
@@ -520,8 +566,8 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
 }
 
 void fill_stats(Workspace& w, imm_stats* s) {
-    double ms[6] = {0, 0, 0, 0, 0, 0};
-    uint64_t launches[2] = {0, 0};
+    double ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    uint64_t launches[3] = {0, 0, 0};
     w.timer.collect(ms, launches);
     s->ms_sample += ms[0];
     s->ms_compact += ms[1];
@@ -529,12 +575,16 @@ void fill_stats(Workspace& w, imm_stats* s) {
     s->ms_select += ms[3];
     s->ms_sample_main += ms[4];
     s->ms_sample_big += ms[5];
+    s->ms_sample_lane += ms[6];
     s->main_launches += launches[0];
     s->big_launches += launches[1];
+    s->lane_launches += launches[2];
     const unsigned long long* t = w.hsc->stats;
-    s->sets = t[kStMainSets] + t[kStBigSets];
-    s->entries = t[kStMainEntries] + t[kStBigEntries];
-    s->edges = t[kStMainEdges] + t[kStBigEdges];
+    s->sets = t[kStMainSets] + t[kStBigSets] + t[kStLaneSets];
+    s->entries = t[kStMainEntries] + t[kStBigEntries] + t[kStLaneSets];
+    s->edges = t[kStMainEdges] + t[kStBigEdges] + t[kStLaneEdges];
+    s->lane_sets = t[kStLaneSets];
+    s->lane_edges = t[kStLaneEdges];
     s->live = t[kStMainLive] + t[kStBigLive];
     s->deferred = t[kStBigSets];
     s->main_sets = t[kStMainSets];

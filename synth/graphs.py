@@ -268,6 +268,10 @@ WORKLOADS = {
     # R-MAT scale 12 under LT (same topology rule as rmat12_wc)
     "rmat12_lt": dict(gen=("rmat", 12, 32768), model="lt", enc=("lt",),
                       k=10, eps=0.5, ell=1.0, seed=42),
+    # the largest instance shape of the multi-instance batch (scale 20,
+    # average degree 32, weighted cascade)
+    "rmat20_wc": dict(gen=("rmat", 20, 32 << 20), model="ic", enc=("wc",),
+                      k=50, eps=0.13, ell=1.0, seed=42),
     # served-stream graphs
     "rmat18_wc": dict(gen=("rmat", 18, 2097152), model="ic", enc=("wc",),
                       k=50, eps=0.13, ell=1.0, seed=42),

@@ -46,13 +46,40 @@ def test_select_every_vertex(imm, orc, stream):
     _parity(imm, orc, g, 6, 0.5, 11, stream)
 
 
-def test_certain_and_impossible_edges(imm, orc, stream):
-    n = 300
+@pytest.mark.parametrize("team", [1, 2, 4])
+def test_certain_and_impossible_edges(imm, orc, stream, monkeypatch, team):
+    # a certain chain 0 -> 1 -> ... -> n-1 (the set of root v is {0..v}) plus
+    # impossible back edges; sets longer than every team's on-chip limit
+    monkeypatch.setenv("IMM_IC_TEAM", str(team))
+    n = 1300
     edges = [(v, v + 1) for v in range(n - 1)] + [(v + 2, v) for v in range(0, n - 2, 7)]
     thr = [T32 - 1] * (n - 1) + [0] * len(range(0, n - 2, 7))
     g = synth.tiny_graph(n, edges, "ic", thr)
+    say(f"certain chain n={n} team={team}")
     r = _parity(imm, orc, g, 3, 0.3, 5, stream)
+    assert r.stats["team"] == team
     assert r.stats["deferred"] > 0  # chains longer than the on-chip set limit
+
+
+@pytest.mark.parametrize("big", [256, 1024])
+def test_sets_beyond_bounded_giant_queue(imm, orc, stream, monkeypatch, big):
+    """A certain chain longer than the giant-set queue bound (65536 members):
+    the sets of roots beyond it go through the full-size second pass. (The
+    launch shapes are fixed: every BFS level of a chain holds one vertex.)"""
+    monkeypatch.setenv("IMM_IC_TEAM", "4")
+    monkeypatch.setenv("IMM_IC_BIG", str(big))
+    n = 70000
+    g = synth.tiny_graph(n, [(v, v + 1) for v in range(n - 1)], "ic", [T32 - 1] * (n - 1))
+    say(f"certain chain n={n}, 300 samples")
+    dg = imm.graph_from(g, stream=stream)
+    pool = imm.imm_sample(dg, 4, 0, 300, stream=stream)
+    so, sv, cn = pool.export()
+    oso, osv = orc.sample(g, 4, 0, 300)
+    cso, csv = canonical(oso, osv, g.n)
+    np.testing.assert_array_equal(so, cso)
+    np.testing.assert_array_equal(sv, csv)
+    np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
+    assert int(np.diff(so).max()) > 65536
 
 
 def test_lt_with_no_live_edge_mass(imm, orc, stream):

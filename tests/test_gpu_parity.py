@@ -64,6 +64,19 @@ def test_ic_pool_giant_sets(imm, orc, stream):
     assert p.stats["deferred"] > 0  # giant sets went through the large-set kernel
 
 
+@pytest.mark.parametrize("big", [256, 1024])
+@pytest.mark.parametrize("team", [1, 2, 4])
+@pytest.mark.parametrize("name", ["rmat12_wc", "rmat12_p10"])
+def test_ic_pool_each_shape(imm, orc, stream, monkeypatch, team, big, name):
+    """Every IC launch shape the autotuner can pick (1, 2 or 4 waves per BFS
+    sample; 256 or 1024 threads per giant set) gives the same pool."""
+    monkeypatch.setenv("IMM_IC_TEAM", str(team))
+    monkeypatch.setenv("IMM_IC_BIG", str(big))
+    g = synth.make_graph(name)
+    p = _pool_parity(imm, orc, g, 9, 0, 3000, stream)
+    assert (p.stats["team"], p.stats["big_block"]) == (team, big)
+
+
 def test_lt_pool_small(imm, orc, stream):
     g = synth.make_graph("cl_lt_xs")
     _pool_parity(imm, orc, g, 42, 0, 20000, stream)
