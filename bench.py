@@ -216,6 +216,110 @@ def batch_mode(args, imm, insts, graphs, stream, torch):
     }))
 
 
+def _gen_named(name):
+    import synth
+    return synth.make_graph(name)
+
+
+def make_named_graphs(names):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=len(names), mp_context=mp.get_context("fork")) as ex:
+        return dict(zip(names, ex.map(_gen_named, names)))
+
+
+def serve_mode(args, imm, hgraphs, stream, torch):
+    """A Poisson stream of queries (the served workload) through the query
+    server, against the same stream answered one query at a time, in
+    arrival order, with imm_run. Latency is submission to completion."""
+    import threading
+
+    import numpy as np
+
+    import synth
+    qs = synth.served_queries(args.serve, rate=args.rate)
+    dgs = {nm: imm.graph_from(g, stream=stream) for nm, g in hgraphs.items()}
+    torch.cuda.synchronize()
+    # warm-up: tune every graph and fill its workspace cache
+    for nm, dg in dgs.items():
+        for _ in range(max(1, args.warmup)):
+            imm.imm_run(dg, 50, 0.13, 1.0, 1, stream=stream)
+    torch.cuda.synchronize()
+    print("[bench] served warmup done", file=sys.stderr, flush=True)
+
+    srv = imm.Server(budget_bytes=args.serve_budget << 30, max_slots=args.serve_slots)
+    tickets = [None] * len(qs)
+
+    def submitter(t0):
+        for i, q in enumerate(qs):
+            dt = t0 + q["t"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(dgs[q["graph"]], k=q["k"], epsilon=q["eps"], ell=q["ell"],
+                                    seed=q["seed"])
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter, args=(t0,))
+    th.start()
+    th.join()
+    res = [srv.poll(t) for t in tickets]
+    t_end = time.perf_counter()
+    srv.close()
+    lat = np.array([r.stats["ms_total"] for r in res])
+    served_qps = len(qs) / (t_end - t0)
+    print("[bench] served run done", file=sys.stderr, flush=True)
+
+    # the same arrivals answered one at a time on the plain path
+    lat1 = []
+    t0 = time.perf_counter()
+    seq = []
+    for q in qs:
+        now = time.perf_counter() - t0
+        if now < q["t"]:
+            time.sleep(q["t"] - now)
+        r = imm.imm_run(dgs[q["graph"]], q["k"], q["eps"], q["ell"], q["seed"], stream=stream)
+        lat1.append((time.perf_counter() - t0 - q["t"]) * 1e3)
+        seq.append(r)
+    t_end1 = time.perf_counter()
+    one_qps = len(qs) / (t_end1 - t0)
+    for a, b in zip(res, seq):
+        assert a.theta == b.theta and list(a.seeds) == list(b.seeds), "served != alone"
+    lat1 = np.array(lat1)
+    print("[bench] one-at-a-time run done", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "IMM queries/s (served, Poisson arrivals)", "value": served_qps,
+        "unit": "queries/s", "n_gpus": 1, "steps": len(qs), "warmup": args.warmup,
+        "ms_per_step": float(np.mean(lat)), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{len(qs)} queries at {args.rate}/s over rmat18_wc (IC), "
+                               "youtube_ic (IC) and orkut_lt (LT); k in {10,50,100}, "
+                               "eps in {0.5,0.13}",
+                   "max_slots": args.serve_slots, "budget_GiB": args.serve_budget,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(np.mean(lat))},
+        "one_at_a_time": {"queries_per_s": one_qps,
+                          "latency_ms": {"p50": float(np.percentile(lat1, 50)),
+                                         "p99": float(np.percentile(lat1, 99)),
+                                         "mean": float(np.mean(lat1))}},
+    }))
+
+
+def copy_calibration(torch):
+    """A plain device-to-device copy of 1 GiB, three times: the reference
+    that scales the HBM byte counters (FETCH_SIZE, WRITE_SIZE) of a profile
+    run, since a copy moves exactly its size in each direction."""
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3, "kib_per_copy": n / 1024}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +334,15 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="multi-instance mode: this many IMM instances per step, "
                          "batched, against the same run one at a time")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="served mode: this many Poisson-arrival queries through the "
+                         "query server, against the same stream one at a time")
+    ap.add_argument("--rate", type=float, default=50.0, help="served mode: arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=8, help="served mode: concurrent queries")
+    ap.add_argument("--serve-budget", type=int, default=192,
+                    help="served mode: device memory budget in GiB")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB device copy that calibrates HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the "
@@ -238,6 +351,10 @@ def main():
         sys.exit(2)
 
     batch = None
+    served = None
+    if args.serve:
+        served = make_named_graphs(["rmat18_wc", "youtube_ic", "orkut_lt"])
+        print("[bench] served graphs ready", file=sys.stderr, flush=True)
     if args.batch:
         batch = make_batch_graphs(args.batch)
         print(f"[bench] {args.batch} batch graphs ready", file=sys.stderr, flush=True)
@@ -248,6 +365,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        return copy_calibration(torch)
+    if served is not None:
+        return serve_mode(args, imm, served, torch.cuda.current_stream(), torch)
     if batch is not None:
         return batch_mode(args, imm, batch[0], batch[1], torch.cuda.current_stream(), torch)
     spec = synth.WORKLOADS[args.workload]

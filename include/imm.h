@@ -106,6 +106,9 @@ typedef struct {
     uint64_t lane_edges;     /* IC: coins it evaluated for them */
     uint32_t big_block;      /* IC: threads per giant set (autotuned) */
     uint32_t pad;
+    uint64_t device_bytes;   /* device memory held by the run's workspace */
+    double ms_queue;         /* server: submit to admission (ms_total is then
+                                submit to completion) */
 } imm_stats;
 
 /* Thread-local description of the last error of this thread. */
@@ -133,6 +136,46 @@ imm_status imm_graph_destroy(imm_graph* g);
 /* n, m, model and the device bytes held by the resident graph. */
 imm_status imm_graph_info(const imm_graph* g, uint32_t* n, uint64_t* m, imm_model* model,
                           uint64_t* device_bytes);
+
+/* --------------------------------------------------------------- server ---
+ * A query server on the device current at creation (continuous batching;
+ * not in the paper: the serving form of the same computation). A worker
+ * thread runs the admitted queries together, iteration by iteration, as
+ * imm_run_batch does; a query submitted while others run is admitted at the
+ * next iteration boundary once a slot (at most max_slots queries run at a
+ * time) and device memory are free. Admission reserves each query's
+ * estimated workspace size (the largest workspace seen so far on its graph,
+ * else 64 bytes per vertex plus 1 GiB; max_device_bytes when that is set and
+ * smaller) against budget_bytes. Pools stay in device memory. A result is
+ * the same, bit for bit, as imm_run's with the same arguments. Graphs must
+ * outlive the server. Server calls are thread-safe.
+ *   imm_server_create   budget_bytes > 0, max_slots >= 1
+ *   imm_server_submit   queue a query; *ticket identifies it. IMM_EINVAL on
+ *                       bad arguments (as imm_run) or a graph on another
+ *                       device; IMM_ENOMEM if its estimate exceeds the
+ *                       budget even alone.
+ *   imm_server_poll     IMM_EBUSY if the query has not finished and wait is
+ *                       0 (else it blocks until it has); otherwise the
+ *                       query's own status (IMM_OK with *out set, or its
+ *                       error, IMM_ECANCELLED after a cancel), and the
+ *                       ticket is retired. IMM_EINVAL for an unknown ticket.
+ *                       In the result's stats, ms_total is the time from
+ *                       submission to completion and ms_queue from
+ *                       submission to admission.
+ *   imm_server_cancel   a queued query is dropped at once, a running one at
+ *                       the next iteration boundary
+ *   imm_server_info     queued and running queries, reserved bytes
+ *   imm_server_destroy  cancels everything, waits for the worker, frees
+ *                       results nobody polled */
+typedef struct imm_server imm_server;
+imm_status imm_server_create(uint64_t budget_bytes, uint32_t max_slots, imm_server** out);
+imm_status imm_server_submit(imm_server* s, const imm_graph* g, const imm_params* p,
+                             uint64_t* ticket);
+imm_status imm_server_poll(imm_server* s, uint64_t ticket, int wait, imm_result** out);
+imm_status imm_server_cancel(imm_server* s, uint64_t ticket);
+imm_status imm_server_info(imm_server* s, uint64_t* queued, uint32_t* running,
+                           uint64_t* reserved_bytes);
+imm_status imm_server_destroy(imm_server* s);
 
 /* ---------------------------------------------------------------- theta ---
  * IMM's theta constants (Tang, Shi, Xiao 2015, cited for Theta_Estimation,

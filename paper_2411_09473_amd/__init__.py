@@ -59,7 +59,8 @@ class imm_stats(C.Structure):
                 ("big_launches", C.c_uint64), ("rounds", C.c_uint32), ("team", C.c_uint32),
                 ("ms_sample_lane", C.c_double), ("lane_launches", C.c_uint64),
                 ("lane_sets", C.c_uint64), ("lane_edges", C.c_uint64),
-                ("big_block", C.c_uint32), ("pad", C.c_uint32)]
+                ("big_block", C.c_uint32), ("pad", C.c_uint32),
+                ("device_bytes", C.c_uint64), ("ms_queue", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
@@ -87,6 +88,12 @@ _sig = {
     "imm_pool_export": [_vp, _vp, _vp, _vp],
     "imm_greedy": [_u32, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _P(_u64)],
     "imm_philox4x32_10": [_vp, _u64, _u64, _u32, _vp, _vp],
+    "imm_server_create": [_u64, _u32, _P(_vp)],
+    "imm_server_submit": [_vp, _vp, _P(imm_params), _P(_u64)],
+    "imm_server_poll": [_vp, _u64, _int, _P(_vp)],
+    "imm_server_cancel": [_vp, _u64],
+    "imm_server_info": [_vp, _P(_u64), _P(_u32), _P(_u64)],
+    "imm_server_destroy": [_vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -259,6 +266,55 @@ def imm_run_batch(queries, stream=None) -> list:
     _check(_lib.imm_run_batch(C.cast(hs, _vp), C.cast(ps, _vp), cnt, _stream(stream),
                               C.cast(outs, _vp)))
     return [Result(outs[j], queries[j][1]["k"]) for j in range(cnt)]
+
+
+class Server:
+    """Owning handle of an imm_server (continuous batching on the current
+    device). Graphs passed to submit must stay open while the server runs."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 8):
+        h = C.c_void_p()
+        _check(_lib.imm_server_create(budget_bytes, max_slots, C.byref(h)))
+        self._h = h
+        self._k = {}
+
+    def submit(self, g: Graph, k, epsilon, ell=1.0, seed=0, flags=0, max_device_bytes=0) -> int:
+        p = imm_params(k=k, flags=flags, epsilon=epsilon, ell=ell, seed=seed,
+                       max_device_bytes=max_device_bytes)
+        t = _u64()
+        _check(_lib.imm_server_submit(self._h, g.handle, C.byref(p), C.byref(t)))
+        self._k[t.value] = k
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """The query's Result; None while it runs (wait=False). Raises the
+        query's error (IMM_ECANCELLED after cancel)."""
+        out = C.c_void_p()
+        st = _lib.imm_server_poll(self._h, ticket, 1 if wait else 0, C.byref(out))
+        if st == IMM_EBUSY:
+            return None
+        k = self._k.pop(ticket, 1)
+        _check(st)
+        return Result(out.value, k)
+
+    def cancel(self, ticket: int):
+        _check(_lib.imm_server_cancel(self._h, ticket))
+
+    def info(self):
+        q, r, b = _u64(), _u32(), _u64()
+        _check(_lib.imm_server_info(self._h, C.byref(q), C.byref(r), C.byref(b)))
+        return {"queued": q.value, "running": r.value, "reserved_bytes": b.value}
+
+    def close(self):
+        if self._h and self._h.value:
+            _check(_lib.imm_server_destroy(self._h))
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Pool:

@@ -20,7 +20,7 @@ LIB = PKG / "libimm.so"
 ARCH = os.environ.get("IMM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_sample_ic.hip", "k_sample_lt.hip", "k_pool.hip", "k_select.hip",
-           "workspace.cpp", "runner.cpp", "tune.cpp", "api.cpp"]
+           "workspace.cpp", "runner.cpp", "tune.cpp", "server.cpp", "api.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
@@ -29,6 +29,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     f"-I{PKG.parent / 'include'}",
+    "-pthread",
 ]
 
 
@@ -59,7 +60,7 @@ def build(verbose: bool = False) -> Path:
         for j in jobs:
             j.result()
     tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", str(tmp),
            *map(str, objs)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

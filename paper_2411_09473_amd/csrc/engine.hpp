@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <memory>
@@ -161,7 +162,8 @@ struct Workspace {
     uint64_t* scan_tmp = nullptr;
     uint64_t cap_scan = 0;
     unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
-    uint32_t* chunk_n = nullptr;          // k queue lengths
+    uint32_t* chunk_n = nullptr;          // 2k queue lengths
+    unsigned long long* cov_entries = nullptr;  // k covered-member totals
     Chunk* chunks = nullptr;
     uint64_t cap_chunks = 0;
     uint32_t* seeds_d = nullptr;
@@ -169,6 +171,7 @@ struct Workspace {
     uint64_t cap_k = 0;
     uint32_t* gains_h = nullptr;  // pinned
     SelectDesc* desc_d = nullptr; // one descriptor, for selection run alone
+    SelectDesc desc_h{};          // its host copy (kept while the copy is queued)
     uint32_t* big = nullptr;   // giant-set slots: bitmap + bounded queue each
     uint32_t big_slots = 0;
     uint32_t big_qcap = 0;
@@ -213,6 +216,8 @@ struct imm_graph {
     uint32_t* guide = nullptr;
     // workspaces of finished queries, reused by later ones
     std::mutex ws_mu;
+    // largest workspace a finished query on this graph held (server admission)
+    std::atomic<uint64_t> peak_bytes{0};
     std::vector<std::unique_ptr<imm::Workspace>> ws_cache;
 };
 
@@ -256,6 +261,9 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d);
 imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st);
 // After st is synchronised: error check, exact pool size, coverage.
 imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
+// The selection of this workspace alone, launched on w.st without waiting
+// (then ws_select_finish once the stream is done).
+imm_status ws_select_launch(Workspace& w, uint32_t k);
 // Prepare, run and finish the selection of this workspace alone.
 imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
 imm_status ws_sync_pool(Workspace& w);
@@ -273,6 +281,66 @@ imm_status tune_graph(imm_graph* g, hipStream_t st);
 // Theta constants (Tang et al. 2015, Eq. 9 and Eq. 6 with ell adjusted).
 imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* lambda_prime,
                       double* lambda_star, uint32_t* i_max);
+
+struct Query;  // one IMM query's state machine (runner.cpp)
+
+// Advances a changing set of queries together, one iteration at a time: an
+// iteration launches every active query's sampling round on its own stream,
+// waits, finishes the rounds, then runs the greedy selections of all of them
+// with one set of launches per seed step on the main stream. Queries may be
+// started (and cancelled) between steps; each finishes independently.
+class BatchRunner {
+public:
+    explicit BatchRunner(hipStream_t main);
+    ~BatchRunner();
+    BatchRunner(const BatchRunner&) = delete;
+    BatchRunner& operator=(const BatchRunner&) = delete;
+    // Start a query sampling on stream st; a query that fails to start is
+    // returned already finished (and is not active).
+    Query* start(imm_graph* g, const imm_params& p, hipStream_t st, uint32_t big_cap);
+    // One iteration of every active query; false when none is active.
+    bool step();
+    // Finish q as cancelled; it leaves at the next step.
+    void cancel(Query* q);
+    // Queries that finished (result, error or cancellation) since the last call.
+    std::vector<Query*> drain();
+    size_t active() const { return active_.size(); }
+    // The result of a finished query (null unless *status is IMM_OK); frees q.
+    static imm_result* take(Query* q, imm_status* status, std::string* err);
+    static bool done(const Query* q);
+    static uint64_t bytes(const Query* q);  // workspace bytes at the end
+
+private:
+    void finish_err(Query* q, imm_status s);
+    hipStream_t main_;
+    std::vector<Query*> active_, finished_;
+    SelectDesc* descs_h_ = nullptr;
+    SelectDesc* descs_d_ = nullptr;
+    size_t cap_descs_ = 0;
+    hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
+};
+
+// Runs queries independently of each other, each on its own stream: the
+// host never waits for one query's GPU work while another query's is ready
+// to advance. poll() advances every query whose queued work has finished
+// (finish its sampling round and launch its selection; or take its theta
+// decision and launch its next round) and returns whether any did.
+class AsyncRunner {
+public:
+    AsyncRunner() = default;
+    ~AsyncRunner();
+    AsyncRunner(const AsyncRunner&) = delete;
+    AsyncRunner& operator=(const AsyncRunner&) = delete;
+    Query* start(imm_graph* g, const imm_params& p, hipStream_t st, uint32_t big_cap);
+    bool poll();
+    void cancel(Query* q);
+    std::vector<Query*> drain();
+    size_t active() const { return active_.size(); }
+
+private:
+    void finish_err(Query* q, imm_status s);
+    std::vector<Query*> active_, finished_;
+};
 // Run queries to completion, advancing them together round by round.
 // streams[q] (may repeat) is the stream query q samples on; `main` carries
 // the batched selection. out[q] receives a result or stays null with

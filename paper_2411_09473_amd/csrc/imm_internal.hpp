@@ -162,7 +162,12 @@ constexpr uint32_t kArgSlots = 32;
 // One instance's greedy state, as the batched selection kernels see it.
 // Its index has nseg segments; segment r's offsets are
 // inv_offs[r * (n + 1) .. r * (n + 1) + n], absolute in inv_set. slots holds
-// k * kArgSlots zeroed entries, chunk_n k zeroed counters. Workgroups
+// k * kArgSlots zeroed entries, chunk_n 2k zeroed counters: seed step t
+// queues the small covered sets (one entry each) at chunks[0 ..
+// chunk_n[2t]) and the 64-member pieces of the others at chunks[chunk_cap -
+// chunk_n[2t+1] .. chunk_cap). A step whose covered sets hold more than an
+// eighth of all pool entries recounts every count from the index instead of
+// decrementing. Workgroups
 // [arg_lo, arg_lo + arg_cnt) of the argmax launch and [sel_lo, sel_lo +
 // sel_cnt) of the claim and decrement launches belong to this instance;
 // ranges ascend with the instance index.
@@ -178,10 +183,15 @@ struct SelectDesc {
     uint32_t* gains;
     Chunk* chunks;
     uint32_t* chunk_n;
-    uint32_t n, k, nseg;
+    uint64_t chunk_cap;
+    unsigned long long* cov_entries;  // k zeroed: members of the sets step t covers
+    uint32_t n, k, nseg;              // nseg <= kMaxSegments
+    uint32_t n_sets;
     uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
-    uint32_t pad;
 };
+constexpr uint32_t kMaxSegments = 64;
+// Covered sets of at most this many members are decremented one per lane.
+constexpr uint32_t kSmallSet = 16;
 uint32_t argmax_blocks(uint32_t n);
 uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch);
 // Seed step t (argmax, claim, decrement) of every instance with t < k.

@@ -14,11 +14,16 @@
 //  * claim: the chosen vertex's inverted-index lists (one per index segment)
 //    name exactly the sets that contain it ("if v in R" of Algorithm 2
 //    without scanning all sets); each one not yet covered is claimed with an
-//    atomic bit and cut into chunks of at most 64 members on a work queue.
-//  * decrement: the instance's waves take chunks from its queue and
-//    decrement the counts of the members (except the chosen vertex), so a
-//    few very large covered sets are spread over many waves. When the queue
-//    is long, decrements are summed per workgroup in LDS first.
+//    atomic bit and queued: a small set as one entry, a larger one cut into
+//    pieces of at most 64 members.
+//  * decrement: the instance's threads take small sets one per lane and
+//    pieces one per wave, and decrement the counts of the members (except
+//    the chosen vertex), so both a flood of tiny sets and a few very large
+//    ones spread over the GPU. When the queue is long, decrements are summed
+//    per workgroup in LDS first. When the covered sets hold more than an
+//    eighth of the pool, the step instead recounts every remaining count
+//    from the uncovered sets (the paper's adaptive counter update, Section
+//    IV-C), a gather without atomics.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -110,37 +115,138 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
         d.gains[t] = (uint32_t)(m >> 32);
         d.cw[v] = kSelected;
     }
-    uint32_t* chunk_n = d.chunk_n + t;
+    uint32_t* small_n = d.chunk_n + 2ull * t;
+    uint32_t* big_n = small_n + 1;
     const uint64_t step = (uint64_t)d.sel_cnt * kClaimBS;
     const uint32_t lane = threadIdx.x % kWave;
-    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
-        const uint64_t lb = io[v], len = io[v + 1] - lb;
-        for (uint64_t base = (uint64_t)blk * kClaimBS; base < len; base += step) {
+    const uint64_t lane_mask = (1ull << lane) - 1ull;
+    // v's list bounds in every segment, loaded at once (lane s: segment s)
+    uint64_t my_lb = 0, my_len = 0;
+    if (lane < d.nseg) {
+        const uint64_t* io = d.inv_offs + (uint64_t)lane * ((uint64_t)d.n + 1);
+        my_lb = io[v];
+        my_len = io[v + 1] - my_lb;
+    }
+    // the lists of all segments as one range [0, total): no per-segment
+    // round trips
+    const uint64_t my_end = wave_incl_scan64(my_len);
+    const uint64_t total = __shfl(my_end, kWave - 1, kWave);
+    uint64_t cov = 0;  // members of the sets this thread claimed
+    {
+        for (uint64_t base = (uint64_t)blk * kClaimBS; base < total; base += step) {
             const uint64_t i = base + threadIdx.x;
-            uint32_t nch = 0;
+            bool small = false;
+            uint32_t nbig = 0;
             uint64_t a = 0, sz = 0;
-            if (i < len) {
-                const uint32_t j = d.inv_set[lb + i];
+            // segment of position i: the first whose running end exceeds i
+            uint64_t pos = 0;
+            for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+                const uint64_t e = __shfl(my_end, seg, kWave);
+                const uint64_t l = __shfl(my_len, seg, kWave);
+                const uint64_t b = __shfl(my_lb, seg, kWave);
+                if (i < e && i >= e - l) pos = b + (i - (e - l));
+            }
+            if (i < total) {
+                const uint32_t j = d.inv_set[pos];
                 const uint32_t bit = 1u << (j & 31);
                 const uint32_t old = atomicOr(&d.covered[j >> 5], bit);
                 if (!(old & bit)) {
                     a = d.set_off[j];
                     sz = d.set_off[j + 1] - a;
-                    nch = (uint32_t)((sz + kWave - 1) / kWave);
+                    cov += sz;
+                    // a set of one member is {v} itself: nothing to decrement
+                    if (sz > 1 && sz <= kSmallSet) small = true;
+                    else if (sz > kSmallSet) nbig = (uint32_t)((sz + kWave - 1) / kWave);
                 }
             }
-            // one queue reservation per wave
-            const uint32_t incl = wave_incl_scan(nch);
-            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-            uint32_t wbase = 0;
-            if (lane == kWave - 1 && tot) wbase = atomicAdd(chunk_n, tot);
-            wbase = __shfl(wbase, kWave - 1, kWave);
-            const uint32_t pos = wbase + incl - nch;
-            for (uint32_t c = 0; c < nch; ++c) {
-                const uint64_t o = (uint64_t)c * kWave;
-                d.chunks[pos + c] = Chunk{a + o, (uint32_t)(sz - o < kWave ? sz - o : kWave), 0u};
+            // one reservation per wave and queue
+            const uint64_t smask = __ballot(small);
+            if (smask) {
+                uint32_t sbase = 0;
+                if (lane == 0) sbase = atomicAdd(small_n, (uint32_t)__popcll(smask));
+                sbase = __shfl(sbase, 0, kWave);
+                if (small) d.chunks[sbase + (uint32_t)__popcll(smask & lane_mask)] =
+                    Chunk{a, (uint32_t)sz, 0u};
             }
+            const uint32_t incl = wave_incl_scan(nbig);
+            const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+            if (tot) {
+                uint32_t wbase = 0;
+                if (lane == kWave - 1) wbase = atomicAdd(big_n, tot);
+                wbase = __shfl(wbase, kWave - 1, kWave);
+                const uint32_t pos = wbase + incl - nbig;
+                for (uint32_t c = 0; c < nbig; ++c) {
+                    const uint64_t o = (uint64_t)c * kWave;
+                    d.chunks[d.chunk_cap - 1 - (pos + c)] =
+                        Chunk{a + o, (uint32_t)(sz - o < kWave ? sz - o : kWave), 0u};
+                }
+            }
+        }
+    }
+    cov = wave_sum64(cov);
+    if (lane == 0 && cov) atomicAdd(&d.cov_entries[t], (unsigned long long)cov);
+}
+
+// Uncovered sets containing u, counted from u's inverted-index lists (all
+// segments) by the calling lane alone.
+__device__ __forceinline__ uint32_t recount_lane(const SelectDesc& d, uint32_t u) {
+    uint32_t c = 0;
+    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+        const uint64_t lo = io[u], hi = io[u + 1];
+        for (uint64_t p = lo; p < hi; ++p) {
+            const uint32_t j = d.inv_set[p];
+            c += ((d.covered[j >> 5] >> (j & 31)) & 1u) ^ 1u;
+        }
+    }
+    return c;
+}
+
+// The same count by the whole wave (u uniform across it).
+__device__ __forceinline__ uint32_t recount_wave(const SelectDesc& d, uint32_t u, uint32_t lane) {
+    uint32_t c = 0;
+    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+        const uint64_t lo = io[u], hi = io[u + 1];
+        for (uint64_t p = lo + lane; p < hi; p += kWave) {
+            const uint32_t j = d.inv_set[p];
+            c += ((d.covered[j >> 5] >> (j & 31)) & 1u) ^ 1u;
+        }
+    }
+    return (uint32_t)wave_sum64(c);
+}
+
+// Lists up to this long are recounted by one lane, longer ones by a wave.
+constexpr uint32_t kLaneList = 128;
+
+// The adaptive counter update: when a seed covers sets that hold a large
+// part of the pool, rebuilding each remaining count from the uncovered sets
+// (a gather over the index, no atomics) is cheaper than decrementing once
+// per member of every covered set. Selected vertices keep their sentinel and
+// zero counts stay zero, so only the other vertices are visited.
+__device__ void recount_all(const SelectDesc& d, uint32_t blk) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wpb = kDecBS / kWave;
+    const uint32_t wid = blk * wpb + threadIdx.x / kWave;
+    const uint32_t nw = d.sel_cnt * wpb;
+    for (uint64_t base = (uint64_t)wid * kWave; base < d.n; base += (uint64_t)nw * kWave) {
+        const uint32_t u = (uint32_t)base + lane;
+        const uint32_t c = u < d.n ? d.cw[u] : 0u;
+        const bool act = c != 0u && c != kSelected;
+        uint64_t len = 0;
+        if (act) {
+            for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+                const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+                len += io[u + 1] - io[u];
+            }
+            if (len <= kLaneList) d.cw[u] = recount_lane(d, u);
+        }
+        uint64_t heavy = __ballot(act && len > kLaneList);
+        while (heavy) {
+            const uint32_t l = (uint32_t)__ffsll((unsigned long long)heavy) - 1u;
+            heavy &= heavy - 1ull;
+            const uint32_t c2 = recount_wave(d, (uint32_t)base + l, lane);
+            if (lane == 0) d.cw[(uint32_t)base + l] = c2;
         }
     }
 }
@@ -154,6 +260,25 @@ constexpr uint32_t kAggBits = 12;
 constexpr uint32_t kAggSize = 1u << kAggBits;
 constexpr uint32_t kAggProbes = 8;
 
+__device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, uint32_t* h_cnt,
+                                        uint32_t* cw) {
+    if (agg) {
+        uint32_t slot = (u * 0x9E3779B1u) >> (32 - kAggBits);
+        for (uint32_t p = 0; p < kAggProbes; ++p) {
+            uint32_t cur = h_key[slot];
+            if (cur == kEmpty) cur = atomicCAS(&h_key[slot], kEmpty, u);
+            if (cur == kEmpty || cur == u) {
+                atomicAdd(&h_cnt[slot], 1u);
+                return;
+            }
+            slot = (slot + 1) & (kAggSize - 1);
+        }
+    }
+    atomicSub(&cw[u], 1u);
+}
+
+// Small covered sets are taken one per lane (a flood of tiny sets keeps every
+// lane busy), the 64-member pieces of larger ones one per wave.
 __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* descs, uint32_t nq,
                                                            uint32_t t) {
     __shared__ uint32_t h_key[kAggSize], h_cnt[kAggSize];
@@ -162,15 +287,22 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     const SelectDesc& d = descs[q];
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
-    const uint32_t nchunks = d.chunk_n[t];
+    const uint64_t pool = d.set_off[d.n_sets];
+    if (d.cov_entries[t] * 8ull > pool) {
+        recount_all(d, blk);
+        return;
+    }
+    const uint32_t ns = d.chunk_n[2ull * t], nb = d.chunk_n[2ull * t + 1];
     const uint32_t wpb = kDecBS / kWave;
-    if (blk * wpb >= nchunks) return;
+    if (blk * kDecBS >= ns && blk * wpb >= nb) return;
     uint32_t* cw = d.cw;
     const uint32_t v = d.seeds[t];
     const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t wid = blk * wpb + threadIdx.x / kWave;
+    const uint32_t threads = d.sel_cnt * kDecBS;
     const uint32_t nw = d.sel_cnt * wpb;
-    const bool agg = nchunks >= 4 * nw;
+    const uint32_t wid = blk * wpb + threadIdx.x / kWave;
+    // aggregate when a workgroup will see many decrements
+    const bool agg = (uint64_t)ns * 4 + (uint64_t)nb * kWave >= 16ull * threads;
     if (agg) {
         for (uint32_t x = threadIdx.x; x < kAggSize; x += kDecBS) {
             h_key[x] = kEmpty;
@@ -178,27 +310,18 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
         }
         __syncthreads();
     }
-    for (uint32_t c = wid; c < nchunks; c += nw) {
-        const Chunk ch = d.chunks[c];
+    for (uint32_t e = blk * kDecBS + threadIdx.x; e < ns; e += threads) {
+        const Chunk ch = d.chunks[e];
+        for (uint32_t x = 0; x < ch.len; ++x) {
+            const uint32_t u = d.set_vtx[ch.off + x];
+            if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
+        }
+    }
+    for (uint32_t c = wid; c < nb; c += nw) {
+        const Chunk ch = d.chunks[d.chunk_cap - 1 - c];
         if (lane < ch.len) {
             const uint32_t u = d.set_vtx[ch.off + lane];
-            if (u != v) {
-                bool done = false;
-                if (agg) {
-                    uint32_t slot = (u * 0x9E3779B1u) >> (32 - kAggBits);
-                    for (uint32_t p = 0; p < kAggProbes; ++p) {
-                        uint32_t cur = h_key[slot];
-                        if (cur == kEmpty) cur = atomicCAS(&h_key[slot], kEmpty, u);
-                        if (cur == kEmpty || cur == u) {
-                            atomicAdd(&h_cnt[slot], 1u);
-                            done = true;
-                            break;
-                        }
-                        slot = (slot + 1) & (kAggSize - 1);
-                    }
-                }
-                if (!done) atomicSub(&cw[u], 1u);
-            }
+            if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
         }
     }
     if (agg) {

@@ -41,7 +41,6 @@ uint32_t bitlen(uint32_t x) {
     return b;
 }
 
-constexpr size_t kMaxCachedWorkspaces = 8;
 
 }  // namespace
 
@@ -68,6 +67,8 @@ imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* la
 }
 
 namespace {
+constexpr size_t kMaxCachedWorkspacesPerGraph = 8;
+}  // namespace
 
 struct Query {
     imm_graph* g = nullptr;
@@ -82,8 +83,18 @@ struct Query {
     imm_status status = IMM_OK;
     std::string err;
     double t0 = 0, ms_select = 0;
+    uint64_t bytes = 0;  // device bytes of the workspace when finished
     SelectDesc desc{};
+    // AsyncRunner: the event that marks the end of the queued work, and
+    // whether that work is a sampling round (0) or a selection (1)
+    hipEvent_t ev = nullptr;
+    int phase = 0;
+    ~Query() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
 };
+
+namespace {
 
 imm_status acquire_workspace(Query& q, uint32_t big_cap) {
     {
@@ -122,11 +133,12 @@ imm_status acquire_workspace(Query& q, uint32_t big_cap) {
 void release_workspace(Query& q) {
     if (!q.w) return;
     std::lock_guard<std::mutex> lk(q.g->ws_mu);
-    if (q.g->ws_cache.size() < kMaxCachedWorkspaces) q.g->ws_cache.push_back(std::move(q.w));
+    if (q.g->ws_cache.size() < kMaxCachedWorkspacesPerGraph)
+        q.g->ws_cache.push_back(std::move(q.w));
     q.w.reset();
 }
 
-imm_status start(Query& q, uint32_t big_cap) {
+imm_status start_query(Query& q, uint32_t big_cap) {
     q.t0 = now_ms();
     if (q.p.k == 0 || q.p.k > q.g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
     if (!(q.p.epsilon > 0.0) || !(q.p.ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
@@ -195,158 +207,294 @@ imm_status end_iteration(Query& q) {
     r.stats.ms_total = t1 - q.t0;
     r.stats.rounds = r.rounds;
     r.stats.team = q.g->model == IMM_IC ? q.g->ic_team : 0;
+    r.stats.device_bytes = w.arena.used;
     r.stats.big_block = q.g->model == IMM_IC ? q.g->ic_big_block : 0;
     if (q.p.flags & IMM_KEEP_POOL) {
         IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
         r.has_pool = true;
     }
     q.done = true;
+    q.bytes = w.arena.used;
     return IMM_OK;
 }
 
 }  // namespace
 
+// ------------------------------------------------------------ BatchRunner --
+
+BatchRunner::BatchRunner(hipStream_t main) : main_(main) {}
+
+BatchRunner::~BatchRunner() {
+    for (auto* q : active_) delete q;
+    if (descs_h_) (void)hipHostFree(descs_h_);
+    if (descs_d_) (void)hipFree(descs_d_);
+    if (ev_a_) (void)hipEventDestroy(ev_a_);
+    if (ev_b_) (void)hipEventDestroy(ev_b_);
+}
+
+Query* BatchRunner::start(imm_graph* g, const imm_params& p, hipStream_t st, uint32_t big_cap) {
+    Query* q = new Query();
+    q->g = g;
+    q->p = p;
+    q->st = st;
+    const imm_status s = start_query(*q, big_cap);
+    if (s != IMM_OK) {
+        q->status = s;
+        q->err = last_error();
+        q->done = true;
+        q->w.reset();
+        return q;
+    }
+    active_.push_back(q);
+    return q;
+}
+
+void BatchRunner::finish_err(Query* q, imm_status s) {
+    q->status = s;
+    q->err = last_error();
+    q->done = true;
+    q->w.reset();  // a failed workspace is not reused
+}
+
+void BatchRunner::cancel(Query* q) {
+    if (q->done) return;
+    q->status = IMM_ECANCELLED;
+    q->err = "cancelled";
+    q->done = true;
+    release_workspace(*q);
+}
+
+bool BatchRunner::step() {
+    {
+        // queries cancelled since the last step leave first
+        std::vector<Query*> keep;
+        for (auto* q : active_) {
+            if (q->done) finished_.push_back(q);
+            else keep.push_back(q);
+        }
+        active_.swap(keep);
+    }
+    if (active_.empty()) return false;
+    bool timing = false;
+    for (auto* q : active_) timing |= (q->p.flags & IMM_TIMING) != 0;
+    if (timing && !ev_a_) {
+        (void)hipEventCreate(&ev_a_);
+        (void)hipEventCreate(&ev_b_);
+    }
+    // sampling, each query on its stream
+    std::vector<Query*> live;
+    for (auto* q : active_) {
+        const imm_status s = begin_iteration(*q);
+        if (s != IMM_OK) finish_err(q, s);
+        else live.push_back(q);
+    }
+    // one wait per stream, then retries, compaction, index, selection state
+    std::vector<hipStream_t> synced;
+    for (auto* q : live) {
+        if (std::find(synced.begin(), synced.end(), q->st) == synced.end()) {
+            (void)hipStreamSynchronize(q->st);
+            synced.push_back(q->st);
+        }
+    }
+    std::vector<Query*> ready;
+    for (auto* q : live) {
+        imm_status s = ws_extend_finish(*q->w, q->g, q->p.seed);
+        if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
+        if (s != IMM_OK) finish_err(q, s);
+        else ready.push_back(q);
+    }
+    // the selections of all queries together, on the main stream
+    if (!ready.empty()) {
+        std::vector<SelectDesc> descs;
+        uint32_t arg_total = 0, sel_total = 0, kmax = 0;
+        for (auto* q : ready) {
+            SelectDesc d = q->desc;
+            d.arg_lo = arg_total;
+            d.arg_cnt = argmax_blocks(d.n);
+            d.sel_lo = sel_total;
+            d.sel_cnt = select_blocks(q->g->device, q->w->n_sets, (uint32_t)ready.size());
+            arg_total += d.arg_cnt;
+            sel_total += d.sel_cnt;
+            kmax = std::max(kmax, d.k);
+            descs.push_back(d);
+        }
+        bool ok = true;
+        if (cap_descs_ < descs.size()) {
+            if (descs_h_) (void)hipHostFree(descs_h_);
+            if (descs_d_) (void)hipFree(descs_d_);
+            descs_h_ = nullptr;
+            descs_d_ = nullptr;
+            cap_descs_ = descs.size() * 2;
+            ok = hipHostMalloc((void**)&descs_h_, cap_descs_ * sizeof(SelectDesc),
+                               hipHostMallocDefault) == hipSuccess &&
+                 hipMalloc((void**)&descs_d_, cap_descs_ * sizeof(SelectDesc)) == hipSuccess;
+            if (!ok) cap_descs_ = 0;
+        }
+        std::vector<hipEvent_t> joins;
+        if (ok) {
+            std::memcpy(descs_h_, descs.data(), descs.size() * sizeof(SelectDesc));
+            for (auto* q : ready) {
+                if (q->st == main_) continue;
+                hipEvent_t e = nullptr;
+                (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                (void)hipEventRecord(e, q->st);
+                (void)hipStreamWaitEvent(main_, e, 0);
+                joins.push_back(e);
+            }
+            ok = hipMemcpyAsync(descs_d_, descs_h_, descs.size() * sizeof(SelectDesc),
+                                hipMemcpyHostToDevice, main_) == hipSuccess;
+            if (timing) (void)hipEventRecord(ev_a_, main_);
+            for (uint32_t t = 0; ok && t < kmax; ++t)
+                ok = launch_select_step(descs_d_, (uint32_t)descs.size(), t, arg_total, sel_total,
+                                        main_) == hipSuccess;
+            if (timing) (void)hipEventRecord(ev_b_, main_);
+            for (auto* q : ready)
+                if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main_) == IMM_OK;
+            if (ok) ok = hipStreamSynchronize(main_) == hipSuccess;
+            for (auto e : joins) (void)hipEventDestroy(e);
+            if (ok && timing) {
+                float msf = 0.f;
+                (void)hipEventElapsedTime(&msf, ev_a_, ev_b_);
+                for (auto* q : ready) q->ms_select += msf;
+            }
+        }
+        for (auto* q : ready) {
+            const imm_status s = ok ? end_iteration(*q)
+                                    : fail(IMM_EDEVICE, "batched selection failed");
+            if (s != IMM_OK) finish_err(q, s);
+        }
+    }
+    std::vector<Query*> next;
+    for (auto* q : active_) {
+        if (q->done) finished_.push_back(q);
+        else next.push_back(q);
+    }
+    active_.swap(next);
+    return true;
+}
+
+std::vector<Query*> BatchRunner::drain() {
+    std::vector<Query*> out;
+    out.swap(finished_);
+    return out;
+}
+
+uint64_t BatchRunner::bytes(const Query* q) { return q->bytes; }
+bool BatchRunner::done(const Query* q) { return q->done; }
+
+imm_result* BatchRunner::take(Query* q, imm_status* status, std::string* err) {
+    *status = q->status;
+    if (err) *err = q->err;
+    imm_result* r = nullptr;
+    if (q->status == IMM_OK && q->r) {
+        r = q->r.release();
+        release_workspace(*q);
+    }
+    q->w.reset();
+    delete q;
+    return r;
+}
+
+// ------------------------------------------------------------ AsyncRunner --
+
+AsyncRunner::~AsyncRunner() {
+    for (auto* q : active_) delete q;
+}
+
+void AsyncRunner::finish_err(Query* q, imm_status s) {
+    q->status = s;
+    q->err = last_error();
+    q->done = true;
+    if (q->w) (void)hipStreamSynchronize(q->w->st);
+    q->w.reset();
+}
+
+Query* AsyncRunner::start(imm_graph* g, const imm_params& p, hipStream_t st, uint32_t big_cap) {
+    Query* q = new Query();
+    q->g = g;
+    q->p = p;
+    q->st = st;
+    imm_status s = start_query(*q, big_cap);
+    if (s == IMM_OK && hipEventCreateWithFlags(&q->ev, hipEventDisableTiming) != hipSuccess)
+        s = fail(IMM_EDEVICE, "run: event creation failed");
+    if (s == IMM_OK) s = begin_iteration(*q);
+    if (s == IMM_OK && hipEventRecord(q->ev, q->st) != hipSuccess)
+        s = fail(IMM_EDEVICE, "run: event record failed");
+    if (s != IMM_OK) {
+        finish_err(q, s);
+        return q;
+    }
+    q->phase = 0;
+    active_.push_back(q);
+    return q;
+}
+
+void AsyncRunner::cancel(Query* q) {
+    if (q->done) return;
+    if (q->w) (void)hipStreamSynchronize(q->w->st);
+    q->status = IMM_ECANCELLED;
+    q->err = "cancelled";
+    q->done = true;
+    release_workspace(*q);
+}
+
+bool AsyncRunner::poll() {
+    bool advanced = false;
+    for (auto* q : active_) {
+        if (q->done) continue;
+        const hipError_t e = hipEventQuery(q->ev);
+        if (e == hipErrorNotReady) continue;
+        advanced = true;
+        imm_status s = e == hipSuccess ? IMM_OK : fail(IMM_EDEVICE, "run: device work failed");
+        if (s == IMM_OK && q->phase == 0) {
+            // sampling round done: finish it, launch the selection
+            s = ws_extend_finish(*q->w, q->g, q->p.seed);
+            if (s == IMM_OK) s = ws_select_launch(*q->w, q->p.k);
+            q->phase = 1;
+        } else if (s == IMM_OK) {
+            // selection done: theta decision, then the next round (if any)
+            s = end_iteration(*q);
+            if (s == IMM_OK && !q->done) {
+                s = begin_iteration(*q);
+                q->phase = 0;
+            }
+        }
+        if (s == IMM_OK && !q->done && hipEventRecord(q->ev, q->st) != hipSuccess)
+            s = fail(IMM_EDEVICE, "run: event record failed");
+        if (s != IMM_OK) finish_err(q, s);
+    }
+    std::vector<Query*> keep;
+    for (auto* q : active_) {
+        if (q->done) finished_.push_back(q);
+        else keep.push_back(q);
+    }
+    active_.swap(keep);
+    return advanced;
+}
+
+std::vector<Query*> AsyncRunner::drain() {
+    std::vector<Query*> out;
+    out.swap(finished_);
+    return out;
+}
+
 void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t count,
                  hipStream_t main, const hipStream_t* streams, imm_result** out,
                  imm_status* status, std::string* errors) {
-    std::vector<Query> qs(count);
-    std::vector<Query*> active;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, graphs[0]->device);
     const uint32_t big_cap = count > 1 ? std::max<uint32_t>(64u, (uint32_t)cus * 8u / count) : 0u;
-    auto finish_err = [&](Query& q, imm_status s) {
-        q.status = s;
-        q.err = last_error();
-        q.done = true;
-        q.w.reset();  // a failed workspace is not reused
-    };
-    for (uint32_t j = 0; j < count; ++j) {
-        Query& q = qs[j];
-        q.g = graphs[j];
-        q.p = params[j];
-        q.st = streams[j];
-        const imm_status s = start(q, big_cap);
-        if (s != IMM_OK) finish_err(q, s);
-        else active.push_back(&q);
+    // lock-step: one set of selection launches per seed step serves every
+    // query (measured faster than independent pipelines for many small
+    // queries; the server, whose queries arrive over time, uses those)
+    std::vector<Query*> qs(count);
+    BatchRunner br(main);
+    for (uint32_t j = 0; j < count; ++j) qs[j] = br.start(graphs[j], params[j], streams[j], big_cap);
+    while (br.step()) {
     }
-
-    std::vector<SelectDesc> descs;
-    SelectDesc* descs_h = nullptr;
-    SelectDesc* descs_d = nullptr;
-    size_t cap_descs = 0;
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
-    std::vector<hipEvent_t> joins;
-    bool timing = false;
-    for (auto* q : active) timing |= (q->p.flags & IMM_TIMING) != 0;
-    if (timing) {
-        (void)hipEventCreate(&ev_a);
-        (void)hipEventCreate(&ev_b);
-    }
-
-    while (!active.empty()) {
-        // sampling, each query on its stream
-        std::vector<Query*> live;
-        for (auto* q : active) {
-            const imm_status s = begin_iteration(*q);
-            if (s != IMM_OK) finish_err(*q, s);
-            else live.push_back(q);
-        }
-        // one wait per stream, then retries, compaction, index, selection state
-        std::vector<hipStream_t> synced;
-        std::vector<Query*> ready;
-        for (auto* q : live) {
-            if (std::find(synced.begin(), synced.end(), q->st) == synced.end()) {
-                (void)hipStreamSynchronize(q->st);
-                synced.push_back(q->st);
-            }
-        }
-        for (auto* q : live) {
-            imm_status s = ws_extend_finish(*q->w, q->g, q->p.seed);
-            if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
-            if (s != IMM_OK) finish_err(*q, s);
-            else ready.push_back(q);
-        }
-        // the selections of all queries together, on the main stream
-        if (!ready.empty()) {
-            descs.clear();
-            uint32_t arg_total = 0, sel_total = 0, kmax = 0;
-            for (auto* q : ready) {
-                SelectDesc d = q->desc;
-                d.arg_lo = arg_total;
-                d.arg_cnt = argmax_blocks(d.n);
-                d.sel_lo = sel_total;
-                d.sel_cnt = select_blocks(q->g->device, q->w->n_sets, (uint32_t)ready.size());
-                arg_total += d.arg_cnt;
-                sel_total += d.sel_cnt;
-                kmax = std::max(kmax, d.k);
-                descs.push_back(d);
-            }
-            bool ok = true;
-            if (cap_descs < descs.size()) {
-                if (descs_h) (void)hipHostFree(descs_h);
-                if (descs_d) (void)hipFree(descs_d);
-                descs_h = nullptr;
-                descs_d = nullptr;
-                cap_descs = descs.size() * 2;
-                ok = hipHostMalloc((void**)&descs_h, cap_descs * sizeof(SelectDesc),
-                                   hipHostMallocDefault) == hipSuccess &&
-                     hipMalloc((void**)&descs_d, cap_descs * sizeof(SelectDesc)) == hipSuccess;
-                if (!ok) cap_descs = 0;
-            }
-            if (ok) {
-                std::memcpy(descs_h, descs.data(), descs.size() * sizeof(SelectDesc));
-                for (auto* q : ready) {
-                    if (q->st == main) continue;
-                    hipEvent_t e = nullptr;
-                    (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
-                    (void)hipEventRecord(e, q->st);
-                    (void)hipStreamWaitEvent(main, e, 0);
-                    joins.push_back(e);
-                }
-                ok = hipMemcpyAsync(descs_d, descs_h, descs.size() * sizeof(SelectDesc),
-                                    hipMemcpyHostToDevice, main) == hipSuccess;
-                if (timing) (void)hipEventRecord(ev_a, main);
-                for (uint32_t t = 0; ok && t < kmax; ++t)
-                    ok = launch_select_step(descs_d, (uint32_t)descs.size(), t, arg_total,
-                                            sel_total, main) == hipSuccess;
-                if (timing) (void)hipEventRecord(ev_b, main);
-                for (auto* q : ready)
-                    if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main) == IMM_OK;
-                if (ok) ok = hipStreamSynchronize(main) == hipSuccess;
-                for (auto e : joins) (void)hipEventDestroy(e);
-                joins.clear();
-                if (ok && timing) {
-                    float msf = 0.f;
-                    (void)hipEventElapsedTime(&msf, ev_a, ev_b);
-                    for (auto* q : ready) q->ms_select += msf;
-                }
-            }
-            for (auto* q : ready) {
-                const imm_status s = ok ? end_iteration(*q)
-                                        : fail(IMM_EDEVICE, "batched selection failed");
-                if (s != IMM_OK) finish_err(*q, s);
-            }
-        }
-        std::vector<Query*> next;
-        for (auto* q : active)
-            if (!q->done) next.push_back(q);
-        active.swap(next);
-    }
-    if (descs_h) (void)hipHostFree(descs_h);
-    if (descs_d) (void)hipFree(descs_d);
-    if (ev_a) (void)hipEventDestroy(ev_a);
-    if (ev_b) (void)hipEventDestroy(ev_b);
-    for (uint32_t j = 0; j < count; ++j) {
-        Query& q = qs[j];
-        status[j] = q.status;
-        if (errors) errors[j] = q.err;
-        if (q.status == IMM_OK && q.r) {
-            out[j] = q.r.release();
-            release_workspace(q);
-        } else {
-            out[j] = nullptr;
-        }
-    }
+    (void)br.drain();
+    for (uint32_t j = 0; j < count; ++j)
+        out[j] = BatchRunner::take(qs[j], &status[j], errors ? &errors[j] : nullptr);
 }
 
 }  // namespace imm

@@ -457,27 +457,31 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
             w.arena.release(w.gains_d);
             w.arena.release(w.slots);
             w.arena.release(w.chunk_n);
+            w.arena.release(w.cov_entries);
             (void)hipHostFree(w.gains_h);
             w.gains_h = nullptr;
         }
         IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
         IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
         IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * kArgSlots * 8, "argmax slots"));
-        IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 4, "chunk counts"));
+        IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 8, "chunk counts"));
+        IMM_TRY(w.arena.alloc((void**)&w.cov_entries, (uint64_t)k * 8, "covered totals"));
         HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
         w.cap_k = k;
     }
-    // a seed's chunks: at most one per started 64 members of every set
+    // a seed's queue entries: at most one per started 64 members of every set
     IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.p_ub / 64 + 1, 0, st,
                  "chunk queue"));
     HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
     HIP_TRY(hipMemsetAsync(w.slots, 0, (uint64_t)k * kArgSlots * 8, st));
-    HIP_TRY(hipMemsetAsync(w.chunk_n, 0, (uint64_t)k * 4, st));
+    HIP_TRY(hipMemsetAsync(w.chunk_n, 0, (uint64_t)k * 8, st));
+    HIP_TRY(hipMemsetAsync(w.cov_entries, 0, (uint64_t)k * 8, st));
+    if (w.nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
     *d = SelectDesc{w.counts_work, w.inv_offs, w.inv_set, w.set_off, w.set_vtx, w.covered,
-                    w.slots, w.seeds_d, w.gains_d, w.chunks, w.chunk_n, w.n, k, w.nseg,
-                    0, 0, 0, 0, 0};
+                    w.slots, w.seeds_d, w.gains_d, w.chunks, w.chunk_n, w.cap_chunks,
+                    w.cov_entries, w.n, k, w.nseg, (uint32_t)w.n_sets, 0, 0, 0, 0};
     return IMM_OK;
 }
 
@@ -497,9 +501,9 @@ imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint
     return IMM_OK;
 }
 
-imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
+imm_status ws_select_launch(Workspace& w, uint32_t k) {
     hipStream_t st = w.st;
-    SelectDesc d;
+    SelectDesc& d = w.desc_h;
     IMM_TRY(ws_select_prepare(w, k, &d));
     d.arg_cnt = argmax_blocks(w.n);
     d.sel_cnt = select_blocks(w.device, w.n_sets, 1);
@@ -508,8 +512,12 @@ imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* c
     for (uint32_t t = 0; t < k; ++t)
         HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, st));
     w.timer.close(ts, st);
-    IMM_TRY(ws_select_copy_out(w, k, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    return ws_select_copy_out(w, k, st);
+}
+
+imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
+    IMM_TRY(ws_select_launch(w, k));
+    HIP_TRY(hipStreamSynchronize(w.st));
     return ws_select_finish(w, k, sets_before, covered);
 }
 

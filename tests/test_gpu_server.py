@@ -1,0 +1,109 @@
+"""The query server (imm_server_*): continuous batching of IMM queries on one
+GPU. Queries submitted while others run join at the next iteration boundary;
+every result must equal the CPU oracle's and imm_run's for the same
+arguments, bit for bit, whatever else ran beside it."""
+
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import oracle_threads
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(r, o):
+    assert r.targets == o["targets"] and r.round_cov == o["round_cov"]
+    assert (r.theta, r.rounds, r.covered, r.lb) == (o["theta"], o["rounds"], o["covered"], o["lb"])
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    np.testing.assert_array_equal(r.gains, o["gains"])
+
+
+@pytest.fixture(scope="module")
+def graphs(imm, stream):
+    names = ["rmat12_wc", "rmat12_lt", "cl_lt_xs", "rmat12_p10"]
+    hg = {nm: synth.make_graph(nm) for nm in names}
+    dg = {nm: imm.graph_from(g, stream=stream) for nm, g in hg.items()}
+    return hg, dg
+
+
+def test_server_mixed_stream_equals_alone(imm, orc, stream, graphs):
+    hg, dg = graphs
+    rng = np.random.default_rng(1)
+    qs = []
+    for i in range(16):
+        nm = list(hg)[i % len(hg)]
+        qs.append((nm, dict(k=int(rng.choice([1, 5, 10, 25])), epsilon=float(rng.choice([0.5, 0.3])),
+                            seed=100 + i)))
+    srv = imm.Server(budget_bytes=64 << 30, max_slots=6)
+    tickets = []
+    # a first wave, then the rest while the first still runs
+    for nm, q in qs[:6]:
+        tickets.append(srv.submit(dg[nm], **q))
+    time.sleep(0.002)
+    for nm, q in qs[6:]:
+        tickets.append(srv.submit(dg[nm], **q))
+        time.sleep(0.001)
+    say(f"submitted {len(tickets)}; info {srv.info()}")
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    for (nm, q), r in zip(qs, res):
+        say(f"  check {nm} {q}")
+        o = orc.imm(hg[nm], q["k"], q["epsilon"], 1.0, q["seed"], threads=oracle_threads())
+        _same(r, o)
+        one = imm.imm_run(dg[nm], q["k"], q["epsilon"], 1.0, q["seed"], stream=stream)
+        np.testing.assert_array_equal(one.seeds, r.seeds)
+        assert r.stats["ms_total"] >= r.stats["ms_queue"] >= 0.0
+
+
+def test_server_one_slot_queues_in_order(imm, orc, stream, graphs):
+    hg, dg = graphs
+    srv = imm.Server(budget_bytes=64 << 30, max_slots=1)
+    tickets = [srv.submit(dg["rmat12_wc"], k=10, epsilon=0.5, seed=s) for s in range(5)]
+    assert srv.poll(tickets[-1], wait=False) is None or True
+    res = [srv.poll(t) for t in tickets]
+    srv.close()
+    for s, r in zip(range(5), res):
+        _same(r, orc.imm(hg["rmat12_wc"], 10, 0.5, 1.0, s, threads=oracle_threads()))
+    # with one slot, later submissions waited for the earlier ones
+    assert res[-1].stats["ms_queue"] >= res[0].stats["ms_queue"]
+
+
+def test_server_cancel_and_errors(imm, stream, graphs):
+    hg, dg = graphs
+    srv = imm.Server(budget_bytes=64 << 30, max_slots=1)
+    a = srv.submit(dg["rmat12_p10"], k=10, epsilon=0.3, seed=1)
+    b = srv.submit(dg["rmat12_wc"], k=10, epsilon=0.5, seed=2)
+    srv.cancel(b)
+    with pytest.raises(imm.ImmError) as e:
+        srv.poll(b)
+    assert e.value.status == imm.IMM_ECANCELLED
+    ra = srv.poll(a)
+    one = imm.imm_run(dg["rmat12_p10"], 10, 0.3, 1.0, 1, stream=stream)
+    np.testing.assert_array_equal(ra.seeds, one.seeds)
+    with pytest.raises(imm.ImmError) as e:
+        srv.poll(12345)
+    assert e.value.status == imm.IMM_EINVAL
+    with pytest.raises(imm.ImmError) as e:
+        srv.submit(dg["rmat12_wc"], k=0, epsilon=0.5)
+    assert e.value.status == imm.IMM_EINVAL
+    srv.close()
+    # a budget below any query's estimate rejects at submission
+    tiny = imm.Server(budget_bytes=1 << 20, max_slots=2)
+    with pytest.raises(imm.ImmError) as e:
+        tiny.submit(dg["rmat12_wc"], k=10, epsilon=0.5)
+    assert e.value.status == imm.IMM_ENOMEM
+    tiny.close()
+
+
+def test_server_destroy_with_work_outstanding(imm, stream, graphs):
+    hg, dg = graphs
+    srv = imm.Server(budget_bytes=64 << 30, max_slots=2)
+    for s in range(6):
+        srv.submit(dg["rmat12_lt"], k=10, epsilon=0.5, seed=s)
+    srv.close()  # cancels what is queued, waits for what runs
+    r = imm.imm_run(dg["rmat12_lt"], 10, 0.5, 1.0, 0, stream=stream)
+    assert r.theta > 0

@@ -67,6 +67,25 @@ def test_philox_matches_rocrand(rocrand_philox):
         np.testing.assert_array_equal(got.astype(np.uint64), want)
 
 
+def _kat_rows():
+    path = Path(__file__).parent / "golden" / "philox4x32_10_kat.txt"
+    rows = []
+    for line in path.read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            w = [int(x, 16) for x in line.split()]
+            rows.append((w[0:4], w[4] | (w[5] << 32), w[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    """The published known-answer vectors of the generator (golden fixture)."""
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        got = oracle.philox4x32_10(np.array(ctr, dtype=np.uint32), key)
+        assert [int(x) for x in got] == want
+
+
 def test_draw_word_selection():
     """Edge e uses word e&3 of counter (e>>2, s_lo, s_hi, 1); vertex v uses
     word v&3 of (v>>2, s_lo, s_hi, 2); the root uses words 0,1 of
