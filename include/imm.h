@@ -105,7 +105,7 @@ typedef struct {
     uint64_t lane_sets;      /* IC: single-vertex sets it finished */
     uint64_t lane_edges;     /* IC: coins it evaluated for them */
     uint32_t big_block;      /* IC: threads per giant set (autotuned) */
-    uint32_t pad;
+    uint32_t bloom_bits;     /* LT: log2 bits of the per-walk path filter (autotuned) */
     uint64_t device_bytes;   /* device memory held by the run's workspace */
     double ms_queue;         /* server: submit to admission (ms_total is then
                                 submit to completion) */

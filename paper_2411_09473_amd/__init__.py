@@ -59,7 +59,7 @@ class imm_stats(C.Structure):
                 ("big_launches", C.c_uint64), ("rounds", C.c_uint32), ("team", C.c_uint32),
                 ("ms_sample_lane", C.c_double), ("lane_launches", C.c_uint64),
                 ("lane_sets", C.c_uint64), ("lane_edges", C.c_uint64),
-                ("big_block", C.c_uint32), ("pad", C.c_uint32),
+                ("big_block", C.c_uint32), ("bloom_bits", C.c_uint32),
                 ("device_bytes", C.c_uint64), ("ms_queue", C.c_double)]
 
     def as_dict(self):

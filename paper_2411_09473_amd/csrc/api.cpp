@@ -84,7 +84,11 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
         if (big == 256 || big == 1024) g->ic_big_block = (uint32_t)big;
         g->team_forced = team == 1 || team == 2 || team == 4;
         g->big_forced = big == 256 || big == 1024;
-        g->tuned = g->team_forced && g->big_forced;
+        const char* el = std::getenv("IMM_LT_BLOOM");
+        const int bloom = el ? std::atoi(el) : 0;
+        if (bloom >= 10 && bloom <= 12) g->lt_bloom_bits = (uint32_t)bloom;
+        g->bloom_forced = bloom >= 10 && bloom <= 12;
+        g->tuned = model == IMM_IC ? (g->team_forced && g->big_forced) : g->bloom_forced;
         HIP_TRY(hipGetDevice(&g->device));
         std::vector<uint32_t> off32((size_t)n + 1);
         for (size_t v = 0; v <= n; ++v) off32[v] = (uint32_t)co[v];
@@ -101,11 +105,14 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
             }
             HIP_TRY(hipStreamSynchronize(st));
         } else {
-            std::vector<uint2> cs(m ? m : 1);
-            for (uint64_t e = 0; e < m; ++e) cs[e] = make_uint2(wt[e], rs[e]);
-            IMM_TRY(g->arena.alloc((void**)&g->cs, (m ? m : 1) * 8, "cum/src pairs"));
+            std::vector<uint4> cs(m ? m : 1);
+            for (uint64_t e = 0; e < m; ++e) {
+                const uint32_t u = rs[e];
+                cs[e] = make_uint4(wt[e], u, off32[u], off32[(size_t)u + 1]);
+            }
+            IMM_TRY(g->arena.alloc((void**)&g->cs, (m ? m : 1) * 16, "edge records"));
             IMM_TRY(g->arena.alloc((void**)&g->guide, (m ? m : 1) * 4, "guide table"));
-            if (m) HIP_TRY(hipMemcpyAsync(g->cs, cs.data(), m * 8, hipMemcpyHostToDevice, st));
+            if (m) HIP_TRY(hipMemcpyAsync(g->cs, cs.data(), m * 16, hipMemcpyHostToDevice, st));
             HIP_TRY(launch_lt_guide(g->off, g->cs, g->guide, n, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
@@ -284,6 +291,7 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         fill_stats(*p->ws, &p->stats);
         p->stats.team = g->model == IMM_IC ? g->ic_team : 0;
         p->stats.big_block = g->model == IMM_IC ? g->ic_big_block : 0;
+        p->stats.bloom_bits = g->model == IMM_LT ? g->lt_bloom_bits : 0;
         *out = p.release();
         return IMM_OK;
     } catch (const std::bad_alloc&) {

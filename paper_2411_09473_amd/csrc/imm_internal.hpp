@@ -18,13 +18,15 @@ struct IcGraphDev {
     uint32_t m;
 };
 
-// Resident LT graph: offsets, (cum, src) pairs per in-edge, and the guide
-// table: for column v of in-degree d, guide[off[v]+j] is the first edge e of
-// the column with cum[e] > ceil(j 2^32 / d) - 1, i.e. the answer for the
-// smallest draw that falls in bucket j = floor(r d / 2^32).
+// Resident LT graph: offsets, one 16-byte record per in-edge (cum, src and
+// the bounds of src's own column, so a walk that follows the edge needs no
+// further offset load), and the guide table: for column v of in-degree d,
+// guide[off[v]+j] is the first edge e of the column with cum[e] > ceil(j
+// 2^32 / d) - 1, i.e. the answer for the smallest draw in bucket j =
+// floor(r d / 2^32).
 struct LtGraphDev {
     const uint32_t* off;   // n+1
-    const uint2* cs;       // m (x = cum, y = src)
+    const uint4* cs;       // m (x = cum, y = src, z = off[src], w = off[src+1])
     const uint32_t* guide; // m
     uint32_t n;
     uint32_t m;
@@ -106,16 +108,18 @@ hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const Samp
                            uint32_t* ticket, const BigScratch& b, uint32_t block,
                            hipStream_t st);
 uint32_t ic_large_slots(int device, uint32_t block);
+// LT: one walk per lane; bloom_bits (10, 11 or 12) sizes the per-lane path
+// filter in LDS.
 hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t grid, hipStream_t st);
+                           uint32_t* ticket, uint32_t bloom_bits, uint32_t grid, hipStream_t st);
 hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
                            uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
                            hipStream_t st);
-hipError_t launch_lt_guide(const uint32_t* off, const uint2* cs, uint32_t* guide, uint32_t n,
+hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint32_t n,
                            hipStream_t st);
 uint32_t ic_small_grid(int device);
-uint32_t lt_small_grid(int device);
+uint32_t lt_small_grid(int device, uint32_t bloom_bits);
 
 // ---- pool, index, canonical order (k_pool.hip)
 // out[0] = B; out[i+1] = B + x[0] + ... + x[i] for N >= 1 entries, where

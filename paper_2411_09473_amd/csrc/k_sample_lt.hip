@@ -7,10 +7,12 @@
 // once (wave-aggregated tickets), which keeps the memory system busy.
 //  * The live in-edge of v is the first e of v's column with r < cum[e]. The
 //    guide table jumps to the first candidate of r's bucket j = floor(r d /
-//    2^32), from where a short forward scan over (cum, src) pairs finds the
-//    same edge the plain search would.
+//    2^32), from where a short forward scan over the edge records finds the
+//    same edge the plain search would. A record also holds the bounds of its
+//    source's column, so the next step needs no offset load.
 //  * The path is written straight into the lane's staging chunk. A per-lane
-//    4096-bit Bloom filter (three hashes) in LDS answers "not on the path"
+//    Bloom filter of 1024 to 4096 bits (three hashes, size picked per graph
+//    by the autotuner) in LDS answers "not on the path"
 //    for most vertices; a hit is confirmed by rescanning the path
 //    (vectorised), so the test is exact.
 //  * Counts are incremented as vertices join the path; a walk that has to
@@ -23,48 +25,50 @@ namespace imm {
 
 namespace {
 
-constexpr uint32_t kBloomBits = 12;   // 4096-bit path filter per lane, 3 hashes
-constexpr uint32_t kBloomWords = (1u << kBloomBits) / 32;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kDirectDeg = 8;    // columns read whole, without the guide
 
-// The three filter positions of v (multiplicative hashes).
+// The three filter positions of v in a 2^BB-bit filter (multiplicative hashes).
+template <uint32_t BB>
 __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t h[3]) {
-    h[0] = (v * 0x9E3779B1u) >> (32 - kBloomBits);
-    h[1] = (v * 0x85EBCA77u) >> (32 - kBloomBits);
-    h[2] = (v * 0xC2B2AE3Du) >> (32 - kBloomBits);
+    h[0] = (v * 0x9E3779B1u) >> (32 - BB);
+    h[1] = (v * 0x85EBCA77u) >> (32 - BB);
+    h[2] = (v * 0xC2B2AE3Du) >> (32 - BB);
 }
 
-// mb points at word 0 of this lane's filter; word w is mb[w * 64].
+// mb points at this lane's filter (2^BB / 32 consecutive words).
+template <uint32_t BB>
 __device__ __forceinline__ void bloom_set(uint32_t* mb, uint32_t v) {
     uint32_t h[3];
-    bloom_pos(v, h);
+    bloom_pos<BB>(v, h);
 #pragma unroll
-    for (uint32_t j = 0; j < 3; ++j) mb[(h[j] >> 5) * kWave] |= 1u << (h[j] & 31);
+    for (uint32_t j = 0; j < 3; ++j) mb[h[j] >> 5] |= 1u << (h[j] & 31);
 }
 
+template <uint32_t BB>
 __device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
     uint32_t h[3];
-    bloom_pos(v, h);
+    bloom_pos<BB>(v, h);
     bool all = true;
 #pragma unroll
-    for (uint32_t j = 0; j < 3; ++j) all &= ((mb[(h[j] >> 5) * kWave] >> (h[j] & 31)) & 1u) != 0;
+    for (uint32_t j = 0; j < 3; ++j) all &= ((mb[h[j] >> 5] >> (h[j] & 31)) & 1u) != 0;
     return all;
 }
 
-// The live in-edge source of `cur` for draw r, or kNone. *reads counts the
-// (cum, src) pairs inspected. A short column is loaded whole in one round of
+// The live in-edge of the column [beg, end) for draw r: its record (src in
+// .y, src's column bounds in .z/.w), or .y = kNone. *reads counts the
+// records inspected. A short column is loaded whole in one round of
 // independent loads; a longer one starts at its guide entry.
-__device__ __forceinline__ uint32_t lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
-                                            uint32_t r, uint32_t* reads) {
+__device__ __forceinline__ uint4 lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
+                                         uint32_t r, uint32_t* reads) {
     const uint32_t d = end - beg;
+    uint4 res = make_uint4(0u, kNone, 0u, 0u);
     if (d <= kDirectDeg) {
-        uint32_t res = kNone;
 #pragma unroll
         for (uint32_t j = 0; j < kDirectDeg; ++j) {
             if (j < d) {
-                const uint2 p = g.cs[beg + j];
-                if (res == kNone && r < p.x) res = p.y;
+                const uint4 p = g.cs[beg + j];
+                if (res.y == kNone && r < p.x) res = p;
             }
         }
         *reads += d;
@@ -73,12 +77,12 @@ __device__ __forceinline__ uint32_t lt_pick(const LtGraphDev& g, uint32_t beg, u
     const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
     uint32_t e = g.guide[beg + jb];
     while (e < end) {
-        const uint2 p = g.cs[e];
+        const uint4 p = g.cs[e];
         ++*reads;
-        if (r < p.x) return p.y;
+        if (r < p.x) return p;
         ++e;
     }
-    return kNone;
+    return res;
 }
 
 // Is w among the len entries of path (which starts at stage[pos])? Entries
@@ -106,14 +110,23 @@ __device__ __forceinline__ bool on_path(const uint32_t* stage, uint64_t pos, uin
     return false;
 }
 
+// BB: log2 of the per-lane path filter size in bits (10..12). A smaller
+// filter leaves more waves resident (more walks in flight) at the price of
+// more false hits, each confirmed by a path rescan.
+template <uint32_t BB>
 __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
                                                       uint32_t* ticket) {
+    constexpr uint32_t kBloomWords = (1u << BB) / 32;
     __shared__ uint32_t bloom[kBloomWords * kWave];
     const uint32_t lane = threadIdx.x;
-    uint32_t* mb = bloom + lane;  // word w of this lane's filter is mb[w * 64]
+    uint32_t* mb = bloom + lane * kBloomWords;  // this lane's filter
+    // the wave's reservoir of sample positions [res_pos, res_end), claimed
+    // from the ticket 64 at a time (uniform across the wave)
+    uint32_t res_pos = 0, res_end = 0;
 
     bool has = false, done = false;
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
+    uint32_t cbeg = 0, cend = 0;  // cur's column
     uint64_t s = 0, chunk_base = 0;
     uint32_t w_steps = 0, w_reads = 0;
     uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
@@ -123,18 +136,31 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
         const bool need = !has && !done;
         const uint64_t mask = __ballot(need);
         if (mask) {
-            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(ticket, (uint32_t)__popcll(mask));
-            base = __shfl(base, leader, kWave);
+            const uint32_t want = (uint32_t)__popcll(mask);
+            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t have = res_end - res_pos;
+            uint32_t pos;
+            if (have >= want) {
+                pos = res_pos + rank;
+                res_pos += want;
+            } else {
+                uint32_t nb = 0;
+                if (lane == 0) nb = atomicAdd(ticket, kWave);
+                nb = __shfl(nb, 0, kWave);
+                pos = rank < have ? res_pos + rank : nb + (rank - have);
+                res_pos = nb + (want - have);
+                res_end = nb + kWave;
+            }
+            bool start = false;
             if (need) {
-                const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
                 if (pos >= total) {
                     done = true;
                 } else {
                     idx = rg.list ? rg.list[pos] : pos;
                     s = rg.id_lo + idx;
                     cur = sample_root(rg.seed, s, g.n);
+                    cbeg = g.off[cur];
+                    cend = g.off[cur + 1];
                     bool ok = true;
                     if (chunk_used >= kLtChunk) {
                         const uint64_t nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
@@ -146,33 +172,40 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                             chunk_used = 0;
                         }
                     }
-                    if (ok) {
-                        for (uint32_t wd = 0; wd < kBloomWords; ++wd) mb[wd * kWave] = 0u;
-                        wstart = chunk_used;
-                        o.stage[chunk_base + wstart] = cur;
-                        atomicAdd(&o.counts[cur], 1u);
-                        bloom_set(mb, cur);
-                        len = 1;
-                        w_steps = 0;
-                        w_reads = 0;
-                        has = true;
-                    }
+                    start = ok;
                 }
+            }
+            // the whole wave clears each starting lane's filter in turn
+            uint64_t smask = __ballot(start);
+            while (smask) {
+                const uint32_t l = (uint32_t)__ffsll((unsigned long long)smask) - 1u;
+                smask &= smask - 1ull;
+                for (uint32_t wd = lane; wd < kBloomWords; wd += kWave) bloom[l * kBloomWords + wd] = 0u;
+            }
+            if (start) {
+                wstart = chunk_used;
+                o.stage[chunk_base + wstart] = cur;
+                atomicAdd(&o.counts[cur], 1u);
+                bloom_set<BB>(mb, cur);
+                len = 1;
+                w_steps = 0;
+                w_reads = 0;
+                has = true;
             }
         }
         if (!__any(has)) break;
         if (has) {
             // one step of the walk
-            const uint32_t beg = g.off[cur], end = g.off[cur + 1];
-            uint32_t nxt = kNone;
-            if (beg < end) {
+            uint4 pk = make_uint4(0u, kNone, 0u, 0u);
+            if (cbeg < cend) {
                 const uint32_t r = lt_draw(rg.seed, s, cur);
                 ++w_steps;
-                nxt = lt_pick(g, beg, end, r, &w_reads);
+                pk = lt_pick(g, cbeg, cend, r, &w_reads);
             }
+            const uint32_t nxt = pk.y;
             bool finish = nxt == kNone;
             if (!finish) {
-                if (bloom_test(mb, nxt) && on_path(o.stage, chunk_base + wstart, len, nxt))
+                if (bloom_test<BB>(mb, nxt) && on_path(o.stage, chunk_base + wstart, len, nxt))
                     finish = true;
                 if (!finish) {
                     bool keep = true;
@@ -203,9 +236,11 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     if (keep) {
                         o.stage[chunk_base + wstart + len] = nxt;
                         atomicAdd(&o.counts[nxt], 1u);
-                        bloom_set(mb, nxt);
+                        bloom_set<BB>(mb, nxt);
                         ++len;
                         cur = nxt;
+                        cbeg = pk.z;
+                        cend = pk.w;
                     }
                 }
             }
@@ -257,20 +292,23 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
         const uint64_t s = rg.id_lo + idx;
         if (lane == 0) {
             uint32_t cur = sample_root(rg.seed, s, g.n);
+            uint32_t beg = g.off[cur], end = g.off[cur + 1];
             uint32_t len = 0, steps = 0, reads = 0;
             q[len++] = cur;
             atomicOr(&bm[cur >> 5], 1u << (cur & 31));
             for (;;) {
-                const uint32_t beg = g.off[cur], end = g.off[cur + 1];
                 if (beg == end) break;
                 const uint32_t r = lt_draw(rg.seed, s, cur);
                 ++steps;
-                const uint32_t nxt = lt_pick(g, beg, end, r, &reads);
+                const uint4 pk = lt_pick(g, beg, end, r, &reads);
+                const uint32_t nxt = pk.y;
                 if (nxt == kNone) break;
                 const uint32_t bit = 1u << (nxt & 31);
                 if (atomicOr(&bm[nxt >> 5], bit) & bit) break;
                 q[len++] = nxt;
                 cur = nxt;
+                beg = pk.z;
+                end = pk.w;
             }
             s_len = len;
             s_steps = steps;
@@ -313,7 +351,7 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
 
 // guide[beg + j] = first e in [beg, end) with cum[e] > ceil(j 2^32 / d) - 1,
 // or end if there is none, for every column (64 columns per wave).
-__global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const uint2* cs,
+__global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const uint4* cs,
                                                       uint32_t* guide, uint32_t n) {
     const uint64_t v = (uint64_t)blockIdx.x * kWave + threadIdx.x;
     uint32_t sz = 0;
@@ -335,18 +373,35 @@ __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const
 
 }  // namespace
 
-uint32_t lt_small_grid(int device) {
+uint32_t lt_small_grid(int device, uint32_t bloom_bits) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    return (uint32_t)cus * 16u;
+    // resident waves per CU as LDS allows (64 lanes x 2^bits bits each, 160 KB
+    // per CU), twice over
+    const uint32_t lds = (1u << bloom_bits) / 8 * kWave;
+    uint32_t per_cu = (160u * 1024u) / lds;
+    if (per_cu > 32) per_cu = 32;
+    return (uint32_t)cus * per_cu * 2u;
 }
 
 hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t grid, hipStream_t st) {
+                           uint32_t* ticket, uint32_t bloom_bits, uint32_t grid, hipStream_t st) {
     const uint32_t need = (r.count + kWave - 1) / kWave;
     if (grid > need) grid = need;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(lt_small_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+    switch (bloom_bits) {
+        case 10:
+            hipLaunchKernelGGL(lt_small_kernel<10>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            break;
+        case 11:
+            hipLaunchKernelGGL(lt_small_kernel<11>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            break;
+        case 12:
+            hipLaunchKernelGGL(lt_small_kernel<12>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -360,7 +415,7 @@ hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const Samp
     return hipGetLastError();
 }
 
-hipError_t launch_lt_guide(const uint32_t* off, const uint2* cs, uint32_t* guide, uint32_t n,
+hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint32_t n,
                            hipStream_t st) {
     const uint32_t blocks = (n + kWave - 1) / kWave;
     hipLaunchKernelGGL(lt_guide_kernel, dim3(blocks), dim3(kWave), 0, st, off, cs, guide, n);

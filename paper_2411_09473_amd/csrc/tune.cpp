@@ -1,6 +1,10 @@
-// tune.cpp -- per-graph choice of the IC sampling launch shapes.
+// tune.cpp -- per-graph choice of the sampling launch shapes.
 //
-// Two shapes matter and depend on the graph: the BFS team (waves per sample:
+// LT: the size of each walk's path filter in LDS (1024, 2048 or 4096 bits):
+// smaller filters leave more waves, hence more walks, in flight, at the cost
+// of more false hits that a path rescan must clear.
+//
+// IC: two shapes matter and depend on the graph: the BFS team (waves per sample:
 // one wave suits graphs whose sets are small and cheap; samples that sweep
 // long in-edge lists of high in-degree hubs finish sooner, and fit LDS more
 // often, with two or four) and the giant-set workgroup (256 threads and many
@@ -28,15 +32,47 @@ constexpr uint64_t kTuneSamples = 1u << 16;
 constexpr uint64_t kProbeSamples = 2048;
 constexpr double kProbeMs = 20.0;
 
+// LT: the per-lane path filter size, among 1024, 2048 and 4096 bits.
+imm_status tune_lt(imm_graph* g, hipStream_t st) {
+    if (g->bloom_forced) {
+        g->tuned = true;
+        return IMM_OK;
+    }
+    Workspace w;
+    IMM_TRY(ws_init(w, g->n, g->device, st, 0));
+    const bool log = std::getenv("IMM_TUNE_LOG") != nullptr;
+    double best = -1.0;
+    uint32_t pick = 12;
+    for (int c = -1; c < 3; ++c) {
+        g->lt_bloom_bits = c < 0 ? 10u : 12u - (uint32_t)c;
+        IMM_TRY(ws_reset(w, st, true));
+        IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneSamples));
+        HIP_TRY(hipStreamSynchronize(st));
+        imm_stats s;
+        std::memset(&s, 0, sizeof(s));
+        fill_stats(w, &s);
+        if (c < 0) continue;
+        const double ms = s.ms_sample_main + s.ms_sample_big;
+        if (log)
+            std::fprintf(stderr, "imm tune: n=%u m=%llu LT filter 2^%u bits: walks %.3f ms, long %.3f ms\n",
+                         g->n, (unsigned long long)g->m, g->lt_bloom_bits, s.ms_sample_main,
+                         s.ms_sample_big);
+        if (best < 0.0 || ms < best) {
+            best = ms;
+            pick = g->lt_bloom_bits;
+        }
+    }
+    g->lt_bloom_bits = pick;
+    g->tuned = true;
+    return IMM_OK;
+}
+
 }  // namespace
 
 imm_status tune_graph(imm_graph* g, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g->tune_mu);
     if (g->tuned) return IMM_OK;
-    if (g->model != IMM_IC) {
-        g->tuned = true;
-        return IMM_OK;
-    }
+    if (g->model == IMM_LT) return tune_lt(g, st);
     struct Cand {
         uint32_t team, big;
     };

@@ -248,7 +248,8 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
         w.timer.close(tm, st);
     } else {
         const int tm = w.timer.open(4, st);
-        HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, lt_small_grid(w.device), st));
+        HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, g->lt_bloom_bits,
+                                lt_small_grid(w.device, g->lt_bloom_bits), st));
         w.timer.close(tm, st);
     }
     const int t3 = w.timer.open(5, st);
@@ -319,7 +320,7 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
             tails = waves * kIcStageChunk;
         } else {
             const uint64_t lanes =
-                std::min<uint64_t>((uint64_t)lt_small_grid(w.device) * 64u, count);
+                std::min<uint64_t>((uint64_t)lt_small_grid(w.device, g->lt_bloom_bits) * 64u, count);
             tails = lanes * kLtChunk;
         }
         uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
