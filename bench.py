@@ -28,6 +28,17 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# 32-bit VALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, in tera lane-ops/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU instructions of one Philox4x32-10 call in the gfx950 code (20 64-bit
+# multiply-adds, 40 xor/add), each one lane-op per lane
+PHILOX_OPS = 60
+
+# HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, scaled by the 1 GiB copy calibration), for the kernel
+# and workload named, as recorded in profiles/; a kernel changed since its
+# counters were taken has no entry.
+MEASURED_TRAFFIC = {}
 
 
 def algorithmic_bytes(model: str, sets: int, entries: int, edges: int, live: int) -> int:
@@ -54,29 +65,47 @@ def kernel_table(model: str, stats: list) -> dict:
     big = (tot("sets") - main[0] - lane[0], tot("entries") - main[1] - lane[1],
            tot("edges") - main[2] - lane[2], tot("live") - main[3])
     ic = model == "ic"
+
+    def philox_ops(edges):
+        # IC: one call per aligned group of four coins (at least edges / 4);
+        # LT: one call per walk step
+        return (edges / 4.0 if ic else float(edges)) * PHILOX_OPS
+
     out = {
         "main": dict(name="ic_bfs_kernel" if ic else "lt_small_kernel", ms=tot("ms_sample_main"),
-                     launches=tot("main_launches"), bytes=algorithmic_bytes(model, *main)),
+                     launches=tot("main_launches"), bytes=algorithmic_bytes(model, *main),
+                     ops=philox_ops(main[2])),
         "large": dict(name="ic_large_kernel" if ic else "lt_large_kernel",
                       ms=tot("ms_sample_big"), launches=tot("big_launches"),
-                      bytes=algorithmic_bytes(model, *big)),
+                      bytes=algorithmic_bytes(model, *big), ops=philox_ops(big[2])),
     }
     if ic:
         out["lane"] = dict(name="ic_lane_kernel", ms=tot("ms_sample_lane"),
-                           launches=tot("lane_launches"), bytes=algorithmic_bytes(model, *lane))
+                           launches=tot("lane_launches"), bytes=algorithmic_bytes(model, *lane),
+                           ops=philox_ops(lane[2]))
     return out
 
 
-def roofline_of(kernels: dict) -> dict:
-    """Roofline entry of the kernel with the most time: algorithmic bytes
-    per launch over its mean launch duration."""
+def roofline_of(kernels: dict, workload: str) -> dict:
+    """Roofline entry of the kernel with the most time. Per launch: its
+    algorithmic bytes and its Philox lane-ops over its mean launch duration;
+    the bound is whichever roof (HBM or 32-bit ALU) it is nearer to."""
     dom = max(kernels.values(), key=lambda k: k["ms"])
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
-    per_launch = dom["bytes"] / max(dom["launches"], 1)
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return {"kernel": dom["name"], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-            "avg_launch_ms": avg_ms, "bytes_per_launch": per_launch}
+    launches = max(dom["launches"], 1)
+    avg_ms = dom["ms"] / launches
+    per_launch = dom["bytes"] / launches
+    ops_launch = dom["ops"] / launches
+    gbps = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    tops = ops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    hbm = {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}
+    alu = {"achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": tops / ALU_PEAK_TOPS}
+    near, other, bound = (alu, hbm, "alu") if alu["frac"] > hbm["frac"] else (hbm, alu, "hbm")
+    out = {"kernel": dom["name"], "bound": bound, **near,
+           "traffic": MEASURED_TRAFFIC.get((workload, dom["name"])),
+           "avg_launch_ms": avg_ms, "bytes_per_launch": per_launch,
+           "philox_ops_per_launch": ops_launch,
+           ("hbm" if bound == "alu" else "alu"): other}
+    return out
 
 
 def kernel_summary(kernels: dict) -> dict:
@@ -137,7 +166,7 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
         "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
         "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
         "deferred": st["deferred"], "ic_team": st["team"], "ic_big_block": st["big_block"], "kernels": kernel_summary(kernels),
-        "roofline": roofline_of(kernels),
+        "roofline": roofline_of(kernels, args.workload),
     }))
 
 
@@ -440,7 +469,7 @@ def main():
         "sampling_GBps": samp_bytes / (ms_sample * 1e-3) / 1e9 if ms_sample > 0 else None,
         "sampling_sets_per_s": sets / (ms_sample * 1e-3) if ms_sample > 0 else None,
         "kernels": kernel_summary(kernels),
-        "roofline": roofline_of(kernels),
+        "roofline": roofline_of(kernels, args.workload),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, spec, args.cpu_seconds)

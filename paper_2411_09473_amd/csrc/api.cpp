@@ -81,9 +81,10 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
         const int team = et ? std::atoi(et) : 0;
         const int big = eb ? std::atoi(eb) : 0;
         if (team == 1 || team == 2 || team == 4) g->ic_team = (uint32_t)team;
-        if (big == 256 || big == 1024) g->ic_big_block = (uint32_t)big;
+        const bool big_ok = big == 256 || big == 1024;
+        if (big_ok) g->ic_big_block = (uint32_t)big;
         g->team_forced = team == 1 || team == 2 || team == 4;
-        g->big_forced = big == 256 || big == 1024;
+        g->big_forced = big_ok;
         const char* el = std::getenv("IMM_LT_BLOOM");
         const int bloom = el ? std::atoi(el) : 0;
         if (bloom >= 10 && bloom <= 12) g->lt_bloom_bits = (uint32_t)bloom;

@@ -562,8 +562,8 @@ hipError_t launch_ic_bfs(const IcGraphDev& g, const SampleRange& r, const Sample
 }
 
 uint32_t ic_large_slots(int device, uint32_t block) {
-    // the same 512 threads per CU either way: many mid-sized giant sets in
-    // flight (256) or fewer, wider ones (1024)
+    // the same 2048 threads per CU either way: many giant sets in flight
+    // (256 threads each) or fewer, wider ones (1024)
     return (uint32_t)cu_count(device) * (block == 256 ? 8u : 2u);
 }
 

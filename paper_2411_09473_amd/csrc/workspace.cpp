@@ -255,10 +255,9 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
     const int t3 = w.timer.open(5, st);
     if (g->model == IMM_IC) {
         // the tuned giant-set shape, unless the pass is expected to defer
-        // far more sets than the wide shape has workgroups
+        // more sets than that shape has workgroups
         uint32_t block = g->ic_big_block;
-        if (!g->big_forced &&
-            g->defer_rate * (double)nitems > 2.0 * ic_large_slots(w.device, 1024))
+        if (!g->big_forced && g->defer_rate * (double)nitems > ic_large_slots(w.device, block))
             block = 256;
         HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n, w.over,
                                 &w.sc->over_n, &w.sc->ticket_big,
