@@ -96,7 +96,8 @@ struct DevScalars {
 
 // Phase timing with HIP events (phases: 0 sample, 1 compact, 2 index,
 // 3 select, 4 main sampling kernel, 5 large-set sampling kernel, 6 IC
-// lane-per-root kernel).
+// lane-per-root kernel, 7 IC pass over sets that outgrew the large-set
+// queues).
 struct Timer {
     bool on = false;
     struct Rec {

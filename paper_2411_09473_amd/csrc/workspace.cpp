@@ -262,14 +262,18 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
         HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n, w.over,
                                 &w.sc->over_n, &w.sc->ticket_big,
                                 big_view(w, ic_large_slots(w.device, block)), block, st));
-        if (w.huge_slots)
+        w.timer.close(t3, st);
+        if (w.huge_slots) {
+            const int t7 = w.timer.open(7, st);
             HIP_TRY(launch_ic_large(ic_view(g), rgl, o, w.over, &w.sc->over_n, fl, fl_n, nullptr,
                                     nullptr, &w.sc->ticket_huge, huge_view(w), 1024, st));
+            w.timer.close(t7, st);
+        }
     } else {
         HIP_TRY(launch_lt_large(lt_view(g), rgl, o, w.defer, &w.sc->defer_n, fl, fl_n,
                                 &w.sc->ticket_big, big_view(w, w.big_slots), st));
+        w.timer.close(t3, st);
     }
-    w.timer.close(t3, st);
     w.timer.close(th, st);
     HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     return IMM_OK;
@@ -574,8 +578,8 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
 }
 
 void fill_stats(Workspace& w, imm_stats* s) {
-    double ms[7] = {0, 0, 0, 0, 0, 0, 0};
-    uint64_t launches[3] = {0, 0, 0};
+    double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t launches[4] = {0, 0, 0, 0};
     w.timer.collect(ms, launches);
     s->ms_sample += ms[0];
     s->ms_compact += ms[1];
