@@ -187,70 +187,6 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
     if (lane == 0 && cov) atomicAdd(&d.cov_entries[t], (unsigned long long)cov);
 }
 
-// Uncovered sets containing u, counted from u's inverted-index lists (all
-// segments) by the calling lane alone.
-__device__ __forceinline__ uint32_t recount_lane(const SelectDesc& d, uint32_t u) {
-    uint32_t c = 0;
-    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
-        const uint64_t lo = io[u], hi = io[u + 1];
-        for (uint64_t p = lo; p < hi; ++p) {
-            const uint32_t j = d.inv_set[p];
-            c += ((d.covered[j >> 5] >> (j & 31)) & 1u) ^ 1u;
-        }
-    }
-    return c;
-}
-
-// The same count by the whole wave (u uniform across it).
-__device__ __forceinline__ uint32_t recount_wave(const SelectDesc& d, uint32_t u, uint32_t lane) {
-    uint32_t c = 0;
-    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
-        const uint64_t lo = io[u], hi = io[u + 1];
-        for (uint64_t p = lo + lane; p < hi; p += kWave) {
-            const uint32_t j = d.inv_set[p];
-            c += ((d.covered[j >> 5] >> (j & 31)) & 1u) ^ 1u;
-        }
-    }
-    return (uint32_t)wave_sum64(c);
-}
-
-// Lists up to this long are recounted by one lane, longer ones by a wave.
-constexpr uint32_t kLaneList = 128;
-
-// The adaptive counter update: when a seed covers sets that hold a large
-// part of the pool, rebuilding each remaining count from the uncovered sets
-// (a gather over the index, no atomics) is cheaper than decrementing once
-// per member of every covered set. Selected vertices keep their sentinel and
-// zero counts stay zero, so only the other vertices are visited.
-__device__ void recount_all(const SelectDesc& d, uint32_t blk) {
-    const uint32_t lane = threadIdx.x % kWave;
-    const uint32_t wpb = kDecBS / kWave;
-    const uint32_t wid = blk * wpb + threadIdx.x / kWave;
-    const uint32_t nw = d.sel_cnt * wpb;
-    for (uint64_t base = (uint64_t)wid * kWave; base < d.n; base += (uint64_t)nw * kWave) {
-        const uint32_t u = (uint32_t)base + lane;
-        const uint32_t c = u < d.n ? d.cw[u] : 0u;
-        const bool act = c != 0u && c != kSelected;
-        uint64_t len = 0;
-        if (act) {
-            for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-                const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
-                len += io[u + 1] - io[u];
-            }
-            if (len <= kLaneList) d.cw[u] = recount_lane(d, u);
-        }
-        uint64_t heavy = __ballot(act && len > kLaneList);
-        while (heavy) {
-            const uint32_t l = (uint32_t)__ffsll((unsigned long long)heavy) - 1u;
-            heavy &= heavy - 1ull;
-            const uint32_t c2 = recount_wave(d, (uint32_t)base + l, lane);
-            if (lane == 0) d.cw[(uint32_t)base + l] = c2;
-        }
-    }
-}
-
 // Decrements summed per workgroup in an LDS table (vertex -> count) are
 // applied with one atomic per distinct vertex: the sets a seed covers share
 // their high-degree vertices, which would otherwise take one global atomic
@@ -277,6 +213,76 @@ __device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, u
     atomicSub(&cw[u], 1u);
 }
 
+// The adaptive counter update: when a seed covers sets that hold a large
+// part of the pool, rebuilding each remaining count from the uncovered sets
+// (a gather over the index, no global atomics) is cheaper than decrementing
+// once per member of every covered set. A wave takes 64 consecutive
+// vertices; their index lists are one contiguous position range per
+// segment, which the wave sweeps coalesced, four positions per lane per
+// round, counting uncovered sets per vertex in LDS (the owner of a position
+// by binary search over the 65 list bounds). Selected vertices keep their
+// sentinel and zero counts stay zero.
+constexpr uint32_t kRecountUnroll = 4;
+
+__device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off,
+                            uint32_t* lds_cnt) {
+    const uint32_t lane = threadIdx.x % kWave;
+    const uint32_t wpb = kDecBS / kWave;
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wid = blk * wpb + wv;
+    const uint32_t nw = d.sel_cnt * wpb;
+    uint32_t* s_off = lds_off + wv * (kWave + 1);  // this wave's 65 bounds
+    uint32_t* s_cnt = lds_cnt + wv * kWave;        // this wave's 64 counters
+    for (uint64_t u0 = (uint64_t)wid * kWave; u0 < d.n; u0 += (uint64_t)nw * kWave) {
+        const uint32_t u = (uint32_t)u0 + lane;
+        const uint32_t c = u < d.n ? d.cw[u] : 0u;
+        const bool act = c != 0u && c != kSelected;
+        if (!__ballot(act)) continue;
+        s_cnt[lane] = 0u;
+        const uint32_t hi_v = u0 + kWave < d.n ? (uint32_t)(u0 + kWave) : d.n;
+        for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+            const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+            const uint64_t base = io[u0];
+            const uint64_t my = io[u < hi_v ? u : hi_v];
+            const uint64_t top = io[hi_v];
+            // bounds relative to the range start (a range of one segment
+            // holds fewer than 2^32 positions)
+            s_off[lane] = (uint32_t)(my - base);
+            if (lane == 0) s_off[kWave] = (uint32_t)(top - base);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint32_t span = (uint32_t)(top - base);
+            for (uint32_t q = lane; q < span; q += kWave * kRecountUnroll) {
+                uint32_t sid[kRecountUnroll];
+#pragma unroll
+                for (uint32_t x = 0; x < kRecountUnroll; ++x) {
+                    const uint32_t r = q + x * kWave;
+                    sid[x] = r < span ? d.inv_set[base + r] : 0u;
+                }
+#pragma unroll
+                for (uint32_t x = 0; x < kRecountUnroll; ++x) {
+                    const uint32_t r = q + x * kWave;
+                    if (r < span && !((d.covered[sid[x] >> 5] >> (sid[x] & 31)) & 1u)) {
+                        // owner: the last lane whose list starts at or before r
+                        uint32_t lo = 0, hi = kWave;
+                        while (hi - lo > 1) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (s_off[mid] <= r) lo = mid; else hi = mid;
+                        }
+                        atomicAdd(&s_cnt[lo], 1u);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (act) d.cw[u] = s_cnt[lane];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Small covered sets are taken one per lane (a flood of tiny sets keeps every
 // lane busy), the 64-member pieces of larger ones one per wave.
 __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* descs, uint32_t nq,
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t pool = d.set_off[d.n_sets];
     if (d.cov_entries[t] * 8ull > pool) {
-        recount_all(d, blk);
+        recount_all(d, blk, h_key, h_cnt);
         return;
     }
     const uint32_t ns = d.chunk_n[2ull * t], nb = d.chunk_n[2ull * t + 1];
