@@ -162,9 +162,11 @@ struct Workspace {
     uint64_t cap_pd = 0;
     uint64_t* scan_tmp = nullptr;
     uint64_t cap_scan = 0;
-    unsigned long long* slots = nullptr;  // k * kArgSlots partial maxima
-    uint32_t* chunk_n = nullptr;          // 2k queue lengths
-    unsigned long long* cov_entries = nullptr;  // k covered-member totals
+    // one allocation: k * kArgSlots partial maxima, then 2k queue lengths,
+    // then k covered-member totals
+    unsigned long long* slots = nullptr;
+    uint32_t* chunk_n = nullptr;
+    unsigned long long* cov_entries = nullptr;
     Chunk* chunks = nullptr;
     uint64_t cap_chunks = 0;
     uint32_t* seeds_d = nullptr;

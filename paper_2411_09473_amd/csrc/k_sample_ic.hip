@@ -146,7 +146,7 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
     uint32_t ow = 0, lo = 0;
     uint32_t hi = nb > 1 ? s_base[1] : G;
     uint32_t g0 = s_g0[0], eb = s_beg[0], ee = s_end[0];
-    for (uint32_t t = threadIdx.x; t < G; t += BS) {
+    auto locate = [&](uint32_t t, uint32_t* grp, uint32_t* b, uint32_t* e) {
         if (t >= hi) {
             ow = owner_from(s_base, nb, t, ow);
             lo = s_base[ow];
@@ -155,23 +155,45 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
             eb = s_beg[ow];
             ee = s_end[ow];
         }
-        const uint32_t grp = g0 + (t - lo);
-        const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
-        const Philox4 r = philox10(grp, slo, shi, 1u, k0, k1);
-        const uint32_t e0 = grp << 2;
+        *grp = g0 + (t - lo);
+        *b = eb;
+        *e = ee;
+    };
+    auto live_mask = [](const Philox4& r, const uint4& th, uint32_t e0, uint32_t b, uint32_t e) {
         uint32_t live = 0;
-        live |= (r.x < th.x && e0 >= eb && e0 < ee) ? 1u : 0u;
-        live |= (r.y < th.y && e0 + 1 >= eb && e0 + 1 < ee) ? 2u : 0u;
-        live |= (r.z < th.z && e0 + 2 >= eb && e0 + 2 < ee) ? 4u : 0u;
-        live |= (r.w < th.w && e0 + 3 >= eb && e0 + 3 < ee) ? 8u : 0u;
-        const bool any = live != 0u;
+        live |= (r.x < th.x && e0 >= b && e0 < e) ? 1u : 0u;
+        live |= (r.y < th.y && e0 + 1 >= b && e0 + 1 < e) ? 2u : 0u;
+        live |= (r.z < th.z && e0 + 2 >= b && e0 + 2 < e) ? 4u : 0u;
+        live |= (r.w < th.w && e0 + 3 >= b && e0 + 3 < e) ? 8u : 0u;
+        return live;
+    };
+    // two groups per thread and round (t and t + BS): both threshold loads
+    // and both Philox chains are in flight together
+    for (uint32_t t = threadIdx.x; t < G; t += 2 * BS) {
+        uint32_t ga, ba, ea, gb = 0, bb = 0, eb2 = 0;
+        locate(t, &ga, &ba, &ea);
+        const bool two = t + BS < G;
+        if (two) locate(t + BS, &gb, &bb, &eb2);
+        const uint4 tha = *reinterpret_cast<const uint4*>(g.thr + 4ull * ga);
+        const uint4 thb = two ? *reinterpret_cast<const uint4*>(g.thr + 4ull * gb)
+                              : make_uint4(0u, 0u, 0u, 0u);
+        const Philox4 ra = philox10(ga, slo, shi, 1u, k0, k1);
+        const Philox4 rb = philox10(gb, slo, shi, 1u, k0, k1);
+        uint32_t la = live_mask(ra, tha, ga << 2, ba, ea);
+        uint32_t lb = two ? live_mask(rb, thb, gb << 2, bb, eb2) : 0u;
+        const bool any = (la | lb) != 0u;
         if (any) {
-            *live_n += (uint32_t)__popc(live);
-            do {
-                const uint32_t j = (uint32_t)__ffs(live) - 1u;
-                live &= live - 1u;
-                on_live(g.src[e0 + j]);
-            } while (live);
+            *live_n += (uint32_t)(__popc(la) + __popc(lb));
+            while (la) {
+                const uint32_t j = (uint32_t)__ffs(la) - 1u;
+                la &= la - 1u;
+                on_live(g.src[(ga << 2) + j]);
+            }
+            while (lb) {
+                const uint32_t j = (uint32_t)__ffs(lb) - 1u;
+                lb &= lb - 1u;
+                on_live(g.src[(gb << 2) + j]);
+            }
         }
         if (__ballot(any) && stop()) break;
     }

@@ -228,13 +228,14 @@ BigScratch huge_view(const Workspace& w) {
 // scalars are copied to the pinned mirror; nothing waits.
 imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
                        uint32_t count, const uint32_t* list, const uint32_t* list_n,
-                       uint32_t nitems, uint32_t* fl, uint32_t* fl_n) {
+                       uint32_t nitems, uint32_t* fl, uint32_t* fl_n, bool fresh) {
     hipStream_t st = w.st;
     const SampleRange rg{seed, id_lo, nitems, list, list_n};
     const SampleRange rgl{seed, id_lo, count, nullptr, nullptr};
     const SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
                       w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
-    HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 7 * sizeof(uint32_t), st));
+    // tickets and list lengths (already zero right after ws_extend_launch's reset)
+    if (!fresh) HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 7 * sizeof(uint32_t), st));
     const int th = w.timer.open(0, st);
     if (g->model == IMM_IC) {
         const int tl = w.timer.open(6, st);
@@ -339,7 +340,7 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
     w.pending_count = count;
     w.pending_lo = id_lo;
     return sample_pass(w, g, seed, id_lo, count, nullptr, nullptr, count, w.retry,
-                       &w.sc->retry_n);
+                       &w.sc->retry_n, true);
 }
 
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
@@ -369,7 +370,7 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
         const unsigned long long cur = old_cap;
         HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemsetAsync(out_n, 0, 4, st));
-        IMM_TRY(sample_pass(w, g, seed, id_lo, count, in, in_n, failed, out_l, out_n));
+        IMM_TRY(sample_pass(w, g, seed, id_lo, count, in, in_n, failed, out_l, out_n, false));
         HIP_TRY(hipStreamSynchronize(st));
         std::swap(in, out_l);
         std::swap(in_n, out_n);
@@ -459,17 +460,18 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
             HIP_TRY(hipStreamSynchronize(st));
             w.arena.release(w.seeds_d);
             w.arena.release(w.gains_d);
-            w.arena.release(w.slots);
-            w.arena.release(w.chunk_n);
-            w.arena.release(w.cov_entries);
+            w.arena.release(w.slots);  // also holds chunk_n and cov_entries
             (void)hipHostFree(w.gains_h);
             w.gains_h = nullptr;
         }
         IMM_TRY(w.arena.alloc((void**)&w.seeds_d, (uint64_t)k * 4, "seeds"));
         IMM_TRY(w.arena.alloc((void**)&w.gains_d, (uint64_t)k * 4, "gains"));
-        IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * kArgSlots * 8, "argmax slots"));
-        IMM_TRY(w.arena.alloc((void**)&w.chunk_n, (uint64_t)k * 8, "chunk counts"));
-        IMM_TRY(w.arena.alloc((void**)&w.cov_entries, (uint64_t)k * 8, "covered totals"));
+        // per seed step: argmax slots, two queue lengths, covered total; one
+        // block, cleared with one fill per selection
+        IMM_TRY(w.arena.alloc((void**)&w.slots, (uint64_t)k * (kArgSlots * 8 + 16),
+                              "seed-step state"));
+        w.chunk_n = reinterpret_cast<uint32_t*>(w.slots + (uint64_t)k * kArgSlots);
+        w.cov_entries = reinterpret_cast<unsigned long long*>(w.chunk_n + 2ull * k);
         HIP_TRY(hipHostMalloc((void**)&w.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
         w.cap_k = k;
     }
@@ -479,9 +481,8 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
     HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4,
                            hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
-    HIP_TRY(hipMemsetAsync(w.slots, 0, (uint64_t)k * kArgSlots * 8, st));
-    HIP_TRY(hipMemsetAsync(w.chunk_n, 0, (uint64_t)k * 8, st));
-    HIP_TRY(hipMemsetAsync(w.cov_entries, 0, (uint64_t)k * 8, st));
+    // the whole block: its layout follows the capacity cap_k, not this k
+    HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
     if (w.nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
     *d = SelectDesc{w.counts_work, w.inv_offs, w.inv_set, w.set_off, w.set_vtx, w.covered,
                     w.slots, w.seeds_d, w.gains_d, w.chunks, w.chunk_n, w.cap_chunks,

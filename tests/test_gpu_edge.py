@@ -176,3 +176,11 @@ def test_repeated_runs_reuse_workspace(imm, orc, stream):
         r = imm.imm_run(dg, 3, 0.3, 1.0, 7, stream=stream)
         np.testing.assert_array_equal(r.seeds, o3["seeds"])
         assert r.theta == o3["theta"]
+    # a larger k first, then smaller ones: per-step selection state sized for
+    # the larger k must start clean for every later run
+    for k, eps, seed in [(25, 0.3, 100), (5, 0.3, 100), (1, 0.5, 3), (5, 0.5, 101), (25, 0.3, 5)]:
+        say(f"reuse k={k} eps={eps} seed={seed}")
+        o = orc.imm(g, k, eps, 1.0, seed)
+        r = imm.imm_run(dg, k, eps, 1.0, seed, stream=stream)
+        np.testing.assert_array_equal(r.seeds, o["seeds"])
+        np.testing.assert_array_equal(r.gains, o["gains"])
