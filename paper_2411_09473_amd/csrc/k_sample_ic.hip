@@ -3,7 +3,7 @@
 // Section II-A).
 //
 // Three kernels share the work of one sampling round:
-//  * ic_lane: a wave takes 64 sample ids at a time. Each lane draws the root
+//  * ic_lane: a wave takes 4 x 64 sample ids at a time. Each lane draws the root
 //    of its own sample and flips the coins of the root's in-edges (roots of
 //    in-degree <= kLaneDegCap); a root with no live in-edge is a complete set
 //    {root}, stored at once (at low edge probabilities that is most samples).
@@ -201,10 +201,16 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
 
 // ----------------------------------------------------------------- ic_lane
 
+// A wave claims kLaneRounds batches of 64 ids per ticket and appends its
+// pending samples once per ticket: the ticket and the pending-list length
+// are single counters that every wave of the launch updates.
+constexpr uint32_t kLaneRounds = 4;
+
 __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRange rg,
                                                         SampleOut o, uint32_t* pend,
                                                         uint32_t* pend_n, uint32_t* ticket) {
-    __shared__ uint32_t s_tk;
+    __shared__ uint32_t s_tk, s_np;
+    __shared__ uint32_t s_pend[kWave * kLaneRounds];
     __shared__ unsigned long long s_chunk;
     const uint32_t lane = threadIdx.x;
     const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
@@ -212,61 +218,76 @@ __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRang
     uint64_t st_sets = 0, st_edges = 0;  // lane-partial
     const uint32_t total = rg.list ? *rg.list_n : rg.count;
     for (;;) {
-        if (lane == 0) s_tk = atomicAdd(ticket, kIcTicketChunk);
-        __syncthreads();
-        const uint32_t base_pos = s_tk;
-        __syncthreads();
-        if (base_pos >= total) break;
-
-        const uint32_t my_pos = base_pos + lane;
-        const bool valid = my_pos < total;
-        const uint32_t my_idx = valid ? (rg.list ? rg.list[my_pos] : my_pos) : 0u;
-        const uint64_t ms = rg.id_lo + my_idx;
-        uint32_t root = 0, rbeg = 0, rend = 0;
-        bool single = false;
-        if (valid) {
-            root = sample_root(rg.seed, ms, g.n);
-            rbeg = g.off[root];
-            rend = g.off[root + 1];
-            single = rend - rbeg <= kLaneDegCap;
-            for (uint32_t grp = rbeg >> 2; single && (grp << 2) < rend; ++grp) {
-                const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
-                const Philox4 r = philox10(grp, (uint32_t)ms, (uint32_t)(ms >> 32), 1u, k0, k1);
-                const uint32_t e0 = grp << 2;
-                if ((r.x < th.x && e0 >= rbeg && e0 < rend) ||
-                    (r.y < th.y && e0 + 1 >= rbeg && e0 + 1 < rend) ||
-                    (r.z < th.z && e0 + 2 >= rbeg && e0 + 2 < rend) ||
-                    (r.w < th.w && e0 + 3 >= rbeg && e0 + 3 < rend))
-                    single = false;
-            }
+        if (lane == 0) {
+            s_tk = atomicAdd(ticket, kWave * kLaneRounds);
+            s_np = 0;
         }
-        const uint64_t smask = __ballot(single);
-        const uint32_t nsingle = (uint32_t)__popcll(smask);
-        if (nsingle) {
-            uint64_t off = 0;
-            const bool ok = stage_reserve(sg, nsingle, &off, &s_chunk, o);
-            const uint32_t rank = (uint32_t)__popcll(smask & ((1ull << lane) - 1ull));
-            if (single) {
-                if (ok) {
-                    o.stage[off + rank] = root;
-                    atomicAdd(&o.counts[root], 1u);
-                    o.stage_off[my_idx] = off + rank;
-                    o.sizes[my_idx] = 1;
-                    st_sets += 1;
-                    st_edges += rend - rbeg;
-                } else {
-                    o.retry[atomicAdd(o.retry_n, 1u)] = my_idx;
+        __syncthreads();
+        const uint32_t ticket_pos = s_tk;
+        __syncthreads();
+        if (ticket_pos >= total) break;
+
+        for (uint32_t round = 0; round < kLaneRounds; ++round) {
+            const uint32_t base_pos = ticket_pos + round * kWave;
+            if (base_pos >= total) break;
+            const uint32_t my_pos = base_pos + lane;
+            const bool valid = my_pos < total;
+            const uint32_t my_idx = valid ? (rg.list ? rg.list[my_pos] : my_pos) : 0u;
+            const uint64_t ms = rg.id_lo + my_idx;
+            uint32_t root = 0, rbeg = 0, rend = 0;
+            bool single = false;
+            if (valid) {
+                root = sample_root(rg.seed, ms, g.n);
+                rbeg = g.off[root];
+                rend = g.off[root + 1];
+                single = rend - rbeg <= kLaneDegCap;
+                for (uint32_t grp = rbeg >> 2; single && (grp << 2) < rend; ++grp) {
+                    const uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4ull * grp);
+                    const Philox4 r = philox10(grp, (uint32_t)ms, (uint32_t)(ms >> 32), 1u, k0, k1);
+                    const uint32_t e0 = grp << 2;
+                    if ((r.x < th.x && e0 >= rbeg && e0 < rend) ||
+                        (r.y < th.y && e0 + 1 >= rbeg && e0 + 1 < rend) ||
+                        (r.z < th.z && e0 + 2 >= rbeg && e0 + 2 < rend) ||
+                        (r.w < th.w && e0 + 3 >= rbeg && e0 + 3 < rend))
+                        single = false;
                 }
             }
+            const uint64_t smask = __ballot(single);
+            const uint32_t nsingle = (uint32_t)__popcll(smask);
+            if (nsingle) {
+                uint64_t off = 0;
+                const bool ok = stage_reserve(sg, nsingle, &off, &s_chunk, o);
+                const uint32_t rank = (uint32_t)__popcll(smask & ((1ull << lane) - 1ull));
+                if (single) {
+                    if (ok) {
+                        o.stage[off + rank] = root;
+                        atomicAdd(&o.counts[root], 1u);
+                        o.stage_off[my_idx] = off + rank;
+                        o.sizes[my_idx] = 1;
+                        st_sets += 1;
+                        st_edges += rend - rbeg;
+                    } else {
+                        o.retry[atomicAdd(o.retry_n, 1u)] = my_idx;
+                    }
+                }
+            }
+            // pending samples wait in LDS until the ticket is done
+            const bool pending = valid && !single;
+            const uint64_t pmask = __ballot(pending);
+            const uint32_t np = s_np;
+            if (pending) s_pend[np + (uint32_t)__popcll(pmask & ((1ull << lane) - 1ull))] = my_idx;
+            __syncthreads();
+            if (lane == 0) s_np = np + (uint32_t)__popcll(pmask);
+            __syncthreads();
         }
-        const bool pending = valid && !single;
-        const uint64_t pmask = __ballot(pending);
-        if (pmask) {
+        const uint32_t np = s_np;
+        if (np) {
             uint32_t pbase = 0;
-            if (lane == 0) pbase = atomicAdd(pend_n, (uint32_t)__popcll(pmask));
+            if (lane == 0) pbase = atomicAdd(pend_n, np);
             pbase = __shfl(pbase, 0, kWave);
-            if (pending) pend[pbase + (uint32_t)__popcll(pmask & ((1ull << lane) - 1ull))] = my_idx;
+            for (uint32_t i = lane; i < np; i += kWave) pend[pbase + i] = s_pend[i];
         }
+        __syncthreads();
     }
     st_sets = wave_sum64(st_sets);
     st_edges = wave_sum64(st_edges);
@@ -550,7 +571,8 @@ uint32_t ic_bfs_grid(int device, uint32_t team) {
 hipError_t launch_ic_lane(const IcGraphDev& g, const SampleRange& r, const SampleOut& o,
                           uint32_t* pend, uint32_t* pend_n, uint32_t* ticket, uint32_t grid,
                           hipStream_t st) {
-    const uint32_t need = (r.count + kIcTicketChunk - 1) / kIcTicketChunk;
+    const uint32_t per = kWave * kLaneRounds;
+    const uint32_t need = (r.count + per - 1) / per;
     if (grid > need) grid = need;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(ic_lane_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, pend, pend_n,
