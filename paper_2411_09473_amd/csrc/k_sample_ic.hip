@@ -37,6 +37,7 @@ namespace {
 
 constexpr uint32_t kLaneDegCap = 32;  // roots tried one per lane up to this in-degree
 constexpr uint32_t kStageChunk = kIcStageChunk;
+constexpr uint32_t kLargePage = 1u << 16;  // groups per start-bitmap page of a giant-set workgroup
 
 // LDS shape of a BFS team of TEAM waves: members kept on chip and a visited
 // hash of twice that many slots (load factor <= 1/2).
@@ -46,6 +47,7 @@ struct Team {
     static constexpr uint32_t CAP = 256 * TEAM;
     static constexpr uint32_t HBITS = TEAM == 1 ? 9 : (TEAM == 2 ? 10 : 11);
     static constexpr uint32_t HSIZE = 1u << HBITS;
+    static constexpr uint32_t PAGE = 4096 * TEAM;  // groups per start-bitmap page
     static_assert(2 * CAP == HSIZE, "hash holds twice the member capacity");
     static_assert(CAP <= kStageChunk, "a set fits one staging chunk");
 };
@@ -80,39 +82,91 @@ __device__ __forceinline__ bool stage_reserve(Stager& c, uint32_t need, uint64_t
     return true;
 }
 
-// Block-wide exclusive scan of one uint32 per thread; returns the total.
+// One chunk of a BFS level: up to BS queued vertices, one per thread. Their
+// in-edges are swept in aligned groups of four edges (one Philox call gives
+// the four coins of a group). The chunk's groups are numbered 0 .. G-1; the
+// k-th entry with in-edges (rank k) owns groups [a_k, a_k + ng_k), which are
+// edge groups g0_k, g0_k + 1, ... of its column [beg_k, end_k), and its layout
+// record is s_ent[k] = (a_k, g0_k, beg_k, end_k).
+//
+// Owner lookup without a search per group: the groups are swept in pages of
+// PAGE groups, and an LDS bitmap holds one bit per group of the page, set
+// where an entry starts. A page is split into one contiguous span per wave (a
+// multiple of 64 groups); the wave finds the owner of its span's first group
+// once, by bisection, and from there the owner of any group is that rank plus
+// the starts between: one 64-bit popcount per row of 64 groups.
+struct LevelChunk {
+    uint32_t G;   // groups of the chunk
+    uint32_t ne;  // entries with at least one in-edge
+    uint32_t a;   // this thread's entry: first group ...
+    uint32_t ng;  // ... and group count (0 past the chunk's entries)
+};
+
+// Span of each wave's share of a page of pn groups (a multiple of 64).
 template <uint32_t BS>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* excl_out,
-                                                    uint32_t* s_wsum) {
-    const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    const uint32_t incl = wave_incl_scan(v);
-    if (BS == kWave) {
-        *excl_out = incl - v;
-        return __shfl(incl, kWave - 1, kWave);
-    }
-    if (lane == kWave - 1) s_wsum[w] = incl;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < BS / kWave; ++i) {
-        const uint32_t x = s_wsum[i];
-        if (i < w) before += x;
-        total += x;
-    }
-    *excl_out = before + incl - v;
-    return total;
+__device__ __forceinline__ uint32_t page_span(uint32_t pn) {
+    constexpr uint32_t NW = BS / kWave;
+    return (((pn + NW - 1u) / NW) + kWave - 1u) & ~(kWave - 1u);
 }
 
-// Lay out the in-edge groups of queue entries [head, head + nb) (nb <= BS):
-// entry i owns groups [s_base[i], s_base[i+1]) of the level, which are edge
-// groups s_g0[i] + 0, 1, ... of its column [s_beg[i], s_end[i]). Returns the
-// level's group count; adds the entries' in-degrees to *edges.
+// Block-wide layout scan: the exclusive prefix sum of ng over the threads
+// (*a), and the rank of the thread among threads with ng > 0 (*rank, from a
+// ballot). Returns (sum of ng, count with ng > 0). s_wsum holds 2 * BS / 64
+// words.
 template <uint32_t BS>
-__device__ __forceinline__ uint32_t level_layout(const IcGraphDev& g, const uint32_t* queue,
-                                                 uint32_t head, uint32_t nb, uint32_t* s_base,
-                                                 uint32_t* s_g0, uint32_t* s_beg,
-                                                 uint32_t* s_end, uint32_t* s_wsum,
-                                                 uint32_t* edges) {
+__device__ __forceinline__ uint2 block_layout_scan(uint32_t ng, uint32_t* a, uint32_t* rank,
+                                                   uint32_t* s_wsum) {
+    constexpr uint32_t NW = BS / kWave;
+    const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const uint32_t incl = wave_incl_scan(ng);
+    const uint64_t nz = __ballot(ng != 0u);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
+    const uint32_t wcount = (uint32_t)__popcll(nz);
+    if (NW == 1) {
+        *a = incl - ng;
+        *rank = below;
+        return make_uint2(__shfl(incl, kWave - 1, kWave), wcount);
+    }
+    if (lane == kWave - 1) {
+        s_wsum[w] = incl;
+        s_wsum[NW + w] = wcount;
+    }
+    __syncthreads();
+    if (NW <= 4) {
+        uint32_t bu = 0, bv = 0, tu = 0, tv = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < NW; ++i) {
+            const uint32_t x = s_wsum[i], y = s_wsum[NW + i];
+            if (i < w) {
+                bu += x;
+                bv += y;
+            }
+            tu += x;
+            tv += y;
+        }
+        *a = bu + incl - ng;
+        *rank = bv + below;
+        return make_uint2(tu, tv);
+    }
+    // many waves: scan the wave totals across the lanes of every wave
+    const uint32_t su = wave_incl_scan(lane < NW ? s_wsum[lane] : 0u);
+    const uint32_t sv = wave_incl_scan(lane < NW ? s_wsum[NW + lane] : 0u);
+    const uint32_t bu = __shfl(su, (int)(w ? w - 1 : 0), kWave);
+    const uint32_t bv = __shfl(sv, (int)(w ? w - 1 : 0), kWave);
+    *a = (w ? bu : 0u) + incl - ng;
+    *rank = (w ? bv : 0u) + below;
+    return make_uint2(__shfl(su, NW - 1, kWave), __shfl(sv, NW - 1, kWave));
+}
+
+// Lay out the chunk of queue entries [head, head + nb) (nb <= BS) and set the
+// start bits of its first page (the bitmap must be all zero on entry). Adds
+// the entries' in-degrees to *edges. The caller synchronises before the sweep.
+template <uint32_t BS, uint32_t PAGE>
+__device__ __forceinline__ LevelChunk level_layout(const IcGraphDev& g, const uint32_t* queue,
+                                                   uint32_t head, uint32_t nb, uint4* s_ent,
+                                                   uint32_t* s_start, uint32_t* s_wsum,
+                                                   uint32_t* edges) {
     const uint32_t tid = threadIdx.x;
     uint32_t beg = 0, end = 0;
     if (tid < nb) {
@@ -121,81 +175,149 @@ __device__ __forceinline__ uint32_t level_layout(const IcGraphDev& g, const uint
         end = g.off[v + 1];
     }
     const uint32_t ng = end > beg ? ((end + 3) >> 2) - (beg >> 2) : 0u;
-    uint32_t excl;
-    const uint32_t G = block_excl_scan<BS>(ng, &excl, s_wsum);
-    s_base[tid] = excl;
-    s_g0[tid] = beg >> 2;
-    s_beg[tid] = beg;
-    s_end[tid] = end;
+    uint32_t a, rank;
+    const uint2 tot = block_layout_scan<BS>(ng, &a, &rank, s_wsum);
+    if (ng) {
+        s_ent[rank] = make_uint4(a, beg >> 2, beg, end);
+        if (a < PAGE) atomicOr(&s_start[a >> 5], 1u << (a & 31));
+    }
     *edges += end - beg;
-    return G;
+    return LevelChunk{tot.x, tot.y, a, ng};
 }
 
-// Flip the coins of one level's G groups (layout from level_layout), BS
-// threads, each taking groups tid, tid + BS, ...; on_live(u) runs for the
-// source u of every live in-edge. After a wave has seen a live edge it asks
-// stop() (uniform across the wave) whether to abandon the level.
-template <uint32_t BS, class OnLive, class Stop>
+// Rank of the entry owning group t: the last k < ne with s_ent[k].x <= t
+// (ne <= 64 * 64, s_ent[0].x == 0). The whole wave searches: 64 candidates
+// per step, two steps at most.
+__device__ __forceinline__ uint32_t owner_rank(const uint4* s_ent, uint32_t ne, uint32_t t) {
+    const uint32_t lane = lane_id();
+    uint32_t base = 0;
+    if (ne > kWave) {
+        const uint32_t i = lane * kWave;
+        const bool le = i < ne && s_ent[i].x <= t;
+        base = ((uint32_t)__popcll(__ballot(le)) - 1u) * kWave;
+    }
+    const uint32_t i = base + lane;
+    const bool le = i < ne && s_ent[i].x <= t;
+    return base + (uint32_t)__popcll(__ballot(le)) - 1u;
+}
+
+// Bits j of the edges 4*grp + j that lie in the column [beg, end).
+__device__ __forceinline__ uint32_t column_bits(uint32_t grp, uint32_t beg, uint32_t end) {
+    const uint32_t e0 = grp << 2;
+    const uint32_t lo = beg > e0 ? beg - e0 : 0u;
+    const uint32_t hi = end - e0 < 4u ? end - e0 : 4u;
+    return (0xFu >> (4u - hi)) & (0xFu << lo);
+}
+
+// Bits j of the four coins of a group that come up live.
+__device__ __forceinline__ uint32_t coin_bits(const Philox4& r, const uint4& th) {
+    return (r.x < th.x ? 1u : 0u) | (r.y < th.y ? 2u : 0u) | (r.z < th.z ? 4u : 0u) |
+           (r.w < th.w ? 8u : 0u);
+}
+
+// Read and clear the 64 start bits of the row at page position r (r % 64 == 0).
+__device__ __forceinline__ uint64_t take_row(uint32_t* s_start, uint32_t r) {
+    uint2* p = reinterpret_cast<uint2*>(s_start + (r >> 5));
+    const uint2 v = *p;
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) *p = make_uint2(0u, 0u);
+    return (uint64_t)v.x | ((uint64_t)v.y << 32);
+}
+
+// Flip the coins of a chunk laid out by level_layout (first page's start bits
+// set, and synchronised). Each wave sweeps its span of every page two rows of
+// 64 groups at a time (both threshold loads and both Philox chains in flight)
+// and clears the start bits it read, so the bitmap is all zero again on
+// return. on_live(u) runs for the source u of every live in-edge. After a
+// wave has seen a live edge it asks stop() whether to abandon the chunk; the
+// whole block takes the stop at the next page boundary.
+template <uint32_t BS, uint32_t PAGE, bool PAIR, class OnLive, class Stop>
 __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, uint32_t shi,
-                                            uint32_t k0, uint32_t k1, const uint32_t* s_base,
-                                            const uint32_t* s_g0, const uint32_t* s_beg,
-                                            const uint32_t* s_end, uint32_t nb, uint32_t G,
+                                            uint32_t k0, uint32_t k1, const uint4* s_ent,
+                                            uint32_t* s_start, const LevelChunk& ch,
                                             uint32_t* live_n, OnLive on_live, Stop stop) {
-    // the owner of the thread's current group and its group range [lo, hi),
-    // kept in registers until the thread's groups move past it
-    uint32_t ow = 0, lo = 0;
-    uint32_t hi = nb > 1 ? s_base[1] : G;
-    uint32_t g0 = s_g0[0], eb = s_beg[0], ee = s_end[0];
-    auto locate = [&](uint32_t t, uint32_t* grp, uint32_t* b, uint32_t* e) {
-        if (t >= hi) {
-            ow = owner_from(s_base, nb, t, ow);
-            lo = s_base[ow];
-            hi = ow + 1 < nb ? s_base[ow + 1] : G;
-            g0 = s_g0[ow];
-            eb = s_beg[ow];
-            ee = s_end[ow];
-        }
-        *grp = g0 + (t - lo);
-        *b = eb;
-        *e = ee;
-    };
-    auto live_mask = [](const Philox4& r, const uint4& th, uint32_t e0, uint32_t b, uint32_t e) {
-        uint32_t live = 0;
-        live |= (r.x < th.x && e0 >= b && e0 < e) ? 1u : 0u;
-        live |= (r.y < th.y && e0 + 1 >= b && e0 + 1 < e) ? 2u : 0u;
-        live |= (r.z < th.z && e0 + 2 >= b && e0 + 2 < e) ? 4u : 0u;
-        live |= (r.w < th.w && e0 + 3 >= b && e0 + 3 < e) ? 8u : 0u;
-        return live;
-    };
-    // two groups per thread and round (t and t + BS): both threshold loads
-    // and both Philox chains are in flight together
-    for (uint32_t t = threadIdx.x; t < G; t += 2 * BS) {
-        uint32_t ga, ba, ea, gb = 0, bb = 0, eb2 = 0;
-        locate(t, &ga, &ba, &ea);
-        const bool two = t + BS < G;
-        if (two) locate(t + BS, &gb, &bb, &eb2);
-        const uint4 tha = *reinterpret_cast<const uint4*>(g.thr + 4ull * ga);
-        const uint4 thb = two ? *reinterpret_cast<const uint4*>(g.thr + 4ull * gb)
-                              : make_uint4(0u, 0u, 0u, 0u);
-        const Philox4 ra = philox10(ga, slo, shi, 1u, k0, k1);
-        const Philox4 rb = philox10(gb, slo, shi, 1u, k0, k1);
-        uint32_t la = live_mask(ra, tha, ga << 2, ba, ea);
-        uint32_t lb = two ? live_mask(rb, thb, gb << 2, bb, eb2) : 0u;
-        const bool any = (la | lb) != 0u;
-        if (any) {
-            *live_n += (uint32_t)(__popc(la) + __popc(lb));
-            while (la) {
-                const uint32_t j = (uint32_t)__ffs(la) - 1u;
-                la &= la - 1u;
-                on_live(g.src[(ga << 2) + j]);
+    static_assert(PAGE % BS == 0, "wave spans of whole rows stay inside the page");
+    constexpr uint32_t STEP = PAIR ? 2 * kWave : kWave;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t upto = ~0ull >> (kWave - 1u - lane);  // row bits 0 .. lane
+    for (uint32_t p = 0; p < ch.G;) {
+        const uint32_t pn = ch.G - p < PAGE ? ch.G - p : PAGE;
+        const uint32_t span = page_span<BS>(pn);
+        const uint32_t w0 = w * span;
+        const uint32_t w1 = w0 + span < pn ? w0 + span : pn;
+        if (w0 < w1) {
+            // rank o owns the last group looked at; cur is its record and
+            // [cur.x, cur_hi) its groups. A row that lies inside that range
+            // after its start holds no start bit and needs no LDS access.
+            uint32_t o = p + w0 ? owner_rank(s_ent, ch.ne, p + w0) : 0u;
+            uint4 cur = s_ent[o];
+            uint32_t cur_hi = cur.x + (((cur.w + 3u) >> 2) - cur.y);
+            // groups and in-column edge bits of the lanes of the row at page position rr
+            auto row = [&](uint32_t rr, uint32_t* grp, uint32_t* cbits) {
+                const uint32_t pos = p + rr;
+                const bool valid = rr + lane < w1;
+                if (cur.x < pos && pos + kWave <= cur_hi) {
+                    *grp = cur.y + (pos + lane - cur.x);
+                    *cbits = valid ? column_bits(*grp, cur.z, cur.w) : 0u;
+                    return;
+                }
+                uint64_t bits = take_row(s_start, rr);
+                if (rr == w0) bits &= ~1ull;  // a start on the span's first group is o's own
+                const uint32_t ol = o + (uint32_t)__popcll(bits & upto);
+                o += (uint32_t)__popcll(bits);
+                const uint4 e = s_ent[ol];
+                *grp = e.y + (pos + lane - e.x);
+                *cbits = valid ? column_bits(*grp, e.z, e.w) : 0u;
+                // lane 63 is owned by rank o
+                cur = make_uint4((uint32_t)__builtin_amdgcn_readlane((int)e.x, 63),
+                                 (uint32_t)__builtin_amdgcn_readlane((int)e.y, 63),
+                                 (uint32_t)__builtin_amdgcn_readlane((int)e.z, 63),
+                                 (uint32_t)__builtin_amdgcn_readlane((int)e.w, 63));
+                cur_hi = cur.x + (((cur.w + 3u) >> 2) - cur.y);
+            };
+            uint32_t r = w0;
+            bool quit = false;
+            for (; r < w1; r += STEP) {
+                const bool two = PAIR && r + kWave < w1;  // wave-uniform
+                uint32_t ga, ca, gb = 0u, cb = 0u;
+                row(r, &ga, &ca);
+                if (two) row(r + kWave, &gb, &cb);
+                const bool va = ca != 0u, vb = cb != 0u;
+                const uint4 tha = va ? *reinterpret_cast<const uint4*>(g.thr + 4ull * ga)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+                const uint4 thb = vb ? *reinterpret_cast<const uint4*>(g.thr + 4ull * gb)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+                const Philox4 ra = philox10(ga, slo, shi, 1u, k0, k1);
+                const Philox4 rb = philox10(gb, slo, shi, 1u, k0, k1);
+                // live edges of both groups: bits 0-3 of group a, 4-7 of group b
+                uint32_t live = (coin_bits(ra, tha) & ca) | ((coin_bits(rb, thb) & cb) << 4);
+                const bool any = live != 0u;
+                if (any) {
+                    *live_n += (uint32_t)__popc(live);
+                    while (live) {
+                        const uint32_t j = (uint32_t)__ffs(live) - 1u;
+                        live &= live - 1u;
+                        on_live(g.src[j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u)]);
+                    }
+                }
+                if (__ballot(any) && stop()) {
+                    quit = true;
+                    break;
+                }
             }
-            while (lb) {
-                const uint32_t j = (uint32_t)__ffs(lb) - 1u;
-                lb &= lb - 1u;
-                on_live(g.src[(gb << 2) + j]);
+            if (quit) {
+                // the rows up to r + STEP are cleared; clear the rest of the span
+                for (uint32_t q = r + STEP; q < w1; q += kWave)
+                    if (lane < 2u) s_start[(q >> 5) + lane] = 0u;
             }
         }
-        if (__ballot(any) && stop()) break;
+        p += PAGE;
+        if (p >= ch.G) break;
+        __syncthreads();  // every wave is done with this page's bits
+        if (stop()) break;
+        if (ch.ng && ch.a >= p && ch.a - p < PAGE)
+            atomicOr(&s_start[(ch.a - p) >> 5], 1u << ((ch.a - p) & 31));
+        __syncthreads();
     }
 }
 
@@ -335,14 +457,16 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
     constexpr uint32_t BS = T::BS;
     __shared__ uint32_t hash[T::HSIZE];
     __shared__ uint32_t members[T::CAP];
-    __shared__ uint32_t s_base[BS], s_g0[BS], s_beg[BS], s_end[BS];
-    __shared__ uint32_t s_wsum[TEAM];
+    __shared__ uint4 s_ent[BS];
+    __shared__ uint32_t s_start[T::PAGE / 32];
+    __shared__ uint32_t s_wsum[2 * TEAM];
     __shared__ uint32_t s_size, s_over, s_tk;
     __shared__ unsigned long long s_chunk;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     for (uint32_t i = tid; i < T::HSIZE; i += BS) hash[i] = kEmpty;
+    for (uint32_t i = tid; i < T::PAGE / 32; i += BS) s_start[i] = 0u;
     Stager sg;
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;  // thread-partial
     const uint32_t total = *pend_n;
@@ -369,11 +493,11 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
         bool over = false;
         while (head < size) {
             const uint32_t nb = min(BS, size - head);
-            const uint32_t G = level_layout<BS>(g, members, head, nb, s_base, s_g0, s_beg, s_end,
-                                                s_wsum, &my_edges);
+            const LevelChunk ch = level_layout<BS, T::PAGE>(g, members, head, nb, s_ent, s_start,
+                                                            s_wsum, &my_edges);
             __syncthreads();
-            level_sweep<BS>(
-                g, slo, shi, k0, k1, s_base, s_g0, s_beg, s_end, nb, G, &my_live,
+            level_sweep<BS, T::PAGE, true>(
+                g, slo, shi, k0, k1, s_ent, s_start, ch, &my_live,
                 [&](uint32_t u) { team_insert<TEAM>(u, hash, members, &s_size, &s_over); },
                 [&]() { return lds_load(&s_over) != 0u; });
             __syncthreads();
@@ -448,8 +572,9 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
                                                              uint32_t* fail, uint32_t* fail_n,
                                                              uint32_t* over, uint32_t* over_n,
                                                              uint32_t* ticket, BigScratch b) {
-    __shared__ uint32_t s_base[kBigBlock], s_g0[kBigBlock], s_beg[kBigBlock], s_end[kBigBlock];
-    __shared__ uint32_t s_wsum[kBigBlock / kWave];
+    __shared__ uint4 s_ent[kBigBlock];
+    __shared__ uint32_t s_start[kLargePage / 32];
+    __shared__ uint32_t s_wsum[2 * kBigBlock / kWave];
     __shared__ uint32_t s_size, s_i;
     __shared__ unsigned long long s_off;
 
@@ -459,6 +584,7 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
     uint32_t* q = b.queues + (size_t)blockIdx.x * b.qcap;
     const uint32_t cnt = *list_n;
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;
+    for (uint32_t i = tid; i < kLargePage / 32; i += kBigBlock) s_start[i] = 0u;
 
     for (;;) {
         if (tid == 0) s_i = atomicAdd(ticket, 1u);
@@ -481,11 +607,11 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
         bool overflow = false;
         while (head < size) {
             const uint32_t nb = min(kBigBlock, size - head);
-            const uint32_t G = level_layout<kBigBlock>(g, q, head, nb, s_base, s_g0, s_beg,
-                                                       s_end, s_wsum, &my_edges);
+            const LevelChunk ch = level_layout<kBigBlock, kLargePage>(g, q, head, nb, s_ent,
+                                                                      s_start, s_wsum, &my_edges);
             __syncthreads();
-            level_sweep<kBigBlock>(
-                g, slo, shi, k0, k1, s_base, s_g0, s_beg, s_end, nb, G, &my_live,
+            level_sweep<kBigBlock, kLargePage, (kBigBlock < 1024)>(
+                g, slo, shi, k0, k1, s_ent, s_start, ch, &my_live,
                 [&](uint32_t u) {
                     const uint32_t bit = 1u << (u & 31);
                     const uint32_t old = atomicOr(&bm[u >> 5], bit);
