@@ -133,6 +133,7 @@ struct Workspace {
     uint32_t* counts_acc = nullptr;   // occurrences over all sets so far
     uint32_t* counts_prev = nullptr;  // ... over the sets already indexed
     uint32_t* counts_work = nullptr;  // the greedy's working copy
+    uint32_t* heavy = nullptr;  // vertices with long index lists; their count at [n]
     uint32_t* inv_cursor = nullptr;
     uint64_t* inv_offs = nullptr;
     uint64_t cap_offs = 0;

@@ -177,6 +177,9 @@ constexpr uint32_t kArgSlots = 32;
 // ranges ascend with the instance index.
 struct SelectDesc {
     uint32_t* cw;
+    const uint32_t* cacc;     // index list length of every vertex (over all segments)
+    const uint32_t* heavy;    // vertices with cacc > kHeavyList ...
+    const uint32_t* n_heavy;  // ... and their number
     const uint64_t* inv_offs;
     const uint32_t* inv_set;
     const uint64_t* set_off;
@@ -194,10 +197,15 @@ struct SelectDesc {
     uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
 };
 constexpr uint32_t kMaxSegments = 64;
+// A recount gives a vertex with a longer index list a wave of its own.
+constexpr uint32_t kHeavyList = 4096;
 // Covered sets of at most this many members are decremented one per lane.
 constexpr uint32_t kSmallSet = 16;
 uint32_t argmax_blocks(uint32_t n);
 uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch);
+// cw = cacc, and the list of vertices with cacc > kHeavyList (*n_heavy zeroed).
+hipError_t launch_select_init(const uint32_t* cacc, uint32_t* cw, uint32_t n, uint32_t* heavy,
+                              uint32_t* n_heavy, hipStream_t st);
 // Seed step t (argmax, claim, decrement) of every instance with t < k.
 hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,
                               uint32_t arg_blocks, uint32_t sel_blocks, hipStream_t st);

@@ -216,13 +216,42 @@ __device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, u
 // The adaptive counter update: when a seed covers sets that hold a large
 // part of the pool, rebuilding each remaining count from the uncovered sets
 // (a gather over the index, no global atomics) is cheaper than decrementing
-// once per member of every covered set. A wave takes 64 consecutive
-// vertices; their index lists are one contiguous position range per
-// segment, which the wave sweeps coalesced, four positions per lane per
-// round, counting uncovered sets per vertex in LDS (the owner of a position
-// by binary search over the 65 list bounds). Selected vertices keep their
-// sentinel and zero counts stay zero.
+// once per member of every covered set. The work items are the vertices with
+// long index lists (more than kHeavyList positions), one wave each, then
+// tiles of 64 consecutive vertices, one wave each, which skip those vertices.
+// A tile's lists are one contiguous position range per segment, swept
+// coalesced, four positions per lane per round, counting uncovered sets per
+// vertex in LDS (the owner of a position by binary search over the 65 list
+// bounds). Selected vertices keep their sentinel and zero counts stay zero.
 constexpr uint32_t kRecountUnroll = 4;
+
+__device__ __forceinline__ bool set_covered(const SelectDesc& d, uint32_t s) {
+    return (d.covered[s >> 5] >> (s & 31)) & 1u;
+}
+
+// Uncovered sets in the index lists of one vertex, summed over the wave.
+__device__ uint32_t count_uncovered(const SelectDesc& d, uint32_t u) {
+    const uint32_t lane = threadIdx.x % kWave;
+    uint32_t cnt = 0;
+    for (uint32_t seg = 0; seg < d.nseg; ++seg) {
+        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+        const uint64_t b = io[u], e = io[u + 1];
+        for (uint64_t q = b + lane; q < e; q += kWave * kRecountUnroll) {
+            uint32_t sid[kRecountUnroll];
+#pragma unroll
+            for (uint32_t x = 0; x < kRecountUnroll; ++x) {
+                const uint64_t r = q + x * kWave;
+                sid[x] = r < e ? d.inv_set[r] : 0u;
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < kRecountUnroll; ++x)
+                if (q + x * kWave < e && !set_covered(d, sid[x])) ++cnt;
+        }
+    }
+#pragma unroll
+    for (uint32_t s = kWave / 2; s >= 1; s >>= 1) cnt += __shfl_xor(cnt, s, kWave);
+    return cnt;
+}
 
 __device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off,
                             uint32_t* lds_cnt) {
@@ -231,13 +260,27 @@ __device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off
     const uint32_t wv = threadIdx.x / kWave;
     const uint32_t wid = blk * wpb + wv;
     const uint32_t nw = d.sel_cnt * wpb;
+    const uint32_t nh = *d.n_heavy;
+    const uint64_t ntiles = ((uint64_t)d.n + kWave - 1) / kWave;
     uint32_t* s_off = lds_off + wv * (kWave + 1);  // this wave's 65 bounds
     uint32_t* s_cnt = lds_cnt + wv * kWave;        // this wave's 64 counters
-    for (uint64_t u0 = (uint64_t)wid * kWave; u0 < d.n; u0 += (uint64_t)nw * kWave) {
+    for (uint64_t item = wid; item < nh + ntiles; item += nw) {
+        if (item < nh) {
+            const uint32_t u = d.heavy[item];
+            const uint32_t c = d.cw[u];
+            if (c == 0u || c == kSelected) continue;
+            const uint32_t cnt = count_uncovered(d, u);
+            if (lane == 0) d.cw[u] = cnt;
+            continue;
+        }
+        const uint64_t u0 = (item - nh) * kWave;
         const uint32_t u = (uint32_t)u0 + lane;
-        const uint32_t c = u < d.n ? d.cw[u] : 0u;
-        const bool act = c != 0u && c != kSelected;
+        const bool in = u < d.n;
+        const uint32_t c = in ? d.cw[u] : 0u;
+        const bool heavy = in && d.cacc[u] > kHeavyList;
+        const bool act = c != 0u && c != kSelected && !heavy;
         if (!__ballot(act)) continue;
+        const uint64_t hmask = __ballot(heavy);
         s_cnt[lane] = 0u;
         const uint32_t hi_v = u0 + kWave < d.n ? (uint32_t)(u0 + kWave) : d.n;
         for (uint32_t seg = 0; seg < d.nseg; ++seg) {
@@ -252,32 +295,42 @@ __device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const uint32_t span = (uint32_t)(top - base);
-            for (uint32_t q = lane; q < span; q += kWave * kRecountUnroll) {
-                uint32_t sid[kRecountUnroll];
+            // sweep the runs of lanes between long-list vertices
+            for (uint32_t l0 = 0; l0 < kWave;) {
+                const uint64_t light_from = ~hmask & (~0ull << l0);
+                if (!light_from) break;
+                l0 = (uint32_t)__ffsll((long long)light_from) - 1u;
+                const uint64_t heavy_after = hmask & (~0ull << l0);
+                const uint32_t l1 =
+                    heavy_after ? (uint32_t)__ffsll((long long)heavy_after) - 1u : kWave;
+                const uint32_t lo_pos = s_off[l0], hi_pos = s_off[l1];
+                for (uint32_t q = lo_pos + lane; q < hi_pos; q += kWave * kRecountUnroll) {
+                    uint32_t sid[kRecountUnroll];
 #pragma unroll
-                for (uint32_t x = 0; x < kRecountUnroll; ++x) {
-                    const uint32_t r = q + x * kWave;
-                    sid[x] = r < span ? d.inv_set[base + r] : 0u;
-                }
+                    for (uint32_t x = 0; x < kRecountUnroll; ++x) {
+                        const uint32_t r = q + x * kWave;
+                        sid[x] = r < hi_pos ? d.inv_set[base + r] : 0u;
+                    }
 #pragma unroll
-                for (uint32_t x = 0; x < kRecountUnroll; ++x) {
-                    const uint32_t r = q + x * kWave;
-                    if (r < span && !((d.covered[sid[x] >> 5] >> (sid[x] & 31)) & 1u)) {
-                        // owner: the last lane whose list starts at or before r
-                        uint32_t lo = 0, hi = kWave;
-                        while (hi - lo > 1) {
-                            const uint32_t mid = (lo + hi) >> 1;
-                            if (s_off[mid] <= r) lo = mid; else hi = mid;
+                    for (uint32_t x = 0; x < kRecountUnroll; ++x) {
+                        const uint32_t r = q + x * kWave;
+                        if (r < hi_pos && !set_covered(d, sid[x])) {
+                            // owner: the last lane whose list starts at or before r
+                            uint32_t lo = 0, hi = kWave;
+                            while (hi - lo > 1) {
+                                const uint32_t mid = (lo + hi) >> 1;
+                                if (s_off[mid] <= r) lo = mid; else hi = mid;
+                            }
+                            atomicAdd(&s_cnt[lo], 1u);
                         }
-                        atomicAdd(&s_cnt[lo], 1u);
                     }
                 }
+                l0 = l1;
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (act) d.cw[u] = s_cnt[lane];
         __builtin_amdgcn_wave_barrier();
     }
@@ -339,6 +392,24 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     }
 }
 
+// cw = cacc; vertices with long index lists are appended to heavy (one
+// atomic per wave).
+__global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, uint32_t* cw,
+                                                          uint32_t n, uint32_t* heavy,
+                                                          uint32_t* n_heavy) {
+    const uint32_t u = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t c = u < n ? cacc[u] : 0u;
+    if (u < n) cw[u] = c;
+    const bool h = c > kHeavyList;
+    const uint64_t m = __ballot(h);
+    if (!m) return;
+    const uint32_t lane = lane_id();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(n_heavy, (uint32_t)__popcll(m));
+    base = __shfl(base, 0, kWave);
+    if (h) heavy[base + __popcll(m & ((1ull << lane) - 1ull))] = u;
+}
+
 }  // namespace
 
 uint32_t argmax_blocks(uint32_t n) {
@@ -355,6 +426,14 @@ uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch) {
     const uint64_t full = (uint64_t)cus * 4u;
     if (batch <= 1) return (uint32_t)full;
     return (uint32_t)std::min<uint64_t>(full, n_sets / 4096 + 8);
+}
+
+hipError_t launch_select_init(const uint32_t* cacc, uint32_t* cw, uint32_t n, uint32_t* heavy,
+                              uint32_t* n_heavy, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(select_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cacc, cw, n,
+                       heavy, n_heavy);
+    return hipGetLastError();
 }
 
 hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,

@@ -143,6 +143,7 @@ imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_
     IMM_TRY(w.arena.alloc((void**)&w.counts_acc, (uint64_t)n * 4, "counts"));
     IMM_TRY(w.arena.alloc((void**)&w.counts_prev, (uint64_t)n * 4, "counts (indexed)"));
     IMM_TRY(w.arena.alloc((void**)&w.counts_work, (uint64_t)n * 4 + 16, "counts_work"));
+    IMM_TRY(w.arena.alloc((void**)&w.heavy, (uint64_t)n * 4 + 16, "heavy vertex list"));
     IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
     IMM_TRY(w.arena.alloc((void**)&w.desc_d, sizeof(SelectDesc), "select descriptor"));
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
@@ -478,15 +479,18 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
     // a seed's queue entries: at most one per started 64 members of every set
     IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.p_ub / 64 + 1, 0, st,
                  "chunk queue"));
-    HIP_TRY(hipMemcpyAsync(w.counts_work, w.counts_acc, (uint64_t)w.n * 4,
-                           hipMemcpyDeviceToDevice, st));
+    // working counts, and the list of vertices whose index lists are long
+    HIP_TRY(hipMemsetAsync(w.heavy + w.n, 0, 4, st));
+    HIP_TRY(launch_select_init(w.counts_acc, w.counts_work, w.n, w.heavy, w.heavy + w.n, st));
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
     // the whole block: its layout follows the capacity cap_k, not this k
     HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
     if (w.nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
-    *d = SelectDesc{w.counts_work, w.inv_offs, w.inv_set, w.set_off, w.set_vtx, w.covered,
-                    w.slots, w.seeds_d, w.gains_d, w.chunks, w.chunk_n, w.cap_chunks,
-                    w.cov_entries, w.n, k, w.nseg, (uint32_t)w.n_sets, 0, 0, 0, 0};
+    *d = SelectDesc{w.counts_work, w.counts_acc, w.heavy,     w.heavy + w.n, w.inv_offs,
+                    w.inv_set,     w.set_off,    w.set_vtx,   w.covered,     w.slots,
+                    w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
+                    w.cov_entries, w.n,          k,           w.nseg,        (uint32_t)w.n_sets,
+                    0,             0,            0,           0};
     return IMM_OK;
 }
 
