@@ -37,6 +37,80 @@ constexpr uint32_t kArgBS = 256;
 constexpr uint32_t kClaimBS = 256;
 constexpr uint32_t kDecBS = 256;
 
+#define IMM_GLOBAL __attribute__((address_space(1)))
+
+// A seed-step descriptor as the kernels use it: a register copy whose
+// pointers are typed as global memory. Accesses through pointers loaded from
+// memory would otherwise compile to flat instructions, which also count
+// against the LDS wait counter, so every LDS wait in a loop would drain the
+// loop's outstanding global loads as well.
+struct SelView {
+    IMM_GLOBAL uint32_t* cw;
+    const IMM_GLOBAL uint32_t* cacc;
+    const IMM_GLOBAL uint32_t* heavy;
+    const IMM_GLOBAL uint32_t* n_heavy;
+    const IMM_GLOBAL uint64_t* inv_offs;
+    const IMM_GLOBAL uint32_t* inv_set;
+    const IMM_GLOBAL uint64_t* set_off;
+    const IMM_GLOBAL uint32_t* set_vtx;
+    IMM_GLOBAL uint32_t* covered;
+    IMM_GLOBAL unsigned long long* slots;
+    IMM_GLOBAL uint32_t* seeds;
+    IMM_GLOBAL uint32_t* gains;
+    IMM_GLOBAL Chunk* chunks;
+    IMM_GLOBAL uint32_t* chunk_n;
+    uint64_t chunk_cap;
+    IMM_GLOBAL unsigned long long* cov_entries;
+    uint32_t n, k, nseg, n_sets;
+    uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
+};
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte records through global pointers (one dwordx4 access each).
+__device__ __forceinline__ uint4 load_u4(const IMM_GLOBAL uint4* p) {
+    const u32x4 v = *(const IMM_GLOBAL u32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ Chunk load_chunk(const IMM_GLOBAL Chunk* p) {
+    const u32x4 v = *(const IMM_GLOBAL u32x4*)p;
+    return Chunk{(uint64_t)v.x | ((uint64_t)v.y << 32), v.z, v.w};
+}
+__device__ __forceinline__ void store_chunk(IMM_GLOBAL Chunk* p, uint64_t off, uint32_t len) {
+    *(IMM_GLOBAL u32x4*)p = u32x4{(uint32_t)off, (uint32_t)(off >> 32), len, 0u};
+}
+
+template <class T>
+__device__ __forceinline__ IMM_GLOBAL T* glb(T* p) {
+    return (IMM_GLOBAL T*)p;
+}
+
+__device__ __forceinline__ SelView view_of(const SelectDesc& d) {
+    return SelView{glb(d.cw),      glb(d.cacc),    glb(d.heavy),   glb(d.n_heavy),
+                   glb(d.inv_offs), glb(d.inv_set), glb(d.set_off), glb(d.set_vtx),
+                   glb(d.covered), glb(d.slots),   glb(d.seeds),   glb(d.gains),
+                   glb(d.chunks),  glb(d.chunk_n), d.chunk_cap,    glb(d.cov_entries),
+                   d.n,            d.k,            d.nseg,         d.n_sets,
+                   d.arg_lo,       d.arg_cnt,      d.sel_lo,       d.sel_cnt};
+}
+
+// Device-scope relaxed atomics on global memory (what atomicAdd and friends do).
+__device__ __forceinline__ uint32_t g_add(IMM_GLOBAL uint32_t* p, uint32_t x) {
+    return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_sub(IMM_GLOBAL uint32_t* p, uint32_t x) {
+    (void)__hip_atomic_fetch_sub(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_or(IMM_GLOBAL uint32_t* p, uint32_t x) {
+    return __hip_atomic_fetch_or(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_add64(IMM_GLOBAL unsigned long long* p, unsigned long long x) {
+    (void)__hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_max64(IMM_GLOBAL unsigned long long* p, unsigned long long x) {
+    (void)__hip_atomic_fetch_max(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t vkey(uint32_t c, uint32_t v) {
     return c == kSelected ? 0ull : (((uint64_t)c << 32) | (uint64_t)(~v));
 }
@@ -60,18 +134,18 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
     __shared__ uint64_t s_w[kArgBS / kWave];
     const uint32_t q = find_inst(descs, nq, blockIdx.x, true);
     if (q == nq) return;
-    const SelectDesc& d = descs[q];
+    const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
-    const uint32_t* cw = d.cw;
+    const IMM_GLOBAL uint32_t* cw = d.cw;
     const uint32_t n = d.n;
     const uint32_t blk = blockIdx.x - d.arg_lo;
     const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const uint32_t gtid = blk * kArgBS + tid, gthreads = d.arg_cnt * kArgBS;
     uint64_t best = 0;
     const uint32_t n4 = n >> 2;
-    const uint4* cw4 = reinterpret_cast<const uint4*>(cw);
+    const IMM_GLOBAL uint4* cw4 = (const IMM_GLOBAL uint4*)cw;
     for (uint32_t x = gtid; x < n4; x += gthreads) {
-        const uint4 c = cw4[x];
+        const uint4 c = load_u4(cw4 + x);
         const uint32_t v = x << 2;
         uint64_t k = vkey(c.x, v);
         uint64_t y = vkey(c.y, v + 1); k = y > k ? y : k;
@@ -90,11 +164,11 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
     if (tid == 0) {
         uint64_t b = s_w[0];
         for (uint32_t x = 1; x < kArgBS / kWave; ++x) b = s_w[x] > b ? s_w[x] : b;
-        atomicMax(&d.slots[(uint64_t)t * kArgSlots + blk % kArgSlots], (unsigned long long)b);
+        g_max64(&d.slots[(uint64_t)t * kArgSlots + blk % kArgSlots], (unsigned long long)b);
     }
 }
 
-__device__ __forceinline__ uint64_t slots_max(const unsigned long long* slots) {
+__device__ __forceinline__ uint64_t slots_max(const IMM_GLOBAL unsigned long long* slots) {
     uint64_t m = 0;
 #pragma unroll
     for (uint32_t x = 0; x < kArgSlots; ++x) m = slots[x] > m ? slots[x] : m;
@@ -105,7 +179,7 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
                                                          uint32_t t) {
     const uint32_t q = find_inst(descs, nq, blockIdx.x, false);
     if (q == nq) return;
-    const SelectDesc& d = descs[q];
+    const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t m = slots_max(d.slots + (uint64_t)t * kArgSlots);
@@ -115,15 +189,15 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
         d.gains[t] = (uint32_t)(m >> 32);
         d.cw[v] = kSelected;
     }
-    uint32_t* small_n = d.chunk_n + 2ull * t;
-    uint32_t* big_n = small_n + 1;
+    IMM_GLOBAL uint32_t* small_n = d.chunk_n + 2ull * t;
+    IMM_GLOBAL uint32_t* big_n = small_n + 1;
     const uint64_t step = (uint64_t)d.sel_cnt * kClaimBS;
     const uint32_t lane = threadIdx.x % kWave;
     const uint64_t lane_mask = (1ull << lane) - 1ull;
     // v's list bounds in every segment, loaded at once (lane s: segment s)
     uint64_t my_lb = 0, my_len = 0;
     if (lane < d.nseg) {
-        const uint64_t* io = d.inv_offs + (uint64_t)lane * ((uint64_t)d.n + 1);
+        const IMM_GLOBAL uint64_t* io = d.inv_offs + (uint64_t)lane * ((uint64_t)d.n + 1);
         my_lb = io[v];
         my_len = io[v + 1] - my_lb;
     }
@@ -149,7 +223,7 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
             if (i < total) {
                 const uint32_t j = d.inv_set[pos];
                 const uint32_t bit = 1u << (j & 31);
-                const uint32_t old = atomicOr(&d.covered[j >> 5], bit);
+                const uint32_t old = g_or(&d.covered[j >> 5], bit);
                 if (!(old & bit)) {
                     a = d.set_off[j];
                     sz = d.set_off[j + 1] - a;
@@ -163,28 +237,29 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
             const uint64_t smask = __ballot(small);
             if (smask) {
                 uint32_t sbase = 0;
-                if (lane == 0) sbase = atomicAdd(small_n, (uint32_t)__popcll(smask));
+                if (lane == 0) sbase = g_add(small_n, (uint32_t)__popcll(smask));
                 sbase = __shfl(sbase, 0, kWave);
-                if (small) d.chunks[sbase + (uint32_t)__popcll(smask & lane_mask)] =
-                    Chunk{a, (uint32_t)sz, 0u};
+                if (small)
+                    store_chunk(d.chunks + sbase + (uint32_t)__popcll(smask & lane_mask), a,
+                                (uint32_t)sz);
             }
             const uint32_t incl = wave_incl_scan(nbig);
             const uint32_t tot = __shfl(incl, kWave - 1, kWave);
             if (tot) {
                 uint32_t wbase = 0;
-                if (lane == kWave - 1) wbase = atomicAdd(big_n, tot);
+                if (lane == kWave - 1) wbase = g_add(big_n, tot);
                 wbase = __shfl(wbase, kWave - 1, kWave);
                 const uint32_t pos = wbase + incl - nbig;
                 for (uint32_t c = 0; c < nbig; ++c) {
                     const uint64_t o = (uint64_t)c * kWave;
-                    d.chunks[d.chunk_cap - 1 - (pos + c)] =
-                        Chunk{a + o, (uint32_t)(sz - o < kWave ? sz - o : kWave), 0u};
+                    store_chunk(d.chunks + (d.chunk_cap - 1 - (pos + c)), a + o,
+                                (uint32_t)(sz - o < kWave ? sz - o : kWave));
                 }
             }
         }
     }
     cov = wave_sum64(cov);
-    if (lane == 0 && cov) atomicAdd(&d.cov_entries[t], (unsigned long long)cov);
+    if (lane == 0 && cov) g_add64(&d.cov_entries[t], (unsigned long long)cov);
 }
 
 // Decrements summed per workgroup in an LDS table (vertex -> count) are
@@ -197,7 +272,7 @@ constexpr uint32_t kAggSize = 1u << kAggBits;
 constexpr uint32_t kAggProbes = 8;
 
 __device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, uint32_t* h_cnt,
-                                        uint32_t* cw) {
+                                        IMM_GLOBAL uint32_t* cw) {
     if (agg) {
         uint32_t slot = (u * 0x9E3779B1u) >> (32 - kAggBits);
         for (uint32_t p = 0; p < kAggProbes; ++p) {
@@ -210,7 +285,7 @@ __device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, u
             slot = (slot + 1) & (kAggSize - 1);
         }
     }
-    atomicSub(&cw[u], 1u);
+    g_sub(&cw[u], 1u);
 }
 
 // The adaptive counter update: when a seed covers sets that hold a large
@@ -220,32 +295,34 @@ __device__ __forceinline__ void agg_dec(uint32_t u, bool agg, uint32_t* h_key, u
 // long index lists (more than kHeavyList positions), one wave each, then
 // tiles of 64 consecutive vertices, one wave each, which skip those vertices.
 // A tile's lists are one contiguous position range per segment, swept
-// coalesced, four positions per lane per round, counting uncovered sets per
+// coalesced, sixteen positions per lane per round, counting uncovered sets per
 // vertex in LDS (the owner of a position by binary search over the 65 list
-// bounds). Selected vertices keep their sentinel and zero counts stay zero.
-constexpr uint32_t kRecountUnroll = 4;
-
-__device__ __forceinline__ bool set_covered(const SelectDesc& d, uint32_t s) {
-    return (d.covered[s >> 5] >> (s & 31)) & 1u;
-}
+// bounds). The index is read once per recount with non-temporal loads, so
+// the covered bitmap, looked up at random once per position, stays in L2.
+// Selected vertices keep their sentinel and zero counts stay zero.
+constexpr uint32_t kRecountUnroll = 16;
 
 // Uncovered sets in the index lists of one vertex, summed over the wave.
-__device__ uint32_t count_uncovered(const SelectDesc& d, uint32_t u) {
+__device__ uint32_t count_uncovered(const SelView& d, uint32_t u) {
     const uint32_t lane = threadIdx.x % kWave;
     uint32_t cnt = 0;
     for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-        const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+        const IMM_GLOBAL uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
         const uint64_t b = io[u], e = io[u + 1];
         for (uint64_t q = b + lane; q < e; q += kWave * kRecountUnroll) {
             uint32_t sid[kRecountUnroll];
 #pragma unroll
             for (uint32_t x = 0; x < kRecountUnroll; ++x) {
                 const uint64_t r = q + x * kWave;
-                sid[x] = r < e ? d.inv_set[r] : 0u;
+                sid[x] = r < e ? __builtin_nontemporal_load(d.inv_set + r) : 0u;
             }
+            uint32_t cw_[kRecountUnroll];  // all covered-bit words in flight together
 #pragma unroll
             for (uint32_t x = 0; x < kRecountUnroll; ++x)
-                if (q + x * kWave < e && !set_covered(d, sid[x])) ++cnt;
+                cw_[x] = q + x * kWave < e ? d.covered[sid[x] >> 5] : ~0u;
+#pragma unroll
+            for (uint32_t x = 0; x < kRecountUnroll; ++x)
+                cnt += ((cw_[x] >> (sid[x] & 31)) & 1u) ^ 1u;
         }
     }
 #pragma unroll
@@ -253,7 +330,7 @@ __device__ uint32_t count_uncovered(const SelectDesc& d, uint32_t u) {
     return cnt;
 }
 
-__device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off,
+__device__ void recount_all(const SelView& d, uint32_t blk, uint32_t* lds_off,
                             uint32_t* lds_cnt) {
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t wpb = kDecBS / kWave;
@@ -284,7 +361,7 @@ __device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off
         s_cnt[lane] = 0u;
         const uint32_t hi_v = u0 + kWave < d.n ? (uint32_t)(u0 + kWave) : d.n;
         for (uint32_t seg = 0; seg < d.nseg; ++seg) {
-            const uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
+            const IMM_GLOBAL uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
             const uint64_t base = io[u0];
             const uint64_t my = io[u < hi_v ? u : hi_v];
             const uint64_t top = io[hi_v];
@@ -304,19 +381,24 @@ __device__ void recount_all(const SelectDesc& d, uint32_t blk, uint32_t* lds_off
                 const uint32_t l1 =
                     heavy_after ? (uint32_t)__ffsll((long long)heavy_after) - 1u : kWave;
                 const uint32_t lo_pos = s_off[l0], hi_pos = s_off[l1];
-                for (uint32_t q = lo_pos + lane; q < hi_pos; q += kWave * kRecountUnroll) {
+                for (uint32_t q0 = lo_pos; q0 < hi_pos; q0 += kWave * kRecountUnroll) {
                     uint32_t sid[kRecountUnroll];
 #pragma unroll
                     for (uint32_t x = 0; x < kRecountUnroll; ++x) {
-                        const uint32_t r = q + x * kWave;
-                        sid[x] = r < hi_pos ? d.inv_set[base + r] : 0u;
+                        const uint32_t r = q0 + x * kWave + lane;
+                        sid[x] =
+                            r < hi_pos ? __builtin_nontemporal_load(d.inv_set + base + r) : 0u;
                     }
+                    uint32_t cw_[kRecountUnroll];  // all covered-bit words in flight together
+#pragma unroll
+                    for (uint32_t x = 0; x < kRecountUnroll; ++x)
+                        cw_[x] = q0 + x * kWave + lane < hi_pos ? d.covered[sid[x] >> 5] : ~0u;
 #pragma unroll
                     for (uint32_t x = 0; x < kRecountUnroll; ++x) {
-                        const uint32_t r = q + x * kWave;
-                        if (r < hi_pos && !set_covered(d, sid[x])) {
+                        const uint32_t r = q0 + x * kWave + lane;
+                        if (!((cw_[x] >> (sid[x] & 31)) & 1u)) {
                             // owner: the last lane whose list starts at or before r
-                            uint32_t lo = 0, hi = kWave;
+                            uint32_t lo = l0, hi = l1;
                             while (hi - lo > 1) {
                                 const uint32_t mid = (lo + hi) >> 1;
                                 if (s_off[mid] <= r) lo = mid; else hi = mid;
@@ -343,7 +425,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     __shared__ uint32_t h_key[kAggSize], h_cnt[kAggSize];
     const uint32_t q = find_inst(descs, nq, blockIdx.x, false);
     if (q == nq) return;
-    const SelectDesc& d = descs[q];
+    const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t pool = d.set_off[d.n_sets];
@@ -354,7 +436,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     const uint32_t ns = d.chunk_n[2ull * t], nb = d.chunk_n[2ull * t + 1];
     const uint32_t wpb = kDecBS / kWave;
     if (blk * kDecBS >= ns && blk * wpb >= nb) return;
-    uint32_t* cw = d.cw;
+    IMM_GLOBAL uint32_t* cw = d.cw;
     const uint32_t v = d.seeds[t];
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t threads = d.sel_cnt * kDecBS;
@@ -370,14 +452,14 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
         __syncthreads();
     }
     for (uint32_t e = blk * kDecBS + threadIdx.x; e < ns; e += threads) {
-        const Chunk ch = d.chunks[e];
+        const Chunk ch = load_chunk(d.chunks + e);
         for (uint32_t x = 0; x < ch.len; ++x) {
             const uint32_t u = d.set_vtx[ch.off + x];
             if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
         }
     }
     for (uint32_t c = wid; c < nb; c += nw) {
-        const Chunk ch = d.chunks[d.chunk_cap - 1 - c];
+        const Chunk ch = load_chunk(d.chunks + (d.chunk_cap - 1 - c));
         if (lane < ch.len) {
             const uint32_t u = d.set_vtx[ch.off + lane];
             if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
@@ -387,7 +469,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
         __syncthreads();
         for (uint32_t x = threadIdx.x; x < kAggSize; x += kDecBS) {
             const uint32_t c = h_cnt[x];
-            if (c) atomicSub(&cw[h_key[x]], c);
+            if (c) g_sub(&cw[h_key[x]], c);
         }
     }
 }
