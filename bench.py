@@ -36,9 +36,13 @@ PHILOX_OPS = 60
 
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, scaled by the 1 GiB copy calibration), for the kernel
-# and workload named, as recorded in profiles/; a kernel changed since its
-# counters were taken has no entry.
-MEASURED_TRAFFIC = {}
+# and workload named, as recorded in profiles/ (ic_large_youtube_ic_pmc.md,
+# lt_small_lj_lt_pmc.md); a kernel changed since its counters were taken has
+# no entry.
+MEASURED_TRAFFIC = {
+    ("youtube_ic", "ic_large_kernel"): 8.156e9,
+    ("lj_lt", "lt_small_kernel"): 1.941e9,
+}
 
 
 def algorithmic_bytes(model: str, sets: int, entries: int, edges: int, live: int) -> int:
