@@ -57,30 +57,44 @@ __device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
 
 // The live in-edge of the column [beg, end) for draw r: its record (src in
 // .y, src's column bounds in .z/.w), or .y = kNone. *reads counts the
-// records inspected. A short column is loaded whole in one round of
-// independent loads; a longer one starts at its guide entry.
+// records inspected. Every lane of a wave issues its first load before any
+// lane consumes one, so the two kinds of columns share one round trip:
+//  * a short column (d <= kDirectDeg) is loaded whole;
+//  * a longer one loads its guide entry, then reads four records per round
+//    trip from there (the answer is almost always within the first four).
 __device__ __forceinline__ uint4 lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
                                          uint32_t r, uint32_t* reads) {
     const uint32_t d = end - beg;
-    uint4 res = make_uint4(0u, kNone, 0u, 0u);
-    if (d <= kDirectDeg) {
+    const bool direct = d <= kDirectDeg;
+    uint4 p[kDirectDeg];
+    uint32_t e = 0;
+    if (direct) {
 #pragma unroll
-        for (uint32_t j = 0; j < kDirectDeg; ++j) {
-            if (j < d) {
-                const uint4 p = g.cs[beg + j];
-                if (res.y == kNone && r < p.x) res = p;
-            }
-        }
+        for (uint32_t j = 0; j < kDirectDeg; ++j)
+            p[j] = j < d ? g.cs[beg + j] : make_uint4(0u, kNone, 0u, 0u);
+    } else {
+        e = g.guide[beg + (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32)];
+    }
+    uint4 res = make_uint4(0u, kNone, 0u, 0u);
+    if (direct) {
+#pragma unroll
+        for (uint32_t j = 0; j < kDirectDeg; ++j)
+            if (j < d && res.y == kNone && r < p[j].x) res = p[j];
         *reads += d;
         return res;
     }
-    const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
-    uint32_t e = g.guide[beg + jb];
-    while (e < end) {
-        const uint4 p = g.cs[e];
-        ++*reads;
-        if (r < p.x) return p;
-        ++e;
+    for (; e < end; e += 4) {
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+            p[j] = e + j < end ? g.cs[e + j] : make_uint4(0xFFFFFFFFu, kNone, 0u, 0u);
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            if (res.y == kNone && e + j < end) {
+                ++*reads;
+                if (r < p[j].x) res = p[j];
+            }
+        }
+        if (res.y != kNone) break;
     }
     return res;
 }
