@@ -9,8 +9,11 @@
 // long in-edge lists of high in-degree hubs finish sooner, and fit LDS more
 // often, with two or four) and the giant-set workgroup (256 threads and many
 // sets in flight, or 1024 threads for fewer, wider BFS levels). The choice
-// is made by timing: one fixed batch of sample ids is drawn with every
-// candidate and the fastest BFS plus giant-set kernel time wins. A pass
+// is made by timing, at a steady-state batch size (smaller batches favour
+// the wider teams, which the full-size passes do not): one fixed batch of
+// sample ids is drawn with each candidate, the team first (with the 256-thread
+// giant-set shape) and then the giant-set shape with that team, and the
+// fastest BFS plus giant-set kernel time wins. A pass
 // that will defer many more giant sets than the wide shape has workgroups
 // uses the 256-thread shape regardless (see sample_pass). Every set is a pure
 // function of (graph, seed, sample id), so the choice never changes a result.
@@ -25,7 +28,12 @@ namespace imm {
 namespace {
 
 constexpr uint64_t kTuneSeed = 0x7475E5EEDull;
-constexpr uint64_t kTuneSamples = 1u << 16;
+// The IC batch is sized to about kTuneEntries set members (from the probe's
+// mean set size), between 2^14 and 2^20 samples.
+constexpr uint64_t kTuneSamples = 1u << 20;
+constexpr uint64_t kTuneEntries = 16u << 20;
+constexpr uint64_t kTuneLtSamples = 1u << 16;  // LT: walks per timed batch
+constexpr int kTuneReps = 2;  // each candidate is timed this often; the minimum counts
 // A probe of kProbeSamples with the wide shapes comes first; a graph whose
 // probe takes longer than kProbeMs (very deep or very large sets) keeps the
 // wide shapes without the full search, which would cost seconds.
@@ -45,14 +53,18 @@ imm_status tune_lt(imm_graph* g, hipStream_t st) {
     uint32_t pick = 12;
     for (int c = -1; c < 3; ++c) {
         g->lt_bloom_bits = c < 0 ? 10u : 12u - (uint32_t)c;
-        IMM_TRY(ws_reset(w, st, true));
-        IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneSamples));
-        HIP_TRY(hipStreamSynchronize(st));
+        double ms = -1.0;
         imm_stats s;
-        std::memset(&s, 0, sizeof(s));
-        fill_stats(w, &s);
+        for (int rep = 0; rep < (c < 0 ? 1 : kTuneReps); ++rep) {
+            IMM_TRY(ws_reset(w, st, true));
+            IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneLtSamples));
+            HIP_TRY(hipStreamSynchronize(st));
+            std::memset(&s, 0, sizeof(s));
+            fill_stats(w, &s);
+            const double t = s.ms_sample_main + s.ms_sample_big;
+            if (ms < 0.0 || t < ms) ms = t;
+        }
         if (c < 0) continue;
-        const double ms = s.ms_sample_main + s.ms_sample_big;
         if (log)
             std::fprintf(stderr, "imm tune: n=%u m=%llu LT filter 2^%u bits: walks %.3f ms, long %.3f ms\n",
                          g->n, (unsigned long long)g->m, g->lt_bloom_bits, s.ms_sample_main,
@@ -73,21 +85,10 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g->tune_mu);
     if (g->tuned) return IMM_OK;
     if (g->model == IMM_LT) return tune_lt(g, st);
-    struct Cand {
-        uint32_t team, big;
-    };
-    Cand cands[6];
-    int nc = 0;
-    for (uint32_t team : {1u, 2u, 4u}) {
-        if (g->team_forced && team != g->ic_team) continue;
-        for (uint32_t big : {256u, 1024u}) {
-            if (g->big_forced && big != g->ic_big_block) continue;
-            cands[nc++] = Cand{team, big};
-        }
-    }
     Workspace w;
     IMM_TRY(ws_init(w, g->n, g->device, st, 0));
     const bool log = std::getenv("IMM_TUNE_LOG") != nullptr;
+    uint64_t batch = kTuneSamples;
     {
         if (!g->team_forced) g->ic_team = 4;
         if (!g->big_forced) g->ic_big_block = 256;  // allocates the most slots
@@ -104,35 +105,76 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
             g->tuned = true;
             return IMM_OK;
         }
+        const double per_set = (double)s.entries / (double)kProbeSamples;
+        const double want = per_set > 0.0 ? (double)kTuneEntries / per_set : (double)kTuneSamples;
+        batch = want >= (double)kTuneSamples ? kTuneSamples
+                                             : (want <= 16384.0 ? 16384u : (uint64_t)want);
     }
-    double best = -1.0, pick_rate = 0.0;
-    Cand pick = cands[0];
-    // the first pass allocates the workspace (with the most giant-set slots
-    // any candidate uses) and is not timed
-    const uint32_t big0 = g->ic_big_block;
-    for (int c = -1; c < nc; ++c) {
-        g->ic_team = c < 0 ? cands[0].team : cands[c].team;
-        g->ic_big_block = c < 0 ? (g->big_forced ? big0 : 256u) : cands[c].big;
-        IMM_TRY(ws_reset(w, st, true));
-        IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneSamples));
-        HIP_TRY(hipStreamSynchronize(st));
-        imm_stats s;
-        std::memset(&s, 0, sizeof(s));
-        fill_stats(w, &s);
-        if (c < 0) continue;
-        const double ms = s.ms_sample_main + s.ms_sample_big;
-        if (log)
-            std::fprintf(stderr, "imm tune: n=%u m=%llu team=%u big=%u: bfs %.3f ms, giant %.3f ms\n",
-                         g->n, (unsigned long long)g->m, g->ic_team, g->ic_big_block,
-                         s.ms_sample_main, s.ms_sample_big);
-        if (best < 0.0 || ms < best) {
-            best = ms;
-            pick = cands[c];
-            pick_rate = (double)s.deferred / (double)kTuneSamples;
+    // one batch drawn with the shapes set on g; the fastest of kTuneReps
+    // timings of the BFS plus giant-set kernels
+    auto time_batch = [&](double* ms_out, double* defer_rate) -> imm_status {
+        double ms = -1.0;
+        for (int rep = 0; rep < kTuneReps; ++rep) {
+            IMM_TRY(ws_reset(w, st, true));
+            IMM_TRY(ws_extend(w, g, kTuneSeed, 0, batch));
+            HIP_TRY(hipStreamSynchronize(st));
+            imm_stats s;
+            std::memset(&s, 0, sizeof(s));
+            fill_stats(w, &s);
+            const double t = s.ms_sample_main + s.ms_sample_big;
+            if (ms < 0.0 || t < ms) ms = t;
+            *defer_rate = (double)s.deferred / (double)batch;
         }
+        if (log)
+            std::fprintf(stderr, "imm tune: n=%u m=%llu batch=%llu team=%u big=%u: %.3f ms\n",
+                         g->n, (unsigned long long)g->m, (unsigned long long)batch, g->ic_team,
+                         g->ic_big_block, ms);
+        *ms_out = ms;
+        return IMM_OK;
+    };
+    // the first pass allocates the workspace (with the most giant-set slots
+    // any shape uses) and is not timed
+    const uint32_t big0 = g->ic_big_block;
+    if (!g->big_forced) g->ic_big_block = 256;
+    IMM_TRY(ws_reset(w, st, true));
+    IMM_TRY(ws_extend(w, g, kTuneSeed, 0, batch));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (g->big_forced) g->ic_big_block = big0;
+    // the BFS team first (with the 256-thread giant-set shape), then the
+    // giant-set shape with that team
+    double best = -1.0, rate = 0.0, pick_rate = 0.0;
+    if (!g->team_forced) {
+        uint32_t pick = 4;
+        for (uint32_t team : {1u, 2u, 4u}) {
+            g->ic_team = team;
+            double ms = 0.0;
+            IMM_TRY(time_batch(&ms, &rate));
+            if (best < 0.0 || ms < best) {
+                best = ms;
+                pick = team;
+                pick_rate = rate;
+            }
+        }
+        g->ic_team = pick;
     }
-    g->ic_team = pick.team;
-    g->ic_big_block = pick.big;
+    if (!g->big_forced) {
+        uint32_t pick = 256;
+        best = -1.0;
+        for (uint32_t big : {256u, 1024u}) {
+            g->ic_big_block = big;
+            double ms = 0.0;
+            IMM_TRY(time_batch(&ms, &rate));
+            if (best < 0.0 || ms < best) {
+                best = ms;
+                pick = big;
+                pick_rate = rate;
+            }
+        }
+        g->ic_big_block = pick;
+    } else if (g->team_forced) {
+        double ms = 0.0;
+        IMM_TRY(time_batch(&ms, &pick_rate));
+    }
     g->defer_rate = pick_rate;
     g->tuned = true;
     return IMM_OK;

@@ -184,3 +184,74 @@ def test_repeated_runs_reuse_workspace(imm, orc, stream):
         r = imm.imm_run(dg, k, eps, 1.0, seed, stream=stream)
         np.testing.assert_array_equal(r.seeds, o["seeds"])
         np.testing.assert_array_equal(r.gains, o["gains"])
+
+
+def _sample_parity(imm, orc, g, seed, count, stream):
+    dg = imm.graph_from(g, stream=stream)
+    pool = imm.imm_sample(dg, seed, 0, count, stream=stream)
+    so, sv, cn = pool.export()
+    oso, osv = orc.sample(g, seed, 0, count)
+    cso, csv = canonical(oso, osv, g.n)
+    np.testing.assert_array_equal(so, cso)
+    np.testing.assert_array_equal(sv, csv)
+    np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
+    return so
+
+
+def _hub_graph(n, p_in):
+    # vertex 0 has an in-edge from every other vertex (probability p_in) and
+    # an out-edge to every other vertex (certain): every set reaches the hub
+    # and sweeps its whole column
+    edges = [(v, 0) for v in range(1, n)] + [(0, v) for v in range(1, n)]
+    thr = [int(p_in * T32)] * (n - 1) + [T32 - 1] * (n - 1)
+    return synth.tiny_graph(n, edges, "ic", thr)
+
+
+@pytest.mark.parametrize("team", [1, 2, 4])
+def test_hub_column_spans_several_pages(imm, orc, stream, monkeypatch, team):
+    """A hub of 70,000 in-edges (17,500 groups of four) in every small set: the
+    BFS team sweeps it over several pages of its owner bitmap (4096 * team
+    groups per page)."""
+    monkeypatch.setenv("IMM_IC_TEAM", str(team))
+    g = _hub_graph(70001, 1e-4)
+    say(f"hub column n={g.n} team={team}")
+    so = _sample_parity(imm, orc, g, 9, 400, stream)
+    assert int(np.diff(so).max()) < 256 * team  # stayed in the team pass
+
+
+@pytest.mark.parametrize("big", [256, 1024])
+def test_giant_set_hub_column_spans_two_pages(imm, orc, stream, monkeypatch, big):
+    """Giant sets (thousands of members) that sweep a hub of 270,000 in-edges:
+    67,500 groups, more than one page (65,536) of the giant-set kernel's
+    owner bitmap."""
+    monkeypatch.setenv("IMM_IC_TEAM", "4")
+    monkeypatch.setenv("IMM_IC_BIG", str(big))
+    g = _hub_graph(270001, 1e-2)
+    say(f"giant hub column n={g.n} big={big}")
+    so = _sample_parity(imm, orc, g, 5, 60, stream)
+    assert int(np.diff(so).max()) > 1024  # went through the giant-set pass
+
+
+def test_recount_with_long_index_lists(imm, orc, stream):
+    """Two hubs, each in most sets of its own parity class and in some of the
+    other's: the first seed covers more than an eighth of the pool, so the
+    next counts are rebuilt by a recount in which the other hub (about 10,000
+    index entries, partly covered) is a work item of its own."""
+    rng = np.random.default_rng(21)
+    n = 20002
+    edges, thr = [], []
+    for v in range(2, n):
+        edges.append((v % 2, v))
+        thr.append(T32 - 1)
+    for hub in (0, 1):
+        same = np.arange(2 + hub, n, 2)
+        other = np.arange(3 - hub, n, 2)
+        src = np.concatenate([rng.choice(same, size=4500, replace=False),
+                              rng.choice(other, size=500, replace=False)])
+        for u in src:
+            edges.append((int(u), hub))
+            thr.append(int(1e-3 * T32))
+    g = synth.tiny_graph(n, edges, "ic", thr)
+    say("two-hub recount")
+    r = _parity(imm, orc, g, 5, 0.1, 17, stream, pool=False)
+    assert r.theta > 2 * 4096 and r.gains[1] > 0
