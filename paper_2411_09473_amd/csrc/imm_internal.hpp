@@ -169,8 +169,8 @@ constexpr uint32_t kArgSlots = 32;
 // k * kArgSlots zeroed entries, chunk_n 2k zeroed counters: seed step t
 // queues the small covered sets (one entry each) at chunks[0 ..
 // chunk_n[2t]) and the 64-member pieces of the others at chunks[chunk_cap -
-// chunk_n[2t+1] .. chunk_cap). A step whose covered sets hold more than an
-// eighth of all pool entries recounts every count from the index instead of
+// chunk_n[2t+1] .. chunk_cap). A step whose covered sets hold more than a
+// quarter of all pool entries recounts every count from the index instead of
 // decrementing. Workgroups
 // [arg_lo, arg_lo + arg_cnt) of the argmax launch and [sel_lo, sel_lo +
 // sel_cnt) of the claim and decrement launches belong to this instance;

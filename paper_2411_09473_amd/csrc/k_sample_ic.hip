@@ -38,6 +38,8 @@ namespace {
 constexpr uint32_t kLaneDegCap = 32;  // roots tried one per lane up to this in-degree
 constexpr uint32_t kStageChunk = kIcStageChunk;
 constexpr uint32_t kLargePage = 1u << 16;  // groups per start-bitmap page of a giant-set workgroup
+constexpr uint32_t kBfsLiveBuf = 64;       // buffered live edges per wave, BFS team
+constexpr uint32_t kLargeLiveBuf = 256;    // ... giant-set workgroup
 
 // LDS shape of a BFS team of TEAM waves: members kept on chip and a visited
 // hash of twice that many slots (load factor <= 1/2).
@@ -228,15 +230,21 @@ __device__ __forceinline__ uint64_t take_row(uint32_t* s_start, uint32_t r) {
 // set, and synchronised). Each wave sweeps its span of every page two rows of
 // 64 groups at a time (both threshold loads and both Philox chains in flight)
 // and clears the start bits it read, so the bitmap is all zero again on
-// return. on_live(u) runs for the source u of every live in-edge. After a
-// wave has seen a live edge it asks stop() whether to abandon the chunk; the
-// whole block takes the stop at the next page boundary.
-template <uint32_t BS, uint32_t PAGE, bool PAIR, class OnLive, class Stop>
+// return. Live in-edges are not followed one at a time: each wave appends
+// their edge ids to its LDS buffer s_lbuf (LBUF entries) and, when the buffer
+// is full and at the end of its span, loads the sources of up to 4 x 64
+// buffered edges at once and hands them to on_live(u[4]) (kEmpty marks an
+// unused entry). After a wave has seen a live edge it asks stop() whether to
+// abandon the chunk; the whole block takes the stop at the next page
+// boundary.
+template <uint32_t BS, uint32_t PAGE, bool PAIR, uint32_t LBUF, class OnLive, class Stop>
 __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, uint32_t shi,
                                             uint32_t k0, uint32_t k1, const uint4* s_ent,
-                                            uint32_t* s_start, const LevelChunk& ch,
-                                            uint32_t* live_n, OnLive on_live, Stop stop) {
+                                            uint32_t* s_start, uint32_t* s_lbuf,
+                                            const LevelChunk& ch, uint32_t* live_n,
+                                            OnLive on_live, Stop stop) {
     static_assert(PAGE % BS == 0, "wave spans of whole rows stay inside the page");
+    static_assert(LBUF >= kWave, "a row of live edges always fits an empty buffer");
     constexpr uint32_t STEP = PAIR ? 2 * kWave : kWave;
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
     const uint64_t upto = ~0ull >> (kWave - 1u - lane);  // row bits 0 .. lane
@@ -275,6 +283,27 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
                                  (uint32_t)__builtin_amdgcn_readlane((int)e.w, 63));
                 cur_hi = cur.x + (((cur.w + 3u) >> 2) - cur.y);
             };
+            uint32_t lcount = 0;  // entries in this wave's live-edge buffer (wave-uniform)
+            auto flush = [&]() {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (uint32_t base = 0; base < lcount; base += 4 * kWave) {
+                    uint32_t e[4], u[4];
+#pragma unroll
+                    for (uint32_t x = 0; x < 4; ++x) {
+                        const uint32_t i = base + x * kWave + lane;
+                        e[x] = i < lcount ? s_lbuf[i] : kEmpty;
+                    }
+#pragma unroll
+                    for (uint32_t x = 0; x < 4; ++x) u[x] = e[x] != kEmpty ? g.src[e[x]] : kEmpty;
+                    on_live(u);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                lcount = 0;
+            };
             uint32_t r = w0;
             bool quit = false;
             for (; r < w1; r += STEP) {
@@ -290,21 +319,32 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
                 const Philox4 ra = philox10(ga, slo, shi, 1u, k0, k1);
                 const Philox4 rb = philox10(gb, slo, shi, 1u, k0, k1);
                 // live edges of both groups: bits 0-3 of group a, 4-7 of group b
-                uint32_t live = (coin_bits(ra, tha) & ca) | ((coin_bits(rb, thb) & cb) << 4);
+                const uint32_t live =
+                    (coin_bits(ra, tha) & ca) | ((coin_bits(rb, thb) & cb) << 4);
                 const bool any = live != 0u;
-                if (any) {
+                if (__ballot(any)) {
                     *live_n += (uint32_t)__popc(live);
-                    while (live) {
-                        const uint32_t j = (uint32_t)__ffs(live) - 1u;
-                        live &= live - 1u;
-                        on_live(g.src[j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u)]);
+#pragma unroll
+                    for (uint32_t j = 0; j < 8; ++j) {
+                        const bool b = (live >> j) & 1u;
+                        const uint64_t m = __ballot(b);
+                        if (!m) continue;
+                        const uint32_t c = (uint32_t)__popcll(m);
+                        if (lcount + c > LBUF) flush();
+                        if (b) {
+                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            s_lbuf[lcount + below] = j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u);
+                        }
+                        lcount += c;
+                    }
+                    if (stop()) {
+                        quit = true;
+                        break;
                     }
                 }
-                if (__ballot(any) && stop()) {
-                    quit = true;
-                    break;
-                }
             }
+            if (!quit) flush();
             if (quit) {
                 // the rows up to r + STEP are cleared; clear the rest of the span
                 for (uint32_t q = r + STEP; q < w1; q += kWave)
@@ -459,6 +499,7 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
     __shared__ uint32_t members[T::CAP];
     __shared__ uint4 s_ent[BS];
     __shared__ uint32_t s_start[T::PAGE / 32];
+    __shared__ uint32_t s_lbuf[TEAM * kBfsLiveBuf];
     __shared__ uint32_t s_wsum[2 * TEAM];
     __shared__ uint32_t s_size, s_over, s_tk;
     __shared__ unsigned long long s_chunk;
@@ -496,9 +537,14 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
             const LevelChunk ch = level_layout<BS, T::PAGE>(g, members, head, nb, s_ent, s_start,
                                                             s_wsum, &my_edges);
             __syncthreads();
-            level_sweep<BS, T::PAGE, true>(
-                g, slo, shi, k0, k1, s_ent, s_start, ch, &my_live,
-                [&](uint32_t u) { team_insert<TEAM>(u, hash, members, &s_size, &s_over); },
+            level_sweep<BS, T::PAGE, true, kBfsLiveBuf>(
+                g, slo, shi, k0, k1, s_ent, s_start, s_lbuf + (tid / kWave) * kBfsLiveBuf, ch,
+                &my_live,
+                [&](const uint32_t(&u)[4]) {
+#pragma unroll
+                    for (uint32_t x = 0; x < 4; ++x)
+                        if (u[x] != kEmpty) team_insert<TEAM>(u[x], hash, members, &s_size, &s_over);
+                },
                 [&]() { return lds_load(&s_over) != 0u; });
             __syncthreads();
             head += nb;
@@ -574,6 +620,7 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
                                                              uint32_t* ticket, BigScratch b) {
     __shared__ uint4 s_ent[kBigBlock];
     __shared__ uint32_t s_start[kLargePage / 32];
+    __shared__ uint32_t s_lbuf[kBigBlock / kWave * kLargeLiveBuf];
     __shared__ uint32_t s_wsum[2 * kBigBlock / kWave];
     __shared__ uint32_t s_size, s_i;
     __shared__ unsigned long long s_off;
@@ -610,14 +657,22 @@ __global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, Sampl
             const LevelChunk ch = level_layout<kBigBlock, kLargePage>(g, q, head, nb, s_ent,
                                                                       s_start, s_wsum, &my_edges);
             __syncthreads();
-            level_sweep<kBigBlock, kLargePage, (kBigBlock < 1024)>(
-                g, slo, shi, k0, k1, s_ent, s_start, ch, &my_live,
-                [&](uint32_t u) {
-                    const uint32_t bit = 1u << (u & 31);
-                    const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                    if (!(old & bit)) {
-                        const uint32_t pos = atomicAdd(&s_size, 1u);
-                        if (pos < b.qcap) q[pos] = u;
+            level_sweep<kBigBlock, kLargePage, (kBigBlock < 1024), kLargeLiveBuf>(
+                g, slo, shi, k0, k1, s_ent, s_start, s_lbuf + (tid / kWave) * kLargeLiveBuf, ch,
+                &my_live,
+                [&](const uint32_t(&u)[4]) {
+                    // all four visited-bit atomics in flight before any result is used
+                    uint32_t old[4];
+#pragma unroll
+                    for (uint32_t x = 0; x < 4; ++x)
+                        old[x] = u[x] != kEmpty ? atomicOr(&bm[u[x] >> 5], 1u << (u[x] & 31))
+                                                : 0xFFFFFFFFu;
+#pragma unroll
+                    for (uint32_t x = 0; x < 4; ++x) {
+                        if (!((old[x] >> (u[x] & 31)) & 1u)) {
+                            const uint32_t pos = atomicAdd(&s_size, 1u);
+                            if (pos < b.qcap) q[pos] = u[x];
+                        }
                     }
                 },
                 []() { return false; });

@@ -20,8 +20,8 @@
 //    pieces one per wave, and decrement the counts of the members (except
 //    the chosen vertex), so both a flood of tiny sets and a few very large
 //    ones spread over the GPU. When the queue is long, decrements are summed
-//    per workgroup in LDS first. When the covered sets hold more than an
-//    eighth of the pool, the step instead recounts every remaining count
+//    per workgroup in LDS first. When the covered sets hold more than a
+//    quarter of the pool, the step instead recounts every remaining count
 //    from the uncovered sets (the paper's adaptive counter update, Section
 //    IV-C), a gather without atomics.
 #include <algorithm>
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t pool = d.set_off[d.n_sets];
-    if (d.cov_entries[t] * 8ull > pool) {
+    if (d.cov_entries[t] * 4ull > pool) {
         recount_all(d, blk, h_key, h_cnt);
         return;
     }

@@ -234,7 +234,7 @@ def test_giant_set_hub_column_spans_two_pages(imm, orc, stream, monkeypatch, big
 
 def test_recount_with_long_index_lists(imm, orc, stream):
     """Two hubs, each in most sets of its own parity class and in some of the
-    other's: the first seed covers more than an eighth of the pool, so the
+    other's: the first seed covers more than a quarter of the pool, so the
     next counts are rebuilt by a recount in which the other hub (about 10,000
     index entries, partly covered) is a work item of its own."""
     rng = np.random.default_rng(21)
