@@ -59,14 +59,17 @@ __device__ __forceinline__ uint32_t lt_draw(uint64_t seed, uint64_t s, uint32_t 
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Inclusive wave64 prefix sum of a uint32.
+// Inclusive wave64 prefix sum of a uint32, with DPP lane moves (no LDS
+// round trips): shifts by 1, 2, 4 and 8 lanes inside each row of 16 (zeros
+// shifted in), then lane 15 of rows 0 and 2 is added to rows 1 and 3, and
+// lane 31 to rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (uint32_t d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
     return v;
 }
 

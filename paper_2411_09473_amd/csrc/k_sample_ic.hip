@@ -323,20 +323,35 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
                     (coin_bits(ra, tha) & ca) | ((coin_bits(rb, thb) & cb) << 4);
                 const bool any = live != 0u;
                 if (__ballot(any)) {
-                    *live_n += (uint32_t)__popc(live);
+                    const uint32_t nl = (uint32_t)__popc(live);
+                    *live_n += nl;
+                    // this lane's slots in the buffer: a wave prefix sum of the counts
+                    const uint32_t incl = wave_incl_scan(nl);
+                    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+                    if (lcount + total > LBUF) flush();
+                    if (total > LBUF) {
+                        // more than a buffer's worth in one iteration (edges
+                        // that are almost surely live): followed in place
+                        for (uint32_t rest = live; __ballot(rest != 0u);) {
+                            uint32_t u[4];  // up to four of this lane's live edges per round
 #pragma unroll
-                    for (uint32_t j = 0; j < 8; ++j) {
-                        const bool b = (live >> j) & 1u;
-                        const uint64_t m = __ballot(b);
-                        if (!m) continue;
-                        const uint32_t c = (uint32_t)__popcll(m);
-                        if (lcount + c > LBUF) flush();
-                        if (b) {
-                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            s_lbuf[lcount + below] = j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u);
+                            for (uint32_t x = 0; x < 4; ++x) {
+                                u[x] = kEmpty;
+                                if (rest) {
+                                    const uint32_t j = (uint32_t)__ffs(rest) - 1u;
+                                    rest &= rest - 1u;
+                                    u[x] = g.src[j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u)];
+                                }
+                            }
+                            on_live(u);
                         }
-                        lcount += c;
+                    } else {
+                        uint32_t slot = lcount + incl - nl;
+                        for (uint32_t rest = live; rest; rest &= rest - 1u) {
+                            const uint32_t j = (uint32_t)__ffs(rest) - 1u;
+                            s_lbuf[slot++] = j < 4u ? (ga << 2) + j : (gb << 2) + (j - 4u);
+                        }
+                        lcount += total;
                     }
                     if (stop()) {
                         quit = true;
@@ -612,7 +627,7 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
 // ---------------------------------------------------------------- ic_large
 
 template <uint32_t kBigBlock>
-__global__ __launch_bounds__(kBigBlock) void ic_large_kernel(IcGraphDev g, SampleRange rg,
+__global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large_kernel(IcGraphDev g, SampleRange rg,
                                                              SampleOut o, const uint32_t* list,
                                                              const uint32_t* list_n,
                                                              uint32_t* fail, uint32_t* fail_n,
