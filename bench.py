@@ -91,10 +91,13 @@ def kernel_table(model: str, stats: list) -> dict:
 
 
 def roofline_of(kernels: dict, workload: str) -> dict:
-    """Roofline entry of the kernel with the most time. Per launch: its
-    algorithmic bytes and its Philox lane-ops over its mean launch duration;
-    the bound is whichever roof (HBM or 32-bit ALU) it is nearer to."""
-    dom = max(kernels.values(), key=lambda k: k["ms"])
+    """Roofline entry of the kernel with the most time among those that
+    finished sets (a launch over an empty list only costs its launch). Per
+    launch: its algorithmic bytes and its Philox lane-ops over its mean launch
+    duration; the bound is whichever roof (HBM or 32-bit ALU) it is nearer
+    to."""
+    working = [k for k in kernels.values() if k["bytes"] > 0] or list(kernels.values())
+    dom = max(working, key=lambda k: k["ms"])
     launches = max(dom["launches"], 1)
     avg_ms = dom["ms"] / launches
     per_launch = dom["bytes"] / launches
