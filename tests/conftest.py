@@ -24,7 +24,7 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def imm():
-    """The HIP library binding; on a GPU machine a missing library is an error."""
+    """The HIP library binding; on a machine with a GPU a missing library is an error."""
     import paper_2411_09473_amd as m
     return m
 
