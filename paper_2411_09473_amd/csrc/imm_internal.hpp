@@ -23,11 +23,15 @@ struct IcGraphDev {
 // further offset load), and the guide table: for column v of in-degree d,
 // guide[off[v]+j] is the first edge e of the column with cum[e] > ceil(j
 // 2^32 / d) - 1, i.e. the answer for the smallest draw in bucket j =
-// floor(r d / 2^32).
+// floor(r d / 2^32). For columns of in-degree above 8, gw holds per bucket a
+// copy of the eight records from its guide entry on (one 128-byte line;
+// entries past the column are records with src = 0xFFFFFFFF and cum = 0), so
+// a walk step almost always finds its edge with one line read.
 struct LtGraphDev {
     const uint32_t* off;   // n+1
     const uint4* cs;       // m (x = cum, y = src, z = off[src], w = off[src+1])
     const uint32_t* guide; // m
+    const uint4* gw;       // 8m
     uint32_t n;
     uint32_t m;
 };
@@ -116,7 +120,8 @@ hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const Samp
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
                            uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
                            hipStream_t st);
-hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint32_t n,
+hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint4* gw,
+                           uint32_t n,
                            hipStream_t st);
 uint32_t ic_small_grid(int device);
 uint32_t lt_small_grid(int device, uint32_t bloom_bits);

@@ -57,33 +57,33 @@ __device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
 
 // The live in-edge of the column [beg, end) for draw r: its record (src in
 // .y, src's column bounds in .z/.w), or .y = kNone. *reads counts the
-// records inspected. Every lane of a wave issues its first load before any
-// lane consumes one, so the two kinds of columns share one round trip:
-//  * a short column (d <= kDirectDeg) is loaded whole;
-//  * a longer one loads its guide entry, then reads four records per round
-//    trip from there (the answer is almost always within the first four).
+// records inspected. Every lane reads eight records in one round trip: a
+// short column (d <= kDirectDeg) whole, a longer one the copy of the eight
+// records from the guide entry of r's bucket. The answer lies further on only
+// when more than seven edges of the column end inside the bucket; then the
+// scan goes on in the column itself, four records per round trip.
 __device__ __forceinline__ uint4 lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
                                          uint32_t r, uint32_t* reads) {
     const uint32_t d = end - beg;
     const bool direct = d <= kDirectDeg;
+    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    const uint4* w = direct ? g.cs + beg : g.gw + 8ull * (beg + jb);
     uint4 p[kDirectDeg];
-    uint32_t e = 0;
-    if (direct) {
 #pragma unroll
-        for (uint32_t j = 0; j < kDirectDeg; ++j)
-            p[j] = j < d ? g.cs[beg + j] : make_uint4(0u, kNone, 0u, 0u);
-    } else {
-        e = g.guide[beg + (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32)];
-    }
+    for (uint32_t j = 0; j < kDirectDeg; ++j)
+        p[j] = (!direct || j < d) ? w[j] : make_uint4(0u, kNone, 0u, 0u);
     uint4 res = make_uint4(0u, kNone, 0u, 0u);
-    if (direct) {
+    uint32_t used = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < kDirectDeg; ++j)
-            if (j < d && res.y == kNone && r < p[j].x) res = p[j];
-        *reads += d;
-        return res;
+    for (uint32_t j = 0; j < kDirectDeg; ++j) {
+        if (res.y == kNone && p[j].y != kNone) {
+            ++used;
+            if (r < p[j].x) res = p[j];
+        }
     }
-    for (; e < end; e += 4) {
+    *reads += direct ? d : used;
+    if (direct || res.y != kNone) return res;
+    for (uint32_t e = g.guide[beg + jb] + kDirectDeg; e < end; e += 4) {
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
             p[j] = e + j < end ? g.cs[e + j] : make_uint4(0xFFFFFFFFu, kNone, 0u, 0u);
@@ -364,9 +364,11 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
 }
 
 // guide[beg + j] = first e in [beg, end) with cum[e] > ceil(j 2^32 / d) - 1,
-// or end if there is none, for every column (64 columns per wave).
+// or end if there is none, for every column (64 columns per wave); for a
+// column of in-degree above kDirectDeg also the window gw[8 (beg + j) + k] =
+// cs[guide[beg + j] + k] (k < 8; an empty record past the column).
 __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const uint4* cs,
-                                                      uint32_t* guide, uint32_t n) {
+                                                      uint32_t* guide, uint4* gw, uint32_t n) {
     const uint64_t v = (uint64_t)blockIdx.x * kWave + threadIdx.x;
     uint32_t sz = 0;
     uint64_t beg = 0;
@@ -382,6 +384,12 @@ __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const
             if ((uint64_t)cs[mid].x > lo) z = mid; else a = mid + 1;
         }
         guide[b0 + j] = a;
+        if (d > kDirectDeg) {
+#pragma unroll
+            for (uint32_t k = 0; k < kDirectDeg; ++k)
+                gw[8ull * (b0 + j) + k] =
+                    a + k < b0 + d ? cs[a + k] : make_uint4(0u, kNone, 0u, 0u);
+        }
     });
 }
 
@@ -429,10 +437,10 @@ hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const Samp
     return hipGetLastError();
 }
 
-hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint32_t n,
-                           hipStream_t st) {
+hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide, uint4* gw,
+                           uint32_t n, hipStream_t st) {
     const uint32_t blocks = (n + kWave - 1) / kWave;
-    hipLaunchKernelGGL(lt_guide_kernel, dim3(blocks), dim3(kWave), 0, st, off, cs, guide, n);
+    hipLaunchKernelGGL(lt_guide_kernel, dim3(blocks), dim3(kWave), 0, st, off, cs, guide, gw, n);
     return hipGetLastError();
 }
 

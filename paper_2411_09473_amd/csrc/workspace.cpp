@@ -128,7 +128,7 @@ IcGraphDev ic_view(const imm_graph* g) {
 }
 
 LtGraphDev lt_view(const imm_graph* g) {
-    return LtGraphDev{g->off, g->cs, g->guide, g->n, (uint32_t)g->m};
+    return LtGraphDev{g->off, g->cs, g->guide, g->gw, g->n, (uint32_t)g->m};
 }
 
 imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_t budget) {
