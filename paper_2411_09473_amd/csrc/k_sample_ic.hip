@@ -14,7 +14,8 @@
 //    an open-addressing hash of visited vertices. Each BFS level takes up to
 //    64*TEAM queued vertices and the team sweeps their in-edges in aligned
 //    groups of four: one Philox call yields the four coins of a group and one
-//    16-byte load its four thresholds; sources are read only for live edges.
+//    16-byte load its four thresholds; sources are read only for live edges,
+//    which each wave collects and follows in batches.
 //    A set that outgrows LDS is abandoned (no side effects) and its sample
 //    index deferred.
 //  * ic_large<BS>: one workgroup of BS (256 or 1024) threads per deferred
@@ -95,8 +96,9 @@ __device__ __forceinline__ bool stage_reserve(Stager& c, uint32_t need, uint64_t
 // PAGE groups, and an LDS bitmap holds one bit per group of the page, set
 // where an entry starts. A page is split into one contiguous span per wave (a
 // multiple of 64 groups); the wave finds the owner of its span's first group
-// once, by bisection, and from there the owner of any group is that rank plus
-// the starts between: one 64-bit popcount per row of 64 groups.
+// once (a wave-wide search over the entries' first groups), and from there
+// the owner of any group is that rank plus the starts between: one 64-bit
+// popcount per row of 64 groups.
 struct LevelChunk {
     uint32_t G;   // groups of the chunk
     uint32_t ne;  // entries with at least one in-edge
