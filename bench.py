@@ -41,7 +41,6 @@ PHILOX_OPS = 60
 # no entry.
 MEASURED_TRAFFIC = {
     ("youtube_ic", "ic_large_kernel"): 8.164e9,
-    ("lj_lt", "lt_small_kernel"): 1.228e9,
 }
 
 

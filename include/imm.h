@@ -109,6 +109,8 @@ typedef struct {
     uint64_t device_bytes;   /* device memory held by the run's workspace */
     double ms_queue;         /* server: submit to admission (ms_total is then
                                 submit to completion) */
+    uint32_t walk_lanes;     /* LT: lanes per walk of the walk kernel (autotuned) */
+    uint32_t pad;
 } imm_stats;
 
 /* Thread-local description of the last error of this thread. */

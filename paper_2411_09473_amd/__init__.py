@@ -60,7 +60,8 @@ class imm_stats(C.Structure):
                 ("ms_sample_lane", C.c_double), ("lane_launches", C.c_uint64),
                 ("lane_sets", C.c_uint64), ("lane_edges", C.c_uint64),
                 ("big_block", C.c_uint32), ("bloom_bits", C.c_uint32),
-                ("device_bytes", C.c_uint64), ("ms_queue", C.c_double)]
+                ("device_bytes", C.c_uint64), ("ms_queue", C.c_double),
+                ("walk_lanes", C.c_uint32), ("pad", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

@@ -89,7 +89,12 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
         const int bloom = el ? std::atoi(el) : 0;
         if (bloom >= 10 && bloom <= 12) g->lt_bloom_bits = (uint32_t)bloom;
         g->bloom_forced = bloom >= 10 && bloom <= 12;
-        g->tuned = model == IMM_IC ? (g->team_forced && g->big_forced) : g->bloom_forced;
+        const char* ew = std::getenv("IMM_LT_LANES");
+        const int lanes = ew ? std::atoi(ew) : 0;
+        g->lanes_forced = lanes == 1 || lanes == 2 || lanes == 4;
+        if (g->lanes_forced) g->lt_lanes = (uint32_t)lanes;
+        g->tuned = model == IMM_IC ? (g->team_forced && g->big_forced)
+                                   : (g->bloom_forced && g->lanes_forced);
         HIP_TRY(hipGetDevice(&g->device));
         std::vector<uint32_t> off32((size_t)n + 1);
         for (size_t v = 0; v <= n; ++v) off32[v] = (uint32_t)co[v];
@@ -294,6 +299,7 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         p->stats.team = g->model == IMM_IC ? g->ic_team : 0;
         p->stats.big_block = g->model == IMM_IC ? g->ic_big_block : 0;
         p->stats.bloom_bits = g->model == IMM_LT ? g->lt_bloom_bits : 0;
+        p->stats.walk_lanes = g->model == IMM_LT ? g->lt_lanes : 0;
         *out = p.release();
         return IMM_OK;
     } catch (const std::bad_alloc&) {

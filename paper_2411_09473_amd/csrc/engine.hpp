@@ -206,11 +206,13 @@ struct imm_graph {
     // IC launch shapes picked by tune_graph on first use: waves per sample of
     // the BFS pass (IMM_IC_TEAM = 1, 2 or 4 forces it) and the giant-set
     // workgroup size (IMM_IC_BIG = 256 or 1024 forces it); for LT, the path
-    // filter size (IMM_LT_BLOOM = 10, 11 or 12 forces it)
+    // filter size (IMM_LT_BLOOM = 10, 11 or 12 forces it) and the lanes per
+    // walk (IMM_LT_LANES = 1, 2 or 4 forces it)
     uint32_t ic_team = 1;
     uint32_t ic_big_block = 256;  // threads per giant set (256 or 1024)
-    uint32_t lt_bloom_bits = 12;  // LT: log2 bits of the per-lane path filter
-    bool team_forced = false, big_forced = false, bloom_forced = false;
+    uint32_t lt_bloom_bits = 12;  // LT: log2 bits of the per-walk path filter
+    uint32_t lt_lanes = 2;        // LT: lanes per walk
+    bool team_forced = false, big_forced = false, bloom_forced = false, lanes_forced = false;
     double defer_rate = 0.0;  // giant sets per sample seen while tuning
     bool tuned = false;
     std::mutex tune_mu;

@@ -112,10 +112,11 @@ hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const Samp
                            uint32_t* ticket, const BigScratch& b, uint32_t block,
                            hipStream_t st);
 uint32_t ic_large_slots(int device, uint32_t block);
-// LT: one walk per lane; bloom_bits (10, 11 or 12) sizes the per-lane path
-// filter in LDS.
+// LT: one walk per group of `lanes` (1, 2 or 4) lanes; bloom_bits (10, 11 or
+// 12) sizes the per-walk path filter in LDS.
 hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t bloom_bits, uint32_t grid, hipStream_t st);
+                           uint32_t* ticket, uint32_t bloom_bits, uint32_t lanes, uint32_t grid,
+                           hipStream_t st);
 hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
                            const uint32_t* list, const uint32_t* list_n, uint32_t* fail,
                            uint32_t* fail_n, uint32_t* ticket, const BigScratch& b,
@@ -124,7 +125,7 @@ hipError_t launch_lt_guide(const uint32_t* off, const uint4* cs, uint32_t* guide
                            uint32_t n,
                            hipStream_t st);
 uint32_t ic_small_grid(int device);
-uint32_t lt_small_grid(int device, uint32_t bloom_bits);
+uint32_t lt_small_grid(int device, uint32_t bloom_bits, uint32_t lanes);
 
 // ---- pool, index, canonical order (k_pool.hip)
 // out[0] = B; out[i+1] = B + x[0] + ... + x[i] for N >= 1 entries, where

@@ -2,15 +2,19 @@
 // occurrence counts (Generate_RRRsets, Algorithm 3; LT model of Section II-A
 // in its live-edge form: every vertex keeps at most one live in-edge).
 //
-// A walk is a chain of dependent loads, so one lane runs one walk and a wave
-// keeps 64 walks in flight; a lane whose walk ends takes the next sample at
-// once (wave-aggregated tickets), which keeps the memory system busy.
+// A walk is a chain of dependent loads. A group of P lanes (2 or 4, picked
+// per graph by the autotuner) runs one walk, so a wave keeps 64/P walks in
+// flight: the lanes split each step's eight-record line read, and a wave load
+// instruction then touches 64/P lines instead of 64, which the vector memory
+// pipeline serves several times faster than 64 lines of one record each. A
+// group whose walk ends takes the next sample at once (wave-aggregated
+// tickets), which keeps the memory system busy.
 //  * The live in-edge of v is the first e of v's column with r < cum[e]. The
 //    guide table jumps to the first candidate of r's bucket j = floor(r d /
 //    2^32), from where a short forward scan over the edge records finds the
 //    same edge the plain search would. A record also holds the bounds of its
 //    source's column, so the next step needs no offset load.
-//  * The path is written straight into the lane's staging chunk. A per-lane
+//  * The path is written straight into the walk's staging chunk. A per-walk
 //    Bloom filter of 1024 to 4096 bits (three hashes, size picked per graph
 //    by the autotuner) in LDS answers "not on the path"
 //    for most vertices; a hit is confirmed by rescanning the path
@@ -99,18 +103,114 @@ __device__ __forceinline__ uint4 lt_pick(const LtGraphDev& g, uint32_t beg, uint
     return res;
 }
 
-// Is w among the len entries of path (which starts at stage[pos])? Entries
-// are read as aligned 16-byte groups, sixteen independent loads per round;
-// words of the groups outside [pos, pos + len) are ignored. The groups never
-// cross the end of the lane's chunk, whose bounds are multiples of four.
-__device__ __forceinline__ bool on_path(const uint32_t* stage, uint64_t pos, uint32_t len,
-                                        uint32_t w) {
+// The lanes of one walk: P consecutive lanes of a wave (P = 1, 2 or 4), the
+// group starting at lane `lead`. Its bits of a wave ballot.
+template <uint32_t P>
+__device__ __forceinline__ uint32_t group_bits(uint64_t ballot, uint32_t lead) {
+    return (uint32_t)(ballot >> lead) & ((1u << P) - 1u);
+}
+
+// Sum of x over the group (every lane gets it).
+template <uint32_t P>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+#pragma unroll
+    for (uint32_t o = 1; o < P; o <<= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+// lt_pick for a walk run by a group of P lanes: each lane reads 8/P of the
+// eight records (a wave load instruction then touches 64/P lines instead of
+// 64, which the memory pipeline serves several times faster), the first lane
+// with a hit supplies the record. Every lane returns the same record and
+// count; the caller's control flow is uniform across the group.
+template <uint32_t P>
+__device__ __forceinline__ uint4 lt_pick_group(const LtGraphDev& g, uint32_t beg, uint32_t end,
+                                               uint32_t r, uint32_t* reads, uint32_t sub,
+                                               uint32_t lead) {
+    constexpr uint32_t R = kDirectDeg / P;
+    const uint32_t d = end - beg;
+    const bool direct = d <= kDirectDeg;
+    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    const uint4* w = (direct ? g.cs + beg : g.gw + 8ull * (beg + jb)) + sub * R;
+    uint4 p[R];
+#pragma unroll
+    for (uint32_t j = 0; j < R; ++j)
+        p[j] = (!direct || sub * R + j < d) ? w[j] : make_uint4(0u, kNone, 0u, 0u);
+    // this lane's first hit (R: none) and records inspected up to it
+    uint32_t hj = R, used = 0;
+    uint4 mine = make_uint4(0u, kNone, 0u, 0u);
+#pragma unroll
+    for (uint32_t j = 0; j < R; ++j) {
+        if (hj == R && p[j].y != kNone) {
+            ++used;
+            if (r < p[j].x) {
+                hj = j;
+                mine = p[j];
+            }
+        }
+    }
+    uint32_t gb = group_bits<P>(__ballot(hj < R), lead);
+    uint4 res = make_uint4(0u, kNone, 0u, 0u);
+    if (gb) {
+        // the lanes before the first hit hold R valid records each
+        const uint32_t src = lead + (uint32_t)__ffs(gb) - 1u;
+        res.y = __shfl(mine.y, src, kWave);
+        res.z = __shfl(mine.z, src, kWave);
+        res.w = __shfl(mine.w, src, kWave);
+        if (!direct) *reads += (src - lead) * R + __shfl(used, src, kWave);
+    } else if (!direct) {
+        *reads += group_sum<P>(used);
+    }
+    if (direct) *reads += d;
+    if (direct || gb) return res;
+    // more than seven edges end inside the bucket: scan on in the column,
+    // four records per lane per round trip
+    for (uint32_t e = g.guide[beg + jb] + kDirectDeg; e < end; e += 4 * P) {
+        const uint32_t e0 = e + 4 * sub;
+        uint4 q[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+            q[j] = e0 + j < end ? g.cs[e0 + j] : make_uint4(0u, kNone, 0u, 0u);
+        uint32_t h = 4, u = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            if (h == 4 && e0 + j < end) {
+                ++u;
+                if (r < q[j].x) {
+                    h = j;
+                    mine = q[j];
+                }
+            }
+        }
+        gb = group_bits<P>(__ballot(h < 4), lead);
+        if (gb) {
+            const uint32_t src = lead + (uint32_t)__ffs(gb) - 1u;
+            res.y = __shfl(mine.y, src, kWave);
+            res.z = __shfl(mine.z, src, kWave);
+            res.w = __shfl(mine.w, src, kWave);
+            *reads += (src - lead) * 4 + __shfl(u, src, kWave);
+            break;
+        }
+        *reads += group_sum<P>(u);
+    }
+    return res;
+}
+
+// Is w among the len entries of the path that starts at stage[pos]? The
+// walk's P lanes take turns over the path's aligned 16-byte groups, sixteen
+// independent loads per lane per round; words of a group outside [pos, pos +
+// len) are ignored. A group never crosses the end of the walk's chunk: every
+// pass starts the staging cursor at a multiple of four, and the kernel
+// reserves whole chunks of kLtChunk entries.
+template <uint32_t P>
+__device__ __forceinline__ bool on_path_group(const uint32_t* stage, uint64_t pos, uint32_t len,
+                                              uint32_t w, uint32_t sub, uint32_t lead) {
     const uint64_t end = pos + len;
-    for (uint64_t q = pos & ~3ull; q < end; q += 64) {
+    for (uint64_t q = pos & ~3ull; q < end; q += 64 * P) {
         bool hit = false;
 #pragma unroll
         for (uint32_t j = 0; j < 16; ++j) {
-            const uint64_t b = q + 4 * j;
+            const uint64_t b = q + 4 * (j * P + sub);
             if (b < end) {
                 const uint4 v = *reinterpret_cast<const uint4*>(stage + b);
                 hit |= (v.x == w) & (b >= pos);
@@ -119,21 +219,29 @@ __device__ __forceinline__ bool on_path(const uint32_t* stage, uint64_t pos, uin
                 hit |= (v.w == w) & (b + 3 >= pos) & (b + 3 < end);
             }
         }
-        if (hit) return true;
+        if (group_bits<P>(__ballot(hit), lead)) return true;
     }
     return false;
 }
 
-// BB: log2 of the per-lane path filter size in bits (10..12). A smaller
-// filter leaves more waves resident (more walks in flight) at the price of
-// more false hits, each confirmed by a path rescan.
-template <uint32_t BB>
+// BB: log2 of the per-walk path filter size in bits (10..12); P: lanes per
+// walk. A wave runs 64/P walks. Every lane of a walk's group holds the same
+// walk state and takes the same branches; the group's first lane alone does
+// what must happen once per walk (count atomics, filter updates, ticket and
+// chunk reservations, list appends), and every lane writes the path entries
+// it later rescans. A smaller filter leaves more waves resident (more walks
+// in flight) at the price of more false hits, each confirmed by a path
+// rescan.
+template <uint32_t BB, uint32_t P>
 __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
                                                       uint32_t* ticket) {
     constexpr uint32_t kBloomWords = (1u << BB) / 32;
-    __shared__ uint32_t bloom[kBloomWords * kWave];
+    constexpr uint32_t kWalks = kWave / P;
+    __shared__ uint32_t bloom[kBloomWords * kWalks];
     const uint32_t lane = threadIdx.x;
-    uint32_t* mb = bloom + lane * kBloomWords;  // this lane's filter
+    const uint32_t sub = lane % P, lead = lane - sub;
+    const bool first = sub == 0;
+    uint32_t* mb = bloom + (lane / P) * kBloomWords;  // this walk's filter
     // the wave's reservoir of sample positions [res_pos, res_end), claimed
     // from the ticket 64 at a time (uniform across the wave)
     uint32_t res_pos = 0, res_end = 0;
@@ -148,10 +256,10 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
     const uint32_t total = rg.list ? *rg.list_n : rg.count;
     for (;;) {
         const bool need = !has && !done;
-        const uint64_t mask = __ballot(need);
+        const uint64_t mask = __ballot(need && first);
         if (mask) {
             const uint32_t want = (uint32_t)__popcll(mask);
-            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lead) - 1ull));
             const uint32_t have = res_end - res_pos;
             uint32_t pos;
             if (have >= want) {
@@ -177,9 +285,11 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     cend = g.off[cur + 1];
                     bool ok = true;
                     if (chunk_used >= kLtChunk) {
-                        const uint64_t nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                        unsigned long long nb = 0;
+                        if (first) nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                        nb = __shfl(nb, lead, kWave);
                         if (nb + kLtChunk > o.stage_cap) {
-                            o.retry[atomicAdd(o.retry_n, 1u)] = idx;
+                            if (first) o.retry[atomicAdd(o.retry_n, 1u)] = idx;
                             ok = false;
                         } else {
                             chunk_base = nb;
@@ -189,59 +299,69 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     start = ok;
                 }
             }
-            // the whole wave clears each starting lane's filter in turn
-            uint64_t smask = __ballot(start);
+            // the whole wave clears each starting walk's filter in turn
+            uint64_t smask = __ballot(start && first);
             while (smask) {
                 const uint32_t l = (uint32_t)__ffsll((unsigned long long)smask) - 1u;
                 smask &= smask - 1ull;
-                for (uint32_t wd = lane; wd < kBloomWords; wd += kWave) bloom[l * kBloomWords + wd] = 0u;
+                for (uint32_t wd = lane; wd < kBloomWords; wd += kWave)
+                    bloom[(l / P) * kBloomWords + wd] = 0u;
             }
             if (start) {
                 wstart = chunk_used;
                 o.stage[chunk_base + wstart] = cur;
-                atomicAdd(&o.counts[cur], 1u);
-                bloom_set<BB>(mb, cur);
+                if (first) {
+                    atomicAdd(&o.counts[cur], 1u);
+                    bloom_set<BB>(mb, cur);
+                }
                 len = 1;
                 w_steps = 0;
                 w_reads = 0;
                 has = true;
             }
         }
-        if (!__any(has)) break;
+        // a walk slot whose start failed (staging full) takes the next
+        // position: the wave leaves only when every slot has run past the
+        // end, so no position it claimed from the ticket goes unprocessed
+        if (!__any(has || !done)) break;
         if (has) {
             // one step of the walk
             uint4 pk = make_uint4(0u, kNone, 0u, 0u);
             if (cbeg < cend) {
                 const uint32_t r = lt_draw(rg.seed, s, cur);
                 ++w_steps;
-                pk = lt_pick(g, cbeg, cend, r, &w_reads);
+                pk = lt_pick_group<P>(g, cbeg, cend, r, &w_reads, sub, lead);
             }
             const uint32_t nxt = pk.y;
             bool finish = nxt == kNone;
             if (!finish) {
-                if (bloom_test<BB>(mb, nxt) && on_path(o.stage, chunk_base + wstart, len, nxt))
+                if (bloom_test<BB>(mb, nxt) &&
+                    on_path_group<P>(o.stage, chunk_base + wstart, len, nxt, sub, lead))
                     finish = true;
                 if (!finish) {
                     bool keep = true;
                     if (wstart + len == kLtChunk) {
                         bool moved = false;
                         if (wstart != 0) {
-                            const uint64_t nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                            unsigned long long nb = 0;
+                            if (first) nb = atomicAdd(o.cursor, (unsigned long long)kLtChunk);
+                            nb = __shfl(nb, lead, kWave);
                             if (nb + kLtChunk <= o.stage_cap) {
                                 for (uint32_t t = 0; t < len; ++t)
                                     o.stage[nb + t] = o.stage[chunk_base + wstart + t];
                                 chunk_base = nb;
                                 wstart = 0;
                                 moved = true;
-                            } else {
+                            } else if (first) {
                                 o.retry[atomicAdd(o.retry_n, 1u)] = idx;
                             }
-                        } else {
+                        } else if (first) {
                             o.defer[atomicAdd(o.defer_n, 1u)] = idx;
                         }
                         if (!moved) {
-                            for (uint32_t t = 0; t < len; ++t)
-                                atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
+                            if (first)
+                                for (uint32_t t = 0; t < len; ++t)
+                                    atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
                             chunk_used = wstart;
                             has = false;
                             keep = false;
@@ -249,8 +369,10 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     }
                     if (keep) {
                         o.stage[chunk_base + wstart + len] = nxt;
-                        atomicAdd(&o.counts[nxt], 1u);
-                        bloom_set<BB>(mb, nxt);
+                        if (first) {
+                            atomicAdd(&o.counts[nxt], 1u);
+                            bloom_set<BB>(mb, nxt);
+                        }
                         ++len;
                         cur = nxt;
                         cbeg = pk.z;
@@ -259,13 +381,15 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                 }
             }
             if (finish) {
-                o.stage_off[idx] = chunk_base + wstart;
-                o.sizes[idx] = len;
+                if (first) {
+                    o.stage_off[idx] = chunk_base + wstart;
+                    o.sizes[idx] = len;
+                    st_sets += 1;
+                    st_entries += len;
+                    st_steps += w_steps;
+                    st_reads += w_reads;
+                }
                 chunk_used = wstart + len;
-                st_sets += 1;
-                st_entries += len;
-                st_steps += w_steps;
-                st_reads += w_reads;
                 has = false;
             }
         }
@@ -395,36 +519,52 @@ __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const
 
 }  // namespace
 
-uint32_t lt_small_grid(int device, uint32_t bloom_bits) {
+uint32_t lt_small_grid(int device, uint32_t bloom_bits, uint32_t lanes) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    // resident waves per CU as LDS allows (64 lanes x 2^bits bits each, 160 KB
-    // per CU), twice over
-    const uint32_t lds = (1u << bloom_bits) / 8 * kWave;
+    // resident waves per CU as LDS allows (64 / lanes walks x 2^bits bits
+    // each, 160 KB per CU), twice over
+    const uint32_t lds = (1u << bloom_bits) / 8 * (kWave / lanes);
     uint32_t per_cu = (160u * 1024u) / lds;
     if (per_cu > 32) per_cu = 32;
     return (uint32_t)cus * per_cu * 2u;
 }
 
-hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
-                           uint32_t* ticket, uint32_t bloom_bits, uint32_t grid, hipStream_t st) {
-    const uint32_t need = (r.count + kWave - 1) / kWave;
-    if (grid > need) grid = need;
-    if (grid == 0) return hipSuccess;
+template <uint32_t P>
+hipError_t launch_lt_small_p(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                             uint32_t* ticket, uint32_t bloom_bits, uint32_t grid, hipStream_t st) {
     switch (bloom_bits) {
         case 10:
-            hipLaunchKernelGGL(lt_small_kernel<10>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            hipLaunchKernelGGL((lt_small_kernel<10, P>), dim3(grid), dim3(kWave), 0, st, g, r, o,
+                               ticket);
             break;
         case 11:
-            hipLaunchKernelGGL(lt_small_kernel<11>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            hipLaunchKernelGGL((lt_small_kernel<11, P>), dim3(grid), dim3(kWave), 0, st, g, r, o,
+                               ticket);
             break;
         case 12:
-            hipLaunchKernelGGL(lt_small_kernel<12>, dim3(grid), dim3(kWave), 0, st, g, r, o, ticket);
+            hipLaunchKernelGGL((lt_small_kernel<12, P>), dim3(grid), dim3(kWave), 0, st, g, r, o,
+                               ticket);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
+                           uint32_t* ticket, uint32_t bloom_bits, uint32_t lanes, uint32_t grid,
+                           hipStream_t st) {
+    const uint32_t walks = kWave / (lanes ? lanes : 1u);
+    const uint32_t need = (r.count + walks - 1) / walks;
+    if (grid > need) grid = need;
+    if (grid == 0) return hipSuccess;
+    switch (lanes) {
+        case 1: return launch_lt_small_p<1>(g, r, o, ticket, bloom_bits, grid, st);
+        case 2: return launch_lt_small_p<2>(g, r, o, ticket, bloom_bits, grid, st);
+        case 4: return launch_lt_small_p<4>(g, r, o, ticket, bloom_bits, grid, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_lt_large(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,

@@ -210,6 +210,7 @@ imm_status end_iteration(Query& q) {
     r.stats.device_bytes = w.arena.used;
     r.stats.big_block = q.g->model == IMM_IC ? q.g->ic_big_block : 0;
     r.stats.bloom_bits = q.g->model == IMM_LT ? q.g->lt_bloom_bits : 0;
+    r.stats.walk_lanes = q.g->model == IMM_LT ? q.g->lt_lanes : 0;
     if (q.p.flags & IMM_KEEP_POOL) {
         IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
         r.has_pool = true;

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -40,41 +41,54 @@ constexpr int kTuneReps = 2;  // each candidate is timed this often; the minimum
 constexpr uint64_t kProbeSamples = 2048;
 constexpr double kProbeMs = 20.0;
 
-// LT: the per-lane path filter size, among 1024, 2048 and 4096 bits.
+// LT: the lanes per walk (2 or 4) and the per-walk path filter size (1024,
+// 2048 or 4096 bits), each unless forced.
 imm_status tune_lt(imm_graph* g, hipStream_t st) {
-    if (g->bloom_forced) {
+    if (g->bloom_forced && g->lanes_forced) {
         g->tuned = true;
         return IMM_OK;
     }
     Workspace w;
     IMM_TRY(ws_init(w, g->n, g->device, st, 0));
     const bool log = std::getenv("IMM_TUNE_LOG") != nullptr;
+    std::vector<uint32_t> lane_opts, bit_opts;
+    if (g->lanes_forced) lane_opts = {g->lt_lanes}; else lane_opts = {2u, 4u};
+    if (g->bloom_forced) bit_opts = {g->lt_bloom_bits}; else bit_opts = {12u, 11u, 10u};
     double best = -1.0;
-    uint32_t pick = 12;
-    for (int c = -1; c < 3; ++c) {
-        g->lt_bloom_bits = c < 0 ? 10u : 12u - (uint32_t)c;
-        double ms = -1.0;
-        imm_stats s;
-        for (int rep = 0; rep < (c < 0 ? 1 : kTuneReps); ++rep) {
-            IMM_TRY(ws_reset(w, st, true));
-            IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneLtSamples));
-            HIP_TRY(hipStreamSynchronize(st));
-            std::memset(&s, 0, sizeof(s));
-            fill_stats(w, &s);
-            const double t = s.ms_sample_main + s.ms_sample_big;
-            if (ms < 0.0 || t < ms) ms = t;
-        }
-        if (c < 0) continue;
-        if (log)
-            std::fprintf(stderr, "imm tune: n=%u m=%llu LT filter 2^%u bits: walks %.3f ms, long %.3f ms\n",
-                         g->n, (unsigned long long)g->m, g->lt_bloom_bits, s.ms_sample_main,
-                         s.ms_sample_big);
-        if (best < 0.0 || ms < best) {
-            best = ms;
-            pick = g->lt_bloom_bits;
+    uint32_t pick_bits = bit_opts[0], pick_lanes = lane_opts[0];
+    // the first candidate runs once untimed (first launches of the kernels)
+    bool warm = false;
+    for (uint32_t lanes : lane_opts) {
+        for (uint32_t bits : bit_opts) {
+            g->lt_lanes = lanes;
+            g->lt_bloom_bits = bits;
+            double ms = -1.0;
+            imm_stats s;
+            for (int rep = warm ? 0 : -1; rep < kTuneReps; ++rep) {
+                IMM_TRY(ws_reset(w, st, true));
+                IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneLtSamples));
+                HIP_TRY(hipStreamSynchronize(st));
+                std::memset(&s, 0, sizeof(s));
+                fill_stats(w, &s);
+                const double t = s.ms_sample_main + s.ms_sample_big;
+                if (rep >= 0 && (ms < 0.0 || t < ms)) ms = t;
+            }
+            warm = true;
+            if (log)
+                std::fprintf(stderr,
+                             "imm tune: n=%u m=%llu LT %u lanes per walk, filter 2^%u bits: walks "
+                             "%.3f ms, long %.3f ms\n",
+                             g->n, (unsigned long long)g->m, lanes, bits, s.ms_sample_main,
+                             s.ms_sample_big);
+            if (best < 0.0 || ms < best) {
+                best = ms;
+                pick_bits = bits;
+                pick_lanes = lanes;
+            }
         }
     }
-    g->lt_bloom_bits = pick;
+    g->lt_bloom_bits = pick_bits;
+    g->lt_lanes = pick_lanes;
     g->tuned = true;
     return IMM_OK;
 }

@@ -251,7 +251,8 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
     } else {
         const int tm = w.timer.open(4, st);
         HIP_TRY(launch_lt_small(lt_view(g), rg, o, &w.sc->ticket_small, g->lt_bloom_bits,
-                                lt_small_grid(w.device, g->lt_bloom_bits), st));
+                                g->lt_lanes, lt_small_grid(w.device, g->lt_bloom_bits, g->lt_lanes),
+                                st));
         w.timer.close(tm, st);
     }
     const int t3 = w.timer.open(5, st);
@@ -324,9 +325,10 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
                 ic_small_grid(w.device), (count + kIcTicketChunk - 1) / kIcTicketChunk);
             tails = waves * kIcStageChunk;
         } else {
-            const uint64_t lanes =
-                std::min<uint64_t>((uint64_t)lt_small_grid(w.device, g->lt_bloom_bits) * 64u, count);
-            tails = lanes * kLtChunk;
+            const uint64_t walks = std::min<uint64_t>(
+                (uint64_t)lt_small_grid(w.device, g->lt_bloom_bits, g->lt_lanes) * 64u / g->lt_lanes,
+                count);
+            tails = walks * kLtChunk;
         }
         uint64_t want = (uint64_t)(mean * 1.5 * (double)count) + 2 * tails + 65536;
         // IMM_STAGE_SCALE (a factor, default 1) scales this first guess; small
@@ -368,7 +370,9 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
         uint64_t cap = w.stage_cap;
         IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
         w.stage_cap = cap;
-        const unsigned long long cur = old_cap;
+        // at a multiple of four: the LT walk kernel reads its chunks in
+        // aligned 16-byte groups (cap >= 2 old_cap, so this stays in bounds)
+        const unsigned long long cur = (old_cap + 3) & ~3ull;
         HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemsetAsync(out_n, 0, 4, st));
         IMM_TRY(sample_pass(w, g, seed, id_lo, count, in, in_n, failed, out_l, out_n, false));

@@ -93,6 +93,43 @@ def test_lt_with_no_live_edge_mass(imm, orc, stream):
     _parity(imm, orc, g, 5, 0.3, 9, stream)
 
 
+def _lt_long_graph(kind):
+    # chain: v's one in-edge comes from v - 1 with weight just below 1, so the
+    # walk from root r is r, r-1, ..., 0 (r + 1 vertices; most are longer
+    # than a walk kernel's staging chunk). ring: the chain closed by the edge
+    # n-1 -> 0, so every walk goes once round and stops at its own root.
+    n = 3000 if kind == "chain" else 700
+    edges = [(v, v + 1) for v in range(n - 1)]
+    if kind == "ring":
+        edges.append((n - 1, 0))
+    return synth.tiny_graph(n, sorted(edges, key=lambda e: (e[1], e[0])), "lt",
+                            [T32 - 1] * len(edges))
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("kind", ["chain", "ring"])
+def test_lt_long_walks(imm, orc, stream, monkeypatch, kind, lanes):
+    """Walks that outgrow the staging chunk (moved to a fresh chunk, or handed
+    to the long-walk kernel) and walks that close a cycle, in every walk
+    shape, give the oracle's sets and counts."""
+    monkeypatch.setenv("IMM_LT_LANES", str(lanes))
+    g = _lt_long_graph(kind)
+    say(f"LT long walks {kind} n={g.n} lanes={lanes}")
+    dg = imm.graph_from(g, stream=stream)
+    pool = imm.imm_sample(dg, 31, 0, 2500, stream=stream)
+    so, sv, cn = pool.export()
+    assert pool.stats["walk_lanes"] == lanes
+    if kind == "chain":
+        assert pool.stats["deferred"] > 0
+    else:
+        assert pool.stats["deferred"] == 0
+    oso, osv = orc.sample(g, 31, 0, 2500)
+    cso, csv = canonical(oso, osv, g.n)
+    np.testing.assert_array_equal(so, cso)
+    np.testing.assert_array_equal(sv, csv)
+    np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
+
+
 def test_zero_thresholds(imm, orc, stream):
     base = synth.make_graph("rmat12_wc")
     g = synth.Graph("rmat12_zero", base.n, base.m, base.col_off, base.row_src,
@@ -114,16 +151,21 @@ def test_sample_ids_across_2_32(imm, orc, stream):
         np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
 
 
-@pytest.mark.parametrize("name", ["rmat12_p10", "cl_lt_xs"])
-def test_staging_growth_path(imm, orc, stream, name):
+@pytest.mark.parametrize("name,lanes", [("rmat12_p10", None), ("cl_lt_xs", None),
+                                        ("cl_lt_xs", 1), ("cl_lt_xs", 2), ("cl_lt_xs", 4)])
+def test_staging_growth_path(imm, orc, stream, monkeypatch, name, lanes):
     """A first staging guess far too small: sets are retried after growth
-    and the result is unchanged."""
+    and the result is unchanged. In the LT walk kernel, every walk of a wave
+    can then fail to start at once while the wave still holds claimed sample
+    positions; each of those must still be walked or listed for a retry."""
     spec = synth.WORKLOADS[name]
-    os.environ["IMM_STAGE_SCALE"] = "0.001"
-    try:
-        _parity(imm, orc, synth.make_graph(name), spec["k"], spec["eps"], 42, stream)
-    finally:
-        del os.environ["IMM_STAGE_SCALE"]
+    if lanes:
+        monkeypatch.setenv("IMM_LT_LANES", str(lanes))
+    monkeypatch.setenv("IMM_STAGE_SCALE", "0.001")
+    say(f"staging growth {name} lanes={lanes}")
+    r = _parity(imm, orc, synth.make_graph(name), spec["k"], spec["eps"], 42, stream)
+    if lanes:
+        assert r.stats["walk_lanes"] == lanes
 
 
 def test_budget_enomem_then_retry(imm, orc, stream):

@@ -91,14 +91,17 @@ def test_ic_pool_each_shape(imm, orc, stream, monkeypatch, team, big, name):
     assert (p.stats["team"], p.stats["big_block"]) == (team, big)
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("bloom", [10, 11, 12])
 @pytest.mark.parametrize("name", ["cl_lt_xs", "rmat12_lt"])
-def test_lt_pool_each_filter_size(imm, orc, stream, monkeypatch, bloom, name):
-    """Every LT path-filter size the autotuner can pick gives the same pool."""
+def test_lt_pool_each_filter_size(imm, orc, stream, monkeypatch, lanes, bloom, name):
+    """Every LT walk shape (lanes per walk, path-filter size) gives the same
+    pool."""
     monkeypatch.setenv("IMM_LT_BLOOM", str(bloom))
+    monkeypatch.setenv("IMM_LT_LANES", str(lanes))
     g = synth.make_graph(name)
     p = _pool_parity(imm, orc, g, 13, 0, 6000, stream)
-    assert p.stats["bloom_bits"] == bloom
+    assert (p.stats["bloom_bits"], p.stats["walk_lanes"]) == (bloom, lanes)
 
 
 def test_lt_pool_small(imm, orc, stream):
