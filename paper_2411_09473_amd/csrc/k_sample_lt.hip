@@ -31,6 +31,7 @@ namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kDirectDeg = 8;    // columns read whole, without the guide
+constexpr uint32_t kScanLoads = 4;     // 16-byte path groups per lane per rescan round
 
 // The three filter positions of v in a 2^BB-bit filter (multiplicative hashes).
 template <uint32_t BB>
@@ -131,11 +132,19 @@ __device__ __forceinline__ uint4 lt_pick_group(const LtGraphDev& g, uint32_t beg
     const uint32_t d = end - beg;
     const bool direct = d <= kDirectDeg;
     const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
-    const uint4* w = (direct ? g.cs + beg : g.gw + 8ull * (beg + jb)) + sub * R;
+    const uint4* w = direct ? g.cs + beg : g.gw + 8ull * (beg + jb);
+    // every load is issued, at a clamped in-bounds position, before any is
+    // used (a guarded load would cost a round trip of its own); records past
+    // a short column are masked afterwards
     uint4 p[R];
 #pragma unroll
+    for (uint32_t j = 0; j < R; ++j) {
+        const uint32_t k = sub * R + j;
+        p[j] = w[direct && k >= d ? d - 1 : k];
+    }
+#pragma unroll
     for (uint32_t j = 0; j < R; ++j)
-        p[j] = (!direct || sub * R + j < d) ? w[j] : make_uint4(0u, kNone, 0u, 0u);
+        if (direct && sub * R + j >= d) p[j] = make_uint4(0u, kNone, 0u, 0u);
     // this lane's first hit (R: none) and records inspected up to it
     uint32_t hj = R, used = 0;
     uint4 mine = make_uint4(0u, kNone, 0u, 0u);
@@ -169,8 +178,7 @@ __device__ __forceinline__ uint4 lt_pick_group(const LtGraphDev& g, uint32_t beg
         const uint32_t e0 = e + 4 * sub;
         uint4 q[4];
 #pragma unroll
-        for (uint32_t j = 0; j < 4; ++j)
-            q[j] = e0 + j < end ? g.cs[e0 + j] : make_uint4(0u, kNone, 0u, 0u);
+        for (uint32_t j = 0; j < 4; ++j) q[j] = g.cs[e0 + j < end ? e0 + j : end - 1];
         uint32_t h = 4, u = 0;
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j) {
@@ -206,17 +214,25 @@ template <uint32_t P>
 __device__ __forceinline__ bool on_path_group(const uint32_t* stage, uint64_t pos, uint32_t len,
                                               uint32_t w, uint32_t sub, uint32_t lead) {
     const uint64_t end = pos + len;
-    for (uint64_t q = pos & ~3ull; q < end; q += 64 * P) {
+    const uint64_t last = (end - 1) & ~3ull;  // the group of the path's last entry
+    for (uint64_t q = pos & ~3ull; q < end; q += 4 * kScanLoads * P) {
         bool hit = false;
+        // kScanLoads loads in flight at once: groups past the end read the
+        // path's last group again and count for nothing
+        uint4 v[kScanLoads];
 #pragma unroll
-        for (uint32_t j = 0; j < 16; ++j) {
+        for (uint32_t j = 0; j < kScanLoads; ++j) {
+            const uint64_t b = q + 4 * (j * P + sub);
+            v[j] = *reinterpret_cast<const uint4*>(stage + (b < end ? b : last));
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kScanLoads; ++j) {
             const uint64_t b = q + 4 * (j * P + sub);
             if (b < end) {
-                const uint4 v = *reinterpret_cast<const uint4*>(stage + b);
-                hit |= (v.x == w) & (b >= pos);
-                hit |= (v.y == w) & (b + 1 >= pos) & (b + 1 < end);
-                hit |= (v.z == w) & (b + 2 >= pos) & (b + 2 < end);
-                hit |= (v.w == w) & (b + 3 >= pos) & (b + 3 < end);
+                hit |= (v[j].x == w) & (b >= pos);
+                hit |= (v[j].y == w) & (b + 1 >= pos) & (b + 1 < end);
+                hit |= (v[j].z == w) & (b + 2 >= pos) & (b + 2 < end);
+                hit |= (v[j].w == w) & (b + 3 >= pos) & (b + 3 < end);
             }
         }
         if (group_bits<P>(__ballot(hit), lead)) return true;
@@ -233,7 +249,7 @@ __device__ __forceinline__ bool on_path_group(const uint32_t* stage, uint64_t po
 // in flight) at the price of more false hits, each confirmed by a path
 // rescan.
 template <uint32_t BB, uint32_t P>
-__global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
+__global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
                                                       uint32_t* ticket) {
     constexpr uint32_t kBloomWords = (1u << BB) / 32;
     constexpr uint32_t kWalks = kWave / P;
@@ -246,9 +262,10 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
     // from the ticket 64 at a time (uniform across the wave)
     uint32_t res_pos = 0, res_end = 0;
 
-    bool has = false, done = false;
+    bool has = false, done = false, fresh = false;
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
     uint32_t cbeg = 0, cend = 0;  // cur's column
+    uint32_t nbeg = 0, nend = 0;  // a new root's column, in flight
     uint64_t s = 0, chunk_base = 0;
     uint32_t w_steps = 0, w_reads = 0;
     uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
@@ -281,8 +298,8 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                     idx = rg.list ? rg.list[pos] : pos;
                     s = rg.id_lo + idx;
                     cur = sample_root(rg.seed, s, g.n);
-                    cbeg = g.off[cur];
-                    cend = g.off[cur + 1];
+                    nbeg = g.off[cur];
+                    nend = g.off[cur + 1];
                     bool ok = true;
                     if (chunk_used >= kLtChunk) {
                         unsigned long long nb = 0;
@@ -318,13 +335,17 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                 w_steps = 0;
                 w_reads = 0;
                 has = true;
+                fresh = true;
             }
         }
         // a walk slot whose start failed (staging full) takes the next
         // position: the wave leaves only when every slot has run past the
         // end, so no position it claimed from the ticket goes unprocessed
         if (!__any(has || !done)) break;
-        if (has) {
+        // a walk started in this iteration takes its first step in the next
+        // one: its column bounds load while the other walks' lines load,
+        // instead of costing the wave a round trip of its own
+        if (has && !fresh) {
             // one step of the walk
             uint4 pk = make_uint4(0u, kNone, 0u, 0u);
             if (cbeg < cend) {
@@ -392,6 +413,11 @@ __global__ __launch_bounds__(64) void lt_small_kernel(LtGraphDev g, SampleRange 
                 chunk_used = wstart + len;
                 has = false;
             }
+        }
+        if (fresh) {
+            cbeg = nbeg;
+            cend = nend;
+            fresh = false;
         }
     }
     st_sets = wave_sum64(st_sets);
