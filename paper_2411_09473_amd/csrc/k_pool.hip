@@ -49,11 +49,19 @@ __device__ __forceinline__ uint64_t block_excl_scan64(uint64_t v, uint64_t* excl
     return total;
 }
 
-// Scanned value of element i: in[i], or in[i] - sub[i] when sub is given.
-__device__ __forceinline__ uint32_t scan_val(const uint32_t* in, const uint32_t* sub, uint64_t i) {
-    return sub ? in[i] - sub[i] : in[i];
+// Scanned value of element i: in[i], or in[i] - sub[i] with SUB; 0 for
+// i >= N. The loads are unguarded (at the clamped position N - 1, N >= 1): a
+// guarded load compiles to a branch with a wait of its own, which would
+// serialise a thread's loads.
+template <bool SUB>
+__device__ __forceinline__ uint32_t scan_val(const uint32_t* in, const uint32_t* sub, uint64_t i,
+                                             uint64_t N) {
+    const uint64_t c = i < N ? i : N - 1;
+    const uint32_t x = SUB ? in[c] - sub[c] : in[c];
+    return i < N ? x : 0u;
 }
 
+template <bool SUB>
 __global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in,
                                                              const uint32_t* sub, uint64_t N,
                                                              uint64_t* tile_sum) {
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(kScanBS) void scan_tiles_kernel(const uint32_t* in,
 #pragma unroll
     for (uint32_t k = 0; k < kScanIPT; ++k) {
         const uint64_t i = base + (uint64_t)k * kScanBS + threadIdx.x;
-        if (i < N) acc += scan_val(in, sub, i);
+        acc += scan_val<SUB>(in, sub, i, N);
     }
     const uint64_t t = block_sum64(acc, s_w);
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
@@ -89,6 +97,7 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint64_t* tile_sum, uin
 
 // base_dev, when given, supplies the base from device memory (it may alias
 // out[0], which is rewritten with the same value).
+template <bool SUB>
 __global__ __launch_bounds__(kScanBS) void scan_apply_kernel(const uint32_t* in,
                                                              const uint32_t* sub, uint64_t N,
                                                              const uint64_t* tile_off,
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(kScanBS) void scan_apply_kernel(const uint32_t* in,
     uint64_t acc = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kScanIPT; ++k) {
-        v[k] = (my + k < N) ? scan_val(in, sub, my + k) : 0u;
+        v[k] = scan_val<SUB>(in, sub, my + k, N);
         acc += v[k];
     }
     uint64_t excl;
@@ -273,11 +282,21 @@ hipError_t launch_scan_u32(const uint32_t* in, const uint32_t* sub, uint64_t* ou
     if (N == 0) return hipErrorInvalidValue;
     const uint64_t tiles = (N + kScanTile - 1) / kScanTile;
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(scan_tiles_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, sub, N,
-                       tile_tmp);
+    if (sub) {
+        hipLaunchKernelGGL(scan_tiles_kernel<true>, dim3((uint32_t)tiles), dim3(kScanBS), 0, st,
+                           in, sub, N, tile_tmp);
+    } else {
+        hipLaunchKernelGGL(scan_tiles_kernel<false>, dim3((uint32_t)tiles), dim3(kScanBS), 0, st,
+                           in, sub, N, tile_tmp);
+    }
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, tile_tmp, tiles);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)tiles), dim3(kScanBS), 0, st, in, sub, N,
-                       tile_tmp, out, base, base_dev);
+    if (sub) {
+        hipLaunchKernelGGL(scan_apply_kernel<true>, dim3((uint32_t)tiles), dim3(kScanBS), 0, st,
+                           in, sub, N, tile_tmp, out, base, base_dev);
+    } else {
+        hipLaunchKernelGGL(scan_apply_kernel<false>, dim3((uint32_t)tiles), dim3(kScanBS), 0, st,
+                           in, sub, N, tile_tmp, out, base, base_dev);
+    }
     return hipGetLastError();
 }
 

@@ -310,19 +310,20 @@ __device__ uint32_t count_uncovered(const SelView& d, uint32_t u) {
         const IMM_GLOBAL uint64_t* io = d.inv_offs + (uint64_t)seg * ((uint64_t)d.n + 1);
         const uint64_t b = io[u], e = io[u + 1];
         for (uint64_t q = b + lane; q < e; q += kWave * kRecountUnroll) {
+            // unguarded loads at clamped positions (a guarded load becomes a
+            // branch with a wait of its own); positions past e count nothing
             uint32_t sid[kRecountUnroll];
 #pragma unroll
             for (uint32_t x = 0; x < kRecountUnroll; ++x) {
                 const uint64_t r = q + x * kWave;
-                sid[x] = r < e ? __builtin_nontemporal_load(d.inv_set + r) : 0u;
+                sid[x] = __builtin_nontemporal_load(d.inv_set + (r < e ? r : e - 1));
             }
             uint32_t cw_[kRecountUnroll];  // all covered-bit words in flight together
 #pragma unroll
-            for (uint32_t x = 0; x < kRecountUnroll; ++x)
-                cw_[x] = q + x * kWave < e ? d.covered[sid[x] >> 5] : ~0u;
+            for (uint32_t x = 0; x < kRecountUnroll; ++x) cw_[x] = d.covered[sid[x] >> 5];
 #pragma unroll
             for (uint32_t x = 0; x < kRecountUnroll; ++x)
-                cnt += ((cw_[x] >> (sid[x] & 31)) & 1u) ^ 1u;
+                if (q + x * kWave < e) cnt += ((cw_[x] >> (sid[x] & 31)) & 1u) ^ 1u;
         }
     }
 #pragma unroll
@@ -382,21 +383,22 @@ __device__ void recount_all(const SelView& d, uint32_t blk, uint32_t* lds_off,
                     heavy_after ? (uint32_t)__ffsll((long long)heavy_after) - 1u : kWave;
                 const uint32_t lo_pos = s_off[l0], hi_pos = s_off[l1];
                 for (uint32_t q0 = lo_pos; q0 < hi_pos; q0 += kWave * kRecountUnroll) {
+                    // unguarded loads at clamped positions, as in
+                    // count_uncovered; positions past hi_pos count nothing
                     uint32_t sid[kRecountUnroll];
 #pragma unroll
                     for (uint32_t x = 0; x < kRecountUnroll; ++x) {
                         const uint32_t r = q0 + x * kWave + lane;
-                        sid[x] =
-                            r < hi_pos ? __builtin_nontemporal_load(d.inv_set + base + r) : 0u;
+                        sid[x] = __builtin_nontemporal_load(d.inv_set + base +
+                                                            (r < hi_pos ? r : hi_pos - 1));
                     }
                     uint32_t cw_[kRecountUnroll];  // all covered-bit words in flight together
 #pragma unroll
-                    for (uint32_t x = 0; x < kRecountUnroll; ++x)
-                        cw_[x] = q0 + x * kWave + lane < hi_pos ? d.covered[sid[x] >> 5] : ~0u;
+                    for (uint32_t x = 0; x < kRecountUnroll; ++x) cw_[x] = d.covered[sid[x] >> 5];
 #pragma unroll
                     for (uint32_t x = 0; x < kRecountUnroll; ++x) {
                         const uint32_t r = q0 + x * kWave + lane;
-                        if (!((cw_[x] >> (sid[x] & 31)) & 1u)) {
+                        if (r < hi_pos && !((cw_[x] >> (sid[x] & 31)) & 1u)) {
                             // owner: the last lane whose list starts at or before r
                             uint32_t lo = l0, hi = l1;
                             while (hi - lo > 1) {
@@ -453,9 +455,16 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     }
     for (uint32_t e = blk * kDecBS + threadIdx.x; e < ns; e += threads) {
         const Chunk ch = load_chunk(d.chunks + e);
-        for (uint32_t x = 0; x < ch.len; ++x) {
-            const uint32_t u = d.set_vtx[ch.off + x];
-            if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
+        // members four at a time, loaded together (clamped to the set; a
+        // repeated member is skipped)
+        for (uint32_t x = 0; x < ch.len; x += 4) {
+            uint32_t u[4];
+#pragma unroll
+            for (uint32_t y = 0; y < 4; ++y)
+                u[y] = d.set_vtx[ch.off + (x + y < ch.len ? x + y : ch.len - 1)];
+#pragma unroll
+            for (uint32_t y = 0; y < 4; ++y)
+                if (x + y < ch.len && u[y] != v) agg_dec(u[y], agg, h_key, h_cnt, cw);
         }
     }
     for (uint32_t c = wid; c < nb; c += nw) {
