@@ -144,25 +144,68 @@ __global__ __launch_bounds__(64) void compact_kernel(const uint32_t* stage,
 
 // A member beyond its vertex's counted occurrences would mean the counts and
 // the pool disagree; it is not written and raises *err instead.
+//
+// A wave takes 64 sets and walks their members as one flattened range. Full
+// rounds of kScatterBatch members per lane issue their loads, then their
+// cursor atomics and list bounds, together, so a round costs two round trips
+// however many members it holds (a wave that owns a giant set walks hundreds
+// of thousands of members; one member at a time, its round trips would set
+// the launch's duration). The rest goes one member per lane at a time.
+constexpr uint32_t kScatterBatch = 8;
+
 __global__ __launch_bounds__(64) void inv_scatter_kernel(const uint64_t* set_off,
                                                          const uint32_t* set_vtx, uint64_t lo,
                                                          uint32_t count, const uint64_t* inv_off,
                                                          uint32_t* cursor, uint32_t* inv_set,
                                                          uint32_t* err) {
-    const uint64_t j = lo + (uint64_t)blockIdx.x * kWave + threadIdx.x;
-    uint32_t sz = 0;
-    uint64_t a = 0;
-    if (j < lo + count) {
-        a = set_off[j];
-        sz = (uint32_t)(set_off[j + 1] - a);
+    __shared__ uint64_t s_base[kWave], s_a[kWave];
+    const uint32_t lane = threadIdx.x;
+    const uint64_t j0 = lo + (uint64_t)blockIdx.x * kWave;
+    const uint64_t j = j0 + lane;
+    const uint64_t jl = j < lo + count ? j : lo + count - 1;
+    const uint64_t a = set_off[jl];
+    const uint32_t sz = j < lo + count ? (uint32_t)(set_off[jl + 1] - a) : 0u;
+    const uint64_t incl = wave_incl_scan64(sz);
+    const uint64_t T = __shfl(incl, kWave - 1, kWave);
+    s_base[lane] = incl - sz;
+    s_a[lane] = a;
+    __syncthreads();
+    uint32_t hint = 0;
+    bool bad = false;
+    constexpr uint64_t kRound = (uint64_t)kWave * kScatterBatch;
+    uint64_t t0 = 0;
+    for (; t0 + kRound <= T; t0 += kRound) {
+        uint32_t ow[kScatterBatch], u[kScatterBatch];
+#pragma unroll
+        for (uint32_t x = 0; x < kScatterBatch; ++x) {
+            const uint64_t t = t0 + (uint64_t)x * kWave + lane;
+            hint = owner_from(s_base, kWave, t, hint);
+            ow[x] = hint;
+            u[x] = set_vtx[s_a[hint] + (t - s_base[hint])];
+        }
+        uint32_t r[kScatterBatch];
+        uint64_t b[kScatterBatch], e[kScatterBatch];
+#pragma unroll
+        for (uint32_t x = 0; x < kScatterBatch; ++x) {
+            r[x] = atomicAdd(&cursor[u[x]], 1u);
+            b[x] = inv_off[u[x]];
+            e[x] = inv_off[u[x] + 1];
+        }
+#pragma unroll
+        for (uint32_t x = 0; x < kScatterBatch; ++x) {
+            if (b[x] + r[x] < e[x]) inv_set[b[x] + r[x]] = (uint32_t)(j0 + ow[x]);
+            else bad = true;
+        }
     }
-    wave_segments(sz, a, j, [&](uint32_t, uint64_t a0, uint64_t jj, uint32_t k) {
-        const uint32_t u = set_vtx[a0 + k];
+    for (uint64_t t = t0 + lane; t < T; t += kWave) {
+        hint = owner_from(s_base, kWave, t, hint);
+        const uint32_t u = set_vtx[s_a[hint] + (t - s_base[hint])];
         const uint32_t r = atomicAdd(&cursor[u], 1u);
-        const uint64_t lo = inv_off[u];
-        if (lo + r < inv_off[u + 1]) inv_set[lo + r] = (uint32_t)jj;
-        else atomicOr(err, 1u);
-    });
+        const uint64_t b = inv_off[u];
+        if (b + r < inv_off[u + 1]) inv_set[b + r] = (uint32_t)(j0 + hint);
+        else bad = true;
+    }
+    if (__any(bad) && lane == 0) atomicOr(err, 1u);
 }
 
 __global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_vtx, uint64_t P,
