@@ -36,9 +36,10 @@ PHILOX_OPS = 60
 
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, scaled by the 1 GiB copy calibration), for the kernel
-# and workload named, as recorded in profiles/ (ic_large_youtube_ic_pmc.md,
-# lt_small_lj_lt_pmc.md); a kernel changed since its counters were taken has
-# no entry.
+# and workload named (an IMM run, or "<workload>:sample<count>" for a
+# steady-state sampling run of that many ids), as recorded in profiles/
+# (ic_large_youtube_ic_pmc.md, lt_small_lj_lt_pmc.md); a kernel changed
+# since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
     ("youtube_ic", "ic_large_kernel"): 8.164e9,
 }
@@ -172,7 +173,7 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
         "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
         "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
         "deferred": st["deferred"], "ic_team": st["team"], "ic_big_block": st["big_block"], "kernels": kernel_summary(kernels),
-        "roofline": roofline_of(kernels, args.workload),
+        "roofline": roofline_of(kernels, f"{args.workload}:sample{args.sample_count}"),
     }))
 
 
