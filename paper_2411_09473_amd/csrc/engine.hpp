@@ -214,6 +214,9 @@ struct imm_graph {
     uint32_t lt_lanes = 2;        // LT: lanes per walk
     bool team_forced = false, big_forced = false, bloom_forced = false, lanes_forced = false;
     double defer_rate = 0.0;  // giant sets per sample seen while tuning
+    // mean set size seen while tuning: a fresh workspace's first staging
+    // estimate, in place of a pilot batch (0 when tuning did not run)
+    double mean_set_hint = 0.0;
     bool tuned = false;
     std::mutex tune_mu;
     imm::Arena arena;

@@ -33,7 +33,11 @@ constexpr uint64_t kTuneSeed = 0x7475E5EEDull;
 // mean set size), between 2^14 and 2^20 samples.
 constexpr uint64_t kTuneSamples = 1u << 20;
 constexpr uint64_t kTuneEntries = 16u << 20;
-constexpr uint64_t kTuneLtSamples = 1u << 16;  // LT: walks per timed batch
+// The LT batch is sized to about kTuneLtSteps walk steps (from a probe of
+// kLtProbeSamples walks), between 2^16 and 2^21 walks: a batch with fewer
+// walks than the kernel has walk slots times only its longest walk.
+constexpr uint64_t kLtProbeSamples = 1u << 14;
+constexpr uint64_t kTuneLtSteps = 1ull << 28;
 constexpr int kTuneReps = 2;  // each candidate is timed this often; the minimum counts
 // A probe of kProbeSamples with the wide shapes comes first; a graph whose
 // probe takes longer than kProbeMs (very deep or very large sets) keeps the
@@ -42,7 +46,9 @@ constexpr uint64_t kProbeSamples = 2048;
 constexpr double kProbeMs = 20.0;
 
 // LT: the lanes per walk (2 or 4) and the per-walk path filter size (1024,
-// 2048 or 4096 bits), each unless forced.
+// 2048 or 4096 bits), each unless forced. A probe with 4 lanes and 4096 bits
+// comes first; a graph whose probe takes longer than kProbeMs (very long
+// walks) keeps that shape.
 imm_status tune_lt(imm_graph* g, hipStream_t st) {
     if (g->bloom_forced && g->lanes_forced) {
         g->tuned = true;
@@ -51,8 +57,31 @@ imm_status tune_lt(imm_graph* g, hipStream_t st) {
     Workspace w;
     IMM_TRY(ws_init(w, g->n, g->device, st, 0));
     const bool log = std::getenv("IMM_TUNE_LOG") != nullptr;
+    if (!g->lanes_forced) g->lt_lanes = 4;
+    if (!g->bloom_forced) g->lt_bloom_bits = 12;
+    uint64_t batch = 0;
+    {
+        IMM_TRY(ws_reset(w, st, true));
+        IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kLtProbeSamples));
+        HIP_TRY(hipStreamSynchronize(st));
+        imm_stats s;
+        std::memset(&s, 0, sizeof(s));
+        fill_stats(w, &s);
+        const double probe_ms = s.ms_sample_main + s.ms_sample_big;
+        const double steps = (double)s.edges / (double)kLtProbeSamples;
+        if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
+        if (log)
+            std::fprintf(stderr, "imm tune: n=%u m=%llu LT probe %.3f ms, %.1f steps per walk\n",
+                         g->n, (unsigned long long)g->m, probe_ms, steps);
+        if (probe_ms > kProbeMs) {
+            g->tuned = true;
+            return IMM_OK;
+        }
+        const double want = (double)kTuneLtSteps / (steps > 1.0 ? steps : 1.0);
+        batch = (uint64_t)std::min(std::max(want, (double)(1u << 16)), (double)(1u << 21));
+    }
     std::vector<uint32_t> lane_opts, bit_opts;
-    if (g->lanes_forced) lane_opts = {g->lt_lanes}; else lane_opts = {2u, 4u};
+    if (g->lanes_forced) lane_opts = {g->lt_lanes}; else lane_opts = {4u, 2u};
     if (g->bloom_forced) bit_opts = {g->lt_bloom_bits}; else bit_opts = {12u, 11u, 10u};
     double best = -1.0;
     uint32_t pick_bits = bit_opts[0], pick_lanes = lane_opts[0];
@@ -66,20 +95,21 @@ imm_status tune_lt(imm_graph* g, hipStream_t st) {
             imm_stats s;
             for (int rep = warm ? 0 : -1; rep < kTuneReps; ++rep) {
                 IMM_TRY(ws_reset(w, st, true));
-                IMM_TRY(ws_extend(w, g, kTuneSeed, 0, kTuneLtSamples));
+                IMM_TRY(ws_extend(w, g, kTuneSeed, 0, batch));
                 HIP_TRY(hipStreamSynchronize(st));
                 std::memset(&s, 0, sizeof(s));
                 fill_stats(w, &s);
                 const double t = s.ms_sample_main + s.ms_sample_big;
                 if (rep >= 0 && (ms < 0.0 || t < ms)) ms = t;
+                if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
             }
             warm = true;
             if (log)
                 std::fprintf(stderr,
-                             "imm tune: n=%u m=%llu LT %u lanes per walk, filter 2^%u bits: walks "
-                             "%.3f ms, long %.3f ms\n",
-                             g->n, (unsigned long long)g->m, lanes, bits, s.ms_sample_main,
-                             s.ms_sample_big);
+                             "imm tune: n=%u m=%llu LT %u lanes per walk, filter 2^%u bits, %llu "
+                             "walks: %.3f ms, long %.3f ms\n",
+                             g->n, (unsigned long long)g->m, lanes, bits,
+                             (unsigned long long)batch, s.ms_sample_main, s.ms_sample_big);
             if (best < 0.0 || ms < best) {
                 best = ms;
                 pick_bits = bits;
@@ -113,6 +143,7 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
         std::memset(&s, 0, sizeof(s));
         fill_stats(w, &s);
         const double ms = s.ms_sample;
+        if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
         if (log) std::fprintf(stderr, "imm tune: n=%u probe %.3f ms\n", g->n, ms);
         if (ms > kProbeMs) {
             if (!g->big_forced) g->ic_big_block = 1024;
@@ -138,6 +169,7 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
             const double t = s.ms_sample_main + s.ms_sample_big;
             if (ms < 0.0 || t < ms) ms = t;
             *defer_rate = (double)s.deferred / (double)batch;
+            if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
         }
         if (log)
             std::fprintf(stderr, "imm tune: n=%u m=%llu batch=%llu team=%u big=%u: %.3f ms\n",

@@ -290,8 +290,12 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
     if (count64 == 0) return IMM_OK;
     if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
     uint32_t count = (uint32_t)count64;
-    // with no set-size estimate yet, a pilot batch measures one first
+    // a large batch with no set-size estimate yet takes the graph's tuning
+    // mean (with a margin), else a pilot batch measures one first; smaller
+    // batches keep the generous default
     constexpr uint32_t kPilot = 1u << 16;
+    if (w.mean_size <= 0.0 && count > 2 * kPilot && g->mean_set_hint > 0.0)
+        w.mean_size = 1.25 * g->mean_set_hint;
     if (w.mean_size <= 0.0 && count > 2 * kPilot) {
         const uint64_t before = w.n_sets;
         IMM_TRY(ws_extend_launch(w, g, seed, id_lo, kPilot));
