@@ -31,7 +31,7 @@ namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kDirectDeg = 8;    // columns read whole, without the guide
-constexpr uint32_t kScanLoads = 4;     // 16-byte path groups per lane per rescan round
+constexpr uint32_t kScanLoads = 2;     // 16-byte path groups per lane per rescan round
 
 // The three filter positions of v in a 2^BB-bit filter (multiplicative hashes).
 template <uint32_t BB>
@@ -119,32 +119,47 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
     return x;
 }
 
-// lt_pick for a walk run by a group of P lanes: each lane reads 8/P of the
-// eight records (a wave load instruction then touches 64/P lines instead of
-// 64, which the memory pipeline serves several times faster), the first lane
-// with a hit supplies the record. Every lane returns the same record and
-// count; the caller's control flow is uniform across the group.
+// The live in-edge of a column for a walk run by a group of P lanes, in two
+// parts so that a step's line read can be in flight while the walk does
+// other work. window_issue: each lane loads 8/P of the eight records (a wave
+// load instruction then touches 64/P lines instead of 64, which the memory
+// pipeline serves several times faster). Every load goes to a clamped
+// in-bounds position (a guarded load compiles to a branch with a wait of its
+// own); records past a short column are masked in window_pick. Needs d >= 1.
 template <uint32_t P>
-__device__ __forceinline__ uint4 lt_pick_group(const LtGraphDev& g, uint32_t beg, uint32_t end,
-                                               uint32_t r, uint32_t* reads, uint32_t sub,
-                                               uint32_t lead) {
+__device__ __forceinline__ void window_issue(const LtGraphDev& g, uint32_t beg, uint32_t end,
+                                             uint32_t r, uint32_t sub,
+                                             uint4 (&p)[kDirectDeg / P]) {
     constexpr uint32_t R = kDirectDeg / P;
     const uint32_t d = end - beg;
     const bool direct = d <= kDirectDeg;
     const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
     const uint4* w = direct ? g.cs + beg : g.gw + 8ull * (beg + jb);
-    // every load is issued, at a clamped in-bounds position, before any is
-    // used (a guarded load would cost a round trip of its own); records past
-    // a short column are masked afterwards
-    uint4 p[R];
 #pragma unroll
     for (uint32_t j = 0; j < R; ++j) {
         const uint32_t k = sub * R + j;
         p[j] = w[direct && k >= d ? d - 1 : k];
     }
+}
+
+// window_pick: the first lane of the group with a hit supplies the record
+// (src in .y, src's column bounds in .z/.w; .y = kNone for no live edge).
+// Every lane returns the same record and count; the caller's control flow is
+// uniform across the group. The answer lies past the window only when more
+// than seven edges of the column end inside r's bucket; the scan then goes
+// on in the column, four records per lane per round trip.
+template <uint32_t P>
+__device__ __forceinline__ uint4 window_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
+                                             uint32_t r, uint32_t* reads, uint32_t sub,
+                                             uint32_t lead, const uint4 (&w)[kDirectDeg / P]) {
+    constexpr uint32_t R = kDirectDeg / P;
+    const uint32_t d = end - beg;
+    const bool direct = d <= kDirectDeg;
+    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    uint4 p[R];
 #pragma unroll
     for (uint32_t j = 0; j < R; ++j)
-        if (direct && sub * R + j >= d) p[j] = make_uint4(0u, kNone, 0u, 0u);
+        p[j] = (direct && sub * R + j >= d) ? make_uint4(0u, kNone, 0u, 0u) : w[j];
     // this lane's first hit (R: none) and records inspected up to it
     uint32_t hj = R, used = 0;
     uint4 mine = make_uint4(0u, kNone, 0u, 0u);
@@ -172,8 +187,6 @@ __device__ __forceinline__ uint4 lt_pick_group(const LtGraphDev& g, uint32_t beg
     }
     if (direct) *reads += d;
     if (direct || gb) return res;
-    // more than seven edges end inside the bucket: scan on in the column,
-    // four records per lane per round trip
     for (uint32_t e = g.guide[beg + jb] + kDirectDeg; e < end; e += 4 * P) {
         const uint32_t e0 = e + 4 * sub;
         uint4 q[4];
@@ -262,10 +275,15 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
     // from the ticket 64 at a time (uniform across the wave)
     uint32_t res_pos = 0, res_end = 0;
 
-    bool has = false, done = false, fresh = false;
+    constexpr uint32_t R = kDirectDeg / P;
+    bool has = false, done = false, fresh = false, primed = false;
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
     uint32_t cbeg = 0, cend = 0;  // cur's column
     uint32_t nbeg = 0, nend = 0;  // a new root's column, in flight
+    uint32_t wr = 0;              // the draw at cur ...
+    uint4 win[R];                 // ... and this lane's part of its window, in flight
+#pragma unroll
+    for (uint32_t j = 0; j < R; ++j) win[j] = make_uint4(0u, kNone, 0u, 0u);
     uint64_t s = 0, chunk_base = 0;
     uint32_t w_steps = 0, w_reads = 0;
     uint64_t st_sets = 0, st_entries = 0, st_steps = 0, st_reads = 0;
@@ -336,26 +354,39 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                 w_reads = 0;
                 has = true;
                 fresh = true;
+                primed = false;
             }
         }
         // a walk slot whose start failed (staging full) takes the next
         // position: the wave leaves only when every slot has run past the
         // end, so no position it claimed from the ticket goes unprocessed
         if (!__any(has || !done)) break;
-        // a walk started in this iteration takes its first step in the next
-        // one: its column bounds load while the other walks' lines load,
-        // instead of costing the wave a round trip of its own
-        if (has && !fresh) {
-            // one step of the walk
-            uint4 pk = make_uint4(0u, kNone, 0u, 0u);
+        // The step is software-pipelined: a walk's window for its current
+        // vertex was issued in the previous iteration. As soon as the pick
+        // names the next vertex, that vertex's draw and window go out, ahead
+        // of the path check and of this step's writes (a load issued after a
+        // store waits for the store too), and are dropped if the walk ends.
+        // A walk started in an iteration draws at its root in the next one
+        // (its column bounds load meanwhile) and picks in the one after.
+        if (has && !fresh && !primed) {
             if (cbeg < cend) {
-                const uint32_t r = lt_draw(rg.seed, s, cur);
+                wr = lt_draw(rg.seed, s, cur);
                 ++w_steps;
-                pk = lt_pick_group<P>(g, cbeg, cend, r, &w_reads, sub, lead);
+                window_issue<P>(g, cbeg, cend, wr, sub, win);
             }
+            primed = true;
+        } else if (has && !fresh) {
+            uint4 pk = make_uint4(0u, kNone, 0u, 0u);
+            if (cbeg < cend) pk = window_pick<P>(g, cbeg, cend, wr, &w_reads, sub, lead, win);
             const uint32_t nxt = pk.y;
             bool finish = nxt == kNone;
             if (!finish) {
+                // the pick has consumed wr and win: they take nxt's draw and
+                // window (meaningless if the walk ends here)
+                if (pk.z < pk.w) {
+                    wr = lt_draw(rg.seed, s, nxt);
+                    window_issue<P>(g, pk.z, pk.w, wr, sub, win);
+                }
                 if (bloom_test<BB>(mb, nxt) &&
                     on_path_group<P>(o.stage, chunk_base + wstart, len, nxt, sub, lead))
                     finish = true;
@@ -398,6 +429,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                         cur = nxt;
                         cbeg = pk.z;
                         cend = pk.w;
+                        if (cbeg < cend) ++w_steps;
                     }
                 }
             }
