@@ -38,10 +38,13 @@ PHILOX_OPS = 60
 # WRITE_SIZE x 1.0, scaled by the 1 GiB copy calibration), for the kernel
 # and workload named (an IMM run, or "<workload>:sample<count>" for a
 # steady-state sampling run of that many ids), as recorded in profiles/
-# (ic_large_youtube_ic_pmc.md, lt_small_lj_lt_pmc.md); a kernel changed
+# (ic_large_youtube_ic_pmc.md, lt_small_lj_lt_pmc.md,
+# lt_small_lj_lt_sample_pmc.md); a kernel changed
 # since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
-    ("youtube_ic", "ic_large_kernel"): 8.164e9,
+    ("youtube_ic", "ic_large_kernel"): 8.168e9,
+    ("lj_lt", "lt_small_kernel"): 1.152e9,
+    ("lj_lt:sample4194304", "lt_small_kernel"): 78.61e9,
 }
 
 
