@@ -205,9 +205,12 @@ def batch_mode(args, imm, insts, graphs, stream, torch):
     """Aggregate IMM queries/s of the multi-instance workload: all instances
     in one imm_run_batch call per step, against the same instances run one
     at a time with imm_run on the same GPU."""
+    if args.graph_select:
+        stream = torch.cuda.Stream()  # a capturable stream (default priority)
     dgs = [imm.graph_from(g, stream=stream) for g in graphs]
     torch.cuda.synchronize()
-    qs = [(d, dict(k=s["k"], epsilon=s["eps"], ell=s["ell"], seed=s["seed"]))
+    fl = imm.IMM_GRAPH_SELECT if args.graph_select else 0
+    qs = [(d, dict(k=s["k"], epsilon=s["eps"], ell=s["ell"], seed=s["seed"], flags=fl))
           for d, s in zip(dgs, insts)]
 
     def batched():
@@ -252,6 +255,9 @@ def batch_mode(args, imm, insts, graphs, stream, torch):
         "speedup": ms_s / ms_b,
         "sets_per_s": sets / (ms_b * 1e-3),
         "theta_range": [min(r.theta for r in rb), max(r.theta for r in rb)],
+        "graph_select": bool(args.graph_select),
+        "select_graphs": sum(r.stats["select_graphs"] for r in rb),
+        "select_captures": sum(r.stats["select_captures"] for r in rb),
     }))
 
 
@@ -373,6 +379,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="multi-instance mode: this many IMM instances per step, "
                          "batched, against the same run one at a time")
+    ap.add_argument("--no-graph-select", dest="graph_select", action="store_false",
+                    help="batch mode: launch the seed steps directly instead of as captured "
+                         "hipGraphs (IMM_GRAPH_SELECT)")
     ap.add_argument("--serve", type=int, default=0,
                     help="served mode: this many Poisson-arrival queries through the "
                          "query server, against the same stream one at a time")

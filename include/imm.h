@@ -59,6 +59,11 @@ typedef enum {
 #define IMM_DEVICE_PTRS 0x1u /* array arguments are device pointers */
 #define IMM_KEEP_POOL 0x2u   /* imm_run: keep the final RRR pool for imm_result_pool */
 #define IMM_TIMING 0x4u      /* record per-phase kernel times with HIP events */
+/* imm_run_batch: capture each iteration's batched seed steps (3 launches
+ * per step for all runs) into a hipGraph, and replay it while the batch's
+ * shape (runs, steps, workgroup counts) repeats. Applies to an iteration
+ * when any of its runs sets it; results are unchanged. */
+#define IMM_GRAPH_SELECT 0x8u
 
 typedef struct imm_graph imm_graph;
 typedef struct imm_result imm_result;
@@ -110,6 +115,9 @@ typedef struct {
     double ms_queue;         /* server: submit to admission (ms_total is then
                                 submit to completion) */
     uint32_t walk_lanes;     /* LT: lanes per walk of the walk kernel (autotuned) */
+    uint32_t select_graphs;  /* imm_run_batch with IMM_GRAPH_SELECT: this run's
+                                selections done by launching a captured graph */
+    uint32_t select_captures;/* ... of which needed a new capture */
     uint32_t pad;
 } imm_stats;
 

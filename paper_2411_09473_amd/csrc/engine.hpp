@@ -324,12 +324,30 @@ public:
 
 private:
     void finish_err(Query* q, imm_status s);
+    // The kmax seed steps of nq runs as one captured graph on main_: the
+    // executable graph of the last shape is relaunched when the shape
+    // repeats, else updated in place or rebuilt; *captured tells whether it
+    // had to be captured. Returns 1 when launched; 0 when no graph could be
+    // made (e.g. main_ is the legacy default stream, which cannot be
+    // captured: nothing was launched, the caller launches the steps itself);
+    // -1 when the launch failed.
+    int select_graph(uint32_t nq, uint32_t kmax, uint32_t arg_total, uint32_t sel_total,
+                     bool* captured);
     hipStream_t main_;
     std::vector<Query*> active_, finished_;
     SelectDesc* descs_h_ = nullptr;
     SelectDesc* descs_d_ = nullptr;
     size_t cap_descs_ = 0;
     hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
+    hipGraphExec_t gexec_ = nullptr;
+    struct GraphShape {
+        const SelectDesc* descs;
+        uint32_t nq, kmax, arg_total, sel_total;
+        bool operator==(const GraphShape& o) const {
+            return descs == o.descs && nq == o.nq && kmax == o.kmax &&
+                   arg_total == o.arg_total && sel_total == o.sel_total;
+        }
+    } gshape_{};
 };
 
 // Runs queries independently of each other, each on its own stream: the

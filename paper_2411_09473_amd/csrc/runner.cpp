@@ -83,6 +83,7 @@ struct Query {
     imm_status status = IMM_OK;
     std::string err;
     double t0 = 0, ms_select = 0;
+    uint32_t select_graphs = 0, select_captures = 0;  // BatchRunner with IMM_GRAPH_SELECT
     uint64_t bytes = 0;  // device bytes of the workspace when finished
     SelectDesc desc{};
     // AsyncRunner: the event that marks the end of the queued work, and
@@ -211,6 +212,8 @@ imm_status end_iteration(Query& q) {
     r.stats.big_block = q.g->model == IMM_IC ? q.g->ic_big_block : 0;
     r.stats.bloom_bits = q.g->model == IMM_LT ? q.g->lt_bloom_bits : 0;
     r.stats.walk_lanes = q.g->model == IMM_LT ? q.g->lt_lanes : 0;
+    r.stats.select_graphs = q.select_graphs;
+    r.stats.select_captures = q.select_captures;
     if (q.p.flags & IMM_KEEP_POOL) {
         IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
         r.has_pool = true;
@@ -228,6 +231,7 @@ BatchRunner::BatchRunner(hipStream_t main) : main_(main) {}
 
 BatchRunner::~BatchRunner() {
     for (auto* q : active_) delete q;
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (descs_h_) (void)hipHostFree(descs_h_);
     if (descs_d_) (void)hipFree(descs_d_);
     if (ev_a_) (void)hipEventDestroy(ev_a_);
@@ -345,10 +349,25 @@ bool BatchRunner::step() {
             }
             ok = hipMemcpyAsync(descs_d_, descs_h_, descs.size() * sizeof(SelectDesc),
                                 hipMemcpyHostToDevice, main_) == hipSuccess;
+            bool graph = false;
+            for (auto* q : ready) graph |= (q->p.flags & IMM_GRAPH_SELECT) != 0;
             if (timing) (void)hipEventRecord(ev_a_, main_);
-            for (uint32_t t = 0; ok && t < kmax; ++t)
-                ok = launch_select_step(descs_d_, (uint32_t)descs.size(), t, arg_total, sel_total,
-                                        main_) == hipSuccess;
+            int launched = 0;
+            if (graph && ok) {
+                bool captured = false;
+                launched = select_graph((uint32_t)descs.size(), kmax, arg_total, sel_total,
+                                        &captured);
+                ok = launched >= 0;
+                for (auto* q : ready) {
+                    q->select_graphs += launched > 0 ? 1u : 0u;
+                    q->select_captures += launched > 0 && captured ? 1u : 0u;
+                }
+            }
+            if (launched == 0) {
+                for (uint32_t t = 0; ok && t < kmax; ++t)
+                    ok = launch_select_step(descs_d_, (uint32_t)descs.size(), t, arg_total,
+                                            sel_total, main_) == hipSuccess;
+            }
             if (timing) (void)hipEventRecord(ev_b_, main_);
             for (auto* q : ready)
                 if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main_) == IMM_OK;
@@ -373,6 +392,55 @@ bool BatchRunner::step() {
     }
     active_.swap(next);
     return true;
+}
+
+int BatchRunner::select_graph(uint32_t nq, uint32_t kmax, uint32_t arg_total, uint32_t sel_total,
+                              bool* captured) {
+    const GraphShape shape{descs_d_, nq, kmax, arg_total, sel_total};
+    *captured = false;
+    if (!gexec_ || !(shape == gshape_)) {
+        // the kernels only: nothing in the captured sequence is a memset or
+        // a copy (the descriptors are copied before each launch)
+        if (hipStreamBeginCapture(main_, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        hipError_t le = hipSuccess;
+        for (uint32_t t = 0; le == hipSuccess && t < kmax; ++t)
+            le = launch_select_step(descs_d_, nq, t, arg_total, sel_total, main_);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(main_, &graph);
+        if (le != hipSuccess || ce != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return 0;
+        }
+        bool have = false;
+        if (gexec_) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            have = hipGraphExecUpdate(gexec_, graph, &bad, &res) == hipSuccess &&
+                   res == hipGraphExecUpdateSuccess;
+            if (!have) {
+                // a refused update (a different topology or launch shape) is
+                // no failure: clear it so no later launch reports it, and
+                // instantiate anew
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(gexec_);
+                gexec_ = nullptr;
+            }
+        }
+        if (!have) have = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(graph);
+        if (!have) {
+            gexec_ = nullptr;
+            (void)hipGetLastError();
+            return 0;
+        }
+        gshape_ = shape;
+        *captured = true;
+    }
+    return hipGraphLaunch(gexec_, main_) == hipSuccess ? 1 : -1;
 }
 
 std::vector<Query*> BatchRunner::drain() {

@@ -26,9 +26,14 @@ def _check(r, o, g=None):
         np.testing.assert_array_equal(sv, csv)
 
 
-def test_batch_mixed_models(imm, orc, stream):
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_mixed_models(imm, orc, stream, graph):
     """IC and LT queries, giant sets, a graph shared by several queries, and
-    kept pools, in one batch."""
+    kept pools, in one batch; with graph, the seed steps run as captured
+    graphs, recaptured or updated as the batch's shape changes."""
+    if graph:
+        import torch
+        stream = torch.cuda.Stream()  # a capturable stream (default priority)
     names = ["rmat12_wc", "rmat12_lt", "cl_lt_xs", "rmat12_p10"]
     graphs = {nm: synth.make_graph(nm) for nm in names}
     dev = {nm: imm.graph_from(g, stream=stream) for nm, g in graphs.items()}
@@ -40,6 +45,9 @@ def test_batch_mixed_models(imm, orc, stream):
     qs.append(("rmat12_wc", dict(k=25, epsilon=0.3, seed=7)))
     qs.append(("rmat12_wc", dict(k=1, epsilon=0.5, seed=8, ell=2.0)))
     qs.append(("rmat12_lt", dict(k=40, epsilon=0.25, seed=9)))
+    if graph:
+        for _, q in qs:
+            q["flags"] = q.get("flags", 0) | imm.IMM_GRAPH_SELECT
     say(f"batch of {len(qs)}: " + ", ".join(f"{nm} k={q['k']}" for nm, q in qs))
     res = imm.imm_run_batch([(dev[nm], q) for nm, q in qs], stream=stream)
     for (nm, q), r in zip(qs, res):
@@ -52,6 +60,35 @@ def test_batch_mixed_models(imm, orc, stream):
                           stream=stream)
         np.testing.assert_array_equal(one.seeds, r.seeds)
         assert one.theta == r.theta
+        if graph:
+            assert r.stats["select_graphs"] == r.rounds + 1
+        else:
+            assert r.stats["select_graphs"] == 0
+
+
+def test_batch_graph_select_replays(imm, orc):
+    """IMM_GRAPH_SELECT on a one-run batch: the batch's shape is the same every
+    round, so the seed steps are captured once and the graph is replayed in
+    every later round, with that round's sampling, compaction and index (run
+    eagerly) between replays. Every round's coverage and the final seeds
+    equal the oracle's, and the eager batch's."""
+    import torch
+    s = torch.cuda.Stream()  # a capturable stream (default priority)
+    for nm in ("rmat12_wc", "rmat12_lt"):
+        g = synth.make_graph(nm)
+        sp = synth.WORKLOADS[nm]
+        dg = imm.graph_from(g, stream=s)
+        q = dict(k=sp["k"], epsilon=sp["eps"], ell=sp["ell"], seed=sp["seed"])
+        say(f"graph replays {nm}")
+        rg = imm.imm_run_batch([(dg, dict(q, flags=imm.IMM_GRAPH_SELECT))], stream=s)[0]
+        re_ = imm.imm_run_batch([(dg, q)], stream=s)[0]
+        o = orc.imm(g, q["k"], q["epsilon"], q["ell"], q["seed"], threads=oracle_threads())
+        _check(rg, o)
+        _check(re_, o)
+        assert rg.rounds >= 2
+        assert rg.stats["select_graphs"] == rg.rounds + 1
+        assert rg.stats["select_captures"] == 1
+        assert re_.stats["select_graphs"] == 0
 
 
 def test_batch_of_64_instances(imm, orc, stream):
