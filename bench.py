@@ -301,7 +301,8 @@ def serve_mode(args, imm, hgraphs, stream, torch):
             if dt > 0:
                 time.sleep(dt)
             tickets[i] = srv.submit(dgs[q["graph"]], k=q["k"], epsilon=q["eps"], ell=q["ell"],
-                                    seed=q["seed"])
+                                    seed=q["seed"],
+                                    flags=imm.IMM_GRAPH_SELECT if args.graph_select else 0)
 
     t0 = time.perf_counter()
     th = threading.Thread(target=submitter, args=(t0,))
@@ -341,6 +342,7 @@ def serve_mode(args, imm, hgraphs, stream, torch):
                                "eps in {0.5,0.13}",
                    "max_slots": args.serve_slots, "budget_GiB": args.serve_budget,
                    "parallelism": "single GPU"},
+        "graph_select": bool(args.graph_select),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(np.mean(lat))},
         "one_at_a_time": {"queries_per_s": one_qps,
@@ -380,8 +382,8 @@ def main():
                     help="multi-instance mode: this many IMM instances per step, "
                          "batched, against the same run one at a time")
     ap.add_argument("--no-graph-select", dest="graph_select", action="store_false",
-                    help="batch mode: launch the seed steps directly instead of as captured "
-                         "hipGraphs (IMM_GRAPH_SELECT)")
+                    help="batch and served modes: launch the seed steps directly instead of "
+                         "as captured hipGraphs (IMM_GRAPH_SELECT)")
     ap.add_argument("--serve", type=int, default=0,
                     help="served mode: this many Poisson-arrival queries through the "
                          "query server, against the same stream one at a time")

@@ -59,10 +59,13 @@ typedef enum {
 #define IMM_DEVICE_PTRS 0x1u /* array arguments are device pointers */
 #define IMM_KEEP_POOL 0x2u   /* imm_run: keep the final RRR pool for imm_result_pool */
 #define IMM_TIMING 0x4u      /* record per-phase kernel times with HIP events */
-/* imm_run_batch: capture each iteration's batched seed steps (3 launches
- * per step for all runs) into a hipGraph, and replay it while the batch's
- * shape (runs, steps, workgroup counts) repeats. Applies to an iteration
- * when any of its runs sets it; results are unchanged. */
+/* imm_run, imm_run_batch, server queries: launch each greedy selection's k
+ * seed steps (3 kernels per step) as a captured hipGraph, relaunched while
+ * the shape (runs, steps, workgroup counts) repeats: a single run captures
+ * once and replays the graph every round. In a batch, an iteration's
+ * selection uses it when any of its runs sets it. On a stream that cannot
+ * be captured (the legacy default stream) the steps are launched directly.
+ * Results are unchanged. */
 #define IMM_GRAPH_SELECT 0x8u
 
 typedef struct imm_graph imm_graph;
@@ -115,8 +118,8 @@ typedef struct {
     double ms_queue;         /* server: submit to admission (ms_total is then
                                 submit to completion) */
     uint32_t walk_lanes;     /* LT: lanes per walk of the walk kernel (autotuned) */
-    uint32_t select_graphs;  /* imm_run_batch with IMM_GRAPH_SELECT: this run's
-                                selections done by launching a captured graph */
+    uint32_t select_graphs;  /* with IMM_GRAPH_SELECT: this run's selections
+                                done by launching a captured graph */
     uint32_t select_captures;/* ... of which needed a new capture */
     uint32_t pad;
 } imm_stats;

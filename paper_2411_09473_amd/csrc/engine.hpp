@@ -120,6 +120,25 @@ struct Timer {
 // segments, one per round, each indexing only that round's sets (segment r
 // occupies inv_set positions [P_{r-1}, P_r), the range its sets occupy in
 // set_vtx), so no set is indexed twice.
+// The kmax seed steps of nq runs (launch_select_step for t < kmax) as one
+// captured hipGraph: launch() relaunches the executable graph while the
+// shape (descriptor buffer, runs, steps, workgroup counts) repeats, else
+// updates it in place or instantiates it anew; *captured tells whether it
+// had to capture. Returns 1 when launched; 0 when no graph could be made
+// (e.g. the legacy default stream cannot be captured): nothing was
+// launched, the caller launches the steps itself; -1 when the launch failed.
+struct SelectGraph {
+    hipGraphExec_t exec = nullptr;
+    const SelectDesc* descs = nullptr;
+    uint32_t nq = 0, kmax = 0, arg_total = 0, sel_total = 0;
+    int launch(const SelectDesc* descs, uint32_t nq, uint32_t kmax, uint32_t arg_total,
+               uint32_t sel_total, hipStream_t st, bool* captured);
+    SelectGraph() = default;
+    SelectGraph(const SelectGraph&) = delete;
+    SelectGraph& operator=(const SelectGraph&) = delete;
+    ~SelectGraph();
+};
+
 struct Workspace {
     int device = 0;
     uint32_t n = 0;
@@ -176,6 +195,7 @@ struct Workspace {
     uint32_t* gains_h = nullptr;  // pinned
     SelectDesc* desc_d = nullptr; // one descriptor, for selection run alone
     SelectDesc desc_h{};          // its host copy (kept while the copy is queued)
+    SelectGraph sel_graph;        // its seed steps as a captured graph (IMM_GRAPH_SELECT)
     uint32_t* big = nullptr;   // giant-set slots: bitmap + bounded queue each
     uint32_t big_slots = 0;
     uint32_t big_qcap = 0;
@@ -275,7 +295,11 @@ imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st);
 imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
 // The selection of this workspace alone, launched on w.st without waiting
 // (then ws_select_finish once the stream is done).
-imm_status ws_select_launch(Workspace& w, uint32_t k);
+// graph: launch the seed steps as w.sel_graph (IMM_GRAPH_SELECT); *graph_out
+// (if given) is 0 when they were launched directly, 1 when a graph was
+// relaunched, 2 when it had to be captured first.
+imm_status ws_select_launch(Workspace& w, uint32_t k, bool graph = false,
+                            int* graph_out = nullptr);
 // Prepare, run and finish the selection of this workspace alone.
 imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
 imm_status ws_sync_pool(Workspace& w);
@@ -324,30 +348,13 @@ public:
 
 private:
     void finish_err(Query* q, imm_status s);
-    // The kmax seed steps of nq runs as one captured graph on main_: the
-    // executable graph of the last shape is relaunched when the shape
-    // repeats, else updated in place or rebuilt; *captured tells whether it
-    // had to be captured. Returns 1 when launched; 0 when no graph could be
-    // made (e.g. main_ is the legacy default stream, which cannot be
-    // captured: nothing was launched, the caller launches the steps itself);
-    // -1 when the launch failed.
-    int select_graph(uint32_t nq, uint32_t kmax, uint32_t arg_total, uint32_t sel_total,
-                     bool* captured);
     hipStream_t main_;
     std::vector<Query*> active_, finished_;
     SelectDesc* descs_h_ = nullptr;
     SelectDesc* descs_d_ = nullptr;
     size_t cap_descs_ = 0;
     hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
-    hipGraphExec_t gexec_ = nullptr;
-    struct GraphShape {
-        const SelectDesc* descs;
-        uint32_t nq, kmax, arg_total, sel_total;
-        bool operator==(const GraphShape& o) const {
-            return descs == o.descs && nq == o.nq && kmax == o.kmax &&
-                   arg_total == o.arg_total && sel_total == o.sel_total;
-        }
-    } gshape_{};
+    SelectGraph graph_;  // the batched seed steps (IMM_GRAPH_SELECT)
 };
 
 // Runs queries independently of each other, each on its own stream: the

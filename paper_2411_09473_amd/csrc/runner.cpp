@@ -231,7 +231,6 @@ BatchRunner::BatchRunner(hipStream_t main) : main_(main) {}
 
 BatchRunner::~BatchRunner() {
     for (auto* q : active_) delete q;
-    if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (descs_h_) (void)hipHostFree(descs_h_);
     if (descs_d_) (void)hipFree(descs_d_);
     if (ev_a_) (void)hipEventDestroy(ev_a_);
@@ -355,8 +354,8 @@ bool BatchRunner::step() {
             int launched = 0;
             if (graph && ok) {
                 bool captured = false;
-                launched = select_graph((uint32_t)descs.size(), kmax, arg_total, sel_total,
-                                        &captured);
+                launched = graph_.launch(descs_d_, (uint32_t)descs.size(), kmax, arg_total,
+                                         sel_total, main_, &captured);
                 ok = launched >= 0;
                 for (auto* q : ready) {
                     q->select_graphs += launched > 0 ? 1u : 0u;
@@ -392,55 +391,6 @@ bool BatchRunner::step() {
     }
     active_.swap(next);
     return true;
-}
-
-int BatchRunner::select_graph(uint32_t nq, uint32_t kmax, uint32_t arg_total, uint32_t sel_total,
-                              bool* captured) {
-    const GraphShape shape{descs_d_, nq, kmax, arg_total, sel_total};
-    *captured = false;
-    if (!gexec_ || !(shape == gshape_)) {
-        // the kernels only: nothing in the captured sequence is a memset or
-        // a copy (the descriptors are copied before each launch)
-        if (hipStreamBeginCapture(main_, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            (void)hipGetLastError();
-            return 0;
-        }
-        hipError_t le = hipSuccess;
-        for (uint32_t t = 0; le == hipSuccess && t < kmax; ++t)
-            le = launch_select_step(descs_d_, nq, t, arg_total, sel_total, main_);
-        hipGraph_t graph = nullptr;
-        const hipError_t ce = hipStreamEndCapture(main_, &graph);
-        if (le != hipSuccess || ce != hipSuccess || !graph) {
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            return 0;
-        }
-        bool have = false;
-        if (gexec_) {
-            hipGraphNode_t bad = nullptr;
-            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
-            have = hipGraphExecUpdate(gexec_, graph, &bad, &res) == hipSuccess &&
-                   res == hipGraphExecUpdateSuccess;
-            if (!have) {
-                // a refused update (a different topology or launch shape) is
-                // no failure: clear it so no later launch reports it, and
-                // instantiate anew
-                (void)hipGetLastError();
-                (void)hipGraphExecDestroy(gexec_);
-                gexec_ = nullptr;
-            }
-        }
-        if (!have) have = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0) == hipSuccess;
-        (void)hipGraphDestroy(graph);
-        if (!have) {
-            gexec_ = nullptr;
-            (void)hipGetLastError();
-            return 0;
-        }
-        gshape_ = shape;
-        *captured = true;
-    }
-    return hipGraphLaunch(gexec_, main_) == hipSuccess ? 1 : -1;
 }
 
 std::vector<Query*> BatchRunner::drain() {
@@ -519,7 +469,11 @@ bool AsyncRunner::poll() {
         if (s == IMM_OK && q->phase == 0) {
             // sampling round done: finish it, launch the selection
             s = ws_extend_finish(*q->w, q->g, q->p.seed);
-            if (s == IMM_OK) s = ws_select_launch(*q->w, q->p.k);
+            int gs = 0;
+            if (s == IMM_OK)
+                s = ws_select_launch(*q->w, q->p.k, (q->p.flags & IMM_GRAPH_SELECT) != 0, &gs);
+            q->select_graphs += gs > 0 ? 1u : 0u;
+            q->select_captures += gs == 2 ? 1u : 0u;
             q->phase = 1;
         } else if (s == IMM_OK) {
             // selection done: theta decision, then the next round (if any)

@@ -518,7 +518,63 @@ imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint
     return IMM_OK;
 }
 
-imm_status ws_select_launch(Workspace& w, uint32_t k) {
+SelectGraph::~SelectGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+int SelectGraph::launch(const SelectDesc* d, uint32_t q, uint32_t km, uint32_t at, uint32_t stot,
+                        hipStream_t st, bool* captured) {
+    *captured = false;
+    if (!exec || d != descs || q != nq || km != kmax || at != arg_total || stot != sel_total) {
+        // the kernels only: nothing in the captured sequence is a memset or
+        // a copy (the descriptors are copied before each launch)
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        hipError_t le = hipSuccess;
+        for (uint32_t t = 0; le == hipSuccess && t < km; ++t)
+            le = launch_select_step(d, q, t, at, stot, st);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (le != hipSuccess || ce != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return 0;
+        }
+        bool have = false;
+        if (exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            have = hipGraphExecUpdate(exec, graph, &bad, &res) == hipSuccess &&
+                   res == hipGraphExecUpdateSuccess;
+            if (!have) {
+                // a refused update (a different topology or launch shape) is
+                // no failure: clear it so no later launch reports it, and
+                // instantiate anew
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+            }
+        }
+        if (!have) have = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(graph);
+        if (!have) {
+            exec = nullptr;
+            (void)hipGetLastError();
+            return 0;
+        }
+        descs = d;
+        nq = q;
+        kmax = km;
+        arg_total = at;
+        sel_total = stot;
+        *captured = true;
+    }
+    return hipGraphLaunch(exec, st) == hipSuccess ? 1 : -1;
+}
+
+imm_status ws_select_launch(Workspace& w, uint32_t k, bool graph, int* graph_out) {
     hipStream_t st = w.st;
     SelectDesc& d = w.desc_h;
     IMM_TRY(ws_select_prepare(w, k, &d));
@@ -526,8 +582,16 @@ imm_status ws_select_launch(Workspace& w, uint32_t k) {
     d.sel_cnt = select_blocks(w.device, w.n_sets, 1);
     HIP_TRY(hipMemcpyAsync(w.desc_d, &d, sizeof(d), hipMemcpyHostToDevice, st));
     const int ts = w.timer.open(3, st);
-    for (uint32_t t = 0; t < k; ++t)
-        HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, st));
+    int launched = 0;
+    bool captured = false;
+    if (graph) {
+        launched = w.sel_graph.launch(w.desc_d, 1, k, d.arg_cnt, d.sel_cnt, st, &captured);
+        if (launched < 0) return fail(IMM_EDEVICE, "select: graph launch failed");
+    }
+    if (launched == 0)
+        for (uint32_t t = 0; t < k; ++t)
+            HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, st));
+    if (graph_out) *graph_out = launched == 0 ? 0 : (captured ? 2 : 1);
     w.timer.close(ts, st);
     return ws_select_copy_out(w, k, st);
 }

@@ -30,14 +30,17 @@ def graphs(imm, stream):
     return hg, dg
 
 
-def test_server_mixed_stream_equals_alone(imm, orc, stream, graphs):
+@pytest.mark.parametrize("graph", [False, True])
+def test_server_mixed_stream_equals_alone(imm, orc, stream, graphs, graph):
+    """With graph, every query's greedy selections run as its captured graph
+    (IMM_GRAPH_SELECT), captured in its first round and replayed after."""
     hg, dg = graphs
     rng = np.random.default_rng(1)
     qs = []
     for i in range(16):
         nm = list(hg)[i % len(hg)]
         qs.append((nm, dict(k=int(rng.choice([1, 5, 10, 25])), epsilon=float(rng.choice([0.5, 0.3])),
-                            seed=100 + i)))
+                            seed=100 + i, flags=imm.IMM_GRAPH_SELECT if graph else 0)))
     srv = imm.Server(budget_bytes=64 << 30, max_slots=6)
     tickets = []
     # a first wave, then the rest while the first still runs
@@ -57,6 +60,16 @@ def test_server_mixed_stream_equals_alone(imm, orc, stream, graphs):
         one = imm.imm_run(dg[nm], q["k"], q["epsilon"], 1.0, q["seed"], stream=stream)
         np.testing.assert_array_equal(one.seeds, r.seeds)
         assert r.stats["ms_total"] >= r.stats["ms_queue"] >= 0.0
+        if graph:
+            assert r.stats["select_graphs"] == r.rounds + 1
+            assert r.stats["select_captures"] <= r.stats["select_graphs"]
+        else:
+            assert r.stats["select_graphs"] == 0
+    if graph:
+        # captured at least once, replayed more often than captured (a
+        # workspace reused from an earlier query may need no capture at all)
+        caps = sum(r.stats["select_captures"] for r in res)
+        assert 1 <= caps < sum(r.stats["select_graphs"] for r in res)
 
 
 def test_server_one_slot_queues_in_order(imm, orc, stream, graphs):
