@@ -34,6 +34,7 @@ namespace imm {
 namespace {
 
 constexpr uint32_t kArgBS = 256;
+constexpr uint32_t kArgLoads = 4;
 constexpr uint32_t kClaimBS = 256;
 constexpr uint32_t kDecBS = 256;
 
@@ -144,14 +145,25 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
     uint64_t best = 0;
     const uint32_t n4 = n >> 2;
     const IMM_GLOBAL uint4* cw4 = (const IMM_GLOBAL uint4*)cw;
-    for (uint32_t x = gtid; x < n4; x += gthreads) {
-        const uint4 c = load_u4(cw4 + x);
-        const uint32_t v = x << 2;
-        uint64_t k = vkey(c.x, v);
-        uint64_t y = vkey(c.y, v + 1); k = y > k ? y : k;
-        y = vkey(c.z, v + 2); k = y > k ? y : k;
-        y = vkey(c.w, v + 3); k = y > k ? y : k;
-        best = k > best ? k : best;
+    // kArgLoads 16-byte loads in flight per thread: unguarded, at clamped
+    // positions (a repeated group changes no maximum)
+    for (uint32_t x0 = gtid; x0 < n4; x0 += kArgLoads * gthreads) {
+        uint4 c[kArgLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kArgLoads; ++u) {
+            const uint32_t x = x0 + u * gthreads;
+            c[u] = load_u4(cw4 + (x < n4 ? x : x0));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kArgLoads; ++u) {
+            const uint32_t x = x0 + u * gthreads;
+            const uint32_t v = (x < n4 ? x : x0) << 2;
+            uint64_t k = vkey(c[u].x, v);
+            uint64_t y = vkey(c[u].y, v + 1); k = y > k ? y : k;
+            y = vkey(c[u].z, v + 2); k = y > k ? y : k;
+            y = vkey(c[u].w, v + 3); k = y > k ? y : k;
+            best = k > best ? k : best;
+        }
     }
     if (gtid < (n & 3u)) {
         const uint32_t v = (n4 << 2) + gtid;
@@ -504,9 +516,9 @@ __global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, 
 }  // namespace
 
 uint32_t argmax_blocks(uint32_t n) {
-    uint32_t g = (n / 4 + kArgBS * 4 - 1) / (kArgBS * 4);
+    uint32_t g = (n / 4 + kArgBS * kArgLoads - 1) / (kArgBS * kArgLoads);
     if (g < 1) g = 1;
-    if (g > 512) g = 512;
+    if (g > 1024) g = 1024;
     return g;
 }
 
