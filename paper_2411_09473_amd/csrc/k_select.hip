@@ -236,14 +236,16 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
                 const uint32_t j = d.inv_set[pos];
                 const uint32_t bit = 1u << (j & 31);
                 const uint32_t old = g_or(&d.covered[j >> 5], bit);
-                if (!(old & bit)) {
-                    a = d.set_off[j];
-                    sz = d.set_off[j + 1] - a;
-                    cov += sz;
-                    // a set of one member is {v} itself: nothing to decrement
-                    if (sz > 1 && sz <= kSmallSet) small = true;
-                    else if (sz > kSmallSet) nbig = (uint32_t)((sz + kWave - 1) / kWave);
-                }
+                // the set's bounds load beside the claim, not after it (the
+                // claim selects them rather than guarding their loads)
+                const uint64_t a0 = d.set_off[j], a1 = d.set_off[j + 1];
+                const bool claimed = !(old & bit);
+                a = claimed ? a0 : 0;
+                sz = claimed ? a1 - a0 : 0;
+                cov += sz;
+                // a set of one member is {v} itself: nothing to decrement
+                small = sz > 1 && sz <= kSmallSet;
+                nbig = sz > kSmallSet ? (uint32_t)((sz + kWave - 1) / kWave) : 0u;
             }
             // one reservation per wave and queue
             const uint64_t smask = __ballot(small);
