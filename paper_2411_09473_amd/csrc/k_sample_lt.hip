@@ -16,9 +16,9 @@
 //    source's column, so the next step needs no offset load.
 //  * The path is written straight into the walk's staging chunk. A per-walk
 //    Bloom filter of 1024 to 4096 bits (three hashes, size picked per graph
-//    by the autotuner) in LDS answers "not on the path"
-//    for most vertices; a hit is confirmed by rescanning the path
-//    (vectorised), so the test is exact.
+//    by the autotuner) in LDS answers "not on the path" for most vertices; a
+//    hit is confirmed by rescanning the path (vectorised), so the test is
+//    exact.
 //  * Counts are incremented as vertices join the path; a walk that has to
 //    move to the large-walk kernel (path longer than a chunk) or to a retry
 //    (staging full) gives its increments back first.
@@ -41,7 +41,7 @@ __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t h[3]) {
     h[2] = (v * 0xC2B2AE3Du) >> (32 - BB);
 }
 
-// mb points at this lane's filter (2^BB / 32 consecutive words).
+// mb points at the walk's filter (2^BB / 32 consecutive words).
 template <uint32_t BB>
 __device__ __forceinline__ void bloom_set(uint32_t* mb, uint32_t v) {
     uint32_t h[3];
@@ -60,9 +60,10 @@ __device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
     return all;
 }
 
-// The live in-edge of the column [beg, end) for draw r: its record (src in
-// .y, src's column bounds in .z/.w), or .y = kNone. *reads counts the
-// records inspected. Every lane reads eight records in one round trip: a
+// The live in-edge of the column [beg, end) for draw r, for a walk run by a
+// single lane (the long-walk kernel): its record (src in .y, src's column
+// bounds in .z/.w), or .y = kNone. *reads counts the records inspected. The
+// lane reads eight records in one round trip: a
 // short column (d <= kDirectDeg) whole, a longer one the copy of the eight
 // records from the guide entry of r's bucket. The answer lies further on only
 // when more than seven edges of the column end inside the bucket; then the
@@ -260,10 +261,11 @@ __device__ __forceinline__ bool on_path_group(const uint32_t* stage, uint64_t po
 // chunk reservations, list appends), and every lane writes the path entries
 // it later rescans. A smaller filter leaves more waves resident (more walks
 // in flight) at the price of more false hits, each confirmed by a path
-// rescan.
+// rescan. The launch bounds hold the kernel to 96 VGPRs, five waves per SIMD
+// (the LDS of 16 walks' 4096-bit filters allows five as well).
 template <uint32_t BB, uint32_t P>
-__global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
-                                                      uint32_t* ticket) {
+__global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRange rg,
+                                                         SampleOut o, uint32_t* ticket) {
     constexpr uint32_t kBloomWords = (1u << BB) / 32;
     constexpr uint32_t kWalks = kWave / P;
     __shared__ uint32_t bloom[kBloomWords * kWalks];
