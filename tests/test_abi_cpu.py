@@ -105,3 +105,31 @@ def test_greedy_rejects_bad_pool_before_device(imm):
     with pytest.raises(imm.ImmError) as e:
         imm.imm_greedy(4, np.array([0, 2], np.uint64), np.array([0, 1], np.uint32), 5)
     assert e.value.status == imm.IMM_EINVAL
+
+
+@pytest.mark.parametrize("struct", ["imm_params", "imm_stats"])
+def test_binding_structs_match_the_header(imm, tmp_path, struct):
+    """The ctypes mirrors of the header's structs have the C layout: every
+    field's offset and the struct's size, as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    py = getattr(imm, struct)
+    fields = [f for f, _ in py._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stddef.h>\n#include <stdio.h>\n#include \"imm.h\"\n"
+        "int main(void) {\n"
+        f"    printf(\"size %zu\\n\", sizeof({struct}));\n"
+        + "".join(f"    printf(\"{f} %zu\\n\", offsetof({struct}, {f}));\n" for f in fields)
+        + "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", str(ROOT / "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(py)
+    for f in fields:
+        assert int(out[f]) == getattr(py, f).offset, f
