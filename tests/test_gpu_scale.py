@@ -10,6 +10,9 @@
   the returned pool; the theta schedule is checked against the host-side
   theta plan.
 * One-tenth-size versions of both, bit-exact on the whole run.
+* The LiveJournal-shaped steady-state sampling call (2^22 ids) in the
+  benchmark's launch configuration: sampled sets one by one, and the fused
+  counts against the whole returned pool.
 """
 
 import math
@@ -92,3 +95,27 @@ def test_youtube_full_size_sampled(imm, orc, stream):
     np.testing.assert_array_equal(r.seeds, os_)
     np.testing.assert_array_equal(r.gains, og)
     assert r.covered == ocov
+
+
+@pytest.mark.timeout(300)
+def test_lj_lt_steady_state_sampled(imm, orc, stream):
+    """The steady-state sampling call the benchmark times on the
+    LiveJournal-shaped graph (2^22 ids, seed 42, the autotuned walk shape):
+    sampled sets recomputed one by one by the oracle, and the fused counts
+    equal to the occurrences in the whole returned pool."""
+    spec = synth.WORKLOADS["lj_lt"]
+    g = synth.make_graph("lj_lt")
+    dg = imm.graph_from(g, stream=stream)
+    count = 1 << 22
+    say(f"steady-state LT sampling, {count} ids")
+    pool = imm.imm_sample(dg, spec["seed"], 0, count, stream=stream)
+    assert pool.stats["walk_lanes"] in (2, 4)
+    so, sv, cn = pool.export()
+    pool.close()
+    assert so.size - 1 == count
+    rng = np.random.default_rng(2025)
+    ids = np.concatenate([[0, 1, count - 1], rng.integers(0, count, 2000)])
+    for s in ids:
+        want = np.sort(orc.rrr_set(g, spec["seed"], int(s)))
+        np.testing.assert_array_equal(sv[so[s]:so[s + 1]], want, err_msg=f"set {s}")
+    np.testing.assert_array_equal(cn, np.bincount(sv, minlength=g.n).astype(cn.dtype))
