@@ -274,11 +274,14 @@ def test_giant_set_hub_column_spans_two_pages(imm, orc, stream, monkeypatch, big
     assert int(np.diff(so).max()) > 1024  # went through the giant-set pass
 
 
-def test_recount_with_long_index_lists(imm, orc, stream):
+@pytest.mark.parametrize("eps,first_gain", [(0.1, 10455), (0.07, 20515)])
+def test_recount_with_long_index_lists(imm, orc, stream, eps, first_gain):
     """Two hubs, each in most sets of its own parity class and in some of the
     other's: the first seed covers more than a quarter of the pool, so the
-    next counts are rebuilt by a recount in which the other hub (about 10,000
-    index entries, partly covered) is a work item of its own."""
+    next counts are rebuilt by a recount in which the other hub (10,000 or
+    more index entries, partly covered) is a work item of its own. The
+    first seed's lists hold about 10,000 positions at eps = 0.1 and about
+    20,000 at eps = 0.07."""
     rng = np.random.default_rng(21)
     n = 20002
     edges, thr = [], []
@@ -294,6 +297,6 @@ def test_recount_with_long_index_lists(imm, orc, stream):
             edges.append((int(u), hub))
             thr.append(int(1e-3 * T32))
     g = synth.tiny_graph(n, edges, "ic", thr)
-    say("two-hub recount")
-    r = _parity(imm, orc, g, 5, 0.1, 17, stream, pool=False)
-    assert r.theta > 2 * 4096 and r.gains[1] > 0
+    say(f"two-hub recount eps={eps}")
+    r = _parity(imm, orc, g, 5, eps, 17, stream, pool=False)
+    assert r.theta > 2 * 4096 and r.gains[1] > 0 and r.gains[0] == first_gain
