@@ -21,7 +21,10 @@
 //    exact.
 //  * Counts are incremented as vertices join the path; a walk that has to
 //    move to the large-walk kernel (path longer than a chunk) or to a retry
-//    (staging full) gives its increments back first.
+//    (staging full) gives its increments back first. The large-walk kernel
+//    picks a walk up where it stopped: the draw at a vertex depends only on
+//    the sample and the vertex, so the chunk's path and the next vertex are
+//    all it needs.
 #include "device_common.hpp"
 #include "imm_internal.hpp"
 
@@ -410,13 +413,22 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                                 o.retry[atomicAdd(o.retry_n, 1u)] = idx;
                             }
                         } else if (first) {
+                            // the large-walk kernel resumes at nxt (checked
+                            // to be off the path): the path stays in this
+                            // chunk, whose offset and nxt go in the sample's
+                            // slots; the steps taken so far count here
+                            o.stage_off[idx] = chunk_base;
+                            o.sizes[idx] = nxt;
+                            st_steps += w_steps;
+                            st_reads += w_reads;
                             o.defer[atomicAdd(o.defer_n, 1u)] = idx;
                         }
                         if (!moved) {
                             if (first)
                                 for (uint32_t t = 0; t < len; ++t)
                                     atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
-                            chunk_used = wstart;
+                            // a deferred path keeps its chunk
+                            chunk_used = wstart == 0 ? kLtChunk : wstart;
                             has = false;
                             keep = false;
                         }
@@ -466,9 +478,11 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
     }
 }
 
-// Walks handed over by lt_small_kernel: one walk per wave, lane 0 walks with
-// an exact visited bitmap in device memory (slot per workgroup), then the
-// wave stages the path and counts it.
+// Walks handed over by lt_small_kernel, one per wave: the wave marks the
+// kLtChunk members it left staged in an exact visited bitmap in device memory
+// (slot per workgroup) and copies them to the workgroup's queue, lane 0
+// continues the walk from the vertex it was about to add, then the wave
+// stages the whole path and counts it.
 __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange rg, SampleOut o,
                                                       const uint32_t* list, const uint32_t* list_n,
                                                       uint32_t* fail, uint32_t* fail_n,
@@ -488,10 +502,18 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
         if (li >= cnt) break;
         const uint32_t idx = list[li];
         const uint64_t s = rg.id_lo + idx;
+        const uint64_t pre = o.stage_off[idx];
+        for (uint32_t i = lane; i < kLtChunk; i += kWave) {
+            const uint32_t u = o.stage[pre + i];
+            q[i] = u;
+            atomicOr(&bm[u >> 5], 1u << (u & 31));
+        }
+        __threadfence();
+        __syncthreads();
         if (lane == 0) {
-            uint32_t cur = sample_root(rg.seed, s, g.n);
+            uint32_t cur = o.sizes[idx];
             uint32_t beg = g.off[cur], end = g.off[cur + 1];
-            uint32_t len = 0, steps = 0, reads = 0;
+            uint32_t len = kLtChunk, steps = 0, reads = 0;
             q[len++] = cur;
             atomicOr(&bm[cur >> 5], 1u << (cur & 31));
             for (;;) {
