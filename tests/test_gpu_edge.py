@@ -130,6 +130,28 @@ def test_lt_long_walks(imm, orc, stream, monkeypatch, kind, lanes):
     np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_lt_long_walks_with_staging_growth(imm, orc, stream, monkeypatch, lanes):
+    """Chain walks of up to 3000 vertices with a first staging guess far too
+    small. A walk handed to the long-walk kernel leaves its first 1024
+    members in its chunk, and that kernel continues from there; when it
+    then finds the staging buffer full, the walk is retried after growth,
+    from its root, and handed over again."""
+    monkeypatch.setenv("IMM_LT_LANES", str(lanes))
+    monkeypatch.setenv("IMM_STAGE_SCALE", "0.001")
+    g = _lt_long_graph("chain")
+    say(f"LT long walks with staging growth lanes={lanes}")
+    dg = imm.graph_from(g, stream=stream)
+    pool = imm.imm_sample(dg, 31, 0, 2500, stream=stream)
+    so, sv, cn = pool.export()
+    assert pool.stats["deferred"] > 0
+    oso, osv = orc.sample(g, 31, 0, 2500)
+    cso, csv = canonical(oso, osv, g.n)
+    np.testing.assert_array_equal(so, cso)
+    np.testing.assert_array_equal(sv, csv)
+    np.testing.assert_array_equal(cn, orc.counts(g.n, oso, osv))
+
+
 def test_zero_thresholds(imm, orc, stream):
     base = synth.make_graph("rmat12_wc")
     g = synth.Graph("rmat12_zero", base.n, base.m, base.col_off, base.row_src,
