@@ -70,8 +70,10 @@ struct SampleOut {
     uint32_t* stage;
     uint64_t stage_cap;
     unsigned long long* cursor;
-    uint64_t* stage_off;   // [count]
-    uint32_t* sizes;       // [count]
+    // [count] each: a finished set's staging offset and size; for an LT walk
+    // handed to the long-walk kernel, its chunk's offset and the next vertex
+    uint64_t* stage_off;
+    uint32_t* sizes;
     uint32_t* counts;      // [n]
     uint32_t* defer;       // [count]
     uint32_t* defer_n;
