@@ -40,6 +40,17 @@ def test_binding_fails_loudly_without_library(tmp_path):
     assert r.returncode != 0 and "libimm.so not found" in r.stderr
 
 
+@pytest.mark.parametrize("n", [0, 2, 8])
+def test_bench_refuses_other_gpu_counts(n):
+    """bench.py measures one GPU: any other count exits with status 2 and a
+    message, before anything touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", str(n)], cwd=ROOT,
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "measures one GPU" in r.stderr and r.stdout == ""
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_theta_plan_bit_identical_to_oracle(imm, seed):
     rng = np.random.default_rng(seed)
