@@ -3,16 +3,20 @@
 
 A step is one full IMM run (all sampling rounds with fused counting, pool
 compaction, inverted index, greedy selection, theta schedule; the graph is
-resident in HBM before timing starts) on the Youtube-shaped workload:
-directed Chung-Lu graph (degree exponent 2.1, n = 1,134,890, m = 2,987,624),
-IC model with p = 0.01 as 32-bit thresholds, k = 50, eps = 0.13, ell = 1,
-Philox seed 42. Inputs are synthetic (seeded generator), standing in for the
-paper's com-YouTube graph.
+resident in HBM before timing starts). The default workload is the
+LiveJournal-shaped one: directed Chung-Lu graph (degree exponent 2.0,
+n = 4.8 M, m = 69 M), LT model with per-column uniform in-weights normalised
+to one as 32-bit cumulative tables, k = 50, eps = 0.13, ell = 1, Philox seed
+42 (`--workload youtube_ic` runs the Youtube-shaped IC workload instead).
+Inputs are synthetic (seeded generator), standing in for the paper's SNAP
+graphs.
 
 Prints one JSON line: whole-run RRR sets/s as `value`, time-to-seeds as
-ms_per_step, the roofline figure of the dominant sampling kernel measured
-with HIP events on the stream it runs on, and the CPU oracle timed on a
-bounded sample of the same workload.
+ms_per_step, the roofline figure of the dominant sampling kernel (its
+algorithmic bytes per launch over its mean launch time, measured with HIP
+events on the stream it runs on), a steady-state sampling figure on the same
+graph (outside the timed steps), and the CPU oracle's time to seeds on the
+same workload.
 """
 
 from __future__ import annotations
@@ -37,28 +41,32 @@ PHILOX_OPS = 60
 # HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, scaled by the 1 GiB copy calibration), for the kernel
 # and workload named (an IMM run, or "<workload>:sample<count>" for a
-# steady-state sampling run of that many ids), as recorded in profiles/
-# (ic_large_youtube_ic_pmc.md, lt_small_lj_lt_pmc.md,
-# lt_small_lj_lt_sample_pmc.md); a kernel changed
-# since its counters were taken has no entry.
+# steady-state sampling run of that many ids), as recorded in profiles/; a
+# kernel changed since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
     ("youtube_ic", "ic_large_kernel"): 8.162e9,
-    ("lj_lt", "lt_small_kernel"): 1.151e9,
-    ("lj_lt:sample4194304", "lt_small_kernel"): 78.58e9,
+}
+
+
+WORKLOAD_TEXT = {
+    "lj_lt": "LT, directed Chung-Lu gamma=2.0 (LiveJournal-shaped)",
+    "youtube_ic": "IC p=0.01, directed Chung-Lu gamma=2.1 (Youtube-shaped)",
 }
 
 
 def algorithmic_bytes(model: str, sets: int, entries: int, edges: int, live: int) -> int:
-    """Bytes the sampling method must move (split CSC layout).
+    """Bytes the sampling method must move, per unit of work:
 
-    IC, per set: 4 B size + 8 B staging offset; per member: 8 B in-edge
-    offsets, 4 B staging write, 8 B count read-modify-write; per coin
-    (in-edge examined): 4 B threshold; per live in-edge: 4 B source id.
-    LT, per set: 12 B; per member: 8 B offsets + 4 B staging + 8 B count;
-    per walk step: 4 B guide entry; per (cum, src) pair inspected: 8 B."""
+    IC, per sample: 8 B column offsets and 8 B of (source, threshold) per
+    in-edge examined of every member, 4 B pool write and 8 B count
+    read-modify-write per member, 4 B set size:
+    20 B x members + 8 B x coins + 4 B x sets.
+    LT, per walk step: 8 B column offsets, 4 B per cumulative-table entry
+    probed, 4 B source; per member 12 B (pool write, count):
+    12 B x steps + 4 B x probes + 12 B x members."""
     if model == "ic":
-        return 12 * sets + 20 * entries + 4 * edges + 4 * live
-    return 12 * sets + 20 * entries + 4 * edges + 8 * live
+        return 20 * entries + 8 * edges + 4 * sets
+    return 12 * edges + 4 * live + 12 * entries
 
 
 def kernel_table(model: str, stats: list) -> dict:
@@ -125,25 +133,64 @@ def kernel_summary(kernels: dict) -> dict:
             for k, v in kernels.items()}
 
 
-def cpu_baseline(g, spec, seconds: float):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, spec, reps: int):
+    """The oracle's whole IMM run (same graph, k, eps, ell, seed) timed on the
+    host: the median of `reps` runs on up to 16 threads (OpenMP over sample
+    ids, atomic counts), and one single-thread run. Value: its RRR sets per
+    second of time to seeds."""
+    import statistics
+
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
-    p = oracle.Pool()
+    times, o = [], None
+    for _ in range(max(1, reps)):
+        t0 = time.perf_counter()
+        o = oracle.imm(g, spec["k"], spec["eps"], spec["ell"], spec["seed"], threads=threads)
+        times.append(time.perf_counter() - t0)
+    t_med = statistics.median(times)
     t0 = time.perf_counter()
-    target = 50_000
-    while True:
-        p.extend(g, spec["seed"], target, threads)
-        el = time.perf_counter() - t0
-        if el >= seconds or target >= 1 << 26:
-            break
-        rate = target / max(el, 1e-3)
-        target = int(min(target * 8, target + rate * (seconds - el) * 1.1 + 1))
-    el = time.perf_counter() - t0
-    return {"value": p.n_sets / el, "unit": "RRR sets/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle Generate_RRRsets (counts included) over sample ids "
-                      f"[0, {p.n_sets}) of the same run (seed {spec['seed']}), "
-                      f"{el:.1f} s wall on {threads} threads; sampling phase only"}
+    o1 = oracle.imm(g, spec["k"], spec["eps"], spec["ell"], spec["seed"], threads=1)
+    t_one = time.perf_counter() - t0
+    assert list(o1["seeds"]) == list(o["seeds"]) and o1["theta"] == o["theta"]
+    return {"value": o["theta"] / t_med, "unit": "RRR sets/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole oracle IMM run (theta {o['theta']}, {o['rounds']} rounds, "
+                      f"k={spec['k']}, eps={spec['eps']}, seed {spec['seed']}): median of "
+                      f"{len(times)} runs on {threads} threads, time to seeds "
+                      f"{t_med * 1e3:.0f} ms; one run on 1 thread {t_one * 1e3:.0f} ms",
+            "time_to_seeds_ms": t_med * 1e3, "time_to_seeds_ms_1thread": t_one * 1e3,
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def steady_state(imm, g, dg, spec, count, reps, stream, workload):
+    """Steady-state Generate_RRRsets: `reps` imm_sample calls of `count` ids
+    (kernel times from HIP events); sets/s, walk steps or coins per second,
+    and the roofline entry of the dominant sampling kernel."""
+    pools = []
+    for _ in range(reps):
+        p = imm.imm_sample(dg, spec["seed"], 0, count, flags=imm.IMM_TIMING, stream=stream)
+        pools.append(p.stats)
+        p.close()
+    st = pools[-1]
+    samp_ms = sum(x["ms_sample"] for x in pools) / len(pools)
+    nbytes = algorithmic_bytes(g.model, st["sets"], st["entries"], st["edges"], st["live"])
+    kernels = kernel_table(g.model, pools)
+    return {"ids": count, "calls": reps, "sets_per_s": st["sets"] / (samp_ms * 1e-3),
+            "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
+            "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
+            "edges": st["edges"], "probes": st["live"], "deferred": st["deferred"],
+            "kernels": kernel_summary(kernels),
+            "roofline": roofline_of(kernels, f"{workload}:sample{count}")}
 
 
 def sample_mode(args, imm, g, dg, spec, stream, torch):
@@ -154,29 +201,17 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
                        stream=stream).close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pools = []
-    for _ in range(args.steps):
-        p = imm.imm_sample(dg, spec["seed"], 0, args.sample_count, flags=imm.IMM_TIMING,
-                           stream=stream)
-        pools.append(p.stats)
-        p.close()
+    ss = steady_state(imm, g, dg, spec, args.sample_count, args.steps, stream, args.workload)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    st = pools[-1]
-    samp_ms = sum(x["ms_sample"] for x in pools) / len(pools)
-    nbytes = algorithmic_bytes(g.model, st["sets"], st["entries"], st["edges"], st["live"])
-    kernels = kernel_table(g.model, pools)
     print(json.dumps({
-        "metric": "RRR sets/s (steady-state sampling)", "value": st["sets"] / (samp_ms * 1e-3),
+        "metric": "RRR sets/s (steady-state sampling)", "value": ss["sets_per_s"],
         "unit": "RRR sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: imm_sample of {args.sample_count} ids",
                    "seed": spec["seed"]},
-        "sampling_ms": samp_ms, "sampling_GBps": nbytes / (samp_ms * 1e-3) / 1e9,
-        "edges_per_s": st["edges"] / (samp_ms * 1e-3), "entries": st["entries"],
-        "deferred": st["deferred"], "ic_team": st["team"], "ic_big_block": st["big_block"], "kernels": kernel_summary(kernels),
-        "roofline": roofline_of(kernels, f"{args.workload}:sample{args.sample_count}"),
+        **{k: v for k, v in ss.items() if k not in ("sets_per_s",)},
     }))
 
 
@@ -372,8 +407,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="youtube_ic")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", default="lj_lt")
+    ap.add_argument("--cpu-reps", type=int, default=3,
+                    help="oracle runs on the host cores (median); plus one single-thread run")
+    ap.add_argument("--steady-ids", type=int, default=1 << 24,
+                    help="ids of the steady-state sampling call reported beside the timed "
+                         "steps (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-count", type=int, default=0,
                     help="steady-state sampling mode: each step generates this many "
@@ -472,9 +511,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: IMM, " + (
-                "IC p=0.01, directed Chung-Lu gamma=2.1" if args.workload == "youtube_ic"
-                else g.model.upper()) + f", n={g.n}, m={g.m}",
+            "workload": f"{args.workload}: IMM, " + WORKLOAD_TEXT.get(
+                args.workload, g.model.upper()) + f", n={g.n}, m={g.m}",
             "k": spec["k"], "epsilon": spec["eps"], "ell": spec["ell"], "seed": spec["seed"],
             "diffusion": g.model.upper(), "parallelism": "single GPU",
         },
@@ -489,11 +527,17 @@ def main():
                      "host_wall": r.stats["ms_total"]},
         "sampling_GBps": samp_bytes / (ms_sample * 1e-3) / 1e9 if ms_sample > 0 else None,
         "sampling_sets_per_s": sets / (ms_sample * 1e-3) if ms_sample > 0 else None,
+        "walk_lanes": r.stats["walk_lanes"],
+        "bloom_bits": r.stats["bloom_bits"],
         "kernels": kernel_summary(kernels),
         "roofline": roofline_of(kernels, args.workload),
     }
+    if args.steady_ids:
+        out["steady_state"] = steady_state(imm, g, dg, spec, args.steady_ids, 2, stream,
+                                           args.workload)
+        print("[bench] steady-state sampling done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, spec, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(g, spec, args.cpu_reps)
         print("[bench] cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
