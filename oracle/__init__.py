@@ -53,6 +53,8 @@ def lib():
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
         u64p = np.ctypeslib.ndpointer(np.uint64, flags="C")
         L.oracle_philox4x32_10.argtypes = [u32p, C.c_uint64, u32p]
+        L.oracle_philox_many.argtypes = [u32p, C.c_uint64, C.c_uint64, u32p]
+        L.oracle_philox_many.restype = None
         L.oracle_root.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32]
         L.oracle_root.restype = C.c_uint32
         L.oracle_ic_draw.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
@@ -112,6 +114,14 @@ def philox4x32_10(ctr, key: int) -> np.ndarray:
     c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(4)
     out = np.zeros(4, dtype=np.uint32)
     lib().oracle_philox4x32_10(c, int(key), out)
+    return out
+
+
+def philox_many(ctr, key: int) -> np.ndarray:
+    """Philox4x32-10 of every row of ctr (uint32[count, 4]) under one key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    lib().oracle_philox_many(c, c.shape[0], int(key), out)
     return out
 
 

@@ -79,6 +79,13 @@ void oracle_philox4x32_10(const uint32_t ctr[4], uint64_t key, uint32_t out[4]) 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* The same generator over `count` counters (ctr and out hold 4 words per
+ * counter), one call per counter: a convenience for tests that compare
+ * millions of outputs. */
+void oracle_philox_many(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out) {
+    for (uint64_t i = 0; i < count; ++i) oracle_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 /* Reading R2: the uniformly selected root of sample s (Section II-B). */
 uint32_t oracle_root(uint64_t seed, uint64_t s, uint32_t n) {
     uint32_t c[4] = {0u, (uint32_t)s, (uint32_t)(s >> 32), 0u}, o[4];

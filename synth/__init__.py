@@ -16,6 +16,7 @@ from .graphs import (  # noqa: F401
     ic_wc_thresholds,
     lt_cumulative,
     make_graph,
+    make_graphs,
     rmat_edges,
     to_csc,
     tiny_graph,

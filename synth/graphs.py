@@ -331,6 +331,28 @@ def make_graph(name: str, gen=None, model=None, enc=None, gseed: int = 1,
     return g
 
 
+def _make_cached(kw: dict) -> str:
+    make_graph(**kw)
+    return kw["name"]
+
+
+def make_graphs(specs, workers: int = 8) -> None:
+    """Build the graphs of ``specs`` (keyword dicts of make_graph) into the
+    on-disk cache, in fresh worker processes (spawned, so a caller that has
+    already initialised a GPU runtime forks nothing); make_graph then loads
+    each one from the cache."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    todo = [dict(kw, cache=True) for kw in specs]
+    if not todo:
+        return
+    with ProcessPoolExecutor(max_workers=max(1, min(workers, len(todo))),
+                             mp_context=mp.get_context("spawn")) as ex:
+        for _ in ex.map(_make_cached, todo):
+            pass
+
+
 def tiny_graph(n: int, edges, model: str, params) -> Graph:
     """Explicit small graph. ``edges`` is a list of (u, v); ``params`` gives,
     per edge in the same order, the IC probability numerator thr (int) or, for

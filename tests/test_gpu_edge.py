@@ -296,8 +296,8 @@ def test_giant_set_hub_column_spans_two_pages(imm, orc, stream, monkeypatch, big
     assert int(np.diff(so).max()) > 1024  # went through the giant-set pass
 
 
-@pytest.mark.parametrize("eps,first_gain", [(0.1, 10455), (0.07, 20515)])
-def test_recount_with_long_index_lists(imm, orc, stream, eps, first_gain):
+@pytest.mark.parametrize("eps,min_first_gain", [(0.1, 2 * 4096), (0.07, 4 * 4096)])
+def test_recount_with_long_index_lists(imm, orc, stream, eps, min_first_gain):
     """Two hubs, each in most sets of its own parity class and in some of the
     other's: the first seed covers more than a quarter of the pool, so the
     next counts are rebuilt by a recount in which the other hub (10,000 or
@@ -321,4 +321,6 @@ def test_recount_with_long_index_lists(imm, orc, stream, eps, first_gain):
     g = synth.tiny_graph(n, edges, "ic", thr)
     say(f"two-hub recount eps={eps}")
     r = _parity(imm, orc, g, 5, eps, 17, stream, pool=False)
-    assert r.theta > 2 * 4096 and r.gains[1] > 0 and r.gains[0] == first_gain
+    # the run equals the oracle's (checked in _parity); the first seed's
+    # index list is longer than two (four) long-list thresholds of 4096
+    assert r.theta > 2 * 4096 and r.gains[1] > 0 and r.gains[0] > min_first_gain

@@ -3,19 +3,13 @@
 * LiveJournal-shaped LT (n = 4.8M, m = 69M, k = 50, eps = 0.13): the whole
   IMM run, bit-exact (theta trajectory, LB, seeds, gains, canonical pool).
 * Youtube-shaped IC (n = 1,134,890, m = 2,987,624, p = 0.01, k = 50,
-  eps = 0.13), the benchmark's configuration: the oracle cannot redo the
-  21M-set run inside a test, so the run is checked on sampled outputs the
-  oracle computes one by one (2000 random sets of the returned pool), and
-  the selection is checked by running the oracle's greedy (Algorithm 2) on
-  the returned pool; the theta schedule is checked against the host-side
-  theta plan.
+  eps = 0.13): the whole 21.6 M-set run, bit-exact, and the fused counts of
+  a sampling call over the same ids.
 * One-tenth-size versions of both, bit-exact on the whole run.
 * The LiveJournal-shaped steady-state sampling call (2^22 ids) in the
   benchmark's launch configuration: sampled sets one by one, and the fused
   counts against the whole returned pool.
 """
-
-import math
 
 import numpy as np
 import pytest
@@ -67,34 +61,42 @@ def test_youtube_small_bit_exact(imm, orc, stream):
     _full_parity(imm, orc, "youtube_ic_s", stream, pool=False)
 
 
-@pytest.mark.timeout(600)
-def test_youtube_full_size_sampled(imm, orc, stream):
+@pytest.mark.timeout(900)
+def test_youtube_full_size_bit_exact(imm, orc, stream):
+    """The benchmark's Youtube-shaped IC configuration at full size (theta
+    about 21.6 M sets, 9 rounds): the whole run against the oracle's, bit for
+    bit (targets, per-round coverage, LB, theta, seeds, gains, the canonical
+    pool), and the fused counts of a sampling call over the same theta ids
+    against the occurrences in the oracle's pool."""
+    name = "youtube_ic"
+    spec = synth.WORKLOADS[name]
+    g = synth.make_graph(name)
     say("full-size Youtube-shaped IC run (benchmark configuration)")
-    g, spec, r = _run(imm, "youtube_ic", stream, imm.IMM_KEEP_POOL)
+    dg = imm.graph_from(g, stream=stream)
+    r = imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                    flags=imm.IMM_KEEP_POOL, stream=stream)
+    say(f"oracle IMM run, {oracle_threads()} threads")
+    o = orc.imm(g, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                threads=oracle_threads(), keep_pool=True)
+    lp, ls, im = orc.theta_plan(g.n, spec["k"], spec["eps"], spec["ell"])
+    assert (o["lambda_prime"], o["lambda_star"], o["i_max"]) == (lp, ls, im)
+    assert r.targets == o["targets"]
+    assert r.round_cov == o["round_cov"]
+    assert (r.theta, r.rounds, r.covered, r.lb) == (o["theta"], o["rounds"], o["covered"], o["lb"])
+    np.testing.assert_array_equal(r.seeds, o["seeds"])
+    np.testing.assert_array_equal(r.gains, o["gains"])
+    say(f"canonical pools, {o['set_vtx'].size} entries")
     so, sv = r.pool()
-    assert so.size - 1 == r.theta
-    # sampled sets, recomputed one by one by the oracle
-    rng = np.random.default_rng(2024)
-    ids = np.concatenate([[0, 1, r.theta - 1], rng.integers(0, r.theta, 2000)])
-    for s in ids:
-        want = np.sort(orc.rrr_set(g, spec["seed"], int(s)))
-        np.testing.assert_array_equal(sv[so[s]:so[s + 1]], want, err_msg=f"set {s}")
-    # the theta schedule (Algorithm 1 with the host-side constants)
-    lp, ls, _ = imm.imm_theta_plan(g.n, spec["k"], spec["eps"], spec["ell"])
-    for i, t in enumerate(r.targets[:-1], start=1):
-        assert t == math.ceil(lp / math.ldexp(g.n, -i))
-    epsp = math.sqrt(2.0) * spec["eps"]
-    x = math.ldexp(g.n, -r.rounds)
-    frac = r.round_cov[-1] / r.targets[r.rounds - 1]
-    if g.n * frac >= (1.0 + epsp) * x:
-        assert r.lb == g.n * frac / (1.0 + epsp)
-    assert r.targets[-1] == math.ceil(ls / r.lb) and r.theta == max(r.targets)
-    # selection: the oracle's greedy over the returned pool
-    say(f"oracle greedy over {so.size - 1} sets / {sv.size} entries")
-    os_, og, ocov = orc.greedy(g.n, so, sv, spec["k"])
-    np.testing.assert_array_equal(r.seeds, os_)
-    np.testing.assert_array_equal(r.gains, og)
-    assert r.covered == ocov
+    r.close()
+    cso, csv = canonical(o["set_off"], o["set_vtx"], g.n)
+    np.testing.assert_array_equal(so, cso)
+    np.testing.assert_array_equal(sv, csv)
+    del so, sv, cso, csv
+    say(f"fused counts of imm_sample over ids [0, {o['theta']})")
+    pool = imm.imm_sample(dg, spec["seed"], 0, o["theta"], stream=stream)
+    _, _, cn = pool.export()
+    pool.close()
+    np.testing.assert_array_equal(cn, orc.counts(g.n, o["set_off"], o["set_vtx"]))
 
 
 @pytest.mark.timeout(300)

@@ -75,10 +75,15 @@ def test_server_mixed_stream_equals_alone(imm, orc, stream, graphs, graph):
 def test_server_one_slot_queues_in_order(imm, orc, stream, graphs):
     hg, dg = graphs
     srv = imm.Server(budget_bytes=64 << 30, max_slots=1)
+    # a query with giant sets and a small eps first (hundreds of thousands of
+    # sets): the five after it stay queued while it runs
+    head = srv.submit(dg["rmat12_p10"], k=10, epsilon=0.1, seed=3)
     tickets = [srv.submit(dg["rmat12_wc"], k=10, epsilon=0.5, seed=s) for s in range(5)]
-    assert srv.poll(tickets[-1], wait=False) is None or True
+    assert srv.poll(tickets[-1], wait=False) is None
+    rh = srv.poll(head)
     res = [srv.poll(t) for t in tickets]
     srv.close()
+    _same(rh, orc.imm(hg["rmat12_p10"], 10, 0.1, 1.0, 3, threads=oracle_threads()))
     for s, r in zip(range(5), res):
         _same(r, orc.imm(hg["rmat12_wc"], 10, 0.5, 1.0, s, threads=oracle_threads()))
     # with one slot, later submissions waited for the earlier ones
