@@ -278,6 +278,27 @@ imm_status imm_greedy(uint32_t n, const uint64_t* set_off, const uint32_t* set_v
                       uint64_t n_sets, uint32_t k, uint32_t flags, void* stream,
                       uint32_t* seeds, uint64_t* gains, uint64_t* covered);
 
+/* imm_greedy_static: imm_greedy that allocates nothing, for callers that
+ * cannot allocate device memory (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same arguments, same results,
+ * bit for bit, as imm_greedy; gains must not be NULL. Every scratch buffer
+ * (counts, index, covered bits, seed-step state, and the pool itself when
+ * it is passed in host memory) is carved out of one fixed array of
+ * IMM_STATIC_SCRATCH_BYTES per device, held from library load until the
+ * process ends. With n vertices, S sets, P entries and k seeds it needs about
+ *   24 n + 4 P + 16 (S + P / 64) + S / 8 + 272 k bytes (device pool), plus
+ *   8 S + 4 P bytes more when the pool is in host memory,
+ * each piece rounded up to 256 bytes; a call that does not fit fails with
+ * IMM_ENOMEM and a message giving the size it needed. The call blocks until
+ * its results are on the host. Calls on one device share its array (each call
+ * clears what must start at zero); calls in one process are serialised per
+ * device, and any other use of the array would race with them. Errors: as
+ * imm_greedy, and IMM_EINVAL for a null gains. */
+#define IMM_STATIC_SCRATCH_BYTES (128ull << 20)
+imm_status imm_greedy_static(uint32_t n, const uint64_t* set_off, const uint32_t* set_vtx,
+                             uint64_t n_sets, uint32_t k, uint32_t flags, void* stream,
+                             uint32_t* seeds, uint64_t* gains, uint64_t* covered);
+
 /* imm_philox4x32_10: evaluate the device Philox4x32-10 (Salmon et al.,
  * SC'11) on `count` counters: ctr uint32[4*count] in, out uint32[4*count]
  * out, key = (key_lo, key_hi). Host pointers unless IMM_DEVICE_PTRS. */

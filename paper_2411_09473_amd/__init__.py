@@ -89,6 +89,7 @@ _sig = {
     "imm_pool_info": [_vp, _P(_u64), _P(_u64), _P(imm_stats)],
     "imm_pool_export": [_vp, _vp, _vp, _vp],
     "imm_greedy": [_u32, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _P(_u64)],
+    "imm_greedy_static": [_u32, _vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _P(_u64)],
     "imm_philox4x32_10": [_vp, _u64, _u64, _u32, _vp, _vp],
     "imm_server_create": [_u64, _u32, _P(_vp)],
     "imm_server_submit": [_vp, _vp, _P(imm_params), _P(_u64)],
@@ -356,6 +357,16 @@ def imm_sample(g: Graph, seed, first_id, count, flags=0, stream=None) -> Pool:
 
 def imm_greedy(n, set_off, set_vtx, k, flags=0, stream=None):
     """Greedy over a caller pool; returns (seeds uint32[k], gains uint64[k], covered)."""
+    return _greedy(_lib.imm_greedy, n, set_off, set_vtx, k, flags, stream)
+
+
+def imm_greedy_static(n, set_off, set_vtx, k, flags=0, stream=None):
+    """imm_greedy without any allocation (scratch in the library's fixed
+    per-device array); same arguments and results."""
+    return _greedy(_lib.imm_greedy_static, n, set_off, set_vtx, k, flags, stream)
+
+
+def _greedy(fn, n, set_off, set_vtx, k, flags, stream):
     p0, k0, d0 = _ptr(set_off, np.uint64)
     n_sets = (len(set_off) - 1)
     if set_vtx is None or len(set_vtx) == 0:
@@ -368,8 +379,8 @@ def imm_greedy(n, set_off, set_vtx, k, flags=0, stream=None):
     seeds = np.zeros(k, dtype=np.uint32)
     gains = np.zeros(k, dtype=np.uint64)
     cov = _u64()
-    _check(_lib.imm_greedy(n, p0, p1, n_sets, k, flags, _stream(stream), seeds.ctypes.data,
-                           gains.ctypes.data, C.byref(cov)))
+    _check(fn(n, p0, p1, n_sets, k, flags, _stream(stream), seeds.ctypes.data,
+              gains.ctypes.data, C.byref(cov)))
     return seeds, gains, cov.value
 
 

@@ -20,7 +20,7 @@ LIB = PKG / "libimm.so"
 ARCH = os.environ.get("IMM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_sample_ic.hip", "k_sample_lt.hip", "k_pool.hip", "k_select.hip",
-           "workspace.cpp", "runner.cpp", "tune.cpp", "server.cpp", "api.cpp"]
+           "greedy_static.hip", "workspace.cpp", "runner.cpp", "tune.cpp", "server.cpp", "api.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

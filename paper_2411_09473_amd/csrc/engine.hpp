@@ -21,6 +21,7 @@ namespace imm {
 // ---------------------------------------------------------------- errors --
 
 imm_status fail(imm_status st, const std::string& msg);
+imm_status fail(imm_status st, const char* msg);  // copies msg; allocates nothing
 const char* last_error();  // this thread's last message
 double now_ms();
 

@@ -12,15 +12,19 @@
 namespace imm {
 
 namespace {
-thread_local std::string g_err;
+// a fixed buffer, so that reporting an error allocates nothing
+thread_local char g_err[512];
 }
 
-imm_status fail(imm_status st, const std::string& msg) {
-    g_err = msg;
+imm_status fail(imm_status st, const char* msg) {
+    std::strncpy(g_err, msg ? msg : "", sizeof(g_err) - 1);
+    g_err[sizeof(g_err) - 1] = '\0';
     return st;
 }
 
-const char* last_error() { return g_err.c_str(); }
+imm_status fail(imm_status st, const std::string& msg) { return fail(st, msg.c_str()); }
+
+const char* last_error() { return g_err; }
 
 double now_ms() {
     using namespace std::chrono;
