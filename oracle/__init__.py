@@ -39,7 +39,14 @@ class ImmInfo(C.Structure):
                 ("lb", C.c_double), ("covered", C.c_uint64),
                 ("lambda_prime", C.c_double), ("lambda_star", C.c_double),
                 ("i_max", C.c_uint32), ("pad", C.c_uint32),
-                ("targets", C.c_uint64 * 64), ("round_cov", C.c_uint64 * 64)]
+                ("targets", C.c_uint64 * 64), ("round_cov", C.c_uint64 * 64),
+                ("sigma_up", C.c_double), ("alpha", C.c_double),
+                ("round_cov2", C.c_uint64 * 64)]
+
+
+#: sampling schedules of imm(): IMM as in Algorithm 1 (the rounds' sets are
+#: reused by the final selection), IMM with a fresh final pool, early stopping
+SCHED_IMM, SCHED_FRESH, SCHED_EARLY = 0, 1, 2
 
 
 _lib = None
@@ -90,6 +97,16 @@ def lib():
                                  C.c_double, C.c_double, C.c_uint64, C.c_int, C.c_void_p,
                                  u32p, u64p, C.POINTER(ImmInfo)]
         L.oracle_imm.restype = C.c_int
+        L.oracle_imm_ex.argtypes = [C.c_uint32, u64p, u32p, u32p, C.c_int, C.c_uint32,
+                                    C.c_double, C.c_double, C.c_uint64, C.c_int, C.c_int,
+                                    C.c_void_p, u32p, u64p, C.POINTER(ImmInfo)]
+        L.oracle_imm_ex.restype = C.c_int
+        L.oracle_coverage.argtypes = [C.c_uint32, u64p, u32p, C.c_uint64, u32p, C.c_uint32]
+        L.oracle_coverage.restype = C.c_uint64
+        L.oracle_early_plan.argtypes = [C.c_uint32, C.c_uint32, C.c_double, C.c_double,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_double)]
+        L.oracle_early_plan.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -238,26 +255,51 @@ def theta_plan(n: int, k: int, eps: float, ell: float):
 
 
 def imm(g, k: int, eps: float, ell: float, seed: int, threads: int = 1,
-        keep_pool: bool = False):
+        keep_pool: bool = False, schedule: int = SCHED_IMM):
     """Full IMM run. Returns a dict with seeds, gains, theta, rounds, lb,
-    covered, targets, round_cov and (optionally) the pool arrays."""
+    covered, targets, round_cov and (optionally) the pool arrays of the final
+    selection; with SCHED_EARLY also sigma_up, alpha and round_cov2."""
     co, rs, w = _arrays(g)
     pool = Pool() if keep_pool else None
     seeds = np.zeros(k, dtype=np.uint32)
     gains = np.zeros(k, dtype=np.uint64)
     info = ImmInfo()
-    _check(lib().oracle_imm(g.n, co, rs, w, _model(g), k, eps, ell, seed, threads,
-                            pool._p if pool else None, seeds, gains, C.byref(info)))
+    _check(lib().oracle_imm_ex(g.n, co, rs, w, _model(g), k, eps, ell, seed, threads, schedule,
+                               pool._p if pool else None, seeds, gains, C.byref(info)))
     out = dict(seeds=seeds, gains=gains, theta=int(info.theta), rounds=int(info.rounds),
                lb=float(info.lb), covered=int(info.covered),
                lambda_prime=info.lambda_prime, lambda_star=info.lambda_star,
                i_max=int(info.i_max),
                targets=[int(info.targets[i]) for i in range(info.n_targets)],
                round_cov=[int(info.round_cov[i]) for i in range(info.rounds)])
+    if schedule == SCHED_EARLY:
+        out["sigma_up"] = info.sigma_up
+        out["alpha"] = info.alpha
+        out["round_cov2"] = [int(info.round_cov2[i]) for i in range(info.rounds)]
     if pool is not None:
         out["set_off"], out["set_vtx"] = pool.arrays()
         out["work"] = pool.work
     return out
+
+
+def coverage(n: int, set_off, set_vtx, seeds) -> int:
+    """Number of sets with at least one member among seeds."""
+    so = np.ascontiguousarray(set_off, dtype=np.uint64)
+    sv = np.ascontiguousarray(set_vtx, dtype=np.uint32)
+    if sv.size == 0:
+        sv = np.zeros(1, dtype=np.uint32)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    c = lib().oracle_coverage(n, so, sv, so.size - 1, sd, sd.size)
+    if c == (1 << 64) - 1:
+        raise MemoryError
+    return int(c)
+
+
+def early_plan(n: int, k: int, eps: float, ell: float):
+    """The early-stopping schedule's (theta_0, i_max, a)."""
+    t0, im, a = C.c_double(), C.c_uint32(), C.c_double()
+    _check(lib().oracle_early_plan(n, k, eps, ell, C.byref(t0), C.byref(im), C.byref(a)))
+    return t0.value, im.value, a.value
 
 
 def max_threads() -> int:

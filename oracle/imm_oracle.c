@@ -212,6 +212,7 @@ typedef struct {
     uint64_t n_sets, n_entries, cap_sets, cap_entries, work;
     uint64_t* set_off; /* n_sets+1 */
     uint32_t* set_vtx; /* n_entries */
+    uint64_t id_base;  /* set j of the pool is the RRR set of sample id id_base + j */
 } oracle_pool;
 
 oracle_pool* oracle_pool_create(void) {
@@ -264,7 +265,8 @@ static int pool_reserve(oracle_pool* p, uint64_t sets, uint64_t entries) {
     return ORC_OK;
 }
 
-/* Append sample ids [p->n_sets, target) to the pool. With threads > 1 the id
+/* Append the sets j in [p->n_sets, target), i.e. sample ids id_base + j, to
+ * the pool. With threads > 1 the id
  * range is cut into contiguous chunks sampled concurrently (one set at a time
  * per thread, as above) and appended in id order, so the pool is identical
  * for every thread count. */
@@ -297,7 +299,7 @@ int oracle_pool_extend(oracle_pool* p, uint32_t n, const uint64_t* col_off,
             c->err = ORC_ENOMEM;
         } else {
             for (uint64_t s = lo; s < hi && !c->err; ++s) {
-                uint32_t sz = rrr_one(&g, seed, s, members, mark, &c->work);
+                uint32_t sz = rrr_one(&g, seed, p->id_base + s, members, mark, &c->work);
                 if (c->len + sz > c->cap) {
                     uint64_t nc = c->cap;
                     while (nc < c->len + sz) nc *= 2;
@@ -435,27 +437,144 @@ typedef struct {
     uint64_t theta;       /* |R| used by the final selection */
     uint32_t rounds;      /* sampling-phase iterations executed */
     uint32_t n_targets;   /* entries used in targets[] */
-    double lb;            /* lower bound LB on OPT */
+    double lb;            /* lower bound LB on OPT (early stop: on the spread of the seeds) */
     uint64_t covered;     /* sets covered by the returned seeds */
     double lambda_prime, lambda_star;
     uint32_t i_max;
     uint32_t pad;
     uint64_t targets[64]; /* theta_1, theta_2, ... then the final theta */
     uint64_t round_cov[64];
+    /* early stop only: the upper bound on OPT and the ratio of the last
+     * iteration, and each iteration's coverage of its seeds in the second pool */
+    double sigma_up, alpha;
+    uint64_t round_cov2[64];
 } oracle_imm_info;
+
+/* Sampling schedules. */
+enum { ORC_SCHED_IMM = 0, ORC_SCHED_FRESH = 1, ORC_SCHED_EARLY = 2 };
+
+/* Number of sets with at least one member in seeds[0..k). */
+uint64_t oracle_coverage(uint32_t n, const uint64_t* set_off, const uint32_t* set_vtx,
+                         uint64_t n_sets, const uint32_t* seeds, uint32_t k) {
+    uint8_t* is_seed = (uint8_t*)calloc(n, 1);
+    if (!is_seed) return UINT64_MAX;
+    for (uint32_t i = 0; i < k; ++i) is_seed[seeds[i]] = 1;
+    uint64_t c = 0;
+    for (uint64_t j = 0; j < n_sets; ++j) {
+        for (uint64_t t = set_off[j]; t < set_off[j + 1]; ++t) {
+            if (is_seed[set_vtx[t]]) { ++c; break; }
+        }
+    }
+    free(is_seed);
+    return c;
+}
+
+/* The early-stopping schedule in the manner of OPIM (Tang, Tang, Xiao, Yuan,
+ * SIGMOD 2018, cited by the paper's related work for terminating sampling
+ * once the coverage suffices). Two independent pools R1 (sample ids j) and
+ * R2 (sample ids 2^32 + j) of theta_i = ceil(theta_0 2^(i-1)) sets each; the
+ * greedy seeds S of R1 are kept as soon as a lower bound on their spread,
+ * from their coverage in R2, is at least (1 - 1/e - eps) times an upper bound
+ * on OPT from the greedy's coverage in R1, or at the last iteration, whose
+ * pools reach theta_max (IMM's bound with OPT >= k). Failure probability
+ * delta = n^-ell; both bounds are Chernoff bounds on a binomial count holding
+ * with probability 1 - delta / (3 i_max) each:
+ *   up = (sqrt(cov1 / g_k + a/2) + sqrt(a/2))^2 n / theta_i,
+ *        g_k = 1 - (1 - 1/k)^k (the greedy's coverage guarantee)
+ *   lo = ((sqrt(cov2 + 2a/9) - sqrt(a/2))^2 - a/18) n / theta_i (0 if that
+ *        is not positive), a = ln(3 i_max / delta).
+ * All FP64, in this order. */
+static int early_plan(uint32_t n, uint32_t k, double eps, double ell, double* theta0,
+                      uint32_t* i_max, double* a) {
+    if (n < 2 || k == 0 || k > n || !(eps > 0.0) || !(ell > 0.0)) return ORC_EINVAL;
+    double ln_n = log((double)n);
+    double logcnk = log_binom(n, k);
+    double one_m = 1.0 - ORC_INV_E;
+    double ln6d = log(6.0) + ell * ln_n;
+    double u = one_m * sqrt(ln6d) + sqrt(one_m * (logcnk + ln6d));
+    double theta_max = 2.0 * (double)n * u * u / (eps * eps * (double)k);
+    double t0 = theta_max * eps * eps * (double)k / (double)n;
+    double r = ceil(log2((double)n / (eps * eps * (double)k)));  /* log2(theta_max / theta_0) */
+    uint32_t im = r < 1.0 ? 1u : (uint32_t)r;
+    *theta0 = t0;
+    *i_max = im;
+    *a = log(3.0 * (double)im) + ell * ln_n;
+    return ORC_OK;
+}
+
+static int oracle_early(uint32_t n, const uint64_t* col_off, const uint32_t* row_src,
+                        const uint32_t* weight, int model, uint32_t k, double eps, double ell,
+                        uint64_t seed, int threads, oracle_pool* keep, uint32_t* seeds,
+                        uint64_t* gains, oracle_imm_info* info) {
+    double t0, a;
+    uint32_t i_max;
+    int rc = early_plan(n, k, eps, ell, &t0, &i_max, &a);
+    if (rc) return rc;
+    oracle_pool* r1 = keep ? keep : oracle_pool_create();
+    oracle_pool* r2 = oracle_pool_create();
+    if (!r1 || !r2) { rc = ORC_ENOMEM; goto done; }
+    r2->id_base = (uint64_t)1 << 32;
+    memset(info, 0, sizeof(*info));
+    info->i_max = i_max;
+    double one_m = 1.0 - ORC_INV_E;
+    double g_k = 1.0 - pow(1.0 - 1.0 / (double)k, (double)k);
+    for (uint32_t i = 1; i <= i_max; ++i) {
+        double tf = ceil(ldexp(t0, (int)i - 1));
+        if (!(tf < 4294967296.0)) { rc = ORC_EOVERFLOW; goto done; }
+        uint64_t target = (uint64_t)tf;
+        if (info->n_targets < 64) info->targets[info->n_targets++] = target;
+        rc = oracle_pool_extend(r1, n, col_off, row_src, weight, model, seed, target, threads);
+        if (!rc) rc = oracle_pool_extend(r2, n, col_off, row_src, weight, model, seed, target,
+                                         threads);
+        if (rc) goto done;
+        uint64_t cov1 = oracle_greedy(n, r1->set_off, r1->set_vtx, r1->n_sets, k, seeds, gains);
+        if (cov1 == UINT64_MAX) { rc = ORC_ENOMEM; goto done; }
+        uint64_t cov2 = oracle_coverage(n, r2->set_off, r2->set_vtx, r2->n_sets, seeds, k);
+        if (cov2 == UINT64_MAX) { rc = ORC_ENOMEM; goto done; }
+        info->round_cov[info->rounds] = cov1;
+        info->round_cov2[info->rounds] = cov2;
+        info->rounds = i;
+        double scale = (double)n / (double)target;
+        double su = sqrt((double)cov1 / g_k + a / 2.0) + sqrt(a / 2.0);
+        double up = su * su * scale;
+        double sl = sqrt((double)cov2 + 2.0 * a / 9.0) - sqrt(a / 2.0);
+        double lo = sl > 0.0 ? (sl * sl - a / 18.0) * scale : 0.0;
+        if (lo < 0.0) lo = 0.0;
+        info->theta = target;
+        info->lb = lo;
+        info->sigma_up = up;
+        info->alpha = lo / up;
+        info->covered = cov1;
+        if (lo / up >= one_m - eps) break;
+    }
+done:
+    if (!keep) oracle_pool_destroy(r1);
+    oracle_pool_destroy(r2);
+    return rc;
+}
 
 /* IMM (Algorithm 1): sampling-phase rounds i = 1..i_max with the early break
  * of Tang et al.'s Algorithm 3, then theta = ceil(lambda_star / LB), top-up, and
- * the final selection over every generated set (reading R6). */
-int oracle_imm(uint32_t n, const uint64_t* col_off, const uint32_t* row_src,
-               const uint32_t* weight, int model, uint32_t k, double eps, double ell,
-               uint64_t seed, int threads, oracle_pool* keep, uint32_t* seeds, uint64_t* gains,
-               oracle_imm_info* info) {
+ * the final selection over every generated set (reading R6). schedule
+ * ORC_SCHED_FRESH instead draws the final selection's theta sets afresh, the
+ * sample ids after those of the rounds (the correction of IMM's reuse of the
+ * rounds' sets pointed out by Chen, 2018); ORC_SCHED_EARLY runs the early
+ * stopping schedule above. keep (may be NULL) receives the pool of the final
+ * selection. */
+int oracle_imm_ex(uint32_t n, const uint64_t* col_off, const uint32_t* row_src,
+                  const uint32_t* weight, int model, uint32_t k, double eps, double ell,
+                  uint64_t seed, int threads, int schedule, oracle_pool* keep, uint32_t* seeds,
+                  uint64_t* gains, oracle_imm_info* info) {
+    if (schedule == ORC_SCHED_EARLY)
+        return oracle_early(n, col_off, row_src, weight, model, k, eps, ell, seed, threads, keep,
+                            seeds, gains, info);
+    if (schedule != ORC_SCHED_IMM && schedule != ORC_SCHED_FRESH) return ORC_EINVAL;
     double lam_p, lam_s;
     uint32_t i_max;
     int rc = oracle_theta_plan(n, k, eps, ell, &lam_p, &lam_s, &i_max);
     if (rc) return rc;
-    oracle_pool* pool = keep ? keep : oracle_pool_create();
+    const int fresh = schedule == ORC_SCHED_FRESH;
+    oracle_pool* pool = keep && !fresh ? keep : oracle_pool_create();
     if (!pool) return ORC_ENOMEM;
     memset(info, 0, sizeof(*info));
     info->lambda_prime = lam_p;
@@ -490,22 +609,46 @@ int oracle_imm(uint32_t n, const uint64_t* col_off, const uint32_t* row_src,
         if (!(tf < 4294967296.0)) { rc = ORC_EOVERFLOW; goto done; }
         uint64_t theta = (uint64_t)tf;
         if (info->n_targets < 64) info->targets[info->n_targets++] = theta;
-        if (pool->n_sets < theta) {
-            rc = oracle_pool_extend(pool, n, col_off, row_src, weight, model, seed, theta, threads);
-            if (rc) goto done;
+        oracle_pool* fin = pool;
+        if (fresh) {
+            /* theta new sets: sample ids after the rounds' ids */
+            fin = keep ? keep : oracle_pool_create();
+            if (!fin) { rc = ORC_ENOMEM; goto done; }
+            fin->id_base = pool->n_sets;
         }
-        uint64_t cov = oracle_greedy(n, pool->set_off, pool->set_vtx, pool->n_sets, k, seeds,
-                                     gains);
-        if (cov == UINT64_MAX) { rc = ORC_ENOMEM; goto done; }
-        info->theta = pool->n_sets;
-        info->lb = lb;
-        info->covered = cov;
+        if (fin->n_sets < theta) {
+            rc = oracle_pool_extend(fin, n, col_off, row_src, weight, model, seed, theta, threads);
+        }
+        uint64_t cov = rc ? UINT64_MAX
+                          : oracle_greedy(n, fin->set_off, fin->set_vtx, fin->n_sets, k, seeds,
+                                          gains);
+        if (!rc && cov == UINT64_MAX) rc = ORC_ENOMEM;
+        if (!rc) {
+            info->theta = fin->n_sets;
+            info->lb = lb;
+            info->covered = cov;
+        }
+        if (fin != pool && !keep) oracle_pool_destroy(fin);
     }
 done:
     free(tmp_seeds);
     free(tmp_gains);
-    if (!keep) oracle_pool_destroy(pool);
+    if (pool != keep) oracle_pool_destroy(pool);
     return rc;
+}
+
+int oracle_imm(uint32_t n, const uint64_t* col_off, const uint32_t* row_src,
+               const uint32_t* weight, int model, uint32_t k, double eps, double ell,
+               uint64_t seed, int threads, oracle_pool* keep, uint32_t* seeds, uint64_t* gains,
+               oracle_imm_info* info) {
+    return oracle_imm_ex(n, col_off, row_src, weight, model, k, eps, ell, seed, threads,
+                         ORC_SCHED_IMM, keep, seeds, gains, info);
+}
+
+/* The early-stopping schedule's constants: theta_0, i_max and a. */
+int oracle_early_plan(uint32_t n, uint32_t k, double eps, double ell, double* theta0,
+                      uint32_t* i_max, double* a) {
+    return early_plan(n, k, eps, ell, theta0, i_max, a);
 }
 
 int oracle_max_threads(void) {

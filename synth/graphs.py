@@ -207,6 +207,12 @@ def ic_uniform_thresholds(m: int, p: float) -> np.ndarray:
     return np.full(m, t, dtype=np.uint32)
 
 
+def ic_random_thresholds(m: int, rng: np.random.Generator) -> np.ndarray:
+    """Edge probabilities p ~ U[0,1) drawn per edge (the paper's IC setting),
+    as thr = floor(p * 2^32)."""
+    return rng.integers(0, TWO32, size=m, dtype=np.uint64).astype(np.uint32)
+
+
 def lt_cumulative(col_off: np.ndarray, rng: np.random.Generator) -> np.ndarray:
     """LT in-weights w ~ U[0,1) per in-edge (CSC order), normalised per column
     to sum to 1, encoded as a cumulative table cum = min(2^32-1,
@@ -272,6 +278,12 @@ WORKLOADS = {
     # average degree 32, weighted cascade)
     "rmat20_wc": dict(gen=("rmat", 20, 32 << 20), model="ic", enc=("wc",),
                       k=50, eps=0.13, ell=1.0, seed=42),
+    # dense IC sets: the Youtube-shaped graph with p ~ U[0,1) per edge (the
+    # paper's IC edge weights), and its one-tenth-size version
+    "youtube_icu": dict(gen=("chunglu", 1134890, 2987624, 2.1), model="ic",
+                        enc=("urand",), k=50, eps=0.13, ell=1.0, seed=42),
+    "youtube_icu_s": dict(gen=("chunglu", 113489, 298762, 2.1), model="ic",
+                          enc=("urand",), k=50, eps=0.5, ell=1.0, seed=42),
     # served-stream graphs
     "rmat18_wc": dict(gen=("rmat", 18, 2097152), model="ic", enc=("wc",),
                       k=50, eps=0.13, ell=1.0, seed=42),
@@ -303,6 +315,8 @@ def _build(name: str, gen, model: str, enc, gseed: int) -> Graph:
         w = ic_uniform_thresholds(row_src.size, enc[1])
     elif enc[0] == "lt":
         w = lt_cumulative(col_off, rng)
+    elif enc[0] == "urand":
+        w = ic_random_thresholds(row_src.size, rng)
     else:
         raise ValueError(enc)
     return Graph(name, int(n), int(row_src.size), col_off, row_src, w, model)
