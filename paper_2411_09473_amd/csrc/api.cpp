@@ -118,7 +118,8 @@ imm_status imm_graph_create(uint32_t n, uint64_t m, const uint64_t* col_off,
             }
             IMM_TRY(g->arena.alloc((void**)&g->cs, (m ? m : 1) * 16, "edge records"));
             IMM_TRY(g->arena.alloc((void**)&g->guide, (m ? m : 1) * 4, "guide table"));
-            IMM_TRY(g->arena.alloc((void**)&g->gw, (m ? m : 1) * 128, "guide windows"));
+            IMM_TRY(g->arena.alloc((void**)&g->gw, (m ? m : 1) * 16 * kLtWindow,
+                                   "guide windows"));
             if (m) HIP_TRY(hipMemcpyAsync(g->cs, cs.data(), m * 16, hipMemcpyHostToDevice, st));
             HIP_TRY(launch_lt_guide(g->off, g->cs, g->guide, g->gw, n, st));
             HIP_TRY(hipStreamSynchronize(st));

@@ -246,7 +246,7 @@ struct imm_graph {
     uint32_t* src = nullptr;
     uint4* cs = nullptr;
     uint32_t* guide = nullptr;
-    uint4* gw = nullptr;  // per guide bucket, the eight records from its guide entry
+    uint4* gw = nullptr;  // per guide bucket, the kLtWindow records from its guide entry
     // workspaces of finished queries, reused by later ones
     std::mutex ws_mu;
     // largest workspace a finished query on this graph held (server admission)

@@ -23,15 +23,16 @@ struct IcGraphDev {
 // further offset load), and the guide table: for column v of in-degree d,
 // guide[off[v]+j] is the first edge e of the column with cum[e] > ceil(j
 // 2^32 / d) - 1, i.e. the answer for the smallest draw in bucket j =
-// floor(r d / 2^32). For columns of in-degree above 8, gw holds per bucket a
-// copy of the eight records from its guide entry on (one 128-byte line;
-// entries past the column are records with src = 0xFFFFFFFF and cum = 0), so
-// a walk step almost always finds its edge with one line read.
+// floor(r d / 2^32). gw holds per bucket a copy of the kLtWindow records
+// from its guide entry on (64 bytes; entries past the column are records
+// with src = 0xFFFFFFFF and cum = 0), so a walk step almost always finds its
+// edge with one window read.
+constexpr uint32_t kLtWindow = 4;
 struct LtGraphDev {
     const uint32_t* off;   // n+1
     const uint4* cs;       // m (x = cum, y = src, z = off[src], w = off[src+1])
     const uint32_t* guide; // m
-    const uint4* gw;       // 8m
+    const uint4* gw;       // kLtWindow * m
     uint32_t n;
     uint32_t m;
 };

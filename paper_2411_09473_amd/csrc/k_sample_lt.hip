@@ -12,7 +12,11 @@
 //  * The live in-edge of v is the first e of v's column with r < cum[e]. The
 //    guide table jumps to the first candidate of r's bucket j = floor(r d /
 //    2^32), from where a short forward scan over the edge records finds the
-//    same edge the plain search would. A record also holds the bounds of its
+//    same edge the plain search would. Each bucket keeps a copy of the four
+//    records from its candidate on (a 64-byte window), which holds the answer
+//    unless more than three of the column's edges end inside the bucket
+//    (about one step in 1300 on a LiveJournal-shaped graph); the scan then
+//    goes on in the column itself. A record also holds the bounds of its
 //    source's column, so the next step needs no offset load.
 //  * The path is written straight into the walk's staging chunk. A per-walk
 //    Bloom filter of 1024 to 4096 bits (three hashes, size picked per graph
@@ -33,7 +37,7 @@ namespace imm {
 namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kDirectDeg = 8;    // columns read whole, without the guide
+constexpr uint32_t kWin = kLtWindow;   // records per guide window
 constexpr uint32_t kScanLoads = 2;     // 16-byte path groups per lane per rescan round
 
 // The three filter positions of v in a 2^BB-bit filter (multiplicative hashes).
@@ -66,33 +70,33 @@ __device__ __forceinline__ bool bloom_test(const uint32_t* mb, uint32_t v) {
 // The live in-edge of the column [beg, end) for draw r, for a walk run by a
 // single lane (the long-walk kernel): its record (src in .y, src's column
 // bounds in .z/.w), or .y = kNone. *reads counts the records inspected. The
-// lane reads eight records in one round trip: a
-// short column (d <= kDirectDeg) whole, a longer one the copy of the eight
-// records from the guide entry of r's bucket. The answer lies further on only
-// when more than seven edges of the column end inside the bucket; then the
-// scan goes on in the column itself, four records per round trip.
+// lane reads the window of r's bucket in one round trip; the answer lies
+// further on only when more than three edges of the column end inside the
+// bucket, and then the scan goes on in the column, four records per round
+// trip. Needs beg < end.
 __device__ __forceinline__ uint4 lt_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
                                          uint32_t r, uint32_t* reads) {
     const uint32_t d = end - beg;
-    const bool direct = d <= kDirectDeg;
-    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
-    const uint4* w = direct ? g.cs + beg : g.gw + 8ull * (beg + jb);
-    uint4 p[kDirectDeg];
+    const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    const uint4* w = g.gw + (uint64_t)kWin * (beg + jb);
+    uint4 p[kWin];
 #pragma unroll
-    for (uint32_t j = 0; j < kDirectDeg; ++j)
-        p[j] = (!direct || j < d) ? w[j] : make_uint4(0u, kNone, 0u, 0u);
+    for (uint32_t j = 0; j < kWin; ++j) p[j] = w[j];
     uint4 res = make_uint4(0u, kNone, 0u, 0u);
-    uint32_t used = 0;
+    bool ended = false;
 #pragma unroll
-    for (uint32_t j = 0; j < kDirectDeg; ++j) {
-        if (res.y == kNone && p[j].y != kNone) {
-            ++used;
-            if (r < p[j].x) res = p[j];
+    for (uint32_t j = 0; j < kWin; ++j) {
+        if (res.y == kNone && !ended) {
+            if (p[j].y == kNone) {
+                ended = true;
+            } else {
+                ++*reads;
+                if (r < p[j].x) res = p[j];
+            }
         }
     }
-    *reads += direct ? d : used;
-    if (direct || res.y != kNone) return res;
-    for (uint32_t e = g.guide[beg + jb] + kDirectDeg; e < end; e += 4) {
+    if (res.y != kNone || ended) return res;
+    for (uint32_t e = g.guide[beg + jb] + kWin; e < end; e += 4) {
 #pragma unroll
         for (uint32_t j = 0; j < 4; ++j)
             p[j] = e + j < end ? g.cs[e + j] : make_uint4(0xFFFFFFFFu, kNone, 0u, 0u);
@@ -124,74 +128,71 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t x) {
 }
 
 // The live in-edge of a column for a walk run by a group of P lanes, in two
-// parts so that a step's line read can be in flight while the walk does
-// other work. window_issue: each lane loads 8/P of the eight records (a wave
-// load instruction then touches 64/P lines instead of 64, which the memory
-// pipeline serves several times faster). Every load goes to a clamped
-// in-bounds position (a guarded load compiles to a branch with a wait of its
-// own); records past a short column are masked in window_pick. Needs d >= 1.
+// parts so that a step's window read can be in flight while the walk does
+// other work. window_issue: each lane loads kWin/P of the window's records
+// (a wave load instruction then touches 64/P windows instead of 64, which the
+// memory pipeline serves several times faster). Needs beg < end.
 template <uint32_t P>
 __device__ __forceinline__ void window_issue(const LtGraphDev& g, uint32_t beg, uint32_t end,
-                                             uint32_t r, uint32_t sub,
-                                             uint4 (&p)[kDirectDeg / P]) {
-    constexpr uint32_t R = kDirectDeg / P;
+                                             uint32_t r, uint32_t sub, uint4 (&p)[kWin / P]) {
+    constexpr uint32_t R = kWin / P;
     const uint32_t d = end - beg;
-    const bool direct = d <= kDirectDeg;
-    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
-    const uint4* w = direct ? g.cs + beg : g.gw + 8ull * (beg + jb);
+    const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    const uint4* w = g.gw + (uint64_t)kWin * (beg + jb) + sub * R;
 #pragma unroll
-    for (uint32_t j = 0; j < R; ++j) {
-        const uint32_t k = sub * R + j;
-        p[j] = w[direct && k >= d ? d - 1 : k];
-    }
+    for (uint32_t j = 0; j < R; ++j) p[j] = w[j];
 }
 
 // window_pick: the first lane of the group with a hit supplies the record
 // (src in .y, src's column bounds in .z/.w; .y = kNone for no live edge).
-// Every lane returns the same record and count; the caller's control flow is
-// uniform across the group. The answer lies past the window only when more
-// than seven edges of the column end inside r's bucket; the scan then goes
-// on in the column, four records per lane per round trip.
+// Records past the column's end are empty (src = kNone): a window that
+// reaches one without a hit has no live edge. Every lane returns the same
+// record and count; the caller's control flow is uniform across the group.
+// The answer lies past the window only when more than three edges of the
+// column end inside r's bucket; the scan then goes on in the column, four
+// records per lane per round trip.
 template <uint32_t P>
 __device__ __forceinline__ uint4 window_pick(const LtGraphDev& g, uint32_t beg, uint32_t end,
                                              uint32_t r, uint32_t* reads, uint32_t sub,
-                                             uint32_t lead, const uint4 (&w)[kDirectDeg / P]) {
-    constexpr uint32_t R = kDirectDeg / P;
-    const uint32_t d = end - beg;
-    const bool direct = d <= kDirectDeg;
-    const uint32_t jb = direct ? 0u : (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
-    uint4 p[R];
-#pragma unroll
-    for (uint32_t j = 0; j < R; ++j)
-        p[j] = (direct && sub * R + j >= d) ? make_uint4(0u, kNone, 0u, 0u) : w[j];
-    // this lane's first hit (R: none) and records inspected up to it
+                                             uint32_t lead, const uint4 (&p)[kWin / P]) {
+    constexpr uint32_t R = kWin / P;
+    // this lane's first hit or column end (R: neither), and records
+    // inspected up to it
     uint32_t hj = R, used = 0;
+    bool hit = false;
     uint4 mine = make_uint4(0u, kNone, 0u, 0u);
 #pragma unroll
     for (uint32_t j = 0; j < R; ++j) {
-        if (hj == R && p[j].y != kNone) {
-            ++used;
-            if (r < p[j].x) {
+        if (hj == R) {
+            if (p[j].y == kNone) {
                 hj = j;
-                mine = p[j];
+            } else {
+                ++used;
+                if (r < p[j].x) {
+                    hj = j;
+                    hit = true;
+                    mine = p[j];
+                }
             }
         }
     }
     uint32_t gb = group_bits<P>(__ballot(hj < R), lead);
     uint4 res = make_uint4(0u, kNone, 0u, 0u);
     if (gb) {
-        // the lanes before the first hit hold R valid records each
+        // the lanes before the first stop hold R inspected records each
         const uint32_t src = lead + (uint32_t)__ffs(gb) - 1u;
-        res.y = __shfl(mine.y, src, kWave);
-        res.z = __shfl(mine.z, src, kWave);
-        res.w = __shfl(mine.w, src, kWave);
-        if (!direct) *reads += (src - lead) * R + __shfl(used, src, kWave);
-    } else if (!direct) {
-        *reads += group_sum<P>(used);
+        if (__shfl((uint32_t)hit, src, kWave)) {
+            res.y = __shfl(mine.y, src, kWave);
+            res.z = __shfl(mine.z, src, kWave);
+            res.w = __shfl(mine.w, src, kWave);
+        }
+        *reads += (src - lead) * R + __shfl(used, src, kWave);
+        return res;
     }
-    if (direct) *reads += d;
-    if (direct || gb) return res;
-    for (uint32_t e = g.guide[beg + jb] + kDirectDeg; e < end; e += 4 * P) {
+    *reads += kWin;
+    const uint32_t d = end - beg;
+    const uint32_t jb = (uint32_t)(((uint64_t)r * (uint64_t)d) >> 32);
+    for (uint32_t e = g.guide[beg + jb] + kWin; e < end; e += 4 * P) {
         const uint32_t e0 = e + 4 * sub;
         uint4 q[4];
 #pragma unroll
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
     // from the ticket 64 at a time (uniform across the wave)
     uint32_t res_pos = 0, res_end = 0;
 
-    constexpr uint32_t R = kDirectDeg / P;
+    constexpr uint32_t R = kWin / P;
     bool has = false, done = false, fresh = false, primed = false;
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
     uint32_t cbeg = 0, cend = 0;  // cur's column
@@ -570,9 +571,9 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
 }
 
 // guide[beg + j] = first e in [beg, end) with cum[e] > ceil(j 2^32 / d) - 1,
-// or end if there is none, for every column (64 columns per wave); for a
-// column of in-degree above kDirectDeg also the window gw[8 (beg + j) + k] =
-// cs[guide[beg + j] + k] (k < 8; an empty record past the column).
+// or end if there is none, and the window gw[kWin (beg + j) + k] =
+// cs[guide[beg + j] + k] (k < kWin; an empty record, src = kNone, past the
+// column), for every column (64 columns per wave).
 __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const uint4* cs,
                                                       uint32_t* guide, uint4* gw, uint32_t n) {
     const uint64_t v = (uint64_t)blockIdx.x * kWave + threadIdx.x;
@@ -590,12 +591,10 @@ __global__ __launch_bounds__(64) void lt_guide_kernel(const uint32_t* off, const
             if ((uint64_t)cs[mid].x > lo) z = mid; else a = mid + 1;
         }
         guide[b0 + j] = a;
-        if (d > kDirectDeg) {
 #pragma unroll
-            for (uint32_t k = 0; k < kDirectDeg; ++k)
-                gw[8ull * (b0 + j) + k] =
-                    a + k < b0 + d ? cs[a + k] : make_uint4(0u, kNone, 0u, 0u);
-        }
+        for (uint32_t k = 0; k < kWin; ++k)
+            gw[(uint64_t)kWin * (b0 + j) + k] =
+                a + k < b0 + d ? cs[a + k] : make_uint4(0u, kNone, 0u, 0u);
     });
 }
 
