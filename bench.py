@@ -215,6 +215,44 @@ def sample_mode(args, imm, g, dg, spec, stream, torch):
     }))
 
 
+def counter_update_mode(args, imm, torch):
+    """Selection time of a whole IMM run under each counter update of the
+    greedy (Section IV-C's adaptive update against decrement-only and
+    recount-only), on each named workload; the seeds must not change."""
+    import statistics
+
+    import synth
+    modes = {"adaptive": 0, "decrement": imm.IMM_UPDATE_DECREMENT,
+             "recount": imm.IMM_UPDATE_RECOUNT}
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name in args.counter_update.split(","):
+        spec = synth.WORKLOADS[name]
+        g = synth.make_graph(name)
+        dg = imm.graph_from(g, stream=stream)
+        torch.cuda.synchronize()
+        row, seeds = {}, None
+        for mode, fl in modes.items():
+            runs = []
+            for i in range(args.warmup + args.steps):
+                r = imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                                flags=imm.IMM_TIMING | fl, stream=stream)
+                if i >= args.warmup:
+                    runs.append(r)
+            if seeds is None:
+                seeds = list(runs[0].seeds)
+            assert all(list(r.seeds) == seeds for r in runs), f"{name}: {mode} changed seeds"
+            row[mode] = {"select_ms": statistics.median(r.stats["ms_select"] for r in runs),
+                         "total_ms": statistics.median(r.stats["ms_total"] for r in runs)}
+        row["speedup_vs_decrement"] = row["decrement"]["select_ms"] / row["adaptive"]["select_ms"]
+        row["speedup_vs_recount"] = row["recount"]["select_ms"] / row["adaptive"]["select_ms"]
+        out[name] = row
+        dg.close()
+        print(f"[bench] counter update {name} done", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "IMM selection time by counter update (median ms)",
+                      "steps": args.steps, "warmup": args.warmup, "workloads": out}))
+
+
 def _gen_instance(arg):
     import synth
     i, s = arg
@@ -327,6 +365,9 @@ def serve_mode(args, imm, hgraphs, stream, torch):
     torch.cuda.synchronize()
     print("[bench] served warmup done", file=sys.stderr, flush=True)
 
+    if args.saturate:
+        # every query is queued at t = 0
+        qs = [dict(q, t=0.0) for q in qs]
     srv = imm.Server(budget_bytes=args.serve_budget << 30, max_slots=args.serve_slots)
     tickets = [None] * len(qs)
 
@@ -368,13 +409,16 @@ def serve_mode(args, imm, hgraphs, stream, torch):
     lat1 = np.array(lat1)
     print("[bench] one-at-a-time run done", file=sys.stderr, flush=True)
     print(json.dumps({
-        "metric": "IMM queries/s (served, Poisson arrivals)", "value": served_qps,
+        "metric": "IMM queries/s (served, " + ("all queued at t=0" if args.saturate
+                                               else "Poisson arrivals") + ")",
+        "value": served_qps,
         "unit": "queries/s", "n_gpus": 1, "steps": len(qs), "warmup": args.warmup,
         "ms_per_step": float(np.mean(lat)), "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"{len(qs)} queries at {args.rate}/s over rmat18_wc (IC), "
-                               "youtube_ic (IC) and orkut_lt (LT); k in {10,50,100}, "
-                               "eps in {0.5,0.13}",
+        "config": {"workload": f"{len(qs)} queries "
+                               + ("queued at once" if args.saturate else f"at {args.rate}/s")
+                               + " over rmat18_wc (IC), youtube_ic (IC) and orkut_lt (LT); "
+                               "k in {10,50,100}, eps in {0.5,0.13}",
                    "max_slots": args.serve_slots, "budget_GiB": args.serve_budget,
                    "parallelism": "single GPU"},
         "graph_select": bool(args.graph_select),
@@ -427,6 +471,12 @@ def main():
                     help="served mode: this many Poisson-arrival queries through the "
                          "query server, against the same stream one at a time")
     ap.add_argument("--rate", type=float, default=50.0, help="served mode: arrivals per second")
+    ap.add_argument("--saturate", action="store_true",
+                    help="served mode: queue every query at t=0 (aggregate throughput) "
+                         "instead of Poisson arrivals")
+    ap.add_argument("--counter-update", default="",
+                    help="comma-separated workloads: selection time of an IMM run under "
+                         "each counter update (adaptive, decrement-only, recount-only)")
     ap.add_argument("--serve-slots", type=int, default=8, help="served mode: concurrent queries")
     ap.add_argument("--serve-budget", type=int, default=192,
                     help="served mode: device memory budget in GiB")
@@ -456,6 +506,8 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         return copy_calibration(torch)
+    if args.counter_update:
+        return counter_update_mode(args, imm, torch)
     if served is not None:
         return serve_mode(args, imm, served, torch.cuda.current_stream(), torch)
     if batch is not None:

@@ -67,6 +67,36 @@ typedef enum {
  * be captured (the legacy default stream) the steps are launched directly.
  * Results are unchanged. */
 #define IMM_GRAPH_SELECT 0x8u
+/* Sampling schedules other than Algorithm 1's (imm_run, imm_run_batch,
+ * server queries; at most one of the two):
+ * IMM_FRESH_FINAL: IMM's rounds and LB as usual, but the final selection runs
+ *   over theta = ceil(lambda* / LB) sets drawn afresh (sample ids right after
+ *   those the rounds used) instead of reusing the rounds' sets: the
+ *   correction of IMM's analysis noted by Chen (2018). theta, the pool and
+ *   the coverage are those of the fresh sets.
+ * IMM_EARLY_STOP: early termination in the manner of OPIM (Tang et al. 2018;
+ *   the paper's related work): two independent pools R1 (sample ids j) and
+ *   R2 (ids 2^32 + j) of theta_i = ceil(theta_0 2^(i-1)) sets each, i = 1 ..
+ *   i_max; the greedy seeds S of R1 are returned as soon as
+ *     lo / up >= 1 - 1/e - eps, or at i = i_max,
+ *   where, with a = ln(3 i_max) + ell ln n and g_k = 1 - (1 - 1/k)^k,
+ *     up = (sqrt(cov_R1(S) / g_k + a/2) + sqrt(a/2))^2 n / theta_i
+ *          (an upper bound on OPT),
+ *     lo = ((sqrt(cov_R2(S) + 2a/9) - sqrt(a/2))^2 - a/18) n / theta_i
+ *          (a lower bound on the spread of S; 0 if not positive),
+ *   theta_max = theta_0 n / (eps^2 k) = lambda* / k of Tang et al. Eq. 6 at
+ *   failure probability n^-ell / 3, and i_max = ceil(log2(n / (eps^2 k))).
+ *   theta is |R1|, LB is lo; imm_result_early gives up, lo / up and the
+ *   coverages in R2. */
+#define IMM_FRESH_FINAL 0x10u
+#define IMM_EARLY_STOP 0x20u
+/* The greedy's counter update after a seed covers its sets (Section IV-C's
+ * adaptive update): by default a step recounts every count from the
+ * uncovered sets when the newly covered sets hold more than a quarter of the
+ * pool, and decrements their members' counts otherwise. These flags fix one
+ * choice for every step (at most one of the two); results are unchanged. */
+#define IMM_UPDATE_DECREMENT 0x40u
+#define IMM_UPDATE_RECOUNT 0x80u
 
 typedef struct imm_graph imm_graph;
 typedef struct imm_result imm_result;
@@ -246,6 +276,11 @@ imm_status imm_result_targets(const imm_result* r, uint32_t* count, uint64_t* ta
  * filled when non-NULL. Requires IMM_KEEP_POOL, else IMM_EINVAL. */
 imm_status imm_result_pool(const imm_result* r, uint64_t* n_sets, uint64_t* n_entries,
                            uint64_t* set_off, uint32_t* set_vtx);
+/* IMM_EARLY_STOP runs: the last iteration's upper bound on OPT (up), the
+ * ratio lo / up, and the coverage of each iteration's seeds in the second
+ * pool (rounds entries, at most 64; NULL ok). All 0 for other runs. */
+imm_status imm_result_early(const imm_result* r, double* sigma_up, double* alpha,
+                            uint64_t* round_cov2);
 imm_status imm_result_stats(const imm_result* r, imm_stats* stats);
 void imm_result_destroy(imm_result* r);
 

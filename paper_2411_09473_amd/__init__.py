@@ -33,6 +33,8 @@ _lib = C.CDLL(str(_LIB_PATH))
 IMM_OK, IMM_EINVAL, IMM_ENOMEM, IMM_EOVERFLOW, IMM_EDEVICE, IMM_EBUSY, IMM_ECANCELLED = range(7)
 IMM_IC, IMM_LT = 0, 1
 IMM_DEVICE_PTRS, IMM_KEEP_POOL, IMM_TIMING, IMM_GRAPH_SELECT = 0x1, 0x2, 0x4, 0x8
+IMM_FRESH_FINAL, IMM_EARLY_STOP = 0x10, 0x20
+IMM_UPDATE_DECREMENT, IMM_UPDATE_RECOUNT = 0x40, 0x80
 _NAMES = {1: "IMM_EINVAL", 2: "IMM_ENOMEM", 3: "IMM_EOVERFLOW", 4: "IMM_EDEVICE",
           5: "IMM_EBUSY", 6: "IMM_ECANCELLED"}
 
@@ -84,6 +86,7 @@ _sig = {
     "imm_result_seeds": [_vp, _vp, _vp],
     "imm_result_targets": [_vp, _P(_u32), _vp, _vp],
     "imm_result_pool": [_vp, _P(_u64), _P(_u64), _vp, _vp],
+    "imm_result_early": [_vp, _P(_dbl), _P(_dbl), _vp],
     "imm_result_stats": [_vp, _P(imm_stats)],
     "imm_sample": [_vp, _u64, _u64, _u64, _u32, _vp, _P(_vp)],
     "imm_pool_info": [_vp, _P(_u64), _P(_u64), _P(imm_stats)],
@@ -215,6 +218,11 @@ class Result:
         _check(_lib.imm_result_targets(self._h, C.byref(cnt), tg.ctypes.data, rc.ctypes.data))
         self.targets = [int(x) for x in tg[: cnt.value]]
         self.round_cov = [int(x) for x in rc[: self.rounds]]
+        su, al = _dbl(), _dbl()
+        rc2 = np.zeros(64, dtype=np.uint64)
+        _check(_lib.imm_result_early(self._h, C.byref(su), C.byref(al), rc2.ctypes.data))
+        self.sigma_up, self.alpha = su.value, al.value
+        self.round_cov2 = [int(x) for x in rc2[: self.rounds]]
         st = imm_stats()
         _check(_lib.imm_result_stats(self._h, C.byref(st)))
         self.stats = st.as_dict()

@@ -269,6 +269,17 @@ imm_status imm_result_pool(const imm_result* r, uint64_t* n_sets, uint64_t* n_en
     return IMM_OK;
 }
 
+imm_status imm_result_early(const imm_result* r, double* sigma_up, double* alpha,
+                            uint64_t* round_cov2) {
+    if (!r) return fail(IMM_EINVAL, "result_early: null result");
+    if (sigma_up) *sigma_up = r->sigma_up;
+    if (alpha) *alpha = r->alpha;
+    if (round_cov2 && !r->round_cov2.empty())
+        std::memcpy(round_cov2, r->round_cov2.data(),
+                    std::min<size_t>(r->round_cov2.size(), 64) * 8);
+    return IMM_OK;
+}
+
 imm_status imm_result_stats(const imm_result* r, imm_stats* stats) {
     if (!r || !stats) return fail(IMM_EINVAL, "result_stats: null argument");
     *stats = r->stats;

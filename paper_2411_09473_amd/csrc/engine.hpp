@@ -204,10 +204,16 @@ struct Workspace {
     uint32_t huge_slots = 0;
     uint32_t* over = nullptr;  // IC: giant sets that outgrew a bounded queue
     uint64_t cap_ov = 0;
+    // coverage of a seed set in this pool (early stopping): a vertex bitmap
+    // and a set bitmap (cap_mark words in all), and the count
+    uint32_t* mark = nullptr;
+    uint64_t cap_mark = 0;
+    unsigned long long* cov_count = nullptr;
     uint64_t n_sets = 0;
     uint64_t p_exact = 0;    // pool size, exact as of the last synchronisation
     uint64_t p_ub = 0;       // upper bound on the pool size
     double mean_size = 0.0;  // mean set size of the last round (staging estimate)
+    uint32_t update_mode = 0;    // SelectDesc::update of this workspace's selections
     uint64_t pending_count = 0;  // sets of the sampling pass in flight
     uint64_t pending_lo = 0;
     Timer timer;
@@ -263,6 +269,10 @@ struct imm_result {
     double lb = 0.0;
     uint64_t covered = 0;
     std::vector<uint64_t> targets, round_cov;
+    // early stopping: the last iteration's upper bound on OPT and ratio, and
+    // each iteration's coverage of its seeds in the second pool
+    double sigma_up = 0.0, alpha = 0.0;
+    std::vector<uint64_t> round_cov2;
     bool has_pool = false;
     std::vector<uint64_t> set_off;
     std::vector<uint32_t> set_vtx;
@@ -304,6 +314,12 @@ imm_status ws_select_launch(Workspace& w, uint32_t k, bool graph = false,
 // Prepare, run and finish the selection of this workspace alone.
 imm_status ws_select(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered);
 imm_status ws_sync_pool(Workspace& w);
+// Empty the pool (sets, counts, index) and keep the buffers, the scalars and
+// the set-size estimate: the next sampling call starts a new pool.
+imm_status ws_restart_pool(Workspace& w);
+// The number of this pool's sets that hold one of seeds[0..k) (device
+// array); waits for the stream.
+imm_status ws_coverage(Workspace& w, const uint32_t* seeds, uint32_t k, uint64_t* out);
 void ws_note_pool(Workspace& w, uint64_t sets_before);
 imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<uint32_t>* sv,
                           std::vector<uint32_t>* counts);
@@ -318,6 +334,10 @@ imm_status tune_graph(imm_graph* g, hipStream_t st);
 // Theta constants (Tang et al. 2015, Eq. 9 and Eq. 6 with ell adjusted).
 imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* lambda_prime,
                       double* lambda_star, uint32_t* i_max);
+// The early-stopping schedule's first pool size theta_0, its iteration count
+// and the exponent a of each bound's failure probability e^-a.
+imm_status early_plan(uint32_t n, uint32_t k, double eps, double ell, double* theta0,
+                      uint32_t* i_max, double* a);
 
 struct Query;  // one IMM query's state machine (runner.cpp)
 

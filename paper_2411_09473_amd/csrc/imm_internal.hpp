@@ -150,6 +150,11 @@ hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, 
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);
+// *count += number of sets of the pool holding one of seeds[0..k); mark
+// (one bit per vertex) and hit (one bit per set) must be zero before.
+hipError_t launch_cover_count(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t n_sets,
+                              const uint32_t* seeds, uint32_t k, uint32_t* mark, uint32_t* hit,
+                              unsigned long long* count, hipStream_t st);
 // Check a caller pool: offsets non-decreasing, ids < n. flag[0] set on error.
 hipError_t launch_validate_pool(const uint64_t* set_off, uint64_t n_sets, const uint32_t* set_vtx,
                                 uint32_t n, uint32_t* flag, hipStream_t st);
@@ -204,7 +209,12 @@ struct SelectDesc {
     uint32_t n, k, nseg;              // nseg <= kMaxSegments
     uint32_t n_sets;
     uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
+    // counter update after a seed's sets are covered: kUpdateAdaptive
+    // (recount when they hold more than a quarter of the pool, else
+    // decrement), kUpdateDecrement or kUpdateRecount (always that one)
+    uint32_t update = 0;
 };
+enum : uint32_t { kUpdateAdaptive = 0, kUpdateDecrement = 1, kUpdateRecount = 2 };
 constexpr uint32_t kMaxSegments = 64;
 // A recount gives a vertex with a longer index list a wave of its own.
 constexpr uint32_t kHeavyList = 4096;

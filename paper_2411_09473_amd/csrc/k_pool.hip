@@ -215,6 +215,37 @@ __global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_
         atomicAdd(&counts[set_vtx[t]], 1u);
 }
 
+// Seeds' bits in a vertex bitmap.
+__global__ __launch_bounds__(256) void mark_seeds_kernel(const uint32_t* seeds, uint32_t k,
+                                                         uint32_t* mark) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) atomicOr(&mark[seeds[i] >> 5], 1u << (seeds[i] & 31));
+}
+
+// Sets holding a marked vertex: an entry of a marked vertex finds its set j
+// (the last j with set_off[j] <= t, so empty sets are never chosen), sets
+// j's bit in hit, and counts j the first time that bit is set.
+__global__ __launch_bounds__(256) void cover_count_kernel(const uint64_t* set_off,
+                                                          const uint32_t* set_vtx,
+                                                          uint64_t n_sets, const uint32_t* mark,
+                                                          uint32_t* hit,
+                                                          unsigned long long* count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t P = set_off[n_sets];
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride) {
+        const uint32_t v = set_vtx[t];
+        if (!((mark[v >> 5] >> (v & 31)) & 1u)) continue;
+        uint64_t a = 0, z = n_sets;  // first j in [0, n_sets] with set_off[j] > t, minus one
+        while (a < z) {
+            const uint64_t mid = a + ((z - a) >> 1);
+            if (set_off[mid] > t) z = mid; else a = mid + 1;
+        }
+        const uint64_t j = a - 1;
+        const uint32_t bit = 1u << (j & 31);
+        if (!(atomicOr(&hit[j >> 5], bit) & bit)) atomicAdd(count, 1ull);
+    }
+}
+
 __global__ __launch_bounds__(256) void validate_kernel(const uint64_t* set_off, uint64_t n_sets,
                                                        const uint32_t* set_vtx, uint32_t n,
                                                        uint32_t* flag) {
@@ -368,6 +399,17 @@ hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* c
     if (P == 0) return hipSuccess;
     hipLaunchKernelGGL(count_entries_kernel, dim3(grid_for(P, 256 * 8, 8192)), dim3(256), 0, st,
                        set_vtx, P, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_cover_count(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t n_sets,
+                              const uint32_t* seeds, uint32_t k, uint32_t* mark, uint32_t* hit,
+                              unsigned long long* count, hipStream_t st) {
+    hipLaunchKernelGGL(mark_seeds_kernel, dim3((k + 255) / 256), dim3(256), 0, st, seeds, k, mark);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_sets == 0) return e;
+    hipLaunchKernelGGL(cover_count_kernel, dim3(2048), dim3(256), 0, st, set_off, set_vtx, n_sets,
+                       mark, hit, count);
     return hipGetLastError();
 }
 

@@ -23,7 +23,9 @@
 //    per workgroup in LDS first. When the covered sets hold more than a
 //    quarter of the pool, the step instead recounts every remaining count
 //    from the uncovered sets (the paper's adaptive counter update, Section
-//    IV-C), a gather without atomics.
+//    IV-C), a gather without atomics. A descriptor can also fix the choice
+//    (decrement always, or recount always) for measurement; every choice
+//    gives the same counts.
 #include <algorithm>
 
 #include "device_common.hpp"
@@ -64,6 +66,7 @@ struct SelView {
     IMM_GLOBAL unsigned long long* cov_entries;
     uint32_t n, k, nseg, n_sets;
     uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
+    uint32_t update;
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -92,7 +95,8 @@ __device__ __forceinline__ SelView view_of(const SelectDesc& d) {
                    glb(d.covered), glb(d.slots),   glb(d.seeds),   glb(d.gains),
                    glb(d.chunks),  glb(d.chunk_n), d.chunk_cap,    glb(d.cov_entries),
                    d.n,            d.k,            d.nseg,         d.n_sets,
-                   d.arg_lo,       d.arg_cnt,      d.sel_lo,       d.sel_cnt};
+                   d.arg_lo,       d.arg_cnt,      d.sel_lo,       d.sel_cnt,
+                   d.update};
 }
 
 // Device-scope relaxed atomics on global memory (what atomicAdd and friends do).
@@ -445,7 +449,8 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t pool = d.set_off[d.n_sets];
-    if (d.cov_entries[t] * 4ull > pool) {
+    if (d.update == kUpdateRecount ||
+        (d.update == kUpdateAdaptive && d.cov_entries[t] * 4ull > pool)) {
         recount_all(d, blk, h_key, h_cnt);
         return;
     }

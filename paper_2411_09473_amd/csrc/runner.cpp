@@ -66,8 +66,32 @@ imm_status theta_plan(uint32_t n, uint32_t k, double eps, double ell, double* la
     return IMM_OK;
 }
 
+imm_status early_plan(uint32_t n, uint32_t k, double eps, double ell, double* theta0,
+                      uint32_t* i_max, double* a) {
+    if (n < 2 || k == 0 || k > n || !(eps > 0.0) || !(ell > 0.0))
+        return fail(IMM_EINVAL, "early_plan: need n >= 2, 1 <= k <= n, eps > 0, ell > 0");
+    // IMM's lambda* (Tang et al. 2015, Eq. 6) at failure probability delta / 3,
+    // delta = n^-ell, with OPT >= k: theta_max; the first pools hold
+    // theta_max eps^2 k / n sets and double until they reach theta_max
+    const double ln_n = std::log((double)n);
+    const double logcnk = log_binom(n, k);
+    const double one_m = 1.0 - kInvE;
+    const double ln6d = std::log(6.0) + ell * ln_n;
+    const double u = one_m * std::sqrt(ln6d) + std::sqrt(one_m * (logcnk + ln6d));
+    const double theta_max = 2.0 * (double)n * u * u / (eps * eps * (double)k);
+    *theta0 = theta_max * eps * eps * (double)k / (double)n;
+    const double r = std::ceil(std::log2((double)n / (eps * eps * (double)k)));
+    *i_max = r < 1.0 ? 1u : (uint32_t)r;
+    // each of the 3 i_max bounds fails with probability at most exp(-a)
+    *a = std::log(3.0 * (double)*i_max) + ell * ln_n;
+    return IMM_OK;
+}
+
 namespace {
 constexpr size_t kMaxCachedWorkspacesPerGraph = 8;
+// sample ids of the early-stopping schedule's second pool start here
+constexpr uint64_t kSecondPoolIds = 1ull << 32;
+enum Schedule { kSchedImm = 0, kSchedFresh = 1, kSchedEarly = 2 };
 }  // namespace
 
 struct Query {
@@ -75,7 +99,10 @@ struct Query {
     imm_params p{};
     hipStream_t st = nullptr;
     std::unique_ptr<Workspace> w;
+    std::unique_ptr<Workspace> w2;  // early stopping: the second pool
+    int sched = kSchedImm;
     double lam_p = 0, lam_s = 0, eps_p = 0, lb = 1.0;
+    double theta0 = 0, a = 0, g_k = 0;  // early stopping
     uint32_t i_max = 0, i = 0;
     bool final = false, done = false;
     uint64_t before = 0, cov = 0;
@@ -97,26 +124,26 @@ struct Query {
 
 namespace {
 
-imm_status acquire_workspace(Query& q, uint32_t big_cap) {
+imm_status acquire_workspace(Query& q, std::unique_ptr<Workspace>& slot, uint32_t big_cap) {
     {
         std::lock_guard<std::mutex> lk(q.g->ws_mu);
         auto& c = q.g->ws_cache;
         for (size_t j = 0; j < c.size(); ++j) {
             if (c[j]->arena.budget == q.p.max_device_bytes) {
-                q.w = std::move(c[j]);
+                slot = std::move(c[j]);
                 c.erase(c.begin() + (long)j);
                 break;
             }
         }
     }
-    if (!q.w) {
-        q.w.reset(new Workspace());
-        q.w->big_cap = big_cap;
-        IMM_TRY(ws_init(*q.w, q.g->n, q.g->device, q.st, q.p.max_device_bytes));
+    if (!slot) {
+        slot.reset(new Workspace());
+        slot->big_cap = big_cap;
+        IMM_TRY(ws_init(*slot, q.g->n, q.g->device, q.st, q.p.max_device_bytes));
     } else {
         // giant-set scratch narrower than this batch width wants (0: all the
         // GPU can use) is reallocated on use; wider scratch is kept
-        Workspace& w = *q.w;
+        Workspace& w = *slot;
         const uint32_t want = big_cap ? big_cap : 0xFFFFFFFFu;
         if (w.big && w.big_cap != big_cap && w.big_slots < want) {
             w.arena.release(w.big);
@@ -128,36 +155,68 @@ imm_status acquire_workspace(Query& q, uint32_t big_cap) {
         }
         w.big_cap = big_cap;
     }
-    return ws_reset(*q.w, q.st, (q.p.flags & IMM_TIMING) != 0);
+    return ws_reset(*slot, q.st, (q.p.flags & IMM_TIMING) != 0);
 }
 
 void release_workspace(Query& q) {
-    if (!q.w) return;
     std::lock_guard<std::mutex> lk(q.g->ws_mu);
-    if (q.g->ws_cache.size() < kMaxCachedWorkspacesPerGraph)
-        q.g->ws_cache.push_back(std::move(q.w));
-    q.w.reset();
+    for (auto* slot : {&q.w, &q.w2}) {
+        if (!*slot) continue;
+        if (q.g->ws_cache.size() < kMaxCachedWorkspacesPerGraph)
+            q.g->ws_cache.push_back(std::move(*slot));
+        slot->reset();
+    }
 }
 
 imm_status start_query(Query& q, uint32_t big_cap) {
     q.t0 = now_ms();
     if (q.p.k == 0 || q.p.k > q.g->n) return fail(IMM_EINVAL, "run: need 1 <= k <= n");
     if (!(q.p.epsilon > 0.0) || !(q.p.ell > 0.0)) return fail(IMM_EINVAL, "run: need eps > 0, ell > 0");
+    const bool fresh = (q.p.flags & IMM_FRESH_FINAL) != 0;
+    const bool early = (q.p.flags & IMM_EARLY_STOP) != 0;
+    if (fresh && early) return fail(IMM_EINVAL, "run: IMM_FRESH_FINAL and IMM_EARLY_STOP exclude each other");
+    q.sched = early ? kSchedEarly : (fresh ? kSchedFresh : kSchedImm);
+    const bool dec = (q.p.flags & IMM_UPDATE_DECREMENT) != 0;
+    const bool rec = (q.p.flags & IMM_UPDATE_RECOUNT) != 0;
+    if (dec && rec)
+        return fail(IMM_EINVAL, "run: IMM_UPDATE_DECREMENT and IMM_UPDATE_RECOUNT exclude each other");
+    const uint32_t update = dec ? kUpdateDecrement : (rec ? kUpdateRecount : kUpdateAdaptive);
     IMM_TRY(theta_plan(q.g->n, q.p.k, q.p.epsilon, q.p.ell, &q.lam_p, &q.lam_s, &q.i_max));
+    if (early) {
+        IMM_TRY(early_plan(q.g->n, q.p.k, q.p.epsilon, q.p.ell, &q.theta0, &q.i_max, &q.a));
+        q.g_k = 1.0 - std::pow(1.0 - 1.0 / (double)q.p.k, (double)q.p.k);
+    }
     IMM_TRY(tune_graph(q.g, q.st));
-    IMM_TRY(acquire_workspace(q, big_cap));
+    IMM_TRY(acquire_workspace(q, q.w, big_cap));
+    if (early) IMM_TRY(acquire_workspace(q, q.w2, big_cap));
+    q.w->update_mode = update;
     q.r.reset(new imm_result());
     q.r->k = q.p.k;
     q.eps_p = std::sqrt(2.0) * q.p.epsilon;
     q.lb = 1.0;
     q.i = 0;
-    q.final = q.i_max == 0;
+    q.final = q.sched != kSchedEarly && q.i_max == 0;
     return IMM_OK;
 }
 
 // This iteration's target, and its sampling launched on the query's stream.
 imm_status begin_iteration(Query& q) {
     double tf;
+    if (q.sched == kSchedEarly) {
+        // both pools grow to theta_0 2^(i-1) sets
+        ++q.i;
+        tf = std::ceil(std::ldexp(q.theta0, (int)q.i - 1));
+        if (!(tf < 4294967296.0)) return fail(IMM_EOVERFLOW, "theta_i >= 2^32");
+        const uint64_t target = (uint64_t)tf;
+        if (q.r->targets.size() < 64) q.r->targets.push_back(target);
+        Workspace& w = *q.w;
+        Workspace& w2 = *q.w2;
+        q.before = w.n_sets;
+        IMM_TRY(ws_extend_launch(w, q.g, q.p.seed, w.n_sets,
+                                 w.n_sets < target ? target - w.n_sets : 0));
+        return ws_extend_launch(w2, q.g, q.p.seed, kSecondPoolIds + w2.n_sets,
+                                w2.n_sets < target ? target - w2.n_sets : 0);
+    }
     if (!q.final) {
         ++q.i;
         tf = std::ceil(q.lam_p / std::ldexp((double)q.g->n, -(int)q.i));
@@ -170,9 +229,24 @@ imm_status begin_iteration(Query& q) {
     }
     const uint64_t target = (uint64_t)tf;
     Workspace& w = *q.w;
+    if (q.final && q.sched == kSchedFresh) {
+        // the final selection's theta sets are drawn afresh: sample ids after
+        // the rounds' ids, into an emptied pool
+        const uint64_t used = w.n_sets;
+        IMM_TRY(ws_restart_pool(w));
+        q.before = 0;
+        return ws_extend_launch(w, q.g, q.p.seed, used, target);
+    }
     q.before = w.n_sets;
     return ws_extend_launch(w, q.g, q.p.seed, w.n_sets,
                             w.n_sets < target ? target - w.n_sets : 0);
+}
+
+// After the round's sampling: retries and compaction of the pool (pools).
+imm_status finish_sampling(Query& q) {
+    IMM_TRY(ws_extend_finish(*q.w, q.g, q.p.seed));
+    if (q.w2) IMM_TRY(ws_extend_finish(*q.w2, q.g, q.p.seed));
+    return IMM_OK;
 }
 
 // After the theta decision of this iteration's coverage.
@@ -180,7 +254,27 @@ imm_status end_iteration(Query& q) {
     Workspace& w = *q.w;
     IMM_TRY(ws_select_finish(w, q.p.k, q.before, &q.cov));
     imm_result& r = *q.r;
-    if (!q.final) {
+    if (q.sched == kSchedEarly) {
+        // the seeds' coverage in the second pool, then both bounds: an upper
+        // bound on OPT from the first pool's coverage (at least g_k of the
+        // best possible there), a lower bound on the seeds' spread from the
+        // second's (Chernoff bounds, each failing with probability <= e^-a)
+        uint64_t cov2 = 0;
+        IMM_TRY(ws_coverage(*q.w2, w.seeds_d, q.p.k, &cov2));
+        r.round_cov.push_back(q.cov);
+        r.round_cov2.push_back(cov2);
+        r.rounds = q.i;
+        const double scale = (double)q.g->n / (double)w.n_sets;
+        const double su = std::sqrt((double)q.cov / q.g_k + q.a / 2.0) + std::sqrt(q.a / 2.0);
+        const double up = su * su * scale;
+        const double sl = std::sqrt((double)cov2 + 2.0 * q.a / 9.0) - std::sqrt(q.a / 2.0);
+        double lo = sl > 0.0 ? (sl * sl - q.a / 18.0) * scale : 0.0;
+        if (lo < 0.0) lo = 0.0;
+        r.sigma_up = up;
+        r.alpha = lo / up;
+        q.lb = lo;
+        if (!(lo / up >= (1.0 - kInvE) - q.p.epsilon) && q.i < q.i_max) return IMM_OK;
+    } else if (!q.final) {
         r.round_cov.push_back(q.cov);
         r.rounds = q.i;
         const double x = std::ldexp((double)q.g->n, -(int)q.i);
@@ -259,6 +353,7 @@ void BatchRunner::finish_err(Query* q, imm_status s) {
     q->err = last_error();
     q->done = true;
     q->w.reset();  // a failed workspace is not reused
+    q->w2.reset();
 }
 
 void BatchRunner::cancel(Query* q) {
@@ -303,7 +398,7 @@ bool BatchRunner::step() {
     }
     std::vector<Query*> ready;
     for (auto* q : live) {
-        imm_status s = ws_extend_finish(*q->w, q->g, q->p.seed);
+        imm_status s = finish_sampling(*q);
         if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
         if (s != IMM_OK) finish_err(q, s);
         else ready.push_back(q);
@@ -411,6 +506,7 @@ imm_result* BatchRunner::take(Query* q, imm_status* status, std::string* err) {
         release_workspace(*q);
     }
     q->w.reset();
+    q->w2.reset();
     delete q;
     return r;
 }
@@ -427,6 +523,7 @@ void AsyncRunner::finish_err(Query* q, imm_status s) {
     q->done = true;
     if (q->w) (void)hipStreamSynchronize(q->w->st);
     q->w.reset();
+    q->w2.reset();
 }
 
 Query* AsyncRunner::start(imm_graph* g, const imm_params& p, hipStream_t st, uint32_t big_cap) {
@@ -468,7 +565,7 @@ bool AsyncRunner::poll() {
         imm_status s = e == hipSuccess ? IMM_OK : fail(IMM_EDEVICE, "run: device work failed");
         if (s == IMM_OK && q->phase == 0) {
             // sampling round done: finish it, launch the selection
-            s = ws_extend_finish(*q->w, q->g, q->p.seed);
+            s = finish_sampling(*q);
             int gs = 0;
             if (s == IMM_OK)
                 s = ws_select_launch(*q->w, q->p.k, (q->p.flags & IMM_GRAPH_SELECT) != 0, &gs);

@@ -423,6 +423,36 @@ imm_status ws_sync_pool(Workspace& w) {
     return IMM_OK;
 }
 
+imm_status ws_restart_pool(Workspace& w) {
+    hipStream_t st = w.st;
+    w.n_sets = 0;
+    w.p_exact = 0;
+    w.p_ub = 0;
+    w.nseg = 0;
+    w.indexed_sets = 0;
+    HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
+    HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
+    return IMM_OK;
+}
+
+imm_status ws_coverage(Workspace& w, const uint32_t* seeds, uint32_t k, uint64_t* out) {
+    hipStream_t st = w.st;
+    const uint64_t vwords = (uint64_t)w.n / 32 + 1;
+    const uint64_t swords = w.n_sets / 32 + 1;
+    IMM_TRY(grow(w.arena, &w.mark, &w.cap_mark, vwords + swords, 0, st, "coverage bitmaps"));
+    if (!w.cov_count) IMM_TRY(w.arena.alloc((void**)&w.cov_count, 8, "coverage count"));
+    HIP_TRY(hipMemsetAsync(w.mark, 0, (vwords + swords) * 4, st));
+    HIP_TRY(hipMemsetAsync(w.cov_count, 0, 8, st));
+    HIP_TRY(launch_cover_count(w.set_off, w.set_vtx, w.n_sets, seeds, k, w.mark,
+                               w.mark + vwords, w.cov_count, st));
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, w.cov_count, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = c;
+    return IMM_OK;
+}
+
 void ws_note_pool(Workspace& w, uint64_t sets_before) {
     const uint64_t p = *w.hp;
     if (w.n_sets > sets_before)
@@ -502,7 +532,7 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
                     w.inv_set,     w.set_off,    w.set_vtx,   w.covered,     w.slots,
                     w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
                     w.cov_entries, w.n,          k,           w.nseg,        (uint32_t)w.n_sets,
-                    0,             0,            0,           0};
+                    0,             0,            0,           0,             w.update_mode};
     return IMM_OK;
 }
 
