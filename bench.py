@@ -253,6 +253,52 @@ def counter_update_mode(args, imm, torch):
                       "steps": args.steps, "warmup": args.warmup, "workloads": out}))
 
 
+def dense_compare_mode(args, imm, torch):
+    """The adaptive set representation against list-only sets on one
+    workload: time to seeds (median of the timed runs), device memory and
+    the number of bitmap sets; the seeds must not change. A list-only run
+    that does not fit the budget reports its error instead."""
+    import statistics
+
+    import synth
+    name = args.dense_compare
+    spec = synth.WORKLOADS[name]
+    g = synth.make_graph(name)
+    stream = torch.cuda.current_stream()
+    dg = imm.graph_from(g, stream=stream)
+    torch.cuda.synchronize()
+    out, seeds = {}, None
+    for label, fl in (("bitmaps", 0), ("lists", imm.IMM_LIST_SETS)):
+        runs, err = [], None
+        try:
+            for i in range(args.warmup + args.steps):
+                t0 = time.perf_counter()
+                r = imm.imm_run(dg, spec["k"], spec["eps"], spec["ell"], spec["seed"],
+                                flags=imm.IMM_TIMING | fl, stream=stream,
+                                max_device_bytes=args.dense_budget << 30)
+                torch.cuda.synchronize()
+                if i >= args.warmup:
+                    runs.append((time.perf_counter() - t0, r))
+                print(f"[bench] {label} run {i + 1} done", file=sys.stderr, flush=True)
+        except imm.ImmError as e:
+            err = str(e)
+        if err or not runs:
+            out[label] = {"error": err}
+            continue
+        r = runs[-1][1]
+        if seeds is None:
+            seeds = list(r.seeds)
+        assert list(r.seeds) == seeds, f"{label}: seeds changed"
+        out[label] = {"time_to_seeds_ms": statistics.median(t for t, _ in runs) * 1e3,
+                      "phase_ms": {k: r.stats[f"ms_{k}"] for k in
+                                   ("sample", "compact", "index", "select")},
+                      "theta": r.theta, "dense_sets": r.stats["dense_sets"],
+                      "entries": r.stats["entries"], "device_GB": r.stats["device_bytes"] / 1e9}
+    print(json.dumps({"metric": "IMM time to seeds, bitmap vs list sets", "workload": name,
+                      "n": g.n, "m": g.m, "steps": args.steps, "warmup": args.warmup,
+                      "budget_GiB": args.dense_budget, **out}))
+
+
 def _gen_instance(arg):
     import synth
     i, s = arg
@@ -474,6 +520,11 @@ def main():
     ap.add_argument("--saturate", action="store_true",
                     help="served mode: queue every query at t=0 (aggregate throughput) "
                          "instead of Poisson arrivals")
+    ap.add_argument("--dense-compare", default="",
+                    help="a workload: time to seeds with dense sets as bitmaps against "
+                         "every set as a list (IMM_LIST_SETS)")
+    ap.add_argument("--dense-budget", type=int, default=240,
+                    help="dense-compare mode: device memory budget in GiB per run")
     ap.add_argument("--counter-update", default="",
                     help="comma-separated workloads: selection time of an IMM run under "
                          "each counter update (adaptive, decrement-only, recount-only)")
@@ -508,6 +559,8 @@ def main():
         return copy_calibration(torch)
     if args.counter_update:
         return counter_update_mode(args, imm, torch)
+    if args.dense_compare:
+        return dense_compare_mode(args, imm, torch)
     if served is not None:
         return serve_mode(args, imm, served, torch.cuda.current_stream(), torch)
     if batch is not None:

@@ -97,6 +97,13 @@ typedef enum {
  * choice for every step (at most one of the two); results are unchanged. */
 #define IMM_UPDATE_DECREMENT 0x40u
 #define IMM_UPDATE_RECOUNT 0x80u
+/* Adaptive set representation (Section IV-C): an IC RRR set of at least
+ * max(ceil(n / 32), 2048) members is kept as an n-bit vertex bitmap instead
+ * of a member list (the bitmap is then no larger), and its members are
+ * counted and decremented by bitmap column sums. IMM_LIST_SETS (imm_run,
+ * imm_run_batch, server queries, imm_sample) keeps every set as a list.
+ * Results, exported pools and counts are the same either way. */
+#define IMM_LIST_SETS 0x100u
 
 typedef struct imm_graph imm_graph;
 typedef struct imm_result imm_result;
@@ -151,7 +158,8 @@ typedef struct {
     uint32_t select_graphs;  /* with IMM_GRAPH_SELECT: this run's selections
                                 done by launching a captured graph */
     uint32_t select_captures;/* ... of which needed a new capture */
-    uint32_t pad;
+    uint32_t dense_sets;     /* IC: sets of the pool kept as vertex bitmaps
+                                (see IMM_LIST_SETS) */
 } imm_stats;
 
 /* Thread-local description of the last error of this thread. */
@@ -187,9 +195,12 @@ imm_status imm_graph_info(const imm_graph* g, uint32_t* n, uint64_t* m, imm_mode
  * imm_run_batch does; a query submitted while others run is admitted at the
  * next iteration boundary once a slot (at most max_slots queries run at a
  * time) and device memory are free. Admission reserves each query's
- * estimated workspace size (the largest workspace seen so far on its graph,
- * else 64 bytes per vertex plus 1 GiB; max_device_bytes when that is set and
- * smaller) against budget_bytes. Pools stay in device memory. A result is
+ * estimated workspace size (the largest workspace any finished query on its
+ * graph has held, else 64 bytes per vertex plus 1 GiB; max_device_bytes when
+ * that is set and smaller) against budget_bytes, counting the idle
+ * workspaces cached on the server's graphs as well: those caches are freed
+ * when they are what keeps a query out. The first query always runs. Pools
+ * stay in device memory. A result is
  * the same, bit for bit, as imm_run's with the same arguments. Graphs must
  * outlive the server. Server calls are thread-safe.
  *   imm_server_create   budget_bytes > 0, max_slots >= 1

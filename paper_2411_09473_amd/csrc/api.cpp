@@ -302,6 +302,7 @@ imm_status imm_sample(const imm_graph* g, uint64_t seed, uint64_t first_id, uint
         p->ws.reset(new Workspace());
         IMM_TRY(ws_init(*p->ws, g->n, g->device, st, 0));
         IMM_TRY(ws_reset(*p->ws, st, (flags & IMM_TIMING) != 0));
+        p->ws->list_only = (flags & IMM_LIST_SETS) != 0;
         IMM_TRY(ws_extend(*p->ws, g, seed, first_id, count));
         IMM_TRY(ws_sync_pool(*p->ws));
         ws_note_pool(*p->ws, 0);
@@ -325,7 +326,8 @@ imm_status imm_pool_info(const imm_pool* p, uint64_t* n_sets, uint64_t* n_entrie
                          imm_stats* stats) {
     if (!p) return fail(IMM_EINVAL, "pool_info: null pool");
     if (n_sets) *n_sets = p->ws->n_sets;
-    if (n_entries) *n_entries = p->ws->p_exact;
+    // list members plus the members of the sets kept as bitmaps
+    if (n_entries) *n_entries = p->ws->p_exact + p->ws->dense_entries;
     if (stats) *stats = p->stats;
     return IMM_OK;
 }

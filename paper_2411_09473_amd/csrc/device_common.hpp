@@ -148,4 +148,62 @@ __device__ __forceinline__ void wave_segments(uint32_t sz, uint64_t a, uint64_t 
     __syncthreads();
 }
 
+// Column sums of a group of vertex bitmaps ("vertical popcount"), by one
+// workgroup of kColBS threads: the 64 words (2048 vertices) from word w0 on,
+// over the bitmaps src(i) names for i in [0, cnt), cnt <= kColChunk (src
+// returns kEmpty to skip one; it is called alike by a whole wave). Wave s
+// takes i = s, s + 4, ...: each lane adds its word of each bitmap into 11
+// bit-planes (a ripple-carry add of 32 one-bit counts at once, 33 operations
+// instead of 96 for 32 separate counts), and the four waves' counts are
+// summed in LDS (lds: 4 * 2048 words). Thread x gets the sums of the
+// vertices 32 w0 + 8x .. 32 w0 + 8x + 7 in out.
+constexpr uint32_t kColBS = 256;
+constexpr uint32_t kColChunk = 4096;  // at most 1024 bitmaps per wave: 11 planes
+constexpr uint32_t kColPlanes = 11;
+template <class Src>
+__device__ __forceinline__ void col_sums(const uint32_t* bits, uint32_t words, uint32_t w0,
+                                         uint32_t cnt, Src src, uint32_t* lds, uint32_t out[8]) {
+    const uint32_t lane = threadIdx.x % kWave, s = threadIdx.x / kWave;
+    const uint32_t w = w0 + lane;
+    const bool in = w < words;
+    uint32_t pl[kColPlanes];
+#pragma unroll
+    for (uint32_t p = 0; p < kColPlanes; ++p) pl[p] = 0u;
+    // four bitmaps' words in flight per lane
+    for (uint32_t i = s; i < cnt; i += 4 * 4) {
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t ii = i + 4 * u;
+            const uint32_t b = ii < cnt ? src(ii) : kEmpty;
+            x[u] = (b != kEmpty && in) ? bits[(size_t)b * words + w] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            uint32_t c = x[u];
+#pragma unroll
+            for (uint32_t p = 0; p < kColPlanes; ++p) {
+                const uint32_t t = pl[p] & c;
+                pl[p] ^= c;
+                c = t;
+            }
+        }
+    }
+    // bit j of this lane's word: vertex 32 lane + j, at lds[s * 2048 + 64 j + lane]
+#pragma unroll
+    for (uint32_t j = 0; j < 32; ++j) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kColPlanes; ++p) c |= ((pl[p] >> j) & 1u) << p;
+        lds[s * 2048u + 64u * j + lane] = c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t v = 8u * threadIdx.x + q;
+        const uint32_t a = 64u * (v & 31u) + (v >> 5);
+        out[q] = lds[a] + lds[2048u + a] + lds[4096u + a] + lds[6144u + a];
+    }
+}
+
 }  // namespace imm

@@ -93,6 +93,10 @@ struct DevScalars {
     uint32_t ticket_small, ticket_big, ticket_bfs, ticket_huge, pend_n, over_n, defer_n;
     uint32_t retry_n, spare_n, big_flag, err;
     unsigned long long stats[kStCount];
+    // kept across passes (cleared with the workspace): the dense-set cursor
+    // and the dense sets' total size
+    uint32_t dense_n, dense_pad;
+    unsigned long long dense_entries;
 };
 
 // Phase timing with HIP events (phases: 0 sample, 1 compact, 2 index,
@@ -131,9 +135,9 @@ struct Timer {
 struct SelectGraph {
     hipGraphExec_t exec = nullptr;
     const SelectDesc* descs = nullptr;
-    uint32_t nq = 0, kmax = 0, arg_total = 0, sel_total = 0;
+    uint32_t nq = 0, kmax = 0, arg_total = 0, sel_total = 0, dense_total = 0;
     int launch(const SelectDesc* descs, uint32_t nq, uint32_t kmax, uint32_t arg_total,
-               uint32_t sel_total, hipStream_t st, bool* captured);
+               uint32_t sel_total, uint32_t dense_total, hipStream_t st, bool* captured);
     SelectGraph() = default;
     SelectGraph(const SelectGraph&) = delete;
     SelectGraph& operator=(const SelectGraph&) = delete;
@@ -204,6 +208,23 @@ struct Workspace {
     uint32_t huge_slots = 0;
     uint32_t* over = nullptr;  // IC: giant sets that outgrew a bounded queue
     uint64_t cap_ov = 0;
+    // dense sets (IC sets of at least dense_threshold(n) members) as
+    // bitmaps: cap_dense slots of dense_words words, their set ids and sizes,
+    // n_dense in use (as of the last synchronisation); dense_counts[n] their
+    // members' occurrences; dense_list / dense_mark the seed steps' claims.
+    // list_only stores every set as a list.
+    uint32_t* dense_bits = nullptr;
+    uint32_t* dense_sid = nullptr;
+    uint32_t* dense_size = nullptr;
+    uint32_t* dense_list = nullptr;
+    uint64_t cap_dense = 0;
+    uint32_t dense_words = 0;
+    uint64_t n_dense = 0;
+    uint64_t dense_entries = 0;
+    uint32_t* dense_counts = nullptr;
+    uint32_t* dense_mark = nullptr;  // k + 1 entries, then the list cursor
+    uint64_t cap_mark_k = 0;
+    bool list_only = false;
     // coverage of a seed set in this pool (early stopping): a vertex bitmap
     // and a set bitmap (cap_mark words in all), and the count
     uint32_t* mark = nullptr;
@@ -214,6 +235,7 @@ struct Workspace {
     uint64_t p_ub = 0;       // upper bound on the pool size
     double mean_size = 0.0;  // mean set size of the last round (staging estimate)
     uint32_t update_mode = 0;    // SelectDesc::update of this workspace's selections
+    bool pending_multi = false;  // the prepared pass waits for a multi-instance launch
     uint64_t pending_count = 0;  // sets of the sampling pass in flight
     uint64_t pending_lo = 0;
     Timer timer;
@@ -241,6 +263,7 @@ struct imm_graph {
     uint32_t lt_lanes = 2;        // LT: lanes per walk
     bool team_forced = false, big_forced = false, bloom_forced = false, lanes_forced = false;
     double defer_rate = 0.0;  // giant sets per sample seen while tuning
+    double dense_rate = 0.0;  // IC: dense (bitmap) sets per sample seen while tuning
     // mean set size seen while tuning: a fresh workspace's first staging
     // estimate, in place of a pilot batch (0 when tuning did not run)
     double mean_set_hint = 0.0;
@@ -291,8 +314,12 @@ imm_status ws_read_scalars(Workspace& w);
 // Sampling of [id_lo, id_lo + count): the pass is launched without waiting
 // (ws_extend_launch), then, after the stream is synchronised and the
 // scalars read, completed (retries, compaction: ws_extend_finish).
+// multi: everything but the pass itself, which a multi-instance launch then
+// runs (ws_ic_task gives its task, ws_after_multi queues the scalar copy).
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count);
+                            uint64_t count, bool multi = false);
+IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap);
+imm_status ws_after_multi(Workspace& w);
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);
 // Both halves and the synchronisation in between.
 imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
@@ -348,7 +375,8 @@ struct Query;  // one IMM query's state machine (runner.cpp)
 // started (and cancelled) between steps; each finishes independently.
 class BatchRunner {
 public:
-    explicit BatchRunner(hipStream_t main);
+    // multi: IC queries sample together in multi-instance launches
+    explicit BatchRunner(hipStream_t main, bool multi = false);
     ~BatchRunner();
     BatchRunner(const BatchRunner&) = delete;
     BatchRunner& operator=(const BatchRunner&) = delete;
@@ -369,7 +397,18 @@ public:
 
 private:
     void finish_err(Query* q, imm_status s);
+    imm_status multi_pass(const std::vector<Query*>& qs);
     hipStream_t main_;
+    bool multi_ = false;
+    // the multi-instance launch: shared giant-set slots, and the task table,
+    // lane-position prefix and tickets (pinned host copy, device copy)
+    void* multi_buf_ = nullptr;
+    uint64_t multi_cap_ = 0;
+    uint32_t multi_words_ = 0;
+    static constexpr size_t kTaskBytes =
+        kMaxTasks * sizeof(IcTask) + (kMaxTasks + 1 + 3) * sizeof(uint32_t);
+    char* tasks_h_ = nullptr;
+    char* tasks_d_ = nullptr;
     std::vector<Query*> active_, finished_;
     SelectDesc* descs_h_ = nullptr;
     SelectDesc* descs_d_ = nullptr;
@@ -399,6 +438,10 @@ private:
     void finish_err(Query* q, imm_status s);
     std::vector<Query*> active_, finished_;
 };
+// Device bytes held by the idle workspaces cached on g, and freeing them all
+// (returns the bytes freed).
+uint64_t cached_bytes(imm_graph* g);
+uint64_t trim_cache(imm_graph* g);
 // Run queries to completion, advancing them together round by round.
 // streams[q] (may repeat) is the stream query q samples on; `main` carries
 // the batched selection. out[q] receives a result or stays null with

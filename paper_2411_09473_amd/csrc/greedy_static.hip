@@ -186,7 +186,7 @@ imm_status run(uint32_t n, const uint64_t* set_off, const uint32_t* set_vtx, uin
     HIP_STATIC(hipMemcpyAsync(desc_d, &d, sizeof(d), hipMemcpyHostToDevice, st),
                "greedy_static: descriptor copy failed");
     for (uint32_t t = 0; t < k; ++t)
-        HIP_STATIC(launch_select_step(desc_d, 1, t, d.arg_cnt, d.sel_cnt, st),
+        HIP_STATIC(launch_select_step(desc_d, 1, t, d.arg_cnt, d.sel_cnt, 0, st),
                    "greedy_static: seed step launch failed");
     // results: gains land in the first half of the caller's uint64 array
     uint32_t err = 0;

@@ -81,7 +81,32 @@ struct SampleOut {
     uint32_t* retry;       // [count]
     uint32_t* retry_n;
     unsigned long long* stats;  // [kStCount]
+    // IC sets of at least dense_min members are stored as vertex bitmaps
+    // (dense_words words each) instead of member lists: bitmap slot b =
+    // atomicAdd(dense_cursor) (< dense_cap, else the set is listed for a
+    // retry), dense_sid[b] = pool_base + sample index, dense_size[b] = its
+    // size, *dense_entries += its size; its list is empty and its members'
+    // counts are left to a bitmap count after the pass. dense_min =
+    // 0xFFFFFFFF stores every set as a list.
+    uint32_t* dense_bits;
+    uint64_t dense_cap;
+    uint32_t* dense_cursor;
+    uint32_t* dense_sid;
+    uint32_t* dense_size;
+    unsigned long long* dense_entries;
+    uint32_t dense_min;
+    uint32_t dense_words;
+    uint64_t pool_base;
 };
+// Sets of at least max(ceil(n / 32), kDenseMinSize) members are dense: a
+// bitmap of n bits then takes no more room than the member list. Every set
+// that large comes from the large-set kernel (the team kernel's sets hold at
+// most 1024 members), which has the set's bitmap at hand.
+constexpr uint32_t kDenseMinSize = 2048;
+inline uint32_t dense_threshold(uint32_t n) {
+    const uint32_t t = (uint32_t)(((uint64_t)n + 31) / 32);
+    return t > kDenseMinSize ? t : kDenseMinSize;
+}
 
 // Scratch of the large-set kernels: per slot a visited bitmap of `words`
 // uint32 (all zero between samples) and a queue of qcap (<= n) uint32.
@@ -92,6 +117,24 @@ struct BigScratch {
     uint32_t slots;
     uint32_t qcap;
 };
+
+// One instance of a multi-instance IC sampling pass: its graph, its range
+// of sample ids (no list), its outputs (SampleOut: staging, counts, deferred
+// and retry lists), its pending list, and the logical queue capacity of its
+// giant sets (min(n, the shared slots' queue length)). A launch over several
+// tasks numbers their work items one after another; a workgroup that moves
+// to another task's items flushes its statistics and staging chunk first.
+struct IcTask {
+    IcGraphDev g;
+    SampleRange rg;
+    SampleOut o;
+    uint32_t* pend;
+    uint32_t* pend_n;
+    uint32_t qcap;
+    uint32_t pad;
+};
+// Tasks of one multi-instance launch at most.
+constexpr uint32_t kMaxTasks = 64;
 
 // ---- sampling (k_sample_ic.hip, k_sample_lt.hip)
 // IC, first pass: lane-per-root tries over the range (or list); samples that
@@ -115,6 +158,17 @@ hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const Samp
                            uint32_t* ticket, const BigScratch& b, uint32_t block,
                            hipStream_t st);
 uint32_t ic_large_slots(int device, uint32_t block);
+// The same three passes over ntask (<= kMaxTasks) tasks at once: the lane
+// pass over their id ranges (task q's positions are [prefix[q], prefix[q+1]),
+// each range rounded up to whole tickets of kLaneTicket ids), the BFS pass
+// over their pending lists, the giant-set pass over their deferred lists
+// with shared scratch slots b (words and queues sized for the largest task).
+// A giant set whose queue overflows is listed in its task's retry list (to be
+// redone alone). Every list length is read on the device.
+constexpr uint32_t kLaneTicket = 256;
+hipError_t launch_ic_multi(const IcTask* tasks, uint32_t ntask, const uint32_t* prefix,
+                           uint32_t* tickets /* 3, zeroed */, uint32_t team, uint32_t block,
+                           const BigScratch& b, int device, hipStream_t st);
 // LT: one walk per group of `lanes` (1, 2 or 4) lanes; bloom_bits (10, 11 or
 // 12) sizes the per-walk path filter in LDS.
 hipError_t launch_lt_small(const LtGraphDev& g, const SampleRange& r, const SampleOut& o,
@@ -150,6 +204,10 @@ hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, 
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);
+// counts[u] += number of bitmaps b in [b_lo, b_hi) with bit u set (each
+// bitmap `words` words long, counts over n = 32 * words vertices at most).
+hipError_t launch_dense_count(const uint32_t* bits, uint32_t words, uint32_t b_lo, uint32_t b_hi,
+                              uint32_t n, uint32_t* counts, hipStream_t st);
 // *count += number of sets of the pool holding one of seeds[0..k); mark
 // (one bit per vertex) and hit (one bit per set) must be zero before.
 hipError_t launch_cover_count(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t n_sets,
@@ -213,6 +271,21 @@ struct SelectDesc {
     // (recount when they hold more than a quarter of the pool, else
     // decrement), kUpdateDecrement or kUpdateRecount (always that one)
     uint32_t update = 0;
+    // dense sets (bitmaps): n_dense of them, dense_words words each, with
+    // their set ids and sizes; dense_entries their total size. Seed step t
+    // claims the uncovered ones holding its seed and appends them to
+    // dense_list (cursor *dense_list_n; dense_mark[t] is the cursor before
+    // step t's claims). Workgroups [dense_lo, dense_lo + dense_cnt) of the
+    // dense update launch belong to this instance.
+    const uint32_t* dense_bits = nullptr;
+    const uint32_t* dense_sid = nullptr;
+    const uint32_t* dense_size = nullptr;
+    uint32_t* dense_list = nullptr;
+    uint32_t* dense_list_n = nullptr;
+    uint32_t* dense_mark = nullptr;
+    uint64_t dense_entries = 0;
+    uint32_t n_dense = 0, dense_words = 0;
+    uint32_t dense_lo = 0, dense_cnt = 0;
 };
 enum : uint32_t { kUpdateAdaptive = 0, kUpdateDecrement = 1, kUpdateRecount = 2 };
 constexpr uint32_t kMaxSegments = 64;
@@ -225,9 +298,17 @@ uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch);
 // cw = cacc, and the list of vertices with cacc > kHeavyList (*n_heavy zeroed).
 hipError_t launch_select_init(const uint32_t* cacc, uint32_t* cw, uint32_t n, uint32_t* heavy,
                               uint32_t* n_heavy, hipStream_t st);
-// Seed step t (argmax, claim, decrement) of every instance with t < k.
+// Seed step t (argmax, claim, decrement, and with dense_blocks > 0 the
+// bitmap update of the dense sets) of every instance with t < k.
 hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,
-                              uint32_t arg_blocks, uint32_t sel_blocks, hipStream_t st);
+                              uint32_t arg_blocks, uint32_t sel_blocks, uint32_t dense_blocks,
+                              hipStream_t st);
+// Workgroups of the dense update for n_dense bitmaps of `words` words.
+uint32_t dense_blocks(uint32_t n_dense, uint32_t words);
+// cw = cacc (+ dc, the dense sets' counts, when given), and the list of
+// vertices with cacc > kHeavyList (*n_heavy zeroed).
+hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_t* cw,
+                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st);
 
 // ---- misc
 hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,

@@ -215,6 +215,26 @@ __global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_
         atomicAdd(&counts[set_vtx[t]], 1u);
 }
 
+// counts[v] += the number of bitmaps b in [b_lo, b_hi) holding v: workgroup
+// (word block wb, bitmap chunk c) sums the 2048 vertices of word block wb over
+// kColChunk bitmaps of chunk c, then one atomic per vertex with a nonzero sum.
+__global__ __launch_bounds__(kColBS) void dense_count_kernel(const uint32_t* bits, uint32_t words,
+                                                             uint32_t b_lo, uint32_t b_hi,
+                                                             uint32_t n, uint32_t* counts) {
+    __shared__ uint32_t lds[4 * 2048];
+    const uint32_t wblocks = (words + 63) / 64;
+    const uint32_t wb = blockIdx.x % wblocks, c = blockIdx.x / wblocks;
+    const uint32_t i0 = b_lo + c * kColChunk;
+    const uint32_t cnt = min(kColChunk, b_hi - i0);
+    uint32_t out[8];
+    col_sums(bits, words, 64u * wb, cnt, [&](uint32_t i) { return i0 + i; }, lds, out);
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t v = 2048u * wb + 8u * threadIdx.x + q;
+        if (v < n && out[q]) atomicAdd(&counts[v], out[q]);
+    }
+}
+
 // Seeds' bits in a vertex bitmap.
 __global__ __launch_bounds__(256) void mark_seeds_kernel(const uint32_t* seeds, uint32_t k,
                                                          uint32_t* mark) {
@@ -399,6 +419,16 @@ hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* c
     if (P == 0) return hipSuccess;
     hipLaunchKernelGGL(count_entries_kernel, dim3(grid_for(P, 256 * 8, 8192)), dim3(256), 0, st,
                        set_vtx, P, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_count(const uint32_t* bits, uint32_t words, uint32_t b_lo, uint32_t b_hi,
+                              uint32_t n, uint32_t* counts, hipStream_t st) {
+    if (b_hi <= b_lo) return hipSuccess;
+    const uint32_t wblocks = (words + 63) / 64;
+    const uint32_t chunks = (b_hi - b_lo + kColChunk - 1) / kColChunk;
+    hipLaunchKernelGGL(dense_count_kernel, dim3(wblocks * chunks), dim3(kColBS), 0, st, bits,
+                       words, b_lo, b_hi, n, counts);
     return hipGetLastError();
 }
 

@@ -59,6 +59,17 @@ __device__ __forceinline__ uint32_t lds_load(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The task whose positions hold pos: the last q with pre[q] <= pos
+// (pre[0] = 0, non-decreasing, ntask + 1 entries).
+__device__ __forceinline__ uint32_t task_of(const uint32_t* pre, uint32_t ntask, uint32_t pos) {
+    uint32_t lo = 0, hi = ntask;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= pos) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Staging space of one workgroup: the rest of its current chunk.
 struct Stager {
     uint64_t base = 0;
@@ -170,11 +181,12 @@ template <uint32_t BS, uint32_t PAGE>
 __device__ __forceinline__ LevelChunk level_layout(const IcGraphDev& g, const uint32_t* queue,
                                                    uint32_t head, uint32_t nb, uint4* s_ent,
                                                    uint32_t* s_start, uint32_t* s_wsum,
-                                                   uint32_t* edges) {
+                                                   uint32_t* edges,
+                                                   uint32_t qmask = 0xFFFFFFFFu) {
     const uint32_t tid = threadIdx.x;
     uint32_t beg = 0, end = 0;
     if (tid < nb) {
-        const uint32_t v = queue[head + tid];
+        const uint32_t v = queue[(head + tid) & qmask];
         beg = g.off[v];
         end = g.off[v + 1];
     }
@@ -385,17 +397,35 @@ __device__ __forceinline__ void level_sweep(const IcGraphDev& g, uint32_t slo, u
 // are single counters that every wave of the launch updates.
 constexpr uint32_t kLaneRounds = 4;
 
+static_assert(kWave * kLaneRounds == kLaneTicket, "lane tickets");
+
+__device__ __forceinline__ void lane_flush(const SampleOut& o, uint64_t* sets, uint64_t* edges) {
+    const uint64_t a = wave_sum64(*sets), b = wave_sum64(*edges);
+    if (lane_id() == 0) {
+        atomicAdd(&o.stats[kStLaneSets], (unsigned long long)a);
+        atomicAdd(&o.stats[kStLaneEdges], (unsigned long long)b);
+    }
+    *sets = 0;
+    *edges = 0;
+}
+
+// ntask = 0: one instance (the arguments). Otherwise the tasks' positions
+// follow each other (prefix), every ticket inside one task.
 __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRange rg,
                                                         SampleOut o, uint32_t* pend,
-                                                        uint32_t* pend_n, uint32_t* ticket) {
+                                                        uint32_t* pend_n, uint32_t* ticket,
+                                                        const IcTask* tasks, uint32_t ntask,
+                                                        const uint32_t* prefix) {
     __shared__ uint32_t s_tk, s_np;
     __shared__ uint32_t s_pend[kWave * kLaneRounds];
     __shared__ unsigned long long s_chunk;
     const uint32_t lane = threadIdx.x;
-    const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
+    uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     Stager sg;
     uint64_t st_sets = 0, st_edges = 0;  // lane-partial
-    const uint32_t total = rg.list ? *rg.list_n : rg.count;
+    uint32_t total = ntask ? 0u : (rg.list ? *rg.list_n : rg.count);
+    const uint32_t end = ntask ? prefix[ntask] : total;
+    uint32_t cur = ntask, base = 0;  // the task in hand (ntask: none yet)
     for (;;) {
         if (lane == 0) {
             s_tk = atomicAdd(ticket, kWave * kLaneRounds);
@@ -404,10 +434,27 @@ __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRang
         __syncthreads();
         const uint32_t ticket_pos = s_tk;
         __syncthreads();
-        if (ticket_pos >= total) break;
+        if (ticket_pos >= end) break;
+        if (ntask) {
+            const uint32_t q = task_of(prefix, ntask, ticket_pos);
+            if (q != cur) {
+                if (cur != ntask) lane_flush(o, &st_sets, &st_edges);
+                cur = q;
+                g = tasks[q].g;
+                rg = tasks[q].rg;
+                o = tasks[q].o;
+                pend = tasks[q].pend;
+                pend_n = tasks[q].pend_n;
+                k0 = (uint32_t)rg.seed;
+                k1 = (uint32_t)(rg.seed >> 32);
+                sg = Stager{};
+                base = prefix[q];
+                total = rg.count;
+            }
+        }
 
         for (uint32_t round = 0; round < kLaneRounds; ++round) {
-            const uint32_t base_pos = ticket_pos + round * kWave;
+            const uint32_t base_pos = ticket_pos - base + round * kWave;
             if (base_pos >= total) break;
             const uint32_t my_pos = base_pos + lane;
             const bool valid = my_pos < total;
@@ -468,12 +515,7 @@ __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRang
         }
         __syncthreads();
     }
-    st_sets = wave_sum64(st_sets);
-    st_edges = wave_sum64(st_edges);
-    if (lane == 0) {
-        atomicAdd(&o.stats[kStLaneSets], (unsigned long long)st_sets);
-        atomicAdd(&o.stats[kStLaneEdges], (unsigned long long)st_edges);
-    }
+    if (cur != ntask || ntask == 0) lane_flush(o, &st_sets, &st_edges);
 }
 
 // ------------------------------------------------------------------ ic_bfs
@@ -505,11 +547,45 @@ __device__ __forceinline__ void team_insert(uint32_t u, uint32_t* hash, uint32_t
     *s_over = 1u;
 }
 
+// Work-item lists of several tasks as one: s_pre[q] = the items of tasks
+// before q (list lengths read on the device), s_pre[ntask] = all of them.
+__device__ __forceinline__ void list_prefix(const IcTask* tasks, uint32_t ntask, bool deferred,
+                                            uint32_t* s_pre) {
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (uint32_t q = 0; q < ntask; ++q) {
+            s_pre[q] = a;
+            a += deferred ? *tasks[q].o.defer_n : *tasks[q].pend_n;
+        }
+        s_pre[ntask] = a;
+    }
+    __syncthreads();
+}
+
+// Per-thread partial statistics of a sampling pass, flushed into a task's
+// counters (every thread of the workgroup calls it alike).
+__device__ __forceinline__ void stats_flush(const SampleOut& o, bool big, uint64_t* sets,
+                                            uint64_t* entries, uint64_t* edges, uint64_t* live) {
+    const uint64_t a = wave_sum64(*sets), b = wave_sum64(*entries), c = wave_sum64(*edges),
+                   d = wave_sum64(*live);
+    if (threadIdx.x % kWave == 0) {
+        atomicAdd(&o.stats[big ? kStBigSets : kStMainSets], (unsigned long long)a);
+        atomicAdd(&o.stats[big ? kStBigEntries : kStMainEntries], (unsigned long long)b);
+        atomicAdd(&o.stats[big ? kStBigEdges : kStMainEdges], (unsigned long long)c);
+        atomicAdd(&o.stats[big ? kStBigLive : kStMainLive], (unsigned long long)d);
+    }
+    *sets = *entries = *edges = *live = 0;
+}
+
+// ntask = 0: one instance (the arguments). Otherwise the pending lists of
+// the tasks, one after another.
 template <uint32_t TEAM>
 __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, SampleRange rg,
                                                               SampleOut o, const uint32_t* pend,
                                                               const uint32_t* pend_n,
-                                                              uint32_t* ticket) {
+                                                              uint32_t* ticket,
+                                                              const IcTask* tasks,
+                                                              uint32_t ntask) {
     using T = Team<TEAM>;
     constexpr uint32_t BS = T::BS;
     __shared__ uint32_t hash[T::HSIZE];
@@ -520,14 +596,17 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
     __shared__ uint32_t s_wsum[2 * TEAM];
     __shared__ uint32_t s_size, s_over, s_tk;
     __shared__ unsigned long long s_chunk;
+    __shared__ uint32_t s_pre[kMaxTasks + 1];
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
+    uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     for (uint32_t i = tid; i < T::HSIZE; i += BS) hash[i] = kEmpty;
     for (uint32_t i = tid; i < T::PAGE / 32; i += BS) s_start[i] = 0u;
     Stager sg;
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;  // thread-partial
-    const uint32_t total = *pend_n;
+    if (ntask) list_prefix(tasks, ntask, false, s_pre);
+    const uint32_t total = ntask ? s_pre[ntask] : *pend_n;
+    uint32_t cur = ntask;  // the task in hand (ntask: none yet)
 
     for (;;) {
         if (tid == 0) s_tk = atomicAdd(ticket, 1u);
@@ -535,7 +614,23 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
         const uint32_t pos = s_tk;
         __syncthreads();
         if (pos >= total) break;
-        const uint32_t idx = pend[pos];
+        uint32_t lpos = pos;
+        if (ntask) {
+            const uint32_t q = task_of(s_pre, ntask, pos);
+            if (q != cur) {
+                if (cur != ntask) stats_flush(o, false, &st_sets, &st_entries, &st_edges, &st_live);
+                cur = q;
+                g = tasks[q].g;
+                rg = tasks[q].rg;
+                o = tasks[q].o;
+                pend = tasks[q].pend;
+                k0 = (uint32_t)rg.seed;
+                k1 = (uint32_t)(rg.seed >> 32);
+                sg = Stager{};
+            }
+            lpos = pos - s_pre[q];
+        }
+        const uint32_t idx = pend[lpos];
         const uint64_t s = rg.id_lo + idx;
         const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
         if (tid == 0) {
@@ -614,39 +709,47 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
         }
         __syncthreads();
     }
-    st_sets = wave_sum64(st_sets);
-    st_entries = wave_sum64(st_entries);
-    st_edges = wave_sum64(st_edges);
-    st_live = wave_sum64(st_live);
-    if (tid % kWave == 0) {
-        atomicAdd(&o.stats[kStMainSets], (unsigned long long)st_sets);
-        atomicAdd(&o.stats[kStMainEntries], (unsigned long long)st_entries);
-        atomicAdd(&o.stats[kStMainEdges], (unsigned long long)st_edges);
-        atomicAdd(&o.stats[kStMainLive], (unsigned long long)st_live);
-    }
+    if (cur != ntask || ntask == 0)
+        stats_flush(o, false, &st_sets, &st_entries, &st_edges, &st_live);
 }
 
 // ---------------------------------------------------------------- ic_large
 
 template <uint32_t kBigBlock>
+// ntask = 0: one instance (the arguments). Otherwise the deferred lists of
+// the tasks, one after another, with b's slots sized for the largest task; a
+// set that overflows its queue goes to its task's retry list.
 __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large_kernel(IcGraphDev g, SampleRange rg,
                                                              SampleOut o, const uint32_t* list,
                                                              const uint32_t* list_n,
                                                              uint32_t* fail, uint32_t* fail_n,
                                                              uint32_t* over, uint32_t* over_n,
-                                                             uint32_t* ticket, BigScratch b) {
+                                                             uint32_t* ticket, BigScratch b,
+                                                             const IcTask* tasks, uint32_t ntask) {
     __shared__ uint4 s_ent[kBigBlock];
     __shared__ uint32_t s_start[kLargePage / 32];
     __shared__ uint32_t s_lbuf[kBigBlock / kWave * kLargeLiveBuf];
     __shared__ uint32_t s_wsum[2 * kBigBlock / kWave];
-    __shared__ uint32_t s_size, s_i;
+    __shared__ uint32_t s_size, s_i, s_b, s_ovf;
     __shared__ unsigned long long s_off;
+    __shared__ uint32_t s_pre[kMaxTasks + 1];
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
+    uint32_t k0 = (uint32_t)rg.seed, k1 = (uint32_t)(rg.seed >> 32);
     uint32_t* bm = b.bitmaps + (size_t)blockIdx.x * b.words;
     uint32_t* q = b.queues + (size_t)blockIdx.x * b.qcap;
-    const uint32_t cnt = *list_n;
+    // this instance's bitmap words and queue capacity (the slot may be larger)
+    uint32_t words = b.words, qcap = b.qcap;
+    // A bounded queue of a power-of-two size is used as a ring when a set
+    // too large for it can still be stored: as a bitmap, whose members need
+    // no list. The BFS then only needs its frontier (the entries not yet
+    // swept) to fit; a set that ends larger than the queue must be dense,
+    // else it goes to the full-size pass like one whose frontier overflows.
+    bool ring = o.dense_min != 0xFFFFFFFFu && qcap < g.n && (qcap & (qcap - 1)) == 0;
+    uint32_t qmask = ring ? qcap - 1 : 0xFFFFFFFFu;
+    if (ntask) list_prefix(tasks, ntask, true, s_pre);
+    const uint32_t cnt = ntask ? s_pre[ntask] : *list_n;
+    uint32_t cur = ntask;  // the task in hand (ntask: none yet)
     uint64_t st_sets = 0, st_entries = 0, st_edges = 0, st_live = 0;
     for (uint32_t i = tid; i < kLargePage / 32; i += kBigBlock) s_start[i] = 0u;
 
@@ -656,7 +759,30 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
         const uint32_t li = s_i;
         __syncthreads();
         if (li >= cnt) break;
-        const uint32_t idx = list[li];
+        uint32_t lpos = li;
+        if (ntask) {
+            const uint32_t tq = task_of(s_pre, ntask, li);
+            if (tq != cur) {
+                if (cur != ntask) stats_flush(o, true, &st_sets, &st_entries, &st_edges, &st_live);
+                cur = tq;
+                g = tasks[tq].g;
+                rg = tasks[tq].rg;
+                o = tasks[tq].o;
+                list = o.defer;
+                fail = o.retry;
+                fail_n = o.retry_n;
+                over = o.retry;
+                over_n = o.retry_n;
+                k0 = (uint32_t)rg.seed;
+                k1 = (uint32_t)(rg.seed >> 32);
+                words = (g.n + 31) / 32;
+                qcap = tasks[tq].qcap;
+                ring = o.dense_min != 0xFFFFFFFFu && qcap < g.n && (qcap & (qcap - 1)) == 0;
+                qmask = ring ? qcap - 1 : 0xFFFFFFFFu;
+            }
+            lpos = li - s_pre[tq];
+        }
+        const uint32_t idx = list[lpos];
         const uint64_t s = rg.id_lo + idx;
         const uint32_t slo = (uint32_t)s, shi = (uint32_t)(s >> 32);
         if (tid == 0) {
@@ -664,6 +790,7 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
             q[0] = root;
             atomicOr(&bm[root >> 5], 1u << (root & 31));
             s_size = 1;
+            s_ovf = 0;
         }
         __syncthreads();
 
@@ -671,8 +798,8 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
         bool overflow = false;
         while (head < size) {
             const uint32_t nb = min(kBigBlock, size - head);
-            const LevelChunk ch = level_layout<kBigBlock, kLargePage>(g, q, head, nb, s_ent,
-                                                                      s_start, s_wsum, &my_edges);
+            const LevelChunk ch = level_layout<kBigBlock, kLargePage>(
+                g, q, head, nb, s_ent, s_start, s_wsum, &my_edges, qmask);
             __syncthreads();
             level_sweep<kBigBlock, kLargePage, (kBigBlock < 1024), kLargeLiveBuf>(
                 g, slo, shi, k0, k1, s_ent, s_start, s_lbuf + (tid / kWave) * kLargeLiveBuf, ch,
@@ -688,7 +815,14 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
                     for (uint32_t x = 0; x < 4; ++x) {
                         if (!((old[x] >> (u[x] & 31)) & 1u)) {
                             const uint32_t pos = atomicAdd(&s_size, 1u);
-                            if (pos < b.qcap) q[pos] = u[x];
+                            // ring: the chunk being swept is already in LDS,
+                            // so positions up to head + qcap - 1 are free
+                            if (ring) {
+                                if (pos - head < qcap) q[pos & qmask] = u[x];
+                                else s_ovf = 1u;
+                            } else if (pos < qcap) {
+                                q[pos] = u[x];
+                            }
                         }
                     }
                 },
@@ -696,17 +830,56 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
             __syncthreads();
             head += nb;
             size = s_size;
-            overflow = size > b.qcap;
+            overflow = ring ? s_ovf != 0u : size > qcap;
             __syncthreads();
             if (overflow) break;
         }
+        // a ring that wrapped lists only its last entries: such a set is
+        // stored as a bitmap, or else redone with a full-size queue
+        if (!overflow && size > qcap && size < o.dense_min) overflow = true;
 
         if (overflow) {
             // the queue no longer lists every visited vertex: clear the whole
             // bitmap, and leave the sample to the pass with full-size queues
-            for (uint32_t i = tid; i < b.words; i += kBigBlock)
+            for (uint32_t i = tid; i < words; i += kBigBlock)
                 __hip_atomic_store(&bm[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (tid == 0) over[atomicAdd(over_n, 1u)] = idx;
+            __syncthreads();
+            continue;
+        }
+
+        if (size >= o.dense_min) {
+            // a dense set: its visited bitmap is the set; it goes to a bitmap
+            // slot (read with device-scope loads, which skip the CU cache the
+            // atomics never updated) and the slot's bitmap is cleared whole
+            if (tid == 0) s_b = atomicAdd(o.dense_cursor, 1u);
+            __syncthreads();
+            const uint32_t slot = s_b;
+            const bool ok = slot < o.dense_cap;
+            uint32_t* dst = o.dense_bits + (ok ? (size_t)slot * o.dense_words : 0);
+            for (uint32_t i = tid; i < words; i += kBigBlock) {
+                if (ok)
+                    dst[i] = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bm[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (tid == 0) {
+                if (ok) {
+                    o.dense_sid[slot] = (uint32_t)(o.pool_base + idx);
+                    o.dense_size[slot] = size;
+                    atomicAdd(o.dense_entries, (unsigned long long)size);
+                    o.stage_off[idx] = 0;
+                    o.sizes[idx] = 0;
+                    st_sets += 1;
+                    st_entries += size;
+                } else {
+                    fail[atomicAdd(fail_n, 1u)] = idx;
+                }
+            }
+            if (ok) {
+                st_edges += my_edges;
+                st_live += my_live;
+            }
             __syncthreads();
             continue;
         }
@@ -739,16 +912,8 @@ __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large
         }
         __syncthreads();
     }
-    st_edges = wave_sum64(st_edges);
-    st_live = wave_sum64(st_live);
-    if (tid % kWave == 0) {
-        atomicAdd(&o.stats[kStBigEdges], (unsigned long long)st_edges);
-        atomicAdd(&o.stats[kStBigLive], (unsigned long long)st_live);
-    }
-    if (tid == 0) {
-        atomicAdd(&o.stats[kStBigSets], (unsigned long long)st_sets);
-        atomicAdd(&o.stats[kStBigEntries], (unsigned long long)st_entries);
-    }
+    if (cur != ntask || ntask == 0)
+        stats_flush(o, true, &st_sets, &st_entries, &st_edges, &st_live);
 }
 
 int cu_count(int device) {
@@ -774,7 +939,7 @@ hipError_t launch_ic_lane(const IcGraphDev& g, const SampleRange& r, const Sampl
     if (grid > need) grid = need;
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(ic_lane_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, pend, pend_n,
-                       ticket);
+                       ticket, (const IcTask*)nullptr, 0u, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -787,15 +952,15 @@ hipError_t launch_ic_bfs(const IcGraphDev& g, const SampleRange& r, const Sample
     switch (team) {
         case 1:
             hipLaunchKernelGGL(ic_bfs_kernel<1>, dim3(grid), dim3(kWave), 0, st, g, r, o, pend,
-                               pend_n, ticket);
+                               pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         case 2:
             hipLaunchKernelGGL(ic_bfs_kernel<2>, dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
-                               pend, pend_n, ticket);
+                               pend, pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         case 4:
             hipLaunchKernelGGL(ic_bfs_kernel<4>, dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
-                               pend, pend_n, ticket);
+                               pend, pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         default:
             return hipErrorInvalidValue;
@@ -818,10 +983,57 @@ hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const Samp
     if (b.qcap < g.n && (over == nullptr || over_n == nullptr)) return hipErrorInvalidValue;
     if (block == 256)
         hipLaunchKernelGGL(ic_large_kernel<256>, dim3(b.slots), dim3(256), 0, st, g, r, o, list,
-                           list_n, fail, fail_n, over, over_n, ticket, b);
+                           list_n, fail, fail_n, over, over_n, ticket, b, (const IcTask*)nullptr,
+                           0u);
     else if (block == 1024)
         hipLaunchKernelGGL(ic_large_kernel<1024>, dim3(b.slots), dim3(1024), 0, st, g, r, o,
-                           list, list_n, fail, fail_n, over, over_n, ticket, b);
+                           list, list_n, fail, fail_n, over, over_n, ticket, b,
+                           (const IcTask*)nullptr, 0u);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_multi(const IcTask* tasks, uint32_t ntask, const uint32_t* prefix,
+                           uint32_t* tickets, uint32_t team, uint32_t block, const BigScratch& b,
+                           int device, hipStream_t st) {
+    if (ntask == 0 || ntask > kMaxTasks || b.slots == 0 || b.qcap == 0) return hipErrorInvalidValue;
+    // the per-task arguments come from the table; these only fill the slots
+    const IcGraphDev g{};
+    const SampleRange r{};
+    const SampleOut o{};
+    hipLaunchKernelGGL(ic_lane_kernel, dim3(ic_small_grid(device)), dim3(kWave), 0, st, g, r, o,
+                       (uint32_t*)nullptr, (uint32_t*)nullptr, tickets, tasks, ntask, prefix);
+    const uint32_t grid = ic_bfs_grid(device, team);
+    switch (team) {
+        case 1:
+            hipLaunchKernelGGL(ic_bfs_kernel<1>, dim3(grid), dim3(kWave), 0, st, g, r, o,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
+                               tasks, ntask);
+            break;
+        case 2:
+            hipLaunchKernelGGL(ic_bfs_kernel<2>, dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
+                               tasks, ntask);
+            break;
+        case 4:
+            hipLaunchKernelGGL(ic_bfs_kernel<4>, dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
+                               tasks, ntask);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    if (block == 256)
+        hipLaunchKernelGGL(ic_large_kernel<256>, dim3(b.slots), dim3(256), 0, st, g, r, o,
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                           (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                           tickets + 2, b, tasks, ntask);
+    else if (block == 1024)
+        hipLaunchKernelGGL(ic_large_kernel<1024>, dim3(b.slots), dim3(1024), 0, st, g, r, o,
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                           (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                           tickets + 2, b, tasks, ntask);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -67,6 +67,14 @@ struct SelView {
     uint32_t n, k, nseg, n_sets;
     uint32_t arg_lo, arg_cnt, sel_lo, sel_cnt;
     uint32_t update;
+    const IMM_GLOBAL uint32_t* dense_bits;
+    const IMM_GLOBAL uint32_t* dense_sid;
+    const IMM_GLOBAL uint32_t* dense_size;
+    IMM_GLOBAL uint32_t* dense_list;
+    IMM_GLOBAL uint32_t* dense_list_n;
+    IMM_GLOBAL uint32_t* dense_mark;
+    uint64_t dense_entries;
+    uint32_t n_dense, dense_words;
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -96,7 +104,9 @@ __device__ __forceinline__ SelView view_of(const SelectDesc& d) {
                    glb(d.chunks),  glb(d.chunk_n), d.chunk_cap,    glb(d.cov_entries),
                    d.n,            d.k,            d.nseg,         d.n_sets,
                    d.arg_lo,       d.arg_cnt,      d.sel_lo,       d.sel_cnt,
-                   d.update};
+                   d.update,       glb(d.dense_bits), glb(d.dense_sid), glb(d.dense_size),
+                   glb(d.dense_list), glb(d.dense_list_n), glb(d.dense_mark), d.dense_entries,
+                   d.n_dense,      d.dense_words};
 }
 
 // Device-scope relaxed atomics on global memory (what atomicAdd and friends do).
@@ -122,22 +132,26 @@ __device__ __forceinline__ uint64_t vkey(uint32_t c, uint32_t v) {
 
 // The instance whose block range [lo, lo + cnt) holds block b (ranges are
 // ascending and disjoint); nq when none does.
+// kind: 0 the claim and decrement launches, 1 argmax, 2 the dense update.
 __device__ __forceinline__ uint32_t find_inst(const SelectDesc* d, uint32_t nq, uint32_t b,
-                                              bool argmax) {
+                                              int kind) {
+    auto lo_of = [&](uint32_t q) {
+        return kind == 1 ? d[q].arg_lo : (kind == 2 ? d[q].dense_lo : d[q].sel_lo);
+    };
     uint32_t lo = 0, hi = nq;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if ((argmax ? d[mid].arg_lo : d[mid].sel_lo) <= b) lo = mid; else hi = mid;
+        if (lo_of(mid) <= b) lo = mid; else hi = mid;
     }
-    const uint32_t l = argmax ? d[lo].arg_lo : d[lo].sel_lo;
-    const uint32_t c = argmax ? d[lo].arg_cnt : d[lo].sel_cnt;
+    const uint32_t l = lo_of(lo);
+    const uint32_t c = kind == 1 ? d[lo].arg_cnt : (kind == 2 ? d[lo].dense_cnt : d[lo].sel_cnt);
     return (b >= l && b < l + c) ? lo : nq;
 }
 
 __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs, uint32_t nq,
                                                         uint32_t t) {
     __shared__ uint64_t s_w[kArgBS / kWave];
-    const uint32_t q = find_inst(descs, nq, blockIdx.x, true);
+    const uint32_t q = find_inst(descs, nq, blockIdx.x, 1);
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
@@ -181,6 +195,8 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
         uint64_t b = s_w[0];
         for (uint32_t x = 1; x < kArgBS / kWave; ++x) b = s_w[x] > b ? s_w[x] : b;
         g_max64(&d.slots[(uint64_t)t * kArgSlots + blk % kArgSlots], (unsigned long long)b);
+        // the dense claims of step t start where those of the earlier steps end
+        if (blk == 0 && d.n_dense) d.dense_mark[t] = *d.dense_list_n;
     }
 }
 
@@ -193,7 +209,7 @@ __device__ __forceinline__ uint64_t slots_max(const IMM_GLOBAL unsigned long lon
 
 __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs, uint32_t nq,
                                                          uint32_t t) {
-    const uint32_t q = find_inst(descs, nq, blockIdx.x, false);
+    const uint32_t q = find_inst(descs, nq, blockIdx.x, 0);
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
@@ -273,6 +289,30 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
                     store_chunk(d.chunks + (d.chunk_cap - 1 - (pos + c)), a + o,
                                 (uint32_t)(sz - o < kWave ? sz - o : kWave));
                 }
+            }
+        }
+    }
+    // dense sets: one bit test per uncovered bitmap; the claimed ones are
+    // listed for the dense update
+    for (uint32_t b0 = blk * kClaimBS; b0 < d.n_dense; b0 += d.sel_cnt * kClaimBS) {
+        const uint32_t b = b0 + threadIdx.x;
+        bool claimed = false;
+        if (b < d.n_dense) {
+            const uint32_t wv = d.dense_bits[(size_t)b * d.dense_words + (v >> 5)];
+            if ((wv >> (v & 31)) & 1u) {
+                const uint32_t j = d.dense_sid[b];
+                const uint32_t bit = 1u << (j & 31);
+                claimed = !(g_or(&d.covered[j >> 5], bit) & bit);
+            }
+        }
+        const uint64_t cm = __ballot(claimed);
+        if (cm) {
+            uint32_t base = 0;
+            if (lane == 0) base = g_add(d.dense_list_n, (uint32_t)__popcll(cm));
+            base = __shfl(base, 0, kWave);
+            if (claimed) {
+                d.dense_list[base + (uint32_t)__popcll(cm & lane_mask)] = b;
+                cov += d.dense_size[b];
             }
         }
     }
@@ -443,12 +483,12 @@ __device__ void recount_all(const SelView& d, uint32_t blk, uint32_t* lds_off,
 __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* descs, uint32_t nq,
                                                            uint32_t t) {
     __shared__ uint32_t h_key[kAggSize], h_cnt[kAggSize];
-    const uint32_t q = find_inst(descs, nq, blockIdx.x, false);
+    const uint32_t q = find_inst(descs, nq, blockIdx.x, 0);
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
-    const uint64_t pool = d.set_off[d.n_sets];
+    const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
     if (d.update == kUpdateRecount ||
         (d.update == kUpdateAdaptive && d.cov_entries[t] * 4ull > pool)) {
         recount_all(d, blk, h_key, h_cnt);
@@ -504,12 +544,59 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
 
 // cw = cacc; vertices with long index lists are appended to heavy (one
 // atomic per wave).
-__global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, uint32_t* cw,
-                                                          uint32_t n, uint32_t* heavy,
-                                                          uint32_t* n_heavy) {
+// The dense sets' part of seed step t's counter update, after the list part
+// (decrement_kernel): when the step recounts, every count gains the bitmap
+// sum of the uncovered dense sets; otherwise it loses that of the dense sets
+// the step claimed. Workgroup (word block wb, bitmap chunk c) of the
+// instance covers 2048 vertices and kColChunk bitmaps; chosen seeds keep
+// their sentinel.
+__global__ __launch_bounds__(kColBS) void dense_update_kernel(const SelectDesc* descs,
+                                                              uint32_t nq, uint32_t t) {
+    __shared__ uint32_t lds[4 * 2048];
+    const uint32_t q = find_inst(descs, nq, blockIdx.x, 2);
+    if (q == nq) return;
+    const SelView d = view_of(descs[q]);
+    if (t >= d.k || d.n_dense == 0) return;
+    const uint32_t blk = blockIdx.x - descs[q].dense_lo;
+    const uint32_t wblocks = (d.dense_words + 63) / 64;
+    const uint32_t wb = blk % wblocks, c = blk / wblocks;
+    const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
+    const bool recount = d.update == kUpdateRecount ||
+                         (d.update == kUpdateAdaptive && d.cov_entries[t] * 4ull > pool);
+    const uint32_t lo = recount ? 0u : d.dense_mark[t];
+    const uint32_t hi = recount ? d.n_dense : *d.dense_list_n;
+    const uint32_t i0 = lo + c * kColChunk;
+    if (i0 >= hi) return;
+    const uint32_t cnt = min(kColChunk, hi - i0);
+    uint32_t out[8];
+    if (recount) {
+        col_sums((const uint32_t*)d.dense_bits, d.dense_words, 64u * wb, cnt,
+                 [&](uint32_t i) {
+                     const uint32_t b = i0 + i;
+                     const uint32_t j = d.dense_sid[b];
+                     return ((d.covered[j >> 5] >> (j & 31)) & 1u) ? kEmpty : b;
+                 },
+                 lds, out);
+    } else {
+        col_sums((const uint32_t*)d.dense_bits, d.dense_words, 64u * wb, cnt,
+                 [&](uint32_t i) { return d.dense_list[i0 + i]; }, lds, out);
+    }
+#pragma unroll
+    for (uint32_t x = 0; x < 8; ++x) {
+        const uint32_t u = 2048u * wb + 8u * threadIdx.x + x;
+        if (u >= d.n || out[x] == 0) continue;
+        if (d.cw[u] == kSelected) continue;
+        if (recount) g_add(&d.cw[u], out[x]);
+        else g_sub(&d.cw[u], out[x]);
+    }
+}
+
+__global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, const uint32_t* dc,
+                                                          uint32_t* cw, uint32_t n,
+                                                          uint32_t* heavy, uint32_t* n_heavy) {
     const uint32_t u = blockIdx.x * 256 + threadIdx.x;
     const uint32_t c = u < n ? cacc[u] : 0u;
-    if (u < n) cw[u] = c;
+    if (u < n) cw[u] = c + (dc ? dc[u] : 0u);
     const bool h = c > kHeavyList;
     const uint64_t m = __ballot(h);
     if (!m) return;
@@ -540,17 +627,31 @@ uint32_t select_blocks(int device, uint64_t n_sets, uint32_t batch) {
 
 hipError_t launch_select_init(const uint32_t* cacc, uint32_t* cw, uint32_t n, uint32_t* heavy,
                               uint32_t* n_heavy, hipStream_t st) {
+    return launch_select_init2(cacc, nullptr, cw, n, heavy, n_heavy, st);
+}
+
+hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_t* cw,
+                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(select_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cacc, cw, n,
-                       heavy, n_heavy);
+    hipLaunchKernelGGL(select_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cacc, dc, cw,
+                       n, heavy, n_heavy);
     return hipGetLastError();
 }
 
+uint32_t dense_blocks(uint32_t n_dense, uint32_t words) {
+    if (n_dense == 0) return 0;
+    return ((words + 63) / 64) * ((n_dense + kColChunk - 1) / kColChunk);
+}
+
 hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,
-                              uint32_t arg_blocks, uint32_t sel_blocks, hipStream_t st) {
+                              uint32_t arg_blocks, uint32_t sel_blocks, uint32_t dense_blocks,
+                              hipStream_t st) {
     hipLaunchKernelGGL(argmax_kernel, dim3(arg_blocks), dim3(kArgBS), 0, st, descs, nq, t);
     hipLaunchKernelGGL(claim_kernel, dim3(sel_blocks), dim3(kClaimBS), 0, st, descs, nq, t);
     hipLaunchKernelGGL(decrement_kernel, dim3(sel_blocks), dim3(kDecBS), 0, st, descs, nq, t);
+    if (dense_blocks)
+        hipLaunchKernelGGL(dense_update_kernel, dim3(dense_blocks), dim3(kColBS), 0, st, descs,
+                           nq, t);
     return hipGetLastError();
 }
 

@@ -117,6 +117,7 @@ struct Query {
     // whether that work is a sampling round (0) or a selection (1)
     hipEvent_t ev = nullptr;
     int phase = 0;
+    bool multi = false;  // BatchRunner: IC sampling passes join the multi-instance launch
     ~Query() {
         if (ev) (void)hipEventDestroy(ev);
     }
@@ -190,6 +191,8 @@ imm_status start_query(Query& q, uint32_t big_cap) {
     IMM_TRY(acquire_workspace(q, q.w, big_cap));
     if (early) IMM_TRY(acquire_workspace(q, q.w2, big_cap));
     q.w->update_mode = update;
+    q.w->list_only = (q.p.flags & IMM_LIST_SETS) != 0;
+    if (q.w2) q.w2->list_only = q.w->list_only;
     q.r.reset(new imm_result());
     q.r->k = q.p.k;
     q.eps_p = std::sqrt(2.0) * q.p.epsilon;
@@ -199,7 +202,8 @@ imm_status start_query(Query& q, uint32_t big_cap) {
     return IMM_OK;
 }
 
-// This iteration's target, and its sampling launched on the query's stream.
+// This iteration's target, and its sampling launched on the query's stream
+// (for a query in the multi-instance launch, only prepared).
 imm_status begin_iteration(Query& q) {
     double tf;
     if (q.sched == kSchedEarly) {
@@ -235,11 +239,11 @@ imm_status begin_iteration(Query& q) {
         const uint64_t used = w.n_sets;
         IMM_TRY(ws_restart_pool(w));
         q.before = 0;
-        return ws_extend_launch(w, q.g, q.p.seed, used, target);
+        return ws_extend_launch(w, q.g, q.p.seed, used, target, q.multi);
     }
     q.before = w.n_sets;
     return ws_extend_launch(w, q.g, q.p.seed, w.n_sets,
-                            w.n_sets < target ? target - w.n_sets : 0);
+                            w.n_sets < target ? target - w.n_sets : 0, q.multi);
 }
 
 // After the round's sampling: retries and compaction of the pool (pools).
@@ -313,7 +317,12 @@ imm_status end_iteration(Query& q) {
         r.has_pool = true;
     }
     q.done = true;
-    q.bytes = w.arena.used;
+    q.bytes = w.arena.used + (q.w2 ? q.w2->arena.used : 0);
+    // the largest workspace a query on this graph has needed (the server's
+    // admission estimate)
+    uint64_t prev = q.g->peak_bytes.load();
+    while (q.bytes > prev && !q.g->peak_bytes.compare_exchange_weak(prev, q.bytes)) {
+    }
     return IMM_OK;
 }
 
@@ -321,10 +330,13 @@ imm_status end_iteration(Query& q) {
 
 // ------------------------------------------------------------ BatchRunner --
 
-BatchRunner::BatchRunner(hipStream_t main) : main_(main) {}
+BatchRunner::BatchRunner(hipStream_t main, bool multi) : main_(main), multi_(multi) {}
 
 BatchRunner::~BatchRunner() {
     for (auto* q : active_) delete q;
+    if (multi_buf_) (void)hipFree(multi_buf_);
+    if (tasks_h_) (void)hipHostFree(tasks_h_);
+    if (tasks_d_) (void)hipFree(tasks_d_);
     if (descs_h_) (void)hipHostFree(descs_h_);
     if (descs_d_) (void)hipFree(descs_d_);
     if (ev_a_) (void)hipEventDestroy(ev_a_);
@@ -336,6 +348,12 @@ Query* BatchRunner::start(imm_graph* g, const imm_params& p, hipStream_t st, uin
     q->g = g;
     q->p = p;
     q->st = st;
+    // IC queries sample together in one multi-instance launch on the main
+    // stream (an early-stopping query's second pool keeps the plain path)
+    if (multi_ && g->model == IMM_IC && !(p.flags & IMM_EARLY_STOP)) {
+        q->st = main_;
+        q->multi = true;
+    }
     const imm_status s = start_query(*q, big_cap);
     if (s != IMM_OK) {
         q->status = s;
@@ -381,12 +399,31 @@ bool BatchRunner::step() {
         (void)hipEventCreate(&ev_a_);
         (void)hipEventCreate(&ev_b_);
     }
-    // sampling, each query on its stream
+    // sampling, each query on its stream; the IC queries' passes prepared
+    // and then run by one multi-instance launch on the main stream
     std::vector<Query*> live;
     for (auto* q : active_) {
         const imm_status s = begin_iteration(*q);
         if (s != IMM_OK) finish_err(q, s);
         else live.push_back(q);
+    }
+    {
+        std::vector<Query*> group;
+        for (auto* q : live)
+            if (q->multi && q->w->pending_multi) group.push_back(q);
+        for (size_t a = 0; a < group.size(); a += kMaxTasks) {
+            std::vector<Query*> part(group.begin() + (long)a,
+                                     group.begin() + (long)std::min(group.size(), a + kMaxTasks));
+            // the host task table is rewritten only after its last copy ran
+            if (a > 0) (void)hipStreamSynchronize(main_);
+            const imm_status s = multi_pass(part);
+            if (s != IMM_OK)
+                for (auto* q : part) finish_err(q, s);
+        }
+        std::vector<Query*> keep;
+        for (auto* q : live)
+            if (!q->done) keep.push_back(q);
+        live.swap(keep);
     }
     // one wait per stream, then retries, compaction, index, selection state
     std::vector<hipStream_t> synced;
@@ -406,15 +443,18 @@ bool BatchRunner::step() {
     // the selections of all queries together, on the main stream
     if (!ready.empty()) {
         std::vector<SelectDesc> descs;
-        uint32_t arg_total = 0, sel_total = 0, kmax = 0;
+        uint32_t arg_total = 0, sel_total = 0, dense_total = 0, kmax = 0;
         for (auto* q : ready) {
             SelectDesc d = q->desc;
             d.arg_lo = arg_total;
             d.arg_cnt = argmax_blocks(d.n);
             d.sel_lo = sel_total;
             d.sel_cnt = select_blocks(q->g->device, q->w->n_sets, (uint32_t)ready.size());
+            d.dense_lo = dense_total;
+            d.dense_cnt = dense_blocks(d.n_dense, d.dense_words);
             arg_total += d.arg_cnt;
             sel_total += d.sel_cnt;
+            dense_total += d.dense_cnt;
             kmax = std::max(kmax, d.k);
             descs.push_back(d);
         }
@@ -450,7 +490,7 @@ bool BatchRunner::step() {
             if (graph && ok) {
                 bool captured = false;
                 launched = graph_.launch(descs_d_, (uint32_t)descs.size(), kmax, arg_total,
-                                         sel_total, main_, &captured);
+                                         sel_total, dense_total, main_, &captured);
                 ok = launched >= 0;
                 for (auto* q : ready) {
                     q->select_graphs += launched > 0 ? 1u : 0u;
@@ -460,7 +500,7 @@ bool BatchRunner::step() {
             if (launched == 0) {
                 for (uint32_t t = 0; ok && t < kmax; ++t)
                     ok = launch_select_step(descs_d_, (uint32_t)descs.size(), t, arg_total,
-                                            sel_total, main_) == hipSuccess;
+                                            sel_total, dense_total, main_) == hipSuccess;
             }
             if (timing) (void)hipEventRecord(ev_b_, main_);
             for (auto* q : ready)
@@ -486,6 +526,68 @@ bool BatchRunner::step() {
     }
     active_.swap(next);
     return true;
+}
+
+// One multi-instance launch of the prepared IC passes of qs (<= kMaxTasks),
+// on the main stream: the task table and the lane pass's position prefix
+// (each range rounded up to whole tickets), shared giant-set slots sized for
+// the largest graph, the three kernels, then every workspace's scalar copy.
+imm_status BatchRunner::multi_pass(const std::vector<Query*>& qs) {
+    const uint32_t nt = (uint32_t)qs.size();
+    uint32_t words = 1, team = 2;
+    uint64_t biggest = 0;
+    for (auto* q : qs) {
+        words = std::max(words, (q->g->n + 31) / 32);
+        if (q->w->pending_count > biggest) {
+            biggest = q->w->pending_count;
+            team = q->g->ic_team;
+        }
+    }
+    const int dev = qs[0]->g->device;
+    const uint32_t slots = ic_large_slots(dev, 256);
+    const uint64_t need = (uint64_t)slots * ((uint64_t)words + kGiantQueue) * 4 + 256;
+    if (multi_cap_ < need || multi_words_ < words) {
+        if (multi_buf_) {
+            HIP_TRY(hipStreamSynchronize(main_));
+            (void)hipFree(multi_buf_);
+            multi_buf_ = nullptr;
+        }
+        multi_cap_ = 0;
+        HIP_TRY(hipMalloc(&multi_buf_, need));
+        // the bitmaps start clear; the kernels leave them clear
+        HIP_TRY(hipMemsetAsync(multi_buf_, 0, (uint64_t)slots * words * 4, main_));
+        multi_cap_ = need;
+        multi_words_ = words;
+    }
+    if (!tasks_h_) {
+        HIP_TRY(hipHostMalloc((void**)&tasks_h_, kTaskBytes, hipHostMallocDefault));
+        HIP_TRY(hipMalloc((void**)&tasks_d_, kTaskBytes));
+    }
+    IcTask* th = reinterpret_cast<IcTask*>(tasks_h_);
+    uint32_t* pre = reinterpret_cast<uint32_t*>(tasks_h_ + kMaxTasks * sizeof(IcTask));
+    uint32_t* tk = pre + kMaxTasks + 1;
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < nt; ++j) {
+        Query* q = qs[j];
+        th[j] = ws_ic_task(*q->w, q->g, q->p.seed, kGiantQueue);
+        pre[j] = (uint32_t)acc;
+        acc += (q->w->pending_count + kLaneTicket - 1) / kLaneTicket * kLaneTicket;
+        if (acc > 0xFFFF0000ull) return fail(IMM_EOVERFLOW, "batched sampling round too large");
+        q->w->pending_multi = false;
+    }
+    pre[nt] = (uint32_t)acc;
+    tk[0] = tk[1] = tk[2] = 0;
+    HIP_TRY(hipMemcpyAsync(tasks_d_, tasks_h_, kTaskBytes, hipMemcpyHostToDevice, main_));
+    const IcTask* td = reinterpret_cast<const IcTask*>(tasks_d_);
+    const uint32_t* pd = reinterpret_cast<const uint32_t*>(tasks_d_ + kMaxTasks * sizeof(IcTask));
+    uint32_t* tkd = const_cast<uint32_t*>(pd) + kMaxTasks + 1;
+    uint32_t* bits = static_cast<uint32_t*>(multi_buf_);
+    const BigScratch b{bits, bits + (uint64_t)slots * words, words, slots, kGiantQueue};
+    HIP_TRY(launch_ic_multi(td, nt, pd, tkd, team, 256, b, dev, main_));
+    for (auto* q : qs) IMM_TRY(ws_after_multi(*q->w));
+    // the host table is rewritten by the next launch only after main_ has
+    // been synchronised (step waits for it before the selections)
+    return IMM_OK;
 }
 
 std::vector<Query*> BatchRunner::drain() {
@@ -599,6 +701,25 @@ std::vector<Query*> AsyncRunner::drain() {
     return out;
 }
 
+uint64_t cached_bytes(imm_graph* g) {
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    uint64_t b = 0;
+    for (auto& w : g->ws_cache) b += w->arena.used;
+    return b;
+}
+
+uint64_t trim_cache(imm_graph* g) {
+    std::vector<std::unique_ptr<Workspace>> drop;
+    {
+        std::lock_guard<std::mutex> lk(g->ws_mu);
+        drop.swap(g->ws_cache);
+    }
+    uint64_t b = 0;
+    for (auto& w : drop) b += w->arena.used;
+    drop.clear();  // frees the device memory (each workspace waits for its device first)
+    return b;
+}
+
 void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t count,
                  hipStream_t main, const hipStream_t* streams, imm_result** out,
                  imm_status* status, std::string* errors) {
@@ -609,7 +730,7 @@ void run_queries(imm_graph* const* graphs, const imm_params* params, uint32_t co
     // query (measured faster than independent pipelines for many small
     // queries; the server, whose queries arrive over time, uses those)
     std::vector<Query*> qs(count);
-    BatchRunner br(main);
+    BatchRunner br(main, count > 1);
     for (uint32_t j = 0; j < count; ++j) qs[j] = br.start(graphs[j], params[j], streams[j], big_cap);
     while (br.step()) {
     }

@@ -7,6 +7,7 @@
 // hands finished results to pollers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -61,6 +62,7 @@ struct imm_server {
     std::deque<uint64_t> queue;  // submitted, not admitted
     uint32_t running = 0;
     uint64_t reserved = 0;
+    std::vector<imm_graph*> graphs;  // every graph a query was submitted on
 
     void run();
     void complete(uint64_t t, Entry& e, imm_status st, const std::string& err, imm_result* r);
@@ -102,11 +104,20 @@ void imm_server::run() {
                 if (stop) {
                     for (auto& kv : owner) entries[kv.second].cancel = true;
                 }
-                // admission at the iteration boundary
+                // admission at the iteration boundary: the running queries'
+                // reservations and the idle workspaces cached on the server's
+                // graphs must leave room for the query's estimate; the caches
+                // are emptied first when they are what stands in the way
                 while (!stop && !queue.empty() && running < max_slots) {
                     const uint64_t t = queue.front();
                     Entry& e = entries[t];
-                    if (running > 0 && reserved + e.reserve > budget) break;
+                    uint64_t cached = 0;
+                    for (imm_graph* g : graphs) cached += cached_bytes(g);
+                    if (reserved + cached + e.reserve > budget && cached) {
+                        for (imm_graph* g : graphs) trim_cache(g);
+                        cached = 0;
+                    }
+                    if (running > 0 && reserved + cached + e.reserve > budget) break;
                     queue.pop_front();
                     ++running;
                     reserved += e.reserve;
@@ -173,9 +184,8 @@ void imm_server::run() {
                 g = entries[t].g;
             }
             imm_result* r = BatchRunner::take(q, &s, &err);
-            uint64_t prev = g->peak_bytes.load();
-            while (bytes > prev && !g->peak_bytes.compare_exchange_weak(prev, bytes)) {
-            }
+            (void)g;
+            (void)bytes;
             std::lock_guard<std::mutex> lk(mu);
             Entry& e = entries[t];
             reserved -= e.reserve;
@@ -230,6 +240,8 @@ imm_status imm_server_submit(imm_server* s, const imm_graph* g, const imm_params
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return fail(IMM_EINVAL, "server_submit: server is shutting down");
         const uint64_t t = s->next_ticket++;
+        if (std::find(s->graphs.begin(), s->graphs.end(), e.g) == s->graphs.end())
+            s->graphs.push_back(e.g);
         s->entries.emplace(t, std::move(e));
         s->queue.push_back(t);
         *ticket = t;

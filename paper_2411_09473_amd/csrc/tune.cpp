@@ -144,6 +144,7 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
         fill_stats(w, &s);
         const double ms = s.ms_sample;
         if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
+        g->dense_rate = (double)w.n_dense / (double)kProbeSamples;
         if (log) std::fprintf(stderr, "imm tune: n=%u probe %.3f ms\n", g->n, ms);
         if (ms > kProbeMs) {
             if (!g->big_forced) g->ic_big_block = 1024;
@@ -169,6 +170,7 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
             const double t = s.ms_sample_main + s.ms_sample_big;
             if (ms < 0.0 || t < ms) ms = t;
             *defer_rate = (double)s.deferred / (double)batch;
+            g->dense_rate = (double)w.n_dense / (double)batch;
             if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
         }
         if (log)

@@ -163,6 +163,10 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.p_ub = 0;
     w.nseg = 0;
     w.indexed_sets = 0;
+    w.n_dense = 0;
+    w.dense_entries = 0;
+    w.list_only = false;
+    if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
@@ -227,6 +231,56 @@ BigScratch huge_view(const Workspace& w) {
     return BigScratch{w.huge, w.huge + (uint64_t)words * w.huge_slots, words, w.huge_slots, w.n};
 }
 
+// Sets of at least this many members are stored as bitmaps (IC only; none
+// when the workspace keeps lists only).
+uint32_t dense_min_of(const Workspace& w, const imm_graph* g) {
+    return (g->model == IMM_IC && !w.list_only) ? dense_threshold(w.n) : 0xFFFFFFFFu;
+}
+
+// Bitmap slots for at least `want` dense sets in all, keeping the first
+// `keep` slots' contents: grown by half or more, within the budget; a
+// shortfall only costs a retry of the sets that found no slot.
+imm_status ws_dense_reserve(Workspace& w, uint64_t want, uint64_t keep) {
+    if (w.dense_words == 0) w.dense_words = (uint32_t)(((uint64_t)w.n + 31) / 32);
+    if (w.cap_dense >= want) return IMM_OK;
+    hipStream_t st = w.st;
+    uint64_t nc = std::max<uint64_t>(want, w.cap_dense + w.cap_dense / 2);
+    const uint64_t per = (uint64_t)w.dense_words * 4 + 12;
+    if (w.arena.budget) {
+        const uint64_t left = w.arena.budget > w.arena.used ? w.arena.budget - w.arena.used : 0;
+        nc = std::min<uint64_t>(nc, std::max<uint64_t>(want, left / 2 / per));
+    }
+    uint64_t cb = w.cap_dense * w.dense_words, cs = w.cap_dense, cz = w.cap_dense,
+             cl = w.cap_dense;
+    IMM_TRY(grow(w.arena, &w.dense_bits, &cb, nc * w.dense_words, keep * w.dense_words, st,
+                 "dense set bitmaps"));
+    IMM_TRY(grow(w.arena, &w.dense_sid, &cs, nc, keep, st, "dense set ids"));
+    IMM_TRY(grow(w.arena, &w.dense_size, &cz, nc, keep, st, "dense set sizes"));
+    IMM_TRY(grow(w.arena, &w.dense_list, &cl, nc, 0, st, "dense claims"));
+    w.cap_dense = std::min(std::min(cb / w.dense_words, cs), std::min(cz, cl));
+    if (!w.dense_counts) {
+        IMM_TRY(w.arena.alloc((void**)&w.dense_counts, (uint64_t)w.n * 4, "dense counts"));
+        HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
+    }
+    return IMM_OK;
+}
+
+// Where a pass of w stores its sets; fl / fl_n take the samples to retry.
+SampleOut sample_out(Workspace& w, const imm_graph* g, uint32_t* fl, uint32_t* fl_n) {
+    SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
+                w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
+    o.dense_bits = w.dense_bits;
+    o.dense_cap = w.cap_dense;
+    o.dense_cursor = &w.sc->dense_n;
+    o.dense_sid = w.dense_sid;
+    o.dense_size = w.dense_size;
+    o.dense_entries = &w.sc->dense_entries;
+    o.dense_min = dense_min_of(w, g);
+    o.dense_words = w.dense_words;
+    o.pool_base = w.n_sets;
+    return o;
+}
+
 // One sampling pass: the fast kernel over the range (list = nullptr) or over
 // a list of indices, then the large-set kernel over what it deferred.
 // Failures for lack of staging land in fl; deferred sets in w.defer. The
@@ -237,8 +291,7 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
     hipStream_t st = w.st;
     const SampleRange rg{seed, id_lo, nitems, list, list_n};
     const SampleRange rgl{seed, id_lo, count, nullptr, nullptr};
-    const SampleOut o{w.stage, w.stage_cap, &w.sc->cursor, w.stage_off, w.sizes, w.counts_acc,
-                      w.defer, &w.sc->defer_n, fl, fl_n, w.sc->stats};
+    const SampleOut o = sample_out(w, g, fl, fl_n);
     // tickets and list lengths (already zero right after ws_extend_launch's reset)
     if (!fresh) HIP_TRY(hipMemsetAsync(&w.sc->ticket_small, 0, 7 * sizeof(uint32_t), st));
     const int th = w.timer.open(0, st);
@@ -289,8 +342,9 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
 }  // namespace
 
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count64) {
+                            uint64_t count64, bool multi) {
     w.pending_count = 0;
+    w.pending_multi = false;
     if (count64 == 0) return IMM_OK;
     if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
     uint32_t count = (uint32_t)count64;
@@ -311,7 +365,9 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
         count -= kPilot;
     }
     hipStream_t st = w.st;
-    IMM_TRY(ws_big_scratch(w, g));
+    // a pass of a multi-instance launch uses the launch's shared giant-set
+    // slots; the workspace's own are made when a retry pass needs them
+    if (!multi) IMM_TRY(ws_big_scratch(w, g));
     IMM_TRY(grow(w.arena, &w.stage_off, &w.cap_so, count, 0, st, "stage_off"));
     IMM_TRY(grow(w.arena, &w.sizes, &w.cap_sz, count, 0, st, "sizes"));
     IMM_TRY(grow(w.arena, &w.defer, &w.cap_df, count, 0, st, "defer list"));
@@ -347,11 +403,43 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
         }
         IMM_TRY(grow(w.arena, &w.stage, &w.stage_cap, want, 0, st, "staging"));
     }
+    if (dense_min_of(w, g) != 0xFFFFFFFFu) {
+        // the rate of dense sets seen while tuning, or among this pool's sets
+        // once there are some
+        double rate = g->dense_rate > 0.0 ? 1.2 * g->dense_rate : 0.0;
+        if (w.n_sets >= 4096) rate = 1.2 * (double)w.n_dense / (double)w.n_sets;
+        // IMM_DENSE_SCALE (a factor, default 1) scales this estimate; 0
+        // exercises the path that adds slots and redoes the sets that found
+        // none
+        if (const char* e = std::getenv("IMM_DENSE_SCALE")) rate *= std::max(0.0, std::atof(e));
+        IMM_TRY(ws_dense_reserve(w, w.n_dense + (uint64_t)(rate * (double)count) + 256,
+                                 w.n_dense));
+    }
     HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));
     w.pending_count = count;
     w.pending_lo = id_lo;
+    if (multi) {
+        w.pending_multi = true;
+        return IMM_OK;
+    }
     return sample_pass(w, g, seed, id_lo, count, nullptr, nullptr, count, w.retry,
                        &w.sc->retry_n, true);
+}
+
+IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap) {
+    IcTask t{};
+    t.g = ic_view(g);
+    t.rg = SampleRange{seed, w.pending_lo, (uint32_t)w.pending_count, nullptr, nullptr};
+    t.o = sample_out(w, g, w.retry, &w.sc->retry_n);
+    t.pend = w.pend;
+    t.pend_n = &w.sc->pend_n;
+    t.qcap = std::min<uint32_t>(w.n, qcap);
+    return t;
+}
+
+imm_status ws_after_multi(Workspace& w) {
+    HIP_TRY(hipMemcpyAsync(w.hsc, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, w.st));
+    return IMM_OK;
 }
 
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
@@ -369,20 +457,33 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
     uint32_t failed = w.hsc->retry_n;
     for (int guard = 0; failed; ++guard) {
         if (guard == 32) return fail(IMM_ENOMEM, "staging could not be grown enough");
-        const uint64_t used = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
-        const uint64_t old_cap = w.stage_cap;
-        const double mean = w.mean_size > 0 ? w.mean_size : 64.0;
-        uint64_t need =
-            old_cap + (uint64_t)(mean * 2.0 * failed) + (uint64_t)failed * 64 + (1u << 20);
-        need = std::max<uint64_t>(need, old_cap * 2);
-        uint64_t cap = w.stage_cap;
-        IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
-        w.stage_cap = cap;
-        // at a multiple of four: the LT walk kernel reads its chunks in
-        // aligned 16-byte groups (cap >= 2 old_cap, so this stays in bounds)
-        const unsigned long long cur = (old_cap + 3) & ~3ull;
-        HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
+        if (w.hsc->dense_n > w.cap_dense) {
+            // dense sets that found no bitmap slot: more slots (every slot
+            // below the old capacity holds a set), the cursor back at the
+            // stored ones; w.n_dense stays the count before this pass, whose
+            // new sets are all counted below
+            const uint64_t stored = w.cap_dense;
+            IMM_TRY(ws_dense_reserve(w, w.hsc->dense_n + w.hsc->dense_n / 4 + 256, stored));
+            const uint32_t cur = (uint32_t)stored;
+            HIP_TRY(hipMemcpyAsync(&w.sc->dense_n, &cur, 4, hipMemcpyHostToDevice, st));
+        }
+        if (w.hsc->cursor > w.stage_cap) {
+            const uint64_t used = w.stage_cap;
+            const uint64_t old_cap = w.stage_cap;
+            const double mean = w.mean_size > 0 ? w.mean_size : 64.0;
+            uint64_t need =
+                old_cap + (uint64_t)(mean * 2.0 * failed) + (uint64_t)failed * 64 + (1u << 20);
+            need = std::max<uint64_t>(need, old_cap * 2);
+            uint64_t cap = w.stage_cap;
+            IMM_TRY(grow(w.arena, &w.stage, &cap, need, used, st, "staging"));
+            w.stage_cap = cap;
+            // at a multiple of four: the LT walk kernel reads its chunks in
+            // aligned 16-byte groups (cap >= 2 old_cap, so this stays in bounds)
+            const unsigned long long cur = (old_cap + 3) & ~3ull;
+            HIP_TRY(hipMemcpyAsync(&w.sc->cursor, &cur, 8, hipMemcpyHostToDevice, st));
+        }
         HIP_TRY(hipMemsetAsync(out_n, 0, 4, st));
+        IMM_TRY(ws_big_scratch(w, g));
         IMM_TRY(sample_pass(w, g, seed, id_lo, count, in, in_n, failed, out_l, out_n, false));
         HIP_TRY(hipStreamSynchronize(st));
         std::swap(in, out_l);
@@ -390,6 +491,18 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
         failed = (in == w.retry) ? w.hsc->retry_n : w.hsc->spare_n;
     }
 
+    // the new dense sets' members in the dense counts (one bitmap column sum)
+    {
+        const uint64_t nd = std::min<uint64_t>(w.hsc->dense_n, w.cap_dense);
+        if (nd > w.n_dense) {
+            const int tc = w.timer.open(1, st);
+            HIP_TRY(launch_dense_count(w.dense_bits, w.dense_words, (uint32_t)w.n_dense,
+                                       (uint32_t)nd, w.n, w.dense_counts, st));
+            w.timer.close(tc, st);
+        }
+        w.n_dense = nd;
+        w.dense_entries = w.hsc->dense_entries;
+    }
     // compaction: set_off[n_sets .. n_sets+count] (based on the device copy of
     // set_off[n_sets]) and the copy into the pool
     const uint64_t stored_bound = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
@@ -433,6 +546,10 @@ imm_status ws_restart_pool(Workspace& w) {
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
+    w.n_dense = 0;
+    w.dense_entries = 0;
+    HIP_TRY(hipMemsetAsync(&w.sc->dense_n, 0, 16, st));
+    if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     return IMM_OK;
 }
 
@@ -523,7 +640,21 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
                  "chunk queue"));
     // working counts, and the list of vertices whose index lists are long
     HIP_TRY(hipMemsetAsync(w.heavy + w.n, 0, 4, st));
-    HIP_TRY(launch_select_init(w.counts_acc, w.counts_work, w.n, w.heavy, w.heavy + w.n, st));
+    HIP_TRY(launch_select_init2(w.counts_acc, w.n_dense ? w.dense_counts : nullptr,
+                                w.counts_work, w.n, w.heavy, w.heavy + w.n, st));
+    // dense claims: per-step marks, then the claim cursor
+    if (w.n_dense) {
+        if (w.cap_mark_k < k) {
+            if (w.dense_mark) {
+                HIP_TRY(hipStreamSynchronize(st));
+                w.arena.release(w.dense_mark);
+                w.dense_mark = nullptr;
+            }
+            IMM_TRY(w.arena.alloc((void**)&w.dense_mark, ((uint64_t)k + 2) * 4, "dense marks"));
+            w.cap_mark_k = k;
+        }
+        HIP_TRY(hipMemsetAsync(w.dense_mark, 0, (w.cap_mark_k + 2) * 4, st));
+    }
     HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
     // the whole block: its layout follows the capacity cap_k, not this k
     HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
@@ -533,6 +664,17 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
                     w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
                     w.cov_entries, w.n,          k,           w.nseg,        (uint32_t)w.n_sets,
                     0,             0,            0,           0,             w.update_mode};
+    if (w.n_dense) {
+        d->dense_bits = w.dense_bits;
+        d->dense_sid = w.dense_sid;
+        d->dense_size = w.dense_size;
+        d->dense_list = w.dense_list;
+        d->dense_list_n = w.dense_mark + w.cap_mark_k + 1;
+        d->dense_mark = w.dense_mark;
+        d->dense_entries = w.dense_entries;
+        d->n_dense = (uint32_t)w.n_dense;
+        d->dense_words = w.dense_words;
+    }
     return IMM_OK;
 }
 
@@ -557,9 +699,10 @@ SelectGraph::~SelectGraph() {
 }
 
 int SelectGraph::launch(const SelectDesc* d, uint32_t q, uint32_t km, uint32_t at, uint32_t stot,
-                        hipStream_t st, bool* captured) {
+                        uint32_t dtot, hipStream_t st, bool* captured) {
     *captured = false;
-    if (!exec || d != descs || q != nq || km != kmax || at != arg_total || stot != sel_total) {
+    if (!exec || d != descs || q != nq || km != kmax || at != arg_total || stot != sel_total ||
+        dtot != dense_total) {
         // the kernels only: nothing in the captured sequence is a memset or
         // a copy (the descriptors are copied before each launch)
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -568,7 +711,7 @@ int SelectGraph::launch(const SelectDesc* d, uint32_t q, uint32_t km, uint32_t a
         }
         hipError_t le = hipSuccess;
         for (uint32_t t = 0; le == hipSuccess && t < km; ++t)
-            le = launch_select_step(d, q, t, at, stot, st);
+            le = launch_select_step(d, q, t, at, stot, dtot, st);
         hipGraph_t graph = nullptr;
         const hipError_t ce = hipStreamEndCapture(st, &graph);
         if (le != hipSuccess || ce != hipSuccess || !graph) {
@@ -603,6 +746,7 @@ int SelectGraph::launch(const SelectDesc* d, uint32_t q, uint32_t km, uint32_t a
         kmax = km;
         arg_total = at;
         sel_total = stot;
+        dense_total = dtot;
         *captured = true;
     }
     return hipGraphLaunch(exec, st) == hipSuccess ? 1 : -1;
@@ -614,17 +758,19 @@ imm_status ws_select_launch(Workspace& w, uint32_t k, bool graph, int* graph_out
     IMM_TRY(ws_select_prepare(w, k, &d));
     d.arg_cnt = argmax_blocks(w.n);
     d.sel_cnt = select_blocks(w.device, w.n_sets, 1);
+    d.dense_cnt = dense_blocks(d.n_dense, d.dense_words);
     HIP_TRY(hipMemcpyAsync(w.desc_d, &d, sizeof(d), hipMemcpyHostToDevice, st));
     const int ts = w.timer.open(3, st);
     int launched = 0;
     bool captured = false;
     if (graph) {
-        launched = w.sel_graph.launch(w.desc_d, 1, k, d.arg_cnt, d.sel_cnt, st, &captured);
+        launched = w.sel_graph.launch(w.desc_d, 1, k, d.arg_cnt, d.sel_cnt, d.dense_cnt, st,
+                                      &captured);
         if (launched < 0) return fail(IMM_EDEVICE, "select: graph launch failed");
     }
     if (launched == 0)
         for (uint32_t t = 0; t < k; ++t)
-            HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, st));
+            HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, d.dense_cnt, st));
     if (graph_out) *graph_out = launched == 0 ? 0 : (captured ? 2 : 1);
     w.timer.close(ts, st);
     return ws_select_copy_out(w, k, st);
@@ -685,6 +831,47 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
         counts->resize(w.n);
         HIP_TRY(hipMemcpy(counts->data(), w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToHost));
     }
+    if (w.n_dense == 0) return IMM_OK;
+    // dense sets: their bitmaps, in set order, replace their empty lists
+    // (members ascending, as a bitmap lists them); their counts are added
+    const uint64_t nd = w.n_dense, words = w.dense_words;
+    std::vector<uint32_t> sid(nd), bits(nd * words);
+    HIP_TRY(hipMemcpy(sid.data(), w.dense_sid, nd * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(bits.data(), w.dense_bits, nd * words * 4, hipMemcpyDeviceToHost));
+    if (counts) {
+        std::vector<uint32_t> dc(w.n);
+        HIP_TRY(hipMemcpy(dc.data(), w.dense_counts, (uint64_t)w.n * 4, hipMemcpyDeviceToHost));
+        for (uint32_t v = 0; v < w.n; ++v) (*counts)[v] += dc[v];
+    }
+    if (!so && !sv) return IMM_OK;
+    std::vector<uint64_t> lso(w.n_sets + 1);
+    HIP_TRY(hipMemcpy(lso.data(), w.set_off, (w.n_sets + 1) * 8, hipMemcpyDeviceToHost));
+    std::vector<int64_t> dense_of(w.n_sets, -1);
+    for (uint64_t b = 0; b < nd; ++b) dense_of[sid[b]] = (int64_t)b;
+    auto popc = [&](uint64_t b) {
+        uint64_t c = 0;
+        for (uint64_t x = 0; x < words; ++x) c += (uint64_t)__builtin_popcount(bits[b * words + x]);
+        return c;
+    };
+    std::vector<uint64_t> off(w.n_sets + 1, 0);
+    for (uint64_t j = 0; j < w.n_sets; ++j)
+        off[j + 1] = off[j] + (dense_of[j] >= 0 ? popc((uint64_t)dense_of[j]) : lso[j + 1] - lso[j]);
+    if (sv) {
+        std::vector<uint32_t> out(off[w.n_sets]);
+        for (uint64_t j = 0; j < w.n_sets; ++j) {
+            uint64_t o = off[j];
+            if (dense_of[j] < 0) {
+                for (uint64_t t = lso[j]; t < lso[j + 1]; ++t) out[o++] = (*sv)[t];
+                continue;
+            }
+            const uint32_t* bm = bits.data() + (uint64_t)dense_of[j] * words;
+            for (uint64_t x = 0; x < words; ++x)
+                for (uint32_t y = bm[x]; y; y &= y - 1)
+                    out[o++] = (uint32_t)(32 * x + (uint64_t)__builtin_ctz(y));
+        }
+        sv->swap(out);
+    }
+    if (so) so->swap(off);
     return IMM_OK;
 }
 
@@ -714,6 +901,7 @@ void fill_stats(Workspace& w, imm_stats* s) {
     s->main_entries = t[kStMainEntries];
     s->main_edges = t[kStMainEdges];
     s->main_live = t[kStMainLive];
+    s->dense_sets = (uint32_t)std::min<uint64_t>(w.n_dense, 0xFFFFFFFFu);
 }
 
 }  // namespace imm

@@ -141,3 +141,33 @@ def test_batch_errors(imm, stream):
     r = imm.imm_run_batch([(dg, dict(k=5, epsilon=0.5, seed=1))], stream=stream)
     one = imm.imm_run(dg, 5, 0.5, 1.0, 1, stream=stream)
     np.testing.assert_array_equal(r[0].seeds, one.seeds)
+
+
+@pytest.mark.parametrize("stage_scale", ["1", "0.01"])
+def test_batch_multi_instance_launch(imm, orc, stream, monkeypatch, stage_scale):
+    """More IC queries than one multi-instance launch takes (64), so each
+    sampling round is two launches; with a tiny first staging estimate, most
+    sets find the staging full and are redone by each query's own retry
+    passes. Every query equals imm_run alone; a sample of them equals the
+    oracle."""
+    monkeypatch.setenv("IMM_STAGE_SCALE", stage_scale)
+    names = ["rmat12_wc", "rmat12_p10", "youtube_ic_s"]
+    graphs = {nm: synth.make_graph(nm) for nm in names}
+    dev = {nm: imm.graph_from(g, stream=stream) for nm, g in graphs.items()}
+    qs = []
+    for i in range(70):
+        nm = names[i % len(names)]
+        qs.append((nm, dict(k=[5, 10, 25][i % 3], epsilon=[0.5, 0.3][i % 2], ell=1.0,
+                            seed=500 + i)))
+    say(f"batch of {len(qs)} IC queries, stage scale {stage_scale}")
+    res = imm.imm_run_batch([(dev[nm], q) for nm, q in qs], stream=stream)
+    monkeypatch.delenv("IMM_STAGE_SCALE")
+    for i, ((nm, q), r) in enumerate(zip(qs, res)):
+        one = imm.imm_run(dev[nm], q["k"], q["epsilon"], q["ell"], q["seed"], stream=stream)
+        np.testing.assert_array_equal(one.seeds, r.seeds)
+        np.testing.assert_array_equal(one.gains, r.gains)
+        assert (one.theta, one.rounds, one.lb) == (r.theta, r.rounds, r.lb)
+        if i % 7 == 0:
+            o = orc.imm(graphs[nm], q["k"], q["epsilon"], q["ell"], q["seed"],
+                        threads=oracle_threads())
+            _check(r, o)

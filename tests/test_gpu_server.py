@@ -125,3 +125,27 @@ def test_server_destroy_with_work_outstanding(imm, stream, graphs):
     srv.close()  # cancels what is queued, waits for what runs
     r = imm.imm_run(dg["rmat12_lt"], 10, 0.5, 1.0, 0, stream=stream)
     assert r.theta > 0
+
+
+def test_server_budget_admits_one_at_a_time(imm, orc, stream, graphs):
+    """A budget that holds one query's workspace but not two: with four slots
+    free, the second query still waits until the first has finished (the
+    workspace the first leaves in its graph's cache is freed for it), and
+    both results equal the oracle's."""
+    hg, dg = graphs
+    q = dict(k=10, epsilon=0.1, ell=1.0)
+    # a run outside the server records the graph's workspace size
+    warm = imm.imm_run(dg["rmat12_p10"], seed=1, stream=stream, **q)
+    need = warm.stats["device_bytes"]
+    assert need > 0
+    srv = imm.Server(budget_bytes=int(need * 1.5), max_slots=4)
+    t1 = srv.submit(dg["rmat12_p10"], seed=2, **q)
+    t2 = srv.submit(dg["rmat12_p10"], seed=3, **q)
+    r1, r2 = srv.poll(t1), srv.poll(t2)
+    srv.close()
+    # the second was admitted only once the first had finished
+    run1 = r1.stats["ms_total"] - r1.stats["ms_queue"]
+    assert r2.stats["ms_queue"] >= r1.stats["ms_queue"] + 0.9 * run1
+    for s, r in ((2, r1), (3, r2)):
+        _same(r, orc.imm(hg["rmat12_p10"], q["k"], q["epsilon"], q["ell"], s,
+                         threads=oracle_threads()))
