@@ -595,7 +595,9 @@ def main():
     r = results[-1]
     for x in results:
         assert x.theta == r.theta and list(x.seeds) == list(r.seeds), "runs must be identical"
-    sets = r.stats["sets"]
+    # the final selection's pool (every set it used); the sets a run drew
+    # ahead and never used are not counted
+    sets = r.theta
     value = sets / (ms_per_step / 1e3)
 
     kernels = kernel_table(g.model, [x.stats for x in results])

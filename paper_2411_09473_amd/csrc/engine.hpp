@@ -236,6 +236,11 @@ struct Workspace {
     double mean_size = 0.0;  // mean set size of the last round (staging estimate)
     uint32_t update_mode = 0;    // SelectDesc::update of this workspace's selections
     bool pending_multi = false;  // the prepared pass waits for a multi-instance launch
+    uint64_t pending_split = 0;  // ... of which the first pending_split join the pool now
+    // sets the last pass drew ahead of the round (sample indices [ahead_split,
+    // ahead_split + ahead_n) of that pass): staged, not counted, not pooled
+    uint64_t ahead_n = 0, ahead_split = 0;
+    uint64_t ahead_bound = 0;  // bound on their entries: that pass's staging bound
     uint64_t pending_count = 0;  // sets of the sampling pass in flight
     uint64_t pending_lo = 0;
     Timer timer;
@@ -316,8 +321,11 @@ imm_status ws_read_scalars(Workspace& w);
 // scalars read, completed (retries, compaction: ws_extend_finish).
 // multi: everything but the pass itself, which a multi-instance launch then
 // runs (ws_ic_task gives its task, ws_after_multi queues the scalar copy).
+// ahead: that many more ids (after the count asked for) are drawn in the same
+// pass but join the pool only when a later call asks for them (the rest of
+// them are then dropped); results do not change.
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count, bool multi = false);
+                            uint64_t count, bool multi = false, uint64_t ahead = 0);
 IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap);
 imm_status ws_after_multi(Workspace& w);
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);

@@ -97,6 +97,10 @@ struct SampleOut {
     uint32_t dense_min;
     uint32_t dense_words;
     uint64_t pool_base;
+    // LT: only samples with index < count_lim add to counts (the others are
+    // drawn ahead of the round that needs them; 0xFFFFFFFF: all count)
+    uint32_t count_lim;
+    uint32_t pad;
 };
 // Sets of at least max(ceil(n / 32), kDenseMinSize) members are dense: a
 // bitmap of n bits then takes no more room than the member list. Every set
@@ -204,6 +208,10 @@ hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, 
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);
+// counts[v] += occurrences of v in the sets [lo, hi) of a pool (their entry
+// range read from set_off on the device).
+hipError_t launch_count_sets(const uint64_t* set_off, uint64_t lo, uint64_t hi,
+                             const uint32_t* set_vtx, uint32_t* counts, hipStream_t st);
 // counts[u] += number of bitmaps b in [b_lo, b_hi) with bit u set (each
 // bitmap `words` words long, counts over n = 32 * words vertices at most).
 hipError_t launch_dense_count(const uint32_t* bits, uint32_t words, uint32_t b_lo, uint32_t b_hi,

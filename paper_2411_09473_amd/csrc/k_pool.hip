@@ -266,6 +266,15 @@ __global__ __launch_bounds__(256) void cover_count_kernel(const uint64_t* set_of
     }
 }
 
+__global__ __launch_bounds__(256) void count_sets_kernel(const uint64_t* set_off, uint64_t lo,
+                                                         uint64_t hi, const uint32_t* set_vtx,
+                                                         uint32_t* counts) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t a = set_off[lo], b = set_off[hi];
+    for (uint64_t t = a + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < b; t += stride)
+        atomicAdd(&counts[set_vtx[t]], 1u);
+}
+
 __global__ __launch_bounds__(256) void validate_kernel(const uint64_t* set_off, uint64_t n_sets,
                                                        const uint32_t* set_vtx, uint32_t n,
                                                        uint32_t* flag) {
@@ -419,6 +428,14 @@ hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* c
     if (P == 0) return hipSuccess;
     hipLaunchKernelGGL(count_entries_kernel, dim3(grid_for(P, 256 * 8, 8192)), dim3(256), 0, st,
                        set_vtx, P, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_sets(const uint64_t* set_off, uint64_t lo, uint64_t hi,
+                             const uint32_t* set_vtx, uint32_t* counts, hipStream_t st) {
+    if (hi <= lo) return hipSuccess;
+    hipLaunchKernelGGL(count_sets_kernel, dim3(2048), dim3(256), 0, st, set_off, lo, hi, set_vtx,
+                       counts);
     return hipGetLastError();
 }
 

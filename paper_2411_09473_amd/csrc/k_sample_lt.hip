@@ -23,9 +23,11 @@
 //    by the autotuner) in LDS answers "not on the path" for most vertices; a
 //    hit is confirmed by rescanning the path (vectorised), so the test is
 //    exact.
-//  * Counts are incremented as vertices join the path; a walk that has to
-//    move to the large-walk kernel (path longer than a chunk) or to a retry
-//    (staging full) gives its increments back first. The large-walk kernel
+//  * Counts are incremented as vertices join the path (only for samples
+//    below the pass's count limit: later ones are drawn ahead for the next
+//    round and counted when they join the pool); a walk that has to move to
+//    the large-walk kernel (path longer than a chunk) or to a retry (staging
+//    full) gives its increments back first. The large-walk kernel
 //    picks a walk up where it stopped: the draw at a vertex depends only on
 //    the sample and the vertex, so the chunk's path and the next vertex are
 //    all it needs.
@@ -283,6 +285,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
 
     constexpr uint32_t R = kWin / P;
     bool has = false, done = false, fresh = false, primed = false;
+    bool counted = false;  // the walk's members count (sample index below count_lim)
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
     uint32_t cbeg = 0, cend = 0;  // cur's column
     uint32_t nbeg = 0, nend = 0;  // a new root's column, in flight
@@ -351,8 +354,9 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
             if (start) {
                 wstart = chunk_used;
                 o.stage[chunk_base + wstart] = cur;
+                counted = idx < o.count_lim;
                 if (first) {
-                    atomicAdd(&o.counts[cur], 1u);
+                    if (counted) atomicAdd(&o.counts[cur], 1u);
                     bloom_set<BB>(mb, cur);
                 }
                 len = 1;
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                             o.defer[atomicAdd(o.defer_n, 1u)] = idx;
                         }
                         if (!moved) {
-                            if (first)
+                            if (first && counted)
                                 for (uint32_t t = 0; t < len; ++t)
                                     atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
                             // a deferred path keeps its chunk
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                     if (keep) {
                         o.stage[chunk_base + wstart + len] = nxt;
                         if (first) {
-                            atomicAdd(&o.counts[nxt], 1u);
+                            if (counted) atomicAdd(&o.counts[nxt], 1u);
                             bloom_set<BB>(mb, nxt);
                         }
                         ++len;
@@ -544,7 +548,7 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
             const uint32_t u = q[i];
             if (fits) {
                 o.stage[off + i] = u;
-                atomicAdd(&o.counts[u], 1u);
+                if (idx < o.count_lim) atomicAdd(&o.counts[u], 1u);
             }
             __hip_atomic_store(&bm[u >> 5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

@@ -242,8 +242,23 @@ imm_status begin_iteration(Query& q) {
         return ws_extend_launch(w, q.g, q.p.seed, used, target, q.multi);
     }
     q.before = w.n_sets;
-    return ws_extend_launch(w, q.g, q.p.seed, w.n_sets,
-                            w.n_sets < target ? target - w.n_sets : 0, q.multi);
+    const uint64_t count = w.n_sets < target ? target - w.n_sets : 0;
+    // An LT round of a few walks per walk slot lasts as long as its longest
+    // walk, whatever its size: such a round also draws the next round's ids
+    // (up to about four walks per slot in all), which then need no launch of
+    // their own if the next round comes. They are counted and pooled only
+    // when a later iteration asks for them; what the run never asks for is
+    // dropped, so results do not change.
+    uint64_t ahead = 0;
+    if (!q.final && q.sched == kSchedImm && q.g->model == IMM_LT && q.i < q.i_max && count) {
+        const double nf = std::ceil(q.lam_p / std::ldexp((double)q.g->n, -(int)(q.i + 1)));
+        const uint64_t slots = (uint64_t)lt_small_grid(q.g->device, q.g->lt_bloom_bits,
+                                                       q.g->lt_lanes) * 64u / q.g->lt_lanes / 2u;
+        const uint64_t cap = 4 * slots;
+        if (nf < 4294967296.0 && (uint64_t)nf > target && count < cap)
+            ahead = std::min<uint64_t>((uint64_t)nf - target, cap - count);
+    }
+    return ws_extend_launch(w, q.g, q.p.seed, w.n_sets, count, q.multi, ahead);
 }
 
 // After the round's sampling: retries and compaction of the pool (pools).

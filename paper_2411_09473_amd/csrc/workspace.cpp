@@ -165,6 +165,7 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.indexed_sets = 0;
     w.n_dense = 0;
     w.dense_entries = 0;
+    w.ahead_n = 0;
     w.list_only = false;
     if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
@@ -278,6 +279,7 @@ SampleOut sample_out(Workspace& w, const imm_graph* g, uint32_t* fl, uint32_t* f
     o.dense_min = dense_min_of(w, g);
     o.dense_words = w.dense_words;
     o.pool_base = w.n_sets;
+    o.count_lim = w.pending_split ? (uint32_t)w.pending_split : 0xFFFFFFFFu;
     return o;
 }
 
@@ -341,12 +343,47 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
 
 }  // namespace
 
+// The first k of the sets the last pass drew ahead join the pool: their
+// offsets, members and counts (the staging, per-sample offsets and sizes of
+// that pass are still in place); the rest are dropped.
+imm_status ws_take_ahead(Workspace& w, uint64_t k) {
+    hipStream_t st = w.st;
+    const uint64_t split = w.ahead_split;
+    w.ahead_n = 0;
+    if (k == 0) return IMM_OK;
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + k + 1, w.n_sets + 1, st,
+                 "set_off"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(k), 0, st, "scan tmp"));
+    const int tc = w.timer.open(1, st);
+    HIP_TRY(launch_scan_u32(w.sizes + split, nullptr, w.set_off + w.n_sets, k, 0,
+                            w.set_off + w.n_sets, w.scan_tmp, st));
+    HIP_TRY(launch_compact(w.stage, w.stage_off + split, w.set_off, w.n_sets, (uint32_t)k,
+                           w.set_vtx, st));
+    HIP_TRY(launch_count_sets(w.set_off, w.n_sets, w.n_sets + k, w.set_vtx, w.counts_acc, st));
+    w.timer.close(tc, st);
+    // set_vtx already has room: the last pass's compaction reserved its whole
+    // staging bound. The pool-size bound (which sizes the index and later
+    // compactions) takes that bound back in: a selection in between has set
+    // it to the exact size of the pool without these sets.
+    w.n_sets += k;
+    w.p_ub += w.ahead_bound;
+    return IMM_OK;
+}
+
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count64, bool multi) {
+                            uint64_t count64, bool multi, uint64_t ahead) {
     w.pending_count = 0;
     w.pending_multi = false;
+    w.pending_split = 0;
+    if (w.ahead_n) {
+        // sets drawn ahead by the last pass, as many as this call wants
+        const uint64_t k = std::min<uint64_t>(w.ahead_n, count64);
+        IMM_TRY(ws_take_ahead(w, k));
+        id_lo += k;
+        count64 -= k;
+    }
     if (count64 == 0) return IMM_OK;
-    if (count64 > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
+    if (count64 + ahead > 0xFFFFFFFFull) return fail(IMM_EOVERFLOW, "sampling round too large");
     uint32_t count = (uint32_t)count64;
     // a large batch with no set-size estimate yet takes the graph's tuning
     // mean (with a margin), else a pilot batch measures one first; smaller
@@ -364,6 +401,11 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
         id_lo += kPilot;
         count -= kPilot;
     }
+    // the ids drawn ahead follow this call's ids in the same pass; they are
+    // staged but not counted, and stay out of the pool until a later call.
+    // Every per-sample array and the staging estimate below cover them.
+    const uint32_t split = count;
+    count += (uint32_t)ahead;
     hipStream_t st = w.st;
     // a pass of a multi-instance launch uses the launch's shared giant-set
     // slots; the workspace's own are made when a retry pass needs them
@@ -417,6 +459,7 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
     }
     HIP_TRY(hipMemsetAsync(w.sc, 0, offsetof(DevScalars, stats), st));
     w.pending_count = count;
+    w.pending_split = split;
     w.pending_lo = id_lo;
     if (multi) {
         w.pending_multi = true;
@@ -445,6 +488,7 @@ imm_status ws_after_multi(Workspace& w) {
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
     if (w.pending_count == 0) return IMM_OK;
     const uint32_t count = (uint32_t)w.pending_count;
+    const uint32_t split = (uint32_t)w.pending_split;
     const uint64_t id_lo = w.pending_lo;
     w.pending_count = 0;
     hipStream_t st = w.st;
@@ -505,19 +549,23 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
     }
     // compaction: set_off[n_sets .. n_sets+count] (based on the device copy of
     // set_off[n_sets]) and the copy into the pool
+    // (only the first `split` sets; the ones drawn ahead wait in staging)
     const uint64_t stored_bound = std::min<uint64_t>(w.hsc->cursor, w.stage_cap);
-    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + count + 1, w.n_sets + 1, st,
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + split + 1, w.n_sets + 1, st,
                  "set_off"));
     IMM_TRY(grow(w.arena, &w.set_vtx, &w.cap_entries, w.p_ub + stored_bound + 1,
                  std::min(w.p_ub, w.cap_entries), st, "set_vtx"));
-    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(count), 0, st, "scan tmp"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(split), 0, st, "scan tmp"));
     const int tc = w.timer.open(1, st);
-    HIP_TRY(launch_scan_u32(w.sizes, nullptr, w.set_off + w.n_sets, count, 0,
+    HIP_TRY(launch_scan_u32(w.sizes, nullptr, w.set_off + w.n_sets, split, 0,
                             w.set_off + w.n_sets, w.scan_tmp, st));
-    HIP_TRY(launch_compact(w.stage, w.stage_off, w.set_off, w.n_sets, count, w.set_vtx, st));
+    HIP_TRY(launch_compact(w.stage, w.stage_off, w.set_off, w.n_sets, split, w.set_vtx, st));
     w.timer.close(tc, st);
-    w.n_sets += count;
+    w.n_sets += split;
     w.p_ub += stored_bound;
+    w.ahead_n = count - split;
+    w.ahead_split = split;
+    w.ahead_bound = w.ahead_n ? stored_bound : 0;
     return IMM_OK;
 }
 
@@ -548,6 +596,7 @@ imm_status ws_restart_pool(Workspace& w) {
     HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
     w.n_dense = 0;
     w.dense_entries = 0;
+    w.ahead_n = 0;
     HIP_TRY(hipMemsetAsync(&w.sc->dense_n, 0, 16, st));
     if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     return IMM_OK;

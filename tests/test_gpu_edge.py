@@ -324,3 +324,26 @@ def test_recount_with_long_index_lists(imm, orc, stream, eps, min_first_gain):
     # the run equals the oracle's (checked in _parity); the first seed's
     # index list is longer than two (four) long-list thresholds of 4096
     assert r.theta > 2 * 4096 and r.gains[1] > 0 and r.gains[0] > min_first_gain
+
+
+def test_lt_ids_drawn_ahead_and_dropped(imm, orc, stream):
+    """An LT graph whose first round already passes IMM's lower-bound test:
+    every vertex but the hub has an in-edge from the hub (weight 0.7) and from
+    two random vertices (0.1 each), so a seed at the hub covers most sets.
+    The first round also draws the second round's ids; the final theta lies
+    between the two targets, so some of those sets join the pool and the rest
+    are dropped. The run, its pool and its counts must equal the oracle's."""
+    rng = np.random.default_rng(33)
+    n = 2048
+    edges, w = [], []
+    for v in range(1, n):
+        srcs = [0] + [int(x) for x in rng.choice(np.arange(1, n), size=2, replace=False) if x != v]
+        for j, u in enumerate(srcs):
+            edges.append((u, v))
+            w.append(int(0.7 * T32) if j == 0 else int(0.1 * T32))
+    g = synth.tiny_graph(n, edges, "lt", w)
+    k, eps = 5, 0.5
+    say("LT run that breaks in its first round")
+    r = _parity(imm, orc, g, k, eps, 11, stream, pool=True)
+    assert r.rounds == 1
+    assert r.targets[0] < r.theta < 2 * r.targets[0]
