@@ -85,6 +85,10 @@ imm_status grow(Arena& a, T** p, uint64_t* cap, uint64_t need, uint64_t keep, hi
 constexpr uint64_t kBigScratchBytes = 16ull << 30;
 constexpr uint32_t kGiantQueue = 1u << 16;
 constexpr uint32_t kHugeSlots = 16;
+constexpr uint32_t kGiantQueueMax = 1u << 20;
+constexpr double kOverRate = 1.0 / 1024;  // outgrown queues per sample that enlarge them
+// Largest pair buffer of the partitioned index build.
+constexpr uint64_t kIndexPairsBytes = 8ull << 30;
 
 // Scalars the kernels update, in one device block.
 struct DevScalars {
@@ -187,6 +191,10 @@ struct Workspace {
     uint64_t cap_pd = 0;
     uint64_t* scan_tmp = nullptr;
     uint64_t cap_scan = 0;
+    IndexPlan* iplan = nullptr;            // partitioned index build: bucket plan
+    unsigned long long* inv_pairs = nullptr;  // ... and its (set, vertex) pairs
+    uint64_t cap_pairs = 0;
+    uint64_t p_indexed = 0;  // entries of the indexed sets (a lower bound)
     // one allocation: k * kArgSlots partial maxima, then 2k queue lengths,
     // then k covered-member totals
     unsigned long long* slots = nullptr;
@@ -269,6 +277,7 @@ struct imm_graph {
     bool team_forced = false, big_forced = false, bloom_forced = false, lanes_forced = false;
     double defer_rate = 0.0;  // giant sets per sample seen while tuning
     double dense_rate = 0.0;  // IC: dense (bitmap) sets per sample seen while tuning
+    double over_rate = 0.0;   // IC: sets per sample that outgrew a bounded queue, ditto
     // mean set size seen while tuning: a fresh workspace's first staging
     // estimate, in place of a pilot batch (0 when tuning did not run)
     double mean_set_hint = 0.0;

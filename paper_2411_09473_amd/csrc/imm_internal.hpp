@@ -205,6 +205,26 @@ hipError_t launch_compact(const uint32_t* stage, const uint64_t* stage_off,
 hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
                               uint32_t count, const uint64_t* inv_off, uint32_t* cursor,
                               uint32_t* inv_set, uint32_t* err, hipStream_t st);
+// The same index segment built by radix partition (no atomic per entry):
+// buckets of 2^shift consecutive vertices, at most kBktMax of them and at
+// most kBktVtxMax vertices each (so n <= kBktMax * kBktVtxMax); tmp holds
+// cap (set, vertex) pairs, at least the segment's entries (else *err |= 1
+// and nothing is indexed); tile_groups: sets per partition tile, in units of
+// 256. cursor: n zeros. pl: one IndexPlan of device memory.
+constexpr uint32_t kBktMax = 2048;
+constexpr uint32_t kBktVtxMax = 4096;
+constexpr uint32_t kSlice = 16384;
+struct IndexPlan {
+    uint64_t off[kBktMax + 1];          // bucket ranges in the segment
+    unsigned long long cur[kBktMax];    // partition cursors
+    uint32_t sl_pre[kBktMax + 1];       // first slice of each bucket
+};
+uint32_t index_bucket_shift(uint32_t n);  // 32 when n is too large for the partition
+hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                                  uint32_t count, uint32_t tile_groups, uint32_t n,
+                                  uint32_t shift, const uint64_t* inv_off, IndexPlan* pl,
+                                  unsigned long long* tmp, uint64_t cap, uint32_t* cursor,
+                                  uint32_t* inv_set, uint32_t* err, int device, hipStream_t st);
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);

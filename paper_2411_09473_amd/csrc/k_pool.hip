@@ -208,6 +208,229 @@ __global__ __launch_bounds__(64) void inv_scatter_kernel(const uint64_t* set_off
     if (__any(bad) && lane == 0) atomicOr(err, 1u);
 }
 
+// ---- index build by radix partition
+//
+// The per-entry cursor atomic above goes to the memory side (the L2 caches of
+// the XCDs are not coherent with each other), and a hub vertex's cursor takes
+// one such atomic per occurrence. The partitioned build needs none per entry:
+//  1. plan: buckets of 2^shift consecutive vertices; bucket b's entries occupy
+//     [off[b], off[b+1]) of the segment, the list space of its vertices, so
+//     its bounds come from the segment offsets already scanned. Each bucket
+//     is cut into slices of kSlice entries, numbered across buckets.
+//  2. partition: a workgroup takes a tile of sets, counts its members per
+//     bucket in LDS, reserves each bucket's share with one atomic, and writes
+//     (set << 32 | vertex) pairs into the bucket's range.
+//  3. place: a workgroup takes a slice of one bucket and ranks its pairs per
+//     vertex with LDS counters; when the bucket has more than one slice, one
+//     atomic per vertex and slice reserves the slice's share of that
+//     vertex's list.
+// Ranks within a list depend on timing, as with the atomic scatter: the
+// selection only counts and tests a list's members, never its order.
+constexpr uint32_t kPartBS = 256;
+constexpr uint32_t kPlaceBS = 256;
+constexpr uint32_t kPlaceBatch = 4;
+
+__global__ __launch_bounds__(1024) void inv_plan_kernel(const uint64_t* io, uint32_t n,
+                                                        uint32_t shift, uint32_t nb,
+                                                        uint64_t cap, IndexPlan* pl,
+                                                        uint32_t* err) {
+    __shared__ uint64_t s_w[1024 / kWave];
+    __shared__ uint64_t s_carry;
+    const uint64_t base = io[0];
+    const uint64_t total = io[n] - base;
+    const bool fits = total <= cap;
+    if (threadIdx.x == 0) {
+        s_carry = 0;
+        if (!fits) atomicOr(err, 1u);
+    }
+    __syncthreads();
+    for (uint32_t c = 0; c <= nb; c += 1024) {
+        const uint32_t b = c + threadIdx.x;
+        uint64_t ns = 0;
+        // a segment beyond the pair buffer gets empty buckets: every
+        // reservation then fails, and no pair is written or placed
+        if (b < nb) {
+            const uint64_t v1 = min((uint64_t)(b + 1) << shift, (uint64_t)n);
+            const uint64_t a0 = io[(uint64_t)b << shift] - base, a1 = io[v1] - base;
+            pl->off[b] = fits ? a0 : 0;
+            pl->cur[b] = 0;
+            ns = fits ? (a1 - a0 + kSlice - 1) / kSlice : 0;
+        } else if (b == nb) {
+            pl->off[nb] = fits ? total : 0;
+        }
+        uint64_t excl;
+        const uint64_t tot = block_excl_scan64(ns, &excl, s_w);
+        const uint64_t carry = s_carry;
+        if (b <= nb) pl->sl_pre[b] = (uint32_t)(carry + excl);
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+}
+
+// The members of the sets [j0, j0 + kPartBS) of [.., jend), walked by the
+// whole workgroup: f(u, j) for each member u of set j, up to eight loads per
+// thread in flight.
+template <class F>
+__device__ __forceinline__ void block_members(const uint64_t* set_off, const uint32_t* set_vtx,
+                                              uint64_t j0, uint64_t jend, uint64_t* s_sb,
+                                              uint64_t* s_sa, uint64_t* s_w, F f) {
+    const uint64_t j = j0 + threadIdx.x;
+    const uint64_t jl = j < jend ? j : jend - 1;
+    const uint64_t a = set_off[jl];
+    const uint64_t sz = j < jend ? set_off[jl + 1] - a : 0;
+    uint64_t excl;
+    const uint64_t T = block_excl_scan64(sz, &excl, s_w);
+    s_sb[threadIdx.x] = excl;
+    s_sa[threadIdx.x] = a;
+    __syncthreads();
+    constexpr uint32_t kB = 8;
+    uint32_t ow = 0;
+    for (uint64_t t0 = 0; t0 < T; t0 += (uint64_t)kPartBS * kB) {
+        uint32_t u[kB], o[kB];
+#pragma unroll
+        for (uint32_t x = 0; x < kB; ++x) {
+            const uint64_t t = t0 + (uint64_t)x * kPartBS + threadIdx.x;
+            const uint64_t tc = t < T ? t : T - 1;
+            ow = owner_from(s_sb, kPartBS, tc, ow);
+            o[x] = ow;
+            u[x] = set_vtx[s_sa[ow] + (tc - s_sb[ow])];
+        }
+#pragma unroll
+        for (uint32_t x = 0; x < kB; ++x)
+            if (t0 + (uint64_t)x * kPartBS + threadIdx.x < T) f(u[x], j0 + o[x]);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kPartBS) void inv_part_kernel(const uint64_t* set_off,
+                                                           const uint32_t* set_vtx, uint64_t lo,
+                                                           uint32_t count, uint32_t tile_groups,
+                                                           uint32_t shift, uint32_t nb,
+                                                           IndexPlan* pl, unsigned long long* tmp,
+                                                           uint32_t* err) {
+    __shared__ uint32_t s_cnt[kBktMax];
+    __shared__ uint64_t s_base[kBktMax];
+    __shared__ uint64_t s_sb[kPartBS], s_sa[kPartBS], s_w[kPartBS / kWave];
+    for (uint32_t b = threadIdx.x; b < nb; b += kPartBS) s_cnt[b] = 0;
+    __syncthreads();
+    const uint64_t jend = lo + count;
+    const uint64_t g0 = lo + (uint64_t)blockIdx.x * tile_groups * kPartBS;
+    const uint64_t g1 = min(g0 + (uint64_t)tile_groups * kPartBS, jend);
+    for (uint64_t j0 = g0; j0 < g1; j0 += kPartBS)
+        block_members(set_off, set_vtx, j0, jend, s_sb, s_sa, s_w,
+                      [&](uint32_t u, uint64_t) {
+                          const uint32_t b = u >> shift;
+                          if (b < nb) atomicAdd(&s_cnt[b], 1u);
+                      });
+    // one reservation per bucket; a bucket whose range would overflow keeps
+    // its pairs out and raises *err
+    bool bad = false;
+    for (uint32_t b = threadIdx.x; b < nb; b += kPartBS) {
+        const uint32_t c = s_cnt[b];
+        uint64_t at = ~0ull;
+        if (c) {
+            at = pl->off[b] + atomicAdd(&pl->cur[b], (unsigned long long)c);
+            if (at + c > pl->off[b + 1]) {
+                at = ~0ull;
+                bad = true;
+            }
+        }
+        s_base[b] = at;
+        s_cnt[b] = 0;
+    }
+    __syncthreads();
+    for (uint64_t j0 = g0; j0 < g1; j0 += kPartBS)
+        block_members(set_off, set_vtx, j0, jend, s_sb, s_sa, s_w, [&](uint32_t u, uint64_t j) {
+            const uint32_t b = u >> shift;
+            if (b >= nb) {  // not a vertex: the pool is corrupt
+                bad = true;
+                return;
+            }
+            const uint32_t r = atomicAdd(&s_cnt[b], 1u);
+            const uint64_t at = s_base[b];
+            if (at != ~0ull) tmp[at + r] = (unsigned long long)j << 32 | u;
+        });
+    if (bad) atomicOr(err, 1u);
+}
+
+__global__ __launch_bounds__(kPlaceBS) void inv_place_kernel(const unsigned long long* tmp,
+                                                             const IndexPlan* pl, uint32_t nb,
+                                                             uint32_t shift, uint32_t n,
+                                                             const uint64_t* io, uint32_t* cursor,
+                                                             uint32_t* inv_set, uint32_t* err) {
+    __shared__ uint32_t s_cnt[kBktVtxMax];
+    __shared__ uint32_t s_base[kBktVtxMax];
+    __shared__ uint32_t s_b;
+    const uint32_t nsl = pl->sl_pre[nb];
+    bool bad = false;
+    for (uint32_t t = blockIdx.x; t < nsl; t += gridDim.x) {
+        if (threadIdx.x == 0) {  // the bucket of slice t: the last b with sl_pre[b] <= t
+            uint32_t a = 0, z = nb;
+            while (z - a > 1) {
+                const uint32_t mid = (a + z) >> 1;
+                if (pl->sl_pre[mid] <= t) a = mid; else z = mid;
+            }
+            s_b = a;
+        }
+        __syncthreads();
+        const uint32_t b = s_b;
+        const uint64_t bo = pl->off[b], be = pl->off[b + 1];
+        const uint64_t e0 = bo + (uint64_t)(t - pl->sl_pre[b]) * kSlice;
+        const uint64_t e1 = min(be, e0 + kSlice);
+        const bool whole = be - bo <= kSlice;
+        const uint32_t v0 = b << shift;
+        const uint32_t wn = min(1u << shift, n - v0);
+        for (uint32_t i = threadIdx.x; i < wn; i += kPlaceBS) s_cnt[i] = 0;
+        __syncthreads();
+        if (!whole) {
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += kPlaceBS) {
+                const uint32_t ul = (uint32_t)tmp[e] - v0;
+                if (ul < wn) atomicAdd(&s_cnt[ul], 1u);
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < wn; i += kPlaceBS) {
+                const uint32_t c = s_cnt[i];
+                s_base[i] = c ? atomicAdd(&cursor[v0 + i], c) : 0u;
+                s_cnt[i] = 0;
+            }
+            __syncthreads();
+        }
+        constexpr uint64_t kRound = (uint64_t)kPlaceBS * kPlaceBatch;
+        for (uint64_t r0 = e0; r0 < e1; r0 += kRound) {
+            unsigned long long p[kPlaceBatch];
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint64_t e = r0 + (uint64_t)x * kPlaceBS + threadIdx.x;
+                p[x] = tmp[e < e1 ? e : e1 - 1];
+            }
+            uint64_t d[kPlaceBatch], de[kPlaceBatch];
+            bool ok[kPlaceBatch];
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint32_t u = (uint32_t)p[x];
+                const uint32_t ul = u - v0;
+                ok[x] = r0 + (uint64_t)x * kPlaceBS + threadIdx.x < e1;
+                bad |= ok[x] && ul >= wn;
+                ok[x] = ok[x] && ul < wn;
+                const uint32_t uc = ok[x] ? u : v0;
+                const uint32_t r = ok[x] ? atomicAdd(&s_cnt[ul], 1u) + (whole ? 0u : s_base[ul])
+                                         : 0u;
+                d[x] = io[uc] + r;
+                de[x] = io[uc + 1];
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                if (!ok[x]) continue;
+                if (d[x] < de[x]) inv_set[d[x]] = (uint32_t)(p[x] >> 32);
+                else bad = true;
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(err, 1u);
+}
+
 __global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_vtx, uint64_t P,
                                                             uint32_t* counts) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -420,6 +643,37 @@ hipError_t launch_inv_scatter(const uint64_t* set_off, const uint32_t* set_vtx, 
     const uint32_t blocks = (count + kWave - 1) / kWave;
     hipLaunchKernelGGL(inv_scatter_kernel, dim3(blocks), dim3(kWave), 0, st, set_off, set_vtx, lo,
                        count, inv_off, cursor, inv_set, err);
+    return hipGetLastError();
+}
+
+uint32_t index_bucket_shift(uint32_t n) {
+    uint32_t shift = 0;
+    while ((((uint64_t)n + (1ull << shift) - 1) >> shift) > kBktMax) ++shift;
+    return (1u << shift) <= kBktVtxMax ? shift : 32u;
+}
+
+hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                                  uint32_t count, uint32_t tile_groups, uint32_t n,
+                                  uint32_t shift, const uint64_t* inv_off, IndexPlan* pl,
+                                  unsigned long long* tmp, uint64_t cap, uint32_t* cursor,
+                                  uint32_t* inv_set, uint32_t* err, int device, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (shift >= 32 || tile_groups == 0) return hipErrorInvalidValue;
+    const uint32_t nb = (uint32_t)(((uint64_t)n + (1ull << shift) - 1) >> shift);
+    hipLaunchKernelGGL(inv_plan_kernel, dim3(1), dim3(1024), 0, st, inv_off, n, shift, nb, cap, pl,
+                       err);
+    const uint64_t tile = (uint64_t)tile_groups * kPartBS;
+    const uint64_t tiles = (count + tile - 1) / tile;
+    hipLaunchKernelGGL(inv_part_kernel, dim3((uint32_t)tiles), dim3(kPartBS), 0, st, set_off,
+                       set_vtx, lo, count, tile_groups, shift, nb, pl, tmp, err);
+    // slices: at most cap / kSlice + nb; the grid strides over them
+    const uint64_t sl_ub = cap / kSlice + nb;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    const uint64_t grid = std::min<uint64_t>(sl_ub, (uint64_t)cus * 8);
+    hipLaunchKernelGGL(inv_place_kernel, dim3((uint32_t)std::max<uint64_t>(grid, 1)),
+                       dim3(kPlaceBS), 0, st, tmp, pl, nb, shift, n, inv_off, cursor, inv_set,
+                       err);
     return hipGetLastError();
 }
 

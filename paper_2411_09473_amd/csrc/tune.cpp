@@ -145,7 +145,10 @@ imm_status tune_graph(imm_graph* g, hipStream_t st) {
         const double ms = s.ms_sample;
         if (s.sets) g->mean_set_hint = (double)s.entries / (double)s.sets;
         g->dense_rate = (double)w.n_dense / (double)kProbeSamples;
-        if (log) std::fprintf(stderr, "imm tune: n=%u probe %.3f ms\n", g->n, ms);
+        g->over_rate = (double)w.hsc->over_n / (double)kProbeSamples;
+        if (log)
+            std::fprintf(stderr, "imm tune: n=%u probe %.3f ms, %u sets outgrew their queue\n",
+                         g->n, ms, w.hsc->over_n);
         if (ms > kProbeMs) {
             if (!g->big_forced) g->ic_big_block = 1024;
             g->tuned = true;

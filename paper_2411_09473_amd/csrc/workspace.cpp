@@ -163,6 +163,7 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.p_ub = 0;
     w.nseg = 0;
     w.indexed_sets = 0;
+    w.p_indexed = 0;
     w.n_dense = 0;
     w.dense_entries = 0;
     w.ahead_n = 0;
@@ -194,17 +195,29 @@ imm_status ws_big_scratch(Workspace& w, const imm_graph* g) {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, w.device);
     const uint64_t words = ((uint64_t)w.n + 31) / 32;
-    const uint32_t qcap = ic ? std::min<uint32_t>(w.n, kGiantQueue) : w.n;
+    // A graph on which tuning saw sets outgrow the bounded queue (the frontier
+    // of a set of hundreds of thousands of members) gets queues of n/4
+    // entries (a power of two: a ring when the set is stored as a bitmap),
+    // and a full-size slot per eight CUs-worth of threads instead of a few.
+    const bool outgrow = ic && g->over_rate > kOverRate;
+    uint32_t qcap = ic ? std::min<uint32_t>(w.n, kGiantQueue) : w.n;
+    if (outgrow) {
+        uint64_t q = kGiantQueue;
+        while (q < (uint64_t)w.n / 4 && q < kGiantQueueMax) q <<= 1;
+        qcap = (uint32_t)std::min<uint64_t>(w.n, q);
+    }
     const uint64_t per = (words + qcap) * 4;
     const uint64_t per_huge = (words + w.n) * 4;
     uint64_t slots = ic ? ic_large_slots(w.device, 256) : (uint64_t)cus;
     if (w.big_cap) slots = std::min<uint64_t>(slots, w.big_cap);
-    const uint64_t huge = ic && qcap < w.n ? kHugeSlots : 0;
     uint64_t limit = kBigScratchBytes;
     if (w.arena.budget) {
         const uint64_t left = w.arena.budget > w.arena.used ? w.arena.budget - w.arena.used : 0;
         limit = std::min(limit, left / 4);
     }
+    uint64_t huge = ic && qcap < w.n ? kHugeSlots : 0;
+    if (huge && outgrow)
+        huge = std::max<uint64_t>(huge, std::min<uint64_t>(2ull * cus, limit / 2 / per_huge));
     const uint64_t huge_bytes = huge * per_huge;
     const uint64_t room = limit > huge_bytes ? limit - huge_bytes : 0;
     slots = std::min<uint64_t>(slots, std::max<uint64_t>(1, room / per));
@@ -591,6 +604,7 @@ imm_status ws_restart_pool(Workspace& w) {
     w.p_ub = 0;
     w.nseg = 0;
     w.indexed_sets = 0;
+    w.p_indexed = 0;
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
@@ -625,6 +639,7 @@ void ws_note_pool(Workspace& w, uint64_t sets_before) {
         w.mean_size = (double)(p - w.p_exact) / (double)(w.n_sets - sets_before);
     w.p_exact = p;
     w.p_ub = p;
+    if (w.indexed_sets == w.n_sets) w.p_indexed = p;
 }
 
 namespace {
@@ -647,9 +662,32 @@ imm_status ws_index_update(Workspace& w) {
     HIP_TRY(launch_scan_u32(w.counts_acc, w.counts_prev, io, w.n, 0, w.set_off + w.indexed_sets,
                             w.scan_tmp, st));
     HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
-    HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets,
-                               (uint32_t)(w.n_sets - w.indexed_sets), io, w.inv_cursor, w.inv_set,
-                               &w.sc->err, st));
+    const uint32_t count = (uint32_t)(w.n_sets - w.indexed_sets);
+    const uint32_t shift = index_bucket_shift(w.n);
+    static const bool atomic_scatter = std::getenv("IMM_INDEX_ATOMIC") != nullptr;
+    // entries of the new sets: at most the pool bound less the indexed ones
+    const uint64_t seg_ub = w.p_ub - std::min(w.p_indexed, w.p_ub);
+    // the pairs take 8 bytes per entry of the segment: a segment too large
+    // for kIndexPairsBytes (or a quarter of what the budget leaves) is
+    // indexed by the atomic scatter instead
+    uint64_t pair_room = kIndexPairsBytes;
+    if (w.arena.budget)
+        pair_room = std::min(pair_room, (w.arena.budget - std::min(w.arena.budget, w.arena.used)) / 4);
+    const bool pairs_fit = w.cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
+    if (shift < 32 && !atomic_scatter && pairs_fit) {
+        IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, seg_ub + 1, 0, st, "index pairs"));
+        if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
+        // partition tiles of about 32 K entries
+        const double mean = std::max(1.0, (double)seg_ub / (double)count);
+        const uint32_t groups =
+            (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
+        HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, w.indexed_sets, count, groups, w.n,
+                                       shift, io, w.iplan, w.inv_pairs, w.cap_pairs,
+                                       w.inv_cursor, w.inv_set, &w.sc->err, w.device, st));
+    } else {
+        HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets, count, io, w.inv_cursor,
+                                   w.inv_set, &w.sc->err, st));
+    }
     HIP_TRY(hipMemcpyAsync(w.counts_prev, w.counts_acc, (uint64_t)w.n * 4,
                            hipMemcpyDeviceToDevice, st));
     w.timer.close(ti, st);
