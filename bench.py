@@ -44,8 +44,7 @@ PHILOX_OPS = 60
 # steady-state sampling run of that many ids), as recorded in profiles/; a
 # kernel changed since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
-    ("youtube_ic", "ic_large_kernel"): 8.162e9,
-    ("lj_lt:sample4194304", "lt_small_kernel"): 74.34e9,
+    ("lj_lt:sample16777216", "lt_small_kernel"): 292.06e9,
 }
 
 

@@ -89,6 +89,8 @@ constexpr uint32_t kGiantQueueMax = 1u << 20;
 constexpr double kOverRate = 1.0 / 1024;  // outgrown queues per sample that enlarge them
 // Largest pair buffer of the partitioned index build.
 constexpr uint64_t kIndexPairsBytes = 8ull << 30;
+// Smallest segment (in entries, by its bound) indexed by the partition.
+constexpr uint64_t kIndexPartitionMin = 1ull << 20;
 
 // Scalars the kernels update, in one device block.
 struct DevScalars {

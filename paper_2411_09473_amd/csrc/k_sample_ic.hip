@@ -409,13 +409,18 @@ __device__ __forceinline__ void lane_flush(const SampleOut& o, uint64_t* sets, u
     *edges = 0;
 }
 
-// ntask = 0: one instance (the arguments). Otherwise the tasks' positions
-// follow each other (prefix), every ticket inside one task.
+// MULTI = false: one instance (the arguments). Otherwise the tasks'
+// positions follow each other (prefix), every ticket inside one task. The
+// single-instance form is compiled apart: its arguments stay in scalar
+// registers, where a task switch would move them into vector registers and
+// halve the waves that fit.
+template <bool MULTI>
 __global__ __launch_bounds__(kWave) void ic_lane_kernel(IcGraphDev g, SampleRange rg,
                                                         SampleOut o, uint32_t* pend,
                                                         uint32_t* pend_n, uint32_t* ticket,
-                                                        const IcTask* tasks, uint32_t ntask,
+                                                        const IcTask* tasks, uint32_t ntask_in,
                                                         const uint32_t* prefix) {
+    const uint32_t ntask = MULTI ? ntask_in : 0u;
     __shared__ uint32_t s_tk, s_np;
     __shared__ uint32_t s_pend[kWave * kLaneRounds];
     __shared__ unsigned long long s_chunk;
@@ -577,15 +582,16 @@ __device__ __forceinline__ void stats_flush(const SampleOut& o, bool big, uint64
     *sets = *entries = *edges = *live = 0;
 }
 
-// ntask = 0: one instance (the arguments). Otherwise the pending lists of
-// the tasks, one after another.
-template <uint32_t TEAM>
+// MULTI = false: one instance (the arguments). Otherwise the pending lists
+// of the tasks, one after another.
+template <uint32_t TEAM, bool MULTI>
 __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, SampleRange rg,
                                                               SampleOut o, const uint32_t* pend,
                                                               const uint32_t* pend_n,
                                                               uint32_t* ticket,
                                                               const IcTask* tasks,
-                                                              uint32_t ntask) {
+                                                              uint32_t ntask_in) {
+    const uint32_t ntask = MULTI ? ntask_in : 0u;
     using T = Team<TEAM>;
     constexpr uint32_t BS = T::BS;
     __shared__ uint32_t hash[T::HSIZE];
@@ -715,17 +721,18 @@ __global__ __launch_bounds__(kWave * TEAM) void ic_bfs_kernel(IcGraphDev g, Samp
 
 // ---------------------------------------------------------------- ic_large
 
-template <uint32_t kBigBlock>
-// ntask = 0: one instance (the arguments). Otherwise the deferred lists of
-// the tasks, one after another, with b's slots sized for the largest task; a
-// set that overflows its queue goes to its task's retry list.
+// MULTI = false: one instance (the arguments). Otherwise the deferred lists
+// of the tasks, one after another, with b's slots sized for the largest
+// task; a set that overflows its queue goes to its task's retry list.
+template <uint32_t kBigBlock, bool MULTI>
 __global__ __launch_bounds__(kBigBlock, kBigBlock == 1024 ? 8 : 1) void ic_large_kernel(IcGraphDev g, SampleRange rg,
                                                              SampleOut o, const uint32_t* list,
                                                              const uint32_t* list_n,
                                                              uint32_t* fail, uint32_t* fail_n,
                                                              uint32_t* over, uint32_t* over_n,
                                                              uint32_t* ticket, BigScratch b,
-                                                             const IcTask* tasks, uint32_t ntask) {
+                                                             const IcTask* tasks, uint32_t ntask_in) {
+    const uint32_t ntask = MULTI ? ntask_in : 0u;
     __shared__ uint4 s_ent[kBigBlock];
     __shared__ uint32_t s_start[kLargePage / 32];
     __shared__ uint32_t s_lbuf[kBigBlock / kWave * kLargeLiveBuf];
@@ -938,7 +945,8 @@ hipError_t launch_ic_lane(const IcGraphDev& g, const SampleRange& r, const Sampl
     const uint32_t need = (r.count + per - 1) / per;
     if (grid > need) grid = need;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(ic_lane_kernel, dim3(grid), dim3(kWave), 0, st, g, r, o, pend, pend_n,
+    hipLaunchKernelGGL(ic_lane_kernel<false>, dim3(grid), dim3(kWave), 0, st, g, r, o, pend,
+                       pend_n,
                        ticket, (const IcTask*)nullptr, 0u, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
@@ -951,15 +959,15 @@ hipError_t launch_ic_bfs(const IcGraphDev& g, const SampleRange& r, const Sample
     if (grid == 0) return hipSuccess;
     switch (team) {
         case 1:
-            hipLaunchKernelGGL(ic_bfs_kernel<1>, dim3(grid), dim3(kWave), 0, st, g, r, o, pend,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<1, false>), dim3(grid), dim3(kWave), 0, st, g, r, o, pend,
                                pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         case 2:
-            hipLaunchKernelGGL(ic_bfs_kernel<2>, dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<2, false>), dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
                                pend, pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         case 4:
-            hipLaunchKernelGGL(ic_bfs_kernel<4>, dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<4, false>), dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
                                pend, pend_n, ticket, (const IcTask*)nullptr, 0u);
             break;
         default:
@@ -982,11 +990,11 @@ hipError_t launch_ic_large(const IcGraphDev& g, const SampleRange& r, const Samp
     if (b.slots == 0 || b.qcap == 0 || b.qcap > g.n) return hipErrorInvalidValue;
     if (b.qcap < g.n && (over == nullptr || over_n == nullptr)) return hipErrorInvalidValue;
     if (block == 256)
-        hipLaunchKernelGGL(ic_large_kernel<256>, dim3(b.slots), dim3(256), 0, st, g, r, o, list,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_large_kernel<256, false>), dim3(b.slots), dim3(256), 0, st, g, r, o, list,
                            list_n, fail, fail_n, over, over_n, ticket, b, (const IcTask*)nullptr,
                            0u);
     else if (block == 1024)
-        hipLaunchKernelGGL(ic_large_kernel<1024>, dim3(b.slots), dim3(1024), 0, st, g, r, o,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_large_kernel<1024, false>), dim3(b.slots), dim3(1024), 0, st, g, r, o,
                            list, list_n, fail, fail_n, over, over_n, ticket, b,
                            (const IcTask*)nullptr, 0u);
     else
@@ -1002,22 +1010,22 @@ hipError_t launch_ic_multi(const IcTask* tasks, uint32_t ntask, const uint32_t* 
     const IcGraphDev g{};
     const SampleRange r{};
     const SampleOut o{};
-    hipLaunchKernelGGL(ic_lane_kernel, dim3(ic_small_grid(device)), dim3(kWave), 0, st, g, r, o,
+    hipLaunchKernelGGL(ic_lane_kernel<true>, dim3(ic_small_grid(device)), dim3(kWave), 0, st, g, r, o,
                        (uint32_t*)nullptr, (uint32_t*)nullptr, tickets, tasks, ntask, prefix);
     const uint32_t grid = ic_bfs_grid(device, team);
     switch (team) {
         case 1:
-            hipLaunchKernelGGL(ic_bfs_kernel<1>, dim3(grid), dim3(kWave), 0, st, g, r, o,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<1, true>), dim3(grid), dim3(kWave), 0, st, g, r, o,
                                (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
                                tasks, ntask);
             break;
         case 2:
-            hipLaunchKernelGGL(ic_bfs_kernel<2>, dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<2, true>), dim3(grid), dim3(2 * kWave), 0, st, g, r, o,
                                (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
                                tasks, ntask);
             break;
         case 4:
-            hipLaunchKernelGGL(ic_bfs_kernel<4>, dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_bfs_kernel<4, true>), dim3(grid), dim3(4 * kWave), 0, st, g, r, o,
                                (const uint32_t*)nullptr, (const uint32_t*)nullptr, tickets + 1,
                                tasks, ntask);
             break;
@@ -1025,12 +1033,12 @@ hipError_t launch_ic_multi(const IcTask* tasks, uint32_t ntask, const uint32_t* 
             return hipErrorInvalidValue;
     }
     if (block == 256)
-        hipLaunchKernelGGL(ic_large_kernel<256>, dim3(b.slots), dim3(256), 0, st, g, r, o,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_large_kernel<256, true>), dim3(b.slots), dim3(256), 0, st, g, r, o,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                            (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
                            tickets + 2, b, tasks, ntask);
     else if (block == 1024)
-        hipLaunchKernelGGL(ic_large_kernel<1024>, dim3(b.slots), dim3(1024), 0, st, g, r, o,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(ic_large_kernel<1024, true>), dim3(b.slots), dim3(1024), 0, st, g, r, o,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                            (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
                            tickets + 2, b, tasks, ntask);

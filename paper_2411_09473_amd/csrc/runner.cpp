@@ -244,14 +244,16 @@ imm_status begin_iteration(Query& q) {
     q.before = w.n_sets;
     const uint64_t count = w.n_sets < target ? target - w.n_sets : 0;
     // An LT round of a few walks per walk slot lasts as long as its longest
-    // walk, whatever its size: such a round also draws the next round's ids
-    // (up to about four walks per slot in all), which then need no launch of
-    // their own if the next round comes. They are counted and pooled only
+    // walk, whatever its size: such a round also draws ids ahead (up to about
+    // four walks per slot in all), which then need no launch of their own.
+    // It draws up to lam* 2^(i+1) / n: the next round's target (lam' < lam*)
+    // and, should this round or the next one pass its test (LB >= n / 2^(i+1)),
+    // the final theta = lam* / LB. Ids drawn ahead are counted and pooled only
     // when a later iteration asks for them; what the run never asks for is
     // dropped, so results do not change.
     uint64_t ahead = 0;
     if (!q.final && q.sched == kSchedImm && q.g->model == IMM_LT && q.i < q.i_max && count) {
-        const double nf = std::ceil(q.lam_p / std::ldexp((double)q.g->n, -(int)(q.i + 1)));
+        const double nf = std::ceil(q.lam_s / std::ldexp((double)q.g->n, -(int)(q.i + 1)));
         const uint64_t slots = (uint64_t)lt_small_grid(q.g->device, q.g->lt_bloom_bits,
                                                        q.g->lt_lanes) * 64u / q.g->lt_lanes / 2u;
         const uint64_t cap = 4 * slots;

@@ -356,13 +356,16 @@ imm_status sample_pass(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t
 
 }  // namespace
 
-// The first k of the sets the last pass drew ahead join the pool: their
+// The next k of the sets the last pass drew ahead join the pool: their
 // offsets, members and counts (the staging, per-sample offsets and sizes of
-// that pass are still in place); the rest are dropped.
+// that pass are still in place). The rest wait for a later call; the next
+// pass or a restart of the pool drops them.
 imm_status ws_take_ahead(Workspace& w, uint64_t k) {
     hipStream_t st = w.st;
     const uint64_t split = w.ahead_split;
-    w.ahead_n = 0;
+    k = std::min(k, w.ahead_n);
+    w.ahead_n -= k;
+    w.ahead_split += k;
     if (k == 0) return IMM_OK;
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, w.n_sets + k + 1, w.n_sets + 1, st,
                  "set_off"));
@@ -664,7 +667,10 @@ imm_status ws_index_update(Workspace& w) {
     HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
     const uint32_t count = (uint32_t)(w.n_sets - w.indexed_sets);
     const uint32_t shift = index_bucket_shift(w.n);
-    static const bool atomic_scatter = std::getenv("IMM_INDEX_ATOMIC") != nullptr;
+    // IMM_INDEX_ATOMIC / IMM_INDEX_PARTITION force either build (comparisons
+    // and tests); results do not depend on it
+    const bool atomic_scatter = std::getenv("IMM_INDEX_ATOMIC") != nullptr;
+    const bool force_partition = std::getenv("IMM_INDEX_PARTITION") != nullptr;
     // entries of the new sets: at most the pool bound less the indexed ones
     const uint64_t seg_ub = w.p_ub - std::min(w.p_indexed, w.p_ub);
     // the pairs take 8 bytes per entry of the segment: a segment too large
@@ -674,7 +680,10 @@ imm_status ws_index_update(Workspace& w) {
     if (w.arena.budget)
         pair_room = std::min(pair_room, (w.arena.budget - std::min(w.arena.budget, w.arena.used)) / 4);
     const bool pairs_fit = w.cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
-    if (shift < 32 && !atomic_scatter && pairs_fit) {
+    // a small segment costs the scatter less than the partition's two extra
+    // launches
+    if (shift < 32 && !atomic_scatter && pairs_fit &&
+        (seg_ub >= kIndexPartitionMin || force_partition)) {
         IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, seg_ub + 1, 0, st, "index pairs"));
         if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
         // partition tiles of about 32 K entries

@@ -330,9 +330,10 @@ def test_lt_ids_drawn_ahead_and_dropped(imm, orc, stream):
     """An LT graph whose first round already passes IMM's lower-bound test:
     every vertex but the hub has an in-edge from the hub (weight 0.7) and from
     two random vertices (0.1 each), so a seed at the hub covers most sets.
-    The first round also draws the second round's ids; the final theta lies
-    between the two targets, so some of those sets join the pool and the rest
-    are dropped. The run, its pool and its counts must equal the oracle's."""
+    The first round also draws ids ahead (the second round's, and more); the
+    final theta lies between the first two targets, so some of those sets
+    join the pool and the rest are dropped. The run, its pool and its counts
+    must equal the oracle's."""
     rng = np.random.default_rng(33)
     n = 2048
     edges, w = [], []
@@ -347,3 +348,17 @@ def test_lt_ids_drawn_ahead_and_dropped(imm, orc, stream):
     r = _parity(imm, orc, g, k, eps, 11, stream, pool=True)
     assert r.rounds == 1
     assert r.targets[0] < r.theta < 2 * r.targets[0]
+
+
+@pytest.mark.parametrize("name,k,eps", [("rmat12_lt", 10, 0.5), ("rmat12_lt", 5, 0.2),
+                                        ("cl_lt_xs", 10, 0.3), ("cl_lt_xs", 5, 0.2)])
+def test_lt_ids_drawn_ahead_taken_over_rounds(imm, orc, stream, name, k, eps):
+    """LT runs of two or three rounds: the first round draws ids up to the
+    final theta that a pass of the next round would allow, and the later
+    rounds and the final selection take them a part at a time, without a
+    launch of their own. Targets, coverage, LB, seeds, gains and the pool
+    must equal the oracle's."""
+    g = synth.make_graph(name)
+    say(f"LT run on {name}, k={k}, eps={eps}")
+    r = _parity(imm, orc, g, k, eps, 3, stream, pool=True)
+    assert r.rounds >= 2
