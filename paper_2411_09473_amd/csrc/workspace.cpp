@@ -686,7 +686,7 @@ imm_status ws_index_update(Workspace& w) {
         (seg_ub >= kIndexPartitionMin || force_partition)) {
         IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, seg_ub + 1, 0, st, "index pairs"));
         if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
-        // partition tiles of about 32 K entries
+        // partition tiles of about 32 K entries (64 K ones were slower)
         const double mean = std::max(1.0, (double)seg_ub / (double)count);
         const uint32_t groups =
             (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
