@@ -104,6 +104,16 @@ typedef enum {
  * imm_run_batch, server queries, imm_sample) keeps every set as a list.
  * Results, exported pools and counts are the same either way. */
 #define IMM_LIST_SETS 0x100u
+/* imm_run_batch: each round's multi-instance IC sampling launch (the lane,
+ * BFS and giant-set kernels over the task table of every IC query sampling
+ * that round; Section IV-C's dynamic job balancing across instances) runs as
+ * a captured hipGraph, relaunched while the launch's shape (number of
+ * tasks, BFS team, shared scratch) repeats, else updated in place or
+ * instantiated anew. The task table and its tickets are copied before each
+ * launch; the graph holds kernels only. A round uses it when any of its IC
+ * queries sets it; on a stream that cannot be captured the kernels are
+ * launched directly. Results are unchanged. */
+#define IMM_GRAPH_SAMPLE 0x200u
 
 typedef struct imm_graph imm_graph;
 typedef struct imm_result imm_result;
@@ -160,6 +170,21 @@ typedef struct {
     uint32_t select_captures;/* ... of which needed a new capture */
     uint32_t dense_sets;     /* IC: sets of the pool kept as vertex bitmaps
                                 (see IMM_LIST_SETS) */
+    uint32_t sample_graphs;  /* with IMM_GRAPH_SAMPLE: this run's sampling
+                                rounds done by launching a captured graph */
+    uint32_t sample_captures;/* ... of which needed a new capture */
+    /* Candidate steps of the greedy: when a selection starts, the vertices
+     * whose count is at least tau (a bin edge of a count histogram chosen so
+     * that at most 4096 of them qualify; the environment variable
+     * IMM_CAND_MAX lowers that bound, 0 turns the steps off) are listed.
+     * Counts only fall, so while the best listed count is at least tau no
+     * unlisted vertex can be the argmax: from seed step 1 on (unless step 0
+     * recounted), a step takes its argmax over the list and decrements only
+     * listed vertices. A step whose best listed count falls below tau halts
+     * the selection; every count is then recounted exactly and the remaining
+     * steps run in full. Results are unchanged. */
+    uint32_t cand_steps;     /* seed steps whose argmax ran over the list */
+    uint32_t cand_halts;     /* selections that halted and finished in full */
 } imm_stats;
 
 /* Thread-local description of the last error of this thread. */

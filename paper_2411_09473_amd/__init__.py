@@ -36,6 +36,7 @@ IMM_DEVICE_PTRS, IMM_KEEP_POOL, IMM_TIMING, IMM_GRAPH_SELECT = 0x1, 0x2, 0x4, 0x
 IMM_FRESH_FINAL, IMM_EARLY_STOP = 0x10, 0x20
 IMM_UPDATE_DECREMENT, IMM_UPDATE_RECOUNT = 0x40, 0x80
 IMM_LIST_SETS = 0x100
+IMM_GRAPH_SAMPLE = 0x200
 _NAMES = {1: "IMM_EINVAL", 2: "IMM_ENOMEM", 3: "IMM_EOVERFLOW", 4: "IMM_EDEVICE",
           5: "IMM_EBUSY", 6: "IMM_ECANCELLED"}
 
@@ -65,7 +66,9 @@ class imm_stats(C.Structure):
                 ("big_block", C.c_uint32), ("bloom_bits", C.c_uint32),
                 ("device_bytes", C.c_uint64), ("ms_queue", C.c_double),
                 ("walk_lanes", C.c_uint32), ("select_graphs", C.c_uint32),
-                ("select_captures", C.c_uint32), ("dense_sets", C.c_uint32)]
+                ("select_captures", C.c_uint32), ("dense_sets", C.c_uint32),
+                ("sample_graphs", C.c_uint32), ("sample_captures", C.c_uint32),
+                ("cand_steps", C.c_uint32), ("cand_halts", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

@@ -150,6 +150,30 @@ struct SelectGraph {
     ~SelectGraph();
 };
 
+// The multi-instance IC sampling launch of a batched round (three kernels
+// over a task table in device memory) as an executable graph: relaunched
+// while the launch's arguments repeat (they are device pointers and shape
+// only; the table's contents change every round and are copied before each
+// launch), else updated in place or instantiated anew.
+struct SampleGraph {
+    hipGraphExec_t exec = nullptr;
+    const IcTask* tasks = nullptr;
+    const uint32_t* prefix = nullptr;
+    uint32_t* tickets = nullptr;
+    uint32_t ntask = 0, team = 0, block = 0;
+    BigScratch b{};
+    int device = -1;
+    // 1: the graph ran; 0: nothing launched (the caller launches directly);
+    // -1: the graph launch failed
+    int launch(const IcTask* tasks, uint32_t ntask, const uint32_t* prefix, uint32_t* tickets,
+               uint32_t team, uint32_t block, const BigScratch& b, int device, hipStream_t st,
+               bool* captured);
+    SampleGraph() = default;
+    SampleGraph(const SampleGraph&) = delete;
+    SampleGraph& operator=(const SampleGraph&) = delete;
+    ~SampleGraph();
+};
+
 struct Workspace {
     int device = 0;
     uint32_t n = 0;
@@ -211,6 +235,17 @@ struct Workspace {
     SelectDesc* desc_d = nullptr; // one descriptor, for selection run alone
     SelectDesc desc_h{};          // its host copy (kept while the copy is queued)
     SelectGraph sel_graph;        // its seed steps as a captured graph (IMM_GRAPH_SELECT)
+    // candidate steps of the greedy (SelectDesc::cand): the list, its
+    // bitmap, the state block and a pinned copy of the state's first words;
+    // the last selection's descriptor (to finish a halted selection); list
+    // bound (IMM_CAND_MAX, default kCandMax; 0: none); steps taken over the
+    // list and halts since the last reset
+    uint32_t* cand = nullptr;
+    uint32_t* cand_bits = nullptr;
+    uint32_t* cand_state = nullptr;
+    uint32_t* cand_h = nullptr;
+    SelectDesc desc_last{};
+    uint64_t cand_steps = 0, cand_halts = 0;
     uint32_t* big = nullptr;   // giant-set slots: bitmap + bounded queue each
     uint32_t big_slots = 0;
     uint32_t big_qcap = 0;
@@ -434,6 +469,7 @@ private:
     size_t cap_descs_ = 0;
     hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;
     SelectGraph graph_;  // the batched seed steps (IMM_GRAPH_SELECT)
+    SampleGraph sgraph_; // the multi-instance sampling launch (IMM_GRAPH_SAMPLE)
 };
 
 // Runs queries independently of each other, each on its own stream: the

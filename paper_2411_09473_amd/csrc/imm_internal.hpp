@@ -314,7 +314,28 @@ struct SelectDesc {
     uint64_t dense_entries = 0;
     uint32_t n_dense = 0, dense_words = 0;
     uint32_t dense_lo = 0, dense_cnt = 0;
+    // Candidate steps (null cand: none). The vertices whose working count is
+    // at least tau when the selection starts (at most kCandMax of them, tau
+    // a bin edge of a count histogram) are listed in cand and flagged in
+    // cand_bits. Counts only fall, so a vertex outside the list never counts
+    // tau or more. From step 1 on, if step 0 did not recount, a step takes
+    // its argmax over the list alone, and the decrements skip the vertices
+    // outside it: while the best listed count is at least tau, it beats
+    // every unlisted vertex, whose stale count is never read. A step whose
+    // best listed count falls below tau halts the selection there; the host
+    // then recounts every count exactly and runs the remaining steps in full.
+    // cand_state: [0] 1 when steps 1.. use the list (decided by step 1's
+    // argmax), 2 when they do not; [1] the halting step (0: none); [2] tau;
+    // [3] the list length; [4 ..] the histogram (kCandBins bins).
+    const uint32_t* cand = nullptr;
+    const uint32_t* cand_bits = nullptr;
+    uint32_t* cand_state = nullptr;
 };
+// Candidate list bound, and the count histogram's bins: counts 0..15 one bin
+// each, then eight bins per octave (bins ascend with the count).
+constexpr uint32_t kCandMax = 4096;
+constexpr uint32_t kCandBins = 240;
+constexpr uint32_t kCandHead = 4;
 enum : uint32_t { kUpdateAdaptive = 0, kUpdateDecrement = 1, kUpdateRecount = 2 };
 constexpr uint32_t kMaxSegments = 64;
 // A recount gives a vertex with a longer index list a wave of its own.
@@ -335,6 +356,17 @@ hipError_t launch_select_step(const SelectDesc* descs, uint32_t nq, uint32_t t,
 uint32_t dense_blocks(uint32_t n_dense, uint32_t words);
 // cw = cacc (+ dc, the dense sets' counts, when given), and the list of
 // vertices with cacc > kHeavyList (*n_heavy zeroed).
+// The candidate list of a selection whose working counts cw are in place:
+// the histogram of cw (cand_state[kCandHead ..], zeroed before), then tau,
+// the list and the bitmap (cand_state[3] zeroed before). cand_max <= kCandMax
+// bounds the list (0: no list, every step in full).
+hipError_t launch_cand_build(const uint32_t* cw, uint32_t n, uint32_t cand_max, uint32_t* cand,
+                             uint32_t* cand_bits, uint32_t* cand_state, hipStream_t st);
+// An exact recount of every working count from the index and the covered
+// sets (descs[0]; its update field must be kUpdateRecount), as a recounting
+// seed step does; chosen seeds keep their sentinel.
+hipError_t launch_select_recount(const SelectDesc* descs, uint32_t t, uint32_t sel_blocks,
+                                 uint32_t dense_blocks, hipStream_t st);
 hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_t* cw,
                                uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st);
 

@@ -75,6 +75,9 @@ struct SelView {
     IMM_GLOBAL uint32_t* dense_mark;
     uint64_t dense_entries;
     uint32_t n_dense, dense_words;
+    const IMM_GLOBAL uint32_t* cand;
+    const IMM_GLOBAL uint32_t* cand_bits;
+    IMM_GLOBAL uint32_t* cand_state;
 };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -106,7 +109,36 @@ __device__ __forceinline__ SelView view_of(const SelectDesc& d) {
                    d.arg_lo,       d.arg_cnt,      d.sel_lo,       d.sel_cnt,
                    d.update,       glb(d.dense_bits), glb(d.dense_sid), glb(d.dense_size),
                    glb(d.dense_list), glb(d.dense_list_n), glb(d.dense_mark), d.dense_entries,
-                   d.n_dense,      d.dense_words};
+                   d.n_dense,      d.dense_words, glb(d.cand), glb(d.cand_bits),
+                   glb(d.cand_state)};
+}
+
+// Candidate steps (SelectDesc::cand). A step at or after the halting step
+// does nothing; the host finishes the selection.
+__device__ __forceinline__ bool step_halted(const SelView& d, uint32_t t) {
+    if (!d.cand_state) return false;
+    const uint32_t h = d.cand_state[1];
+    return h != 0u && t >= h;
+}
+// Whether step t >= 1 takes its argmax over the list and filters its
+// decrements (decided by step 1's argmax).
+__device__ __forceinline__ bool cand_step(const SelView& d, uint32_t t) {
+    return d.cand_state && t >= 1 && d.cand_state[0] == 1u;
+}
+
+// The count histogram's bin of c and the smallest count of bin b.
+__device__ __forceinline__ uint32_t cand_bin(uint32_t c) {
+    if (c < 16u) return c;
+    const uint32_t e = 31u - (uint32_t)__clz(c);
+    return 16u + 8u * (e - 4u) + ((c >> (e - 3u)) & 7u);
+}
+__device__ __forceinline__ uint32_t cand_edge(uint32_t b) {
+    if (b < 16u) return b;
+    const uint32_t e = 4u + (b - 16u) / 8u, sub = (b - 16u) % 8u;
+    return (8u + sub) << (e - 3u);
+}
+__device__ __forceinline__ bool is_cand(const SelView& d, uint32_t u) {
+    return (d.cand_bits[u >> 5] >> (u & 31u)) & 1u;
 }
 
 // Device-scope relaxed atomics on global memory (what atomicAdd and friends do).
@@ -159,6 +191,57 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
     const uint32_t n = d.n;
     const uint32_t blk = blockIdx.x - d.arg_lo;
     const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    if (d.cand_state && t >= 1) {
+        if (step_halted(d, t)) return;
+        bool use;
+        if (t == 1) {
+            // the list serves steps 1.. unless it is empty, the update is
+            // fixed, or step 0 recounted (its seed covered much of the pool)
+            const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
+            use = d.cand_state[3] != 0u && d.update == kUpdateAdaptive &&
+                  d.cov_entries[0] * 4ull <= pool;
+            if (blk == 0 && tid == 0) d.cand_state[0] = use ? 1u : 2u;
+        } else {
+            use = d.cand_state[0] == 1u;
+        }
+        if (use) {
+            // the list's counts, four per thread per round, spread over the
+            // instance's workgroups (a small graph has one)
+            const uint32_t nc = d.cand_state[3];
+            const uint32_t first = blk * kArgBS * 4u;
+            if (first >= nc) {
+                if (blk == 0 && tid == 0 && d.n_dense) d.dense_mark[t] = *d.dense_list_n;
+                return;
+            }
+            uint64_t best = 0;
+            for (uint32_t base = first; base < nc; base += d.arg_cnt * kArgBS * 4u) {
+                uint32_t v[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const uint32_t i = base + u * kArgBS + tid;
+                    v[u] = d.cand[i < nc ? i : nc - 1];
+                }
+                uint32_t c[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) c[u] = cw[v[u]];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const uint64_t k = vkey(c[u], v[u]);
+                    best = k > best ? k : best;
+                }
+            }
+            best = wave_max64(best);
+            if (lane == 0) s_w[w] = best;
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t b = s_w[0];
+                for (uint32_t x = 1; x < kArgBS / kWave; ++x) b = s_w[x] > b ? s_w[x] : b;
+                g_max64(&d.slots[(uint64_t)t * kArgSlots + blk % kArgSlots], (unsigned long long)b);
+                if (blk == 0 && d.n_dense) d.dense_mark[t] = *d.dense_list_n;
+            }
+            return;
+        }
+    }
     const uint32_t gtid = blk * kArgBS + tid, gthreads = d.arg_cnt * kArgBS;
     uint64_t best = 0;
     const uint32_t n4 = n >> 2;
@@ -213,8 +296,15 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
+    if (step_halted(d, t)) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t m = slots_max(d.slots + (uint64_t)t * kArgSlots);
+    if (cand_step(d, t) && (uint32_t)(m >> 32) < d.cand_state[2]) {
+        // no listed vertex reaches tau: an unlisted one might now be the
+        // argmax, so the selection halts here (every workgroup agrees)
+        if (blk == 0 && threadIdx.x == 0) d.cand_state[1] = t;
+        return;
+    }
     const uint32_t v = ~(uint32_t)m;
     if (blk == 0 && threadIdx.x == 0) {
         d.seeds[t] = v;
@@ -487,6 +577,7 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
+    if (step_halted(d, t)) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
     const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
     if (d.update == kUpdateRecount ||
@@ -499,6 +590,8 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     if (blk * kDecBS >= ns && blk * wpb >= nb) return;
     IMM_GLOBAL uint32_t* cw = d.cw;
     const uint32_t v = d.seeds[t];
+    // a candidate step decrements only the listed vertices
+    const bool filt = cand_step(d, t);
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t threads = d.sel_cnt * kDecBS;
     const uint32_t nw = d.sel_cnt * wpb;
@@ -521,16 +614,24 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
 #pragma unroll
             for (uint32_t y = 0; y < 4; ++y)
                 u[y] = d.set_vtx[ch.off + (x + y < ch.len ? x + y : ch.len - 1)];
+            bool keep[4];
+            if (filt) {
+#pragma unroll
+                for (uint32_t y = 0; y < 4; ++y) keep[y] = is_cand(d, u[y]);
+            } else {
+#pragma unroll
+                for (uint32_t y = 0; y < 4; ++y) keep[y] = true;
+            }
 #pragma unroll
             for (uint32_t y = 0; y < 4; ++y)
-                if (x + y < ch.len && u[y] != v) agg_dec(u[y], agg, h_key, h_cnt, cw);
+                if (x + y < ch.len && u[y] != v && keep[y]) agg_dec(u[y], agg, h_key, h_cnt, cw);
         }
     }
     for (uint32_t c = wid; c < nb; c += nw) {
         const Chunk ch = load_chunk(d.chunks + (d.chunk_cap - 1 - c));
         if (lane < ch.len) {
             const uint32_t u = d.set_vtx[ch.off + lane];
-            if (u != v) agg_dec(u, agg, h_key, h_cnt, cw);
+            if (u != v && (!filt || is_cand(d, u))) agg_dec(u, agg, h_key, h_cnt, cw);
         }
     }
     if (agg) {
@@ -557,6 +658,7 @@ __global__ __launch_bounds__(kColBS) void dense_update_kernel(const SelectDesc* 
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k || d.n_dense == 0) return;
+    if (step_halted(d, t)) return;
     const uint32_t blk = blockIdx.x - descs[q].dense_lo;
     const uint32_t wblocks = (d.dense_words + 63) / 64;
     const uint32_t wb = blk % wblocks, c = blk / wblocks;
@@ -588,6 +690,93 @@ __global__ __launch_bounds__(kColBS) void dense_update_kernel(const SelectDesc* 
         if (d.cw[u] == kSelected) continue;
         if (recount) g_add(&d.cw[u], out[x]);
         else g_sub(&d.cw[u], out[x]);
+    }
+}
+
+// The histogram of the working counts over kCandBins bins (LDS per
+// workgroup, then one global add per bin), zero counts left out.
+__global__ __launch_bounds__(256) void cand_hist_kernel(const uint32_t* cw, uint32_t n,
+                                                        uint32_t* hist) {
+    __shared__ uint32_t s_h[kCandBins];
+    for (uint32_t x = threadIdx.x; x < kCandBins; x += 256) s_h[x] = 0u;
+    __syncthreads();
+    const uint32_t stride = gridDim.x * 256;
+    const uint32_t n4 = n >> 2;
+    const uint4* cw4 = reinterpret_cast<const uint4*>(cw);
+    for (uint32_t x = blockIdx.x * 256 + threadIdx.x; x < n4; x += stride) {
+        const uint4 c = cw4[x];
+        if (c.x) atomicAdd(&s_h[cand_bin(c.x)], 1u);
+        if (c.y) atomicAdd(&s_h[cand_bin(c.y)], 1u);
+        if (c.z) atomicAdd(&s_h[cand_bin(c.z)], 1u);
+        if (c.w) atomicAdd(&s_h[cand_bin(c.w)], 1u);
+    }
+    const uint32_t tail = (n4 << 2) + blockIdx.x * 256 + threadIdx.x;
+    if (tail < n && blockIdx.x * 256 + threadIdx.x < 4u) {
+        const uint32_t c = cw[tail];
+        if (c) atomicAdd(&s_h[cand_bin(c)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < kCandBins; x += 256)
+        if (s_h[x]) atomicAdd(&hist[x], s_h[x]);
+}
+
+// tau, the lowest bin edge with at most cand_max vertices counting that much
+// or more (never below 1; no list when even the top bin holds more), then
+// one bitmap word (32 vertices) per thread and the list, one reservation
+// per wave.
+__global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint32_t n,
+                                                        uint32_t cand_max, uint32_t* cand,
+                                                        uint32_t* cand_bits, uint32_t* state) {
+    __shared__ uint32_t s_tau;
+    if (threadIdx.x == 0) {
+        const uint32_t* hist = state + kCandHead;
+        uint32_t acc = 0, b = kCandBins;
+        for (uint32_t x = kCandBins; x-- > 1;) {
+            acc += hist[x];
+            if (acc > cand_max) break;
+            b = x;
+        }
+        const uint32_t tau = b < kCandBins ? cand_edge(b) : 0xFFFFFFFFu;
+        s_tau = tau;
+        if (blockIdx.x == 0) state[2] = tau;
+    }
+    __syncthreads();
+    const uint32_t tau = s_tau;
+    const uint32_t words = (n + 31) / 32;
+    const uint32_t wd = blockIdx.x * 256 + threadIdx.x;
+    uint32_t bits = 0;
+    if (wd < words) {
+        const uint32_t v0 = wd * 32u;
+        if (v0 + 32u <= n) {
+            const uint4* p = reinterpret_cast<const uint4*>(cw + v0);
+            uint4 c[8];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) c[j] = p[j];
+#pragma unroll
+            for (uint32_t j = 0; j < 8; ++j) {
+                bits |= (uint32_t)(c[j].x >= tau) << (4 * j);
+                bits |= (uint32_t)(c[j].y >= tau) << (4 * j + 1);
+                bits |= (uint32_t)(c[j].z >= tau) << (4 * j + 2);
+                bits |= (uint32_t)(c[j].w >= tau) << (4 * j + 3);
+            }
+        } else {
+            for (uint32_t j = 0; v0 + j < n; ++j) bits |= (uint32_t)(cw[v0 + j] >= tau) << j;
+        }
+        cand_bits[wd] = bits;
+    }
+    const uint32_t cnt = (uint32_t)__popc(bits);
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+    if (tot == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == kWave - 1) base = atomicAdd(&state[3], tot);
+    base = __shfl(base, kWave - 1, kWave);
+    uint32_t pos = base + incl - cnt;
+    while (bits) {
+        const uint32_t j = (uint32_t)__ffs(bits) - 1u;
+        bits &= bits - 1u;
+        if (pos < kCandMax) cand[pos] = wd * 32u + j;
+        ++pos;
     }
 }
 
@@ -635,6 +824,28 @@ hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(select_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cacc, dc, cw,
                        n, heavy, n_heavy);
+    return hipGetLastError();
+}
+
+hipError_t launch_cand_build(const uint32_t* cw, uint32_t n, uint32_t cand_max, uint32_t* cand,
+                             uint32_t* cand_bits, uint32_t* cand_state, hipStream_t st) {
+    if (n == 0 || cand_max == 0) return hipSuccess;
+    if (cand_max > kCandMax) cand_max = kCandMax;
+    const uint32_t hb = std::min<uint32_t>(256u, (n + 1023u) / 1024u);
+    hipLaunchKernelGGL(cand_hist_kernel, dim3(hb), dim3(256), 0, st, cw, n,
+                       cand_state + kCandHead);
+    const uint32_t words = (n + 31) / 32;
+    hipLaunchKernelGGL(cand_list_kernel, dim3((words + 255) / 256), dim3(256), 0, st, cw, n,
+                       cand_max, cand, cand_bits, cand_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_recount(const SelectDesc* descs, uint32_t t, uint32_t sel_blocks,
+                                 uint32_t dense_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(decrement_kernel, dim3(sel_blocks), dim3(kDecBS), 0, st, descs, 1u, t);
+    if (dense_blocks)
+        hipLaunchKernelGGL(dense_update_kernel, dim3(dense_blocks), dim3(kColBS), 0, st, descs,
+                           1u, t);
     return hipGetLastError();
 }
 

@@ -111,6 +111,7 @@ struct Query {
     std::string err;
     double t0 = 0, ms_select = 0;
     uint32_t select_graphs = 0, select_captures = 0;  // BatchRunner with IMM_GRAPH_SELECT
+    uint32_t sample_graphs = 0, sample_captures = 0;  // ... with IMM_GRAPH_SAMPLE
     uint64_t bytes = 0;  // device bytes of the workspace when finished
     SelectDesc desc{};
     // AsyncRunner: the event that marks the end of the queued work, and
@@ -329,6 +330,8 @@ imm_status end_iteration(Query& q) {
     r.stats.walk_lanes = q.g->model == IMM_LT ? q.g->lt_lanes : 0;
     r.stats.select_graphs = q.select_graphs;
     r.stats.select_captures = q.select_captures;
+    r.stats.sample_graphs = q.sample_graphs;
+    r.stats.sample_captures = q.sample_captures;
     if (q.p.flags & IMM_KEEP_POOL) {
         IMM_TRY(ws_export_pool(w, &r.set_off, &r.set_vtx, nullptr));
         r.has_pool = true;
@@ -600,7 +603,19 @@ imm_status BatchRunner::multi_pass(const std::vector<Query*>& qs) {
     uint32_t* tkd = const_cast<uint32_t*>(pd) + kMaxTasks + 1;
     uint32_t* bits = static_cast<uint32_t*>(multi_buf_);
     const BigScratch b{bits, bits + (uint64_t)slots * words, words, slots, kGiantQueue};
-    HIP_TRY(launch_ic_multi(td, nt, pd, tkd, team, 256, b, dev, main_));
+    bool graph = false;
+    for (auto* q : qs) graph |= (q->p.flags & IMM_GRAPH_SAMPLE) != 0;
+    int launched = 0;
+    if (graph) {
+        bool captured = false;
+        launched = sgraph_.launch(td, nt, pd, tkd, team, 256, b, dev, main_, &captured);
+        if (launched < 0) return fail(IMM_EDEVICE, "batched sampling: graph launch failed");
+        for (auto* q : qs) {
+            q->sample_graphs += launched > 0 ? 1u : 0u;
+            q->sample_captures += launched > 0 && captured ? 1u : 0u;
+        }
+    }
+    if (launched == 0) HIP_TRY(launch_ic_multi(td, nt, pd, tkd, team, 256, b, dev, main_));
     for (auto* q : qs) IMM_TRY(ws_after_multi(*q->w));
     // the host table is rewritten by the next launch only after main_ has
     // been synchronised (step waits for it before the selections)

@@ -125,6 +125,7 @@ Workspace::~Workspace() {
     if (hp) (void)hipHostFree(hp);
     if (herr) (void)hipHostFree(herr);
     if (gains_h) (void)hipHostFree(gains_h);
+    if (cand_h) (void)hipHostFree(cand_h);
 }
 
 IcGraphDev ic_view(const imm_graph* g) {
@@ -150,6 +151,11 @@ imm_status ws_init(Workspace& w, uint32_t n, int device, hipStream_t st, uint64_
     IMM_TRY(w.arena.alloc((void**)&w.heavy, (uint64_t)n * 4 + 16, "heavy vertex list"));
     IMM_TRY(w.arena.alloc((void**)&w.inv_cursor, (uint64_t)n * 4, "inv_cursor"));
     IMM_TRY(w.arena.alloc((void**)&w.desc_d, sizeof(SelectDesc), "select descriptor"));
+    IMM_TRY(w.arena.alloc((void**)&w.cand, (uint64_t)kCandMax * 4, "candidate list"));
+    IMM_TRY(w.arena.alloc((void**)&w.cand_bits, ((uint64_t)n + 31) / 32 * 4 + 16,
+                          "candidate bitmap"));
+    IMM_TRY(w.arena.alloc((void**)&w.cand_state, (kCandHead + kCandBins) * 4, "candidate state"));
+    HIP_TRY(hipHostMalloc((void**)&w.cand_h, kCandHead * 4, hipHostMallocDefault));
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, 1024, 0, st, "set_off"));
     return IMM_OK;
 }
@@ -168,6 +174,8 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.dense_entries = 0;
     w.ahead_n = 0;
     w.list_only = false;
+    w.cand_steps = 0;
+    w.cand_halts = 0;
     if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
@@ -755,6 +763,17 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
     // the whole block: its layout follows the capacity cap_k, not this k
     HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
     if (w.nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
+    // the candidate list from the working counts (steps 1 .. k-1 may use it);
+    // IMM_CAND_MAX bounds it (0: every step in full)
+    uint32_t cand_max = kCandMax;
+    if (const char* e = std::getenv("IMM_CAND_MAX"))
+        cand_max = (uint32_t)std::min<long>(std::max<long>(std::atol(e), 0), (long)kCandMax);
+    const bool cand = cand_max > 0 && k >= 2;
+    if (cand) {
+        HIP_TRY(hipMemsetAsync(w.cand_state, 0, (kCandHead + kCandBins) * 4, st));
+        HIP_TRY(launch_cand_build(w.counts_work, w.n, cand_max, w.cand, w.cand_bits,
+                                  w.cand_state, st));
+    }
     *d = SelectDesc{w.counts_work, w.counts_acc, w.heavy,     w.heavy + w.n, w.inv_offs,
                     w.inv_set,     w.set_off,    w.set_vtx,   w.covered,     w.slots,
                     w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
@@ -771,18 +790,64 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
         d->n_dense = (uint32_t)w.n_dense;
         d->dense_words = w.dense_words;
     }
+    if (cand) {
+        d->cand = w.cand;
+        d->cand_bits = w.cand_bits;
+        d->cand_state = w.cand_state;
+    }
+    w.desc_last = *d;
     return IMM_OK;
 }
 
 imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));
+    if (w.desc_last.cand_state)
+        HIP_TRY(hipMemcpyAsync(w.cand_h, w.cand_state, kCandHead * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(w.hp, w.set_off + w.n_sets, 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(w.herr, &w.sc->err, 4, hipMemcpyDeviceToHost, st));
     return IMM_OK;
 }
 
+// A selection that halted at step h (its best listed count fell below tau):
+// every working count recounted exactly from the index and the covered sets,
+// then steps h .. k-1 in full, on the workspace's stream, waited for.
+imm_status ws_select_resume(Workspace& w, uint32_t k, uint32_t h) {
+    hipStream_t st = w.st;
+    SelectDesc d = w.desc_last;
+    d.cand = nullptr;
+    d.cand_bits = nullptr;
+    d.cand_state = nullptr;
+    d.arg_lo = 0;
+    d.arg_cnt = argmax_blocks(w.n);
+    d.sel_lo = 0;
+    d.sel_cnt = select_blocks(w.device, w.n_sets, 1);
+    d.dense_lo = 0;
+    d.dense_cnt = dense_blocks(d.n_dense, d.dense_words);
+    SelectDesc r = d;
+    r.update = kUpdateRecount;
+    const int ts = w.timer.open(3, st);
+    HIP_TRY(hipMemcpyAsync(w.desc_d, &r, sizeof(r), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_select_recount(w.desc_d, h - 1, d.sel_cnt, d.dense_cnt, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpyAsync(w.desc_d, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    for (uint32_t t = h; t < k; ++t)
+        HIP_TRY(launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, d.dense_cnt, st));
+    w.timer.close(ts, st);
+    HIP_TRY(hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IMM_OK;
+}
+
 imm_status ws_select_finish(Workspace& w, uint32_t k, uint64_t sets_before, uint64_t* covered) {
     if (*w.herr) return fail(IMM_EDEVICE, "internal error: occurrence counts disagree with the pool");
+    if (w.desc_last.cand_state) {
+        const uint32_t h = w.cand_h[1];
+        if (w.cand_h[0] == 1u) w.cand_steps += (h ? h : k) - 1u;
+        if (h) {
+            ++w.cand_halts;
+            IMM_TRY(ws_select_resume(w, k, h));
+        }
+    }
     ws_note_pool(w, sets_before);
     uint64_t c = 0;
     for (uint32_t i = 0; i < k; ++i) c += w.gains_h[i];
@@ -843,6 +908,66 @@ int SelectGraph::launch(const SelectDesc* d, uint32_t q, uint32_t km, uint32_t a
         arg_total = at;
         sel_total = stot;
         dense_total = dtot;
+        *captured = true;
+    }
+    return hipGraphLaunch(exec, st) == hipSuccess ? 1 : -1;
+}
+
+SampleGraph::~SampleGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+int SampleGraph::launch(const IcTask* t, uint32_t nt, const uint32_t* pre, uint32_t* tk,
+                        uint32_t tm, uint32_t blk, const BigScratch& bs, int dev, hipStream_t st,
+                        bool* captured) {
+    *captured = false;
+    const bool same = exec && t == tasks && nt == ntask && pre == prefix && tk == tickets &&
+                      tm == team && blk == block && bs.bitmaps == b.bitmaps &&
+                      bs.queues == b.queues && bs.words == b.words && bs.slots == b.slots &&
+                      bs.qcap == b.qcap && dev == device;
+    if (!same) {
+        // kernels only: the task table and its tickets are copied to the
+        // device before every launch of the graph
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        const hipError_t le = launch_ic_multi(t, nt, pre, tk, tm, blk, bs, dev, st);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (le != hipSuccess || ce != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return 0;
+        }
+        bool have = false;
+        if (exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            have = hipGraphExecUpdate(exec, graph, &bad, &res) == hipSuccess &&
+                   res == hipGraphExecUpdateSuccess;
+            if (!have) {
+                // a refused update is no failure: clear it and instantiate anew
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+            }
+        }
+        if (!have) have = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(graph);
+        if (!have) {
+            exec = nullptr;
+            (void)hipGetLastError();
+            return 0;
+        }
+        tasks = t;
+        ntask = nt;
+        prefix = pre;
+        tickets = tk;
+        team = tm;
+        block = blk;
+        b = bs;
+        device = dev;
         *captured = true;
     }
     return hipGraphLaunch(exec, st) == hipSuccess ? 1 : -1;
@@ -998,6 +1123,8 @@ void fill_stats(Workspace& w, imm_stats* s) {
     s->main_edges = t[kStMainEdges];
     s->main_live = t[kStMainLive];
     s->dense_sets = (uint32_t)std::min<uint64_t>(w.n_dense, 0xFFFFFFFFu);
+    s->cand_steps = (uint32_t)std::min<uint64_t>(w.cand_steps, 0xFFFFFFFFu);
+    s->cand_halts = (uint32_t)std::min<uint64_t>(w.cand_halts, 0xFFFFFFFFu);
 }
 
 }  // namespace imm

@@ -91,6 +91,49 @@ def test_batch_graph_select_replays(imm, orc):
         assert re_.stats["select_graphs"] == 0
 
 
+@pytest.mark.parametrize("select_graph", [False, True])
+def test_batch_graph_sample_replays(imm, orc, select_graph):
+    """IMM_GRAPH_SAMPLE: the IC queries of a batch sample each round through
+    one captured multi-instance launch, relaunched while the set of sampling
+    queries repeats and updated or captured anew when it changes (queries of
+    different k and eps stop sampling at different rounds), with each round's
+    compaction, index and selection run eagerly (or, with select_graph, as
+    their own captured graph) between the replays. Every round's coverage and
+    the seeds equal the oracle's and the eager batch's."""
+    import torch
+    s = torch.cuda.Stream()  # a capturable stream (default priority)
+    names = ["rmat12_wc", "rmat12_p10", "youtube_ic_s"]
+    graphs = {nm: synth.make_graph(nm) for nm in names}
+    dev = {nm: imm.graph_from(g, stream=s) for nm, g in graphs.items()}
+    qs = []
+    for nm in names:
+        sp = synth.WORKLOADS[nm]
+        qs.append((nm, dict(k=sp["k"], epsilon=sp["eps"], ell=sp["ell"], seed=sp["seed"])))
+    qs.append(("rmat12_wc", dict(k=25, epsilon=0.3, ell=1.0, seed=7)))
+    qs.append(("rmat12_p10", dict(k=5, epsilon=0.5, ell=1.0, seed=11)))
+    fl = imm.IMM_GRAPH_SAMPLE | (imm.IMM_GRAPH_SELECT if select_graph else 0)
+    say(f"graph-captured sampling rounds, {len(qs)} IC queries, select graph {select_graph}")
+    rg = imm.imm_run_batch([(dev[nm], dict(q, flags=fl)) for nm, q in qs], stream=s)
+    re_ = imm.imm_run_batch([(dev[nm], q) for nm, q in qs], stream=s)
+    replays = 0
+    for (nm, q), a, b in zip(qs, rg, re_):
+        say(f"  check {nm} k={q['k']} eps={q['epsilon']} seed={q['seed']}: rounds {a.rounds}, "
+            f"sample graphs {a.stats['sample_graphs']} ({a.stats['sample_captures']} captured)")
+        o = orc.imm(graphs[nm], q["k"], q["epsilon"], q["ell"], q["seed"],
+                    threads=oracle_threads())
+        _check(a, o)
+        _check(b, o)
+        assert a.stats["sample_graphs"] >= 1
+        assert b.stats["sample_graphs"] == 0 and b.stats["sample_captures"] == 0
+        replays += a.stats["sample_graphs"] - a.stats["sample_captures"]
+        if select_graph:
+            assert a.stats["select_graphs"] == a.rounds + 1
+        else:
+            assert a.stats["select_graphs"] == 0
+    # the set of sampling queries repeated at least once: a graph was relaunched
+    assert replays > 0
+
+
 def test_batch_of_64_instances(imm, orc, stream):
     """The multi-instance workload's draws (k, eps, degree, seeds) at graph
     scale <= 13: 64 queries on 64 graphs in one call."""
