@@ -286,6 +286,11 @@ struct Workspace {
     // ahead_split + ahead_n) of that pass): staged, not counted, not pooled
     uint64_t ahead_n = 0, ahead_split = 0;
     uint64_t ahead_bound = 0;  // bound on their entries: that pass's staging bound
+    // the first ahead_next of them are counted in counts_next (LT); a take of
+    // exactly those adds counts_next to counts_acc
+    uint32_t* counts_next = nullptr;
+    uint64_t ahead_next = 0;
+    uint64_t pending_next = 0;  // ... as asked of the pass in flight
     uint64_t pending_count = 0;  // sets of the sampling pass in flight
     uint64_t pending_lo = 0;
     Timer timer;
@@ -369,9 +374,13 @@ imm_status ws_read_scalars(Workspace& w);
 // runs (ws_ic_task gives its task, ws_after_multi queues the scalar copy).
 // ahead: that many more ids (after the count asked for) are drawn in the same
 // pass but join the pool only when a later call asks for them (the rest of
-// them are then dropped); results do not change.
+// them are then dropped); results do not change. next (<= ahead): the first
+// ids drawn ahead that the next call is expected to ask for; the pass counts
+// their members apart, so that a call asking for exactly these ids adds one
+// count vector instead of counting their members again.
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count, bool multi = false, uint64_t ahead = 0);
+                            uint64_t count, bool multi = false, uint64_t ahead = 0,
+                            uint64_t next = 0);
 IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap);
 imm_status ws_after_multi(Workspace& w);
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);

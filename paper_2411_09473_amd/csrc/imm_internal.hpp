@@ -98,9 +98,12 @@ struct SampleOut {
     uint32_t dense_words;
     uint64_t pool_base;
     // LT: only samples with index < count_lim add to counts (the others are
-    // drawn ahead of the round that needs them; 0xFFFFFFFF: all count)
+    // drawn ahead of the round that needs them; 0xFFFFFFFF: all count);
+    // those with count_lim <= index < count_lim2, the ids the next round
+    // would take, add to counts_next instead
     uint32_t count_lim;
-    uint32_t pad;
+    uint32_t count_lim2;
+    uint32_t* counts_next;
 };
 // Sets of at least max(ceil(n / 32), kDenseMinSize) members are dense: a
 // bitmap of n bits then takes no more room than the member list. Every set
@@ -228,6 +231,8 @@ hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_v
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);
+// dst[v] += src[v] for v < n.
+hipError_t launch_add_counts(const uint32_t* src, uint32_t* dst, uint32_t n, hipStream_t st);
 // counts[v] += occurrences of v in the sets [lo, hi) of a pool (their entry
 // range read from set_off on the device).
 hipError_t launch_count_sets(const uint64_t* set_off, uint64_t lo, uint64_t hi,

@@ -567,6 +567,24 @@ __global__ __launch_bounds__(256) void count_sets_kernel(const uint64_t* set_off
     }
 }
 
+// dst[v] += src[v] for v < n, four at a time where they fit.
+__global__ __launch_bounds__(256) void add_counts_kernel(const uint32_t* src, uint32_t* dst,
+                                                         uint32_t n) {
+    const uint32_t stride = gridDim.x * 256;
+    const uint32_t n4 = n >> 2;
+    for (uint32_t x = blockIdx.x * 256 + threadIdx.x; x < n4; x += stride) {
+        const uint4 a = reinterpret_cast<const uint4*>(src)[x];
+        uint4 b = reinterpret_cast<const uint4*>(dst)[x];
+        b.x += a.x;
+        b.y += a.y;
+        b.z += a.z;
+        b.w += a.w;
+        reinterpret_cast<uint4*>(dst)[x] = b;
+    }
+    const uint32_t v = (n4 << 2) + blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256 + threadIdx.x < 4u && v < n) dst[v] += src[v];
+}
+
 __global__ __launch_bounds__(256) void validate_kernel(const uint64_t* set_off, uint64_t n_sets,
                                                        const uint32_t* set_vtx, uint32_t n,
                                                        uint32_t* flag) {
@@ -752,6 +770,14 @@ hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* c
     if (P == 0) return hipSuccess;
     hipLaunchKernelGGL(count_entries_kernel, dim3(grid_for(P, 256 * 8, 8192)), dim3(256), 0, st,
                        set_vtx, P, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_counts(const uint32_t* src, uint32_t* dst, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t n4 = (n + 3) / 4;
+    hipLaunchKernelGGL(add_counts_kernel, dim3(std::min<uint32_t>((n4 + 255) / 256, 4096u)),
+                       dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

@@ -285,7 +285,10 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
 
     constexpr uint32_t R = kWin / P;
     bool has = false, done = false, fresh = false, primed = false;
-    bool counted = false;  // the walk's members count (sample index below count_lim)
+    // where the walk's members are counted: counts (sample index below
+    // count_lim), counts_next (below count_lim2: the ids the next round will
+    // take) or nowhere (drawn further ahead)
+    uint32_t* cnt = nullptr;
     uint32_t idx = 0, cur = 0, len = 0, wstart = 0, chunk_used = kLtChunk;
     uint32_t cbeg = 0, cend = 0;  // cur's column
     uint32_t nbeg = 0, nend = 0;  // a new root's column, in flight
@@ -354,9 +357,10 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
             if (start) {
                 wstart = chunk_used;
                 o.stage[chunk_base + wstart] = cur;
-                counted = idx < o.count_lim;
+                cnt = idx < o.count_lim ? o.counts
+                                        : (idx < o.count_lim2 ? o.counts_next : nullptr);
                 if (first) {
-                    if (counted) atomicAdd(&o.counts[cur], 1u);
+                    if (cnt) atomicAdd(&cnt[cur], 1u);
                     bloom_set<BB>(mb, cur);
                 }
                 len = 1;
@@ -429,9 +433,9 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                             o.defer[atomicAdd(o.defer_n, 1u)] = idx;
                         }
                         if (!moved) {
-                            if (first && counted)
+                            if (first && cnt)
                                 for (uint32_t t = 0; t < len; ++t)
-                                    atomicSub(&o.counts[o.stage[chunk_base + wstart + t]], 1u);
+                                    atomicSub(&cnt[o.stage[chunk_base + wstart + t]], 1u);
                             // a deferred path keeps its chunk
                             chunk_used = wstart == 0 ? kLtChunk : wstart;
                             has = false;
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                     if (keep) {
                         o.stage[chunk_base + wstart + len] = nxt;
                         if (first) {
-                            if (counted) atomicAdd(&o.counts[nxt], 1u);
+                            if (cnt) atomicAdd(&cnt[nxt], 1u);
                             bloom_set<BB>(mb, nxt);
                         }
                         ++len;
@@ -549,6 +553,7 @@ __global__ __launch_bounds__(64) void lt_large_kernel(LtGraphDev g, SampleRange 
             if (fits) {
                 o.stage[off + i] = u;
                 if (idx < o.count_lim) atomicAdd(&o.counts[u], 1u);
+                else if (idx < o.count_lim2) atomicAdd(&o.counts_next[u], 1u);
             }
             __hip_atomic_store(&bm[u >> 5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

@@ -252,7 +252,7 @@ imm_status begin_iteration(Query& q) {
     // the final theta = lam* / LB. Ids drawn ahead are counted and pooled only
     // when a later iteration asks for them; what the run never asks for is
     // dropped, so results do not change.
-    uint64_t ahead = 0;
+    uint64_t ahead = 0, next = 0;
     if (!q.final && q.sched == kSchedImm && q.g->model == IMM_LT && q.i < q.i_max && count) {
         const double nf = std::ceil(q.lam_s / std::ldexp((double)q.g->n, -(int)(q.i + 1)));
         const uint64_t slots = (uint64_t)lt_small_grid(q.g->device, q.g->lt_bloom_bits,
@@ -260,8 +260,13 @@ imm_status begin_iteration(Query& q) {
         const uint64_t cap = 4 * slots;
         if (nf < 4294967296.0 && (uint64_t)nf > target && count < cap)
             ahead = std::min<uint64_t>((uint64_t)nf - target, cap - count);
+        // should this round fail its test, the next one asks for the ids up
+        // to its own target: those are counted apart in the same pass
+        const double tn = std::ceil(q.lam_p / std::ldexp((double)q.g->n, -(int)(q.i + 1)));
+        if (ahead && tn < 4294967296.0 && (uint64_t)tn > target)
+            next = std::min<uint64_t>((uint64_t)tn - target, ahead);
     }
-    return ws_extend_launch(w, q.g, q.p.seed, w.n_sets, count, q.multi, ahead);
+    return ws_extend_launch(w, q.g, q.p.seed, w.n_sets, count, q.multi, ahead, next);
 }
 
 // After the round's sampling: retries and compaction of the pool (pools).
@@ -479,7 +484,14 @@ bool BatchRunner::step() {
             descs.push_back(d);
         }
         bool ok = true;
-        if (cap_descs_ < descs.size()) {
+        // a lone query uses its workspace's descriptor (allocated with the
+        // cached workspace); a batch, the runner's buffers
+        SelectDesc* dd = nullptr;
+        if (ready.size() == 1) {
+            Workspace& w1 = *ready[0]->w;
+            w1.desc_h = descs[0];
+            dd = w1.desc_d;
+        } else if (cap_descs_ < descs.size()) {
             if (descs_h_) (void)hipHostFree(descs_h_);
             if (descs_d_) (void)hipFree(descs_d_);
             descs_h_ = nullptr;
@@ -490,9 +502,13 @@ bool BatchRunner::step() {
                  hipMalloc((void**)&descs_d_, cap_descs_ * sizeof(SelectDesc)) == hipSuccess;
             if (!ok) cap_descs_ = 0;
         }
+        if (ok && !dd) dd = descs_d_;
         std::vector<hipEvent_t> joins;
         if (ok) {
-            std::memcpy(descs_h_, descs.data(), descs.size() * sizeof(SelectDesc));
+            const void* src = descs.size() == 1 ? (const void*)&ready[0]->w->desc_h
+                                                : (const void*)descs_h_;
+            if (descs.size() > 1)
+                std::memcpy(descs_h_, descs.data(), descs.size() * sizeof(SelectDesc));
             for (auto* q : ready) {
                 if (q->st == main_) continue;
                 hipEvent_t e = nullptr;
@@ -501,7 +517,7 @@ bool BatchRunner::step() {
                 (void)hipStreamWaitEvent(main_, e, 0);
                 joins.push_back(e);
             }
-            ok = hipMemcpyAsync(descs_d_, descs_h_, descs.size() * sizeof(SelectDesc),
+            ok = hipMemcpyAsync(dd, src, descs.size() * sizeof(SelectDesc),
                                 hipMemcpyHostToDevice, main_) == hipSuccess;
             bool graph = false;
             for (auto* q : ready) graph |= (q->p.flags & IMM_GRAPH_SELECT) != 0;
@@ -509,7 +525,7 @@ bool BatchRunner::step() {
             int launched = 0;
             if (graph && ok) {
                 bool captured = false;
-                launched = graph_.launch(descs_d_, (uint32_t)descs.size(), kmax, arg_total,
+                launched = graph_.launch(dd, (uint32_t)descs.size(), kmax, arg_total,
                                          sel_total, dense_total, main_, &captured);
                 ok = launched >= 0;
                 for (auto* q : ready) {
@@ -519,7 +535,7 @@ bool BatchRunner::step() {
             }
             if (launched == 0) {
                 for (uint32_t t = 0; ok && t < kmax; ++t)
-                    ok = launch_select_step(descs_d_, (uint32_t)descs.size(), t, arg_total,
+                    ok = launch_select_step(dd, (uint32_t)descs.size(), t, arg_total,
                                             sel_total, dense_total, main_) == hipSuccess;
             }
             if (timing) (void)hipEventRecord(ev_b_, main_);

@@ -173,6 +173,7 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.n_dense = 0;
     w.dense_entries = 0;
     w.ahead_n = 0;
+    w.ahead_next = 0;
     w.list_only = false;
     w.cand_steps = 0;
     w.cand_halts = 0;
@@ -301,6 +302,9 @@ SampleOut sample_out(Workspace& w, const imm_graph* g, uint32_t* fl, uint32_t* f
     o.dense_words = w.dense_words;
     o.pool_base = w.n_sets;
     o.count_lim = w.pending_split ? (uint32_t)w.pending_split : 0xFFFFFFFFu;
+    o.count_lim2 = o.count_lim;
+    o.counts_next = w.counts_next;
+    if (w.pending_next && w.counts_next) o.count_lim2 = (uint32_t)(w.pending_split + w.pending_next);
     return o;
 }
 
@@ -383,7 +387,14 @@ imm_status ws_take_ahead(Workspace& w, uint64_t k) {
                             w.set_off + w.n_sets, w.scan_tmp, st));
     HIP_TRY(launch_compact(w.stage, w.stage_off + split, w.set_off, w.n_sets, (uint32_t)k,
                            w.set_vtx, st));
-    HIP_TRY(launch_count_sets(w.set_off, w.n_sets, w.n_sets + k, w.set_vtx, w.counts_acc, st));
+    if (w.ahead_next && k == w.ahead_next) {
+        // exactly the ids the pass counted apart
+        HIP_TRY(launch_add_counts(w.counts_next, w.counts_acc, w.n, st));
+    } else {
+        HIP_TRY(launch_count_sets(w.set_off, w.n_sets, w.n_sets + k, w.set_vtx, w.counts_acc,
+                                  st));
+    }
+    w.ahead_next = 0;
     w.timer.close(tc, st);
     // set_vtx already has room: the last pass's compaction reserved its whole
     // staging bound. The pool-size bound (which sizes the index and later
@@ -395,10 +406,11 @@ imm_status ws_take_ahead(Workspace& w, uint64_t k) {
 }
 
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
-                            uint64_t count64, bool multi, uint64_t ahead) {
+                            uint64_t count64, bool multi, uint64_t ahead, uint64_t next) {
     w.pending_count = 0;
     w.pending_multi = false;
     w.pending_split = 0;
+    w.pending_next = 0;
     if (w.ahead_n) {
         // sets drawn ahead by the last pass, as many as this call wants
         const uint64_t k = std::min<uint64_t>(w.ahead_n, count64);
@@ -431,6 +443,13 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
     const uint32_t split = count;
     count += (uint32_t)ahead;
     hipStream_t st = w.st;
+    if (next && ahead && g->model == IMM_LT) {
+        if (!w.counts_next)
+            IMM_TRY(w.arena.alloc((void**)&w.counts_next, (uint64_t)w.n * 4,
+                                  "counts (next round's ids)"));
+        HIP_TRY(hipMemsetAsync(w.counts_next, 0, (uint64_t)w.n * 4, st));
+        w.pending_next = std::min<uint64_t>(next, ahead);
+    }
     // a pass of a multi-instance launch uses the launch's shared giant-set
     // slots; the workspace's own are made when a retry pass needs them
     if (!multi) IMM_TRY(ws_big_scratch(w, g));
@@ -589,6 +608,7 @@ imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed) {
     w.p_ub += stored_bound;
     w.ahead_n = count - split;
     w.ahead_split = split;
+    w.ahead_next = std::min<uint64_t>(w.pending_next, w.ahead_n);
     w.ahead_bound = w.ahead_n ? stored_bound : 0;
     return IMM_OK;
 }
@@ -622,6 +642,7 @@ imm_status ws_restart_pool(Workspace& w) {
     w.n_dense = 0;
     w.dense_entries = 0;
     w.ahead_n = 0;
+    w.ahead_next = 0;
     HIP_TRY(hipMemsetAsync(&w.sc->dense_n, 0, 16, st));
     if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     return IMM_OK;
