@@ -44,8 +44,8 @@ PHILOX_OPS = 60
 # steady-state sampling run of that many ids), as recorded in profiles/; a
 # kernel changed since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
-    ("lj_lt", "lt_small_kernel"): 3.832e9,
-    ("lj_lt:sample16777216", "lt_small_kernel"): 292.06e9,
+    ("lj_lt", "lt_small_kernel"): 4.089e9,
+    ("lj_lt:sample16777216", "lt_small_kernel"): 292.42e9,
     ("youtube_ic", "ic_large_kernel"): 8.162e9,
     ("youtube_ic:sample16777216", "ic_large_kernel"): 63.37e9,
 }
@@ -495,6 +495,39 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes": n, "copies": 3, "kib_per_copy": n / 1024}))
 
 
+def chase_probe():
+    """Dependent random 64-byte row reads, the LT walk's memory pattern
+    without its arithmetic (libimm_probe.so): chains of reads through a table
+    of 69 M rows (4.4 GB, the LiveJournal-shaped window table's size) or 2 M
+    rows (128 MB, inside the Infinity Cache), with 2 to 8 waves of 16
+    chains per SIMD, and with one random count atomic per step (counters of
+    a 4.8 M-vertex graph) or none. 2000 steps per chain; chain steps per
+    second from HIP events around the kernel."""
+    import ctypes as C
+
+    lib = C.CDLL(str(ROOT / "paper_2411_09473_amd" / "libimm_probe.so"))
+    lib.imm_probe_chase.restype = C.c_int
+    lib.imm_probe_chase.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                    C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    out = []
+    for rows, waves, count in ((69_000_000, 2, 0), (69_000_000, 4, 0), (69_000_000, 5, 0),
+                               (69_000_000, 8, 0), (69_000_000, 5, 1), (69_000_000, 8, 1),
+                               (2_000_000, 5, 0), (2_000_000, 5, 1)):
+        wg = waves  # four-wave workgroups per CU: one wave per SIMD each
+        lds = min(64 * 1024, (160 * 1024) // wg // 256 * 256)
+        ms, steps = C.c_double(), C.c_uint64()
+        rc = lib.imm_probe_chase(rows, wg, lds, 2000, count, 4_800_000, C.byref(ms), C.byref(steps))
+        if rc != 0:
+            raise RuntimeError(f"imm_probe_chase failed ({rc})")
+        out.append({"table_GB": rows * 64 / 1e9, "waves_per_simd": waves,
+                    "chains": steps.value // 2000, "count_atomic": bool(count), "ms": ms.value,
+                    "G_steps_per_s": steps.value / (ms.value * 1e-3) / 1e9,
+                    "row_GBps": steps.value * 64 / (ms.value * 1e-3) / 1e9})
+        print(f"[bench] chase {out[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "dependent random 64-byte row reads (chase probe)",
+                      "steps_per_chain": 2000, "runs": out}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -534,6 +567,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8, help="served mode: concurrent queries")
     ap.add_argument("--serve-budget", type=int, default=192,
                     help="served mode: device memory budget in GiB")
+    ap.add_argument("--chase-probe", action="store_true",
+                    help="only run the random-read chase probe (the LT walk's memory pattern "
+                         "without its arithmetic)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB device copy that calibrates HBM byte counters")
     args = ap.parse_args()
@@ -560,6 +596,8 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         return copy_calibration(torch)
+    if args.chase_probe:
+        return chase_probe()
     if args.counter_update:
         return counter_update_mode(args, imm, torch)
     if args.dense_compare:

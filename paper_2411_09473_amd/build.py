@@ -17,6 +17,9 @@ PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 BUILD = PKG.parent / "_build"
 LIB = PKG / "libimm.so"
+# a memory probe for bench.py (random-read chains), not part of the IMM path
+PROBE = PKG / "libimm_probe.so"
+PROBE_SOURCES = ["probe_chase.hip"]
 ARCH = os.environ.get("IMM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_sample_ic.hip", "k_sample_lt.hip", "k_pool.hip", "k_select.hip",
@@ -47,27 +50,33 @@ def _compile(src: Path, obj: Path) -> None:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
 
 
-def build(verbose: bool = False) -> Path:
-    BUILD.mkdir(exist_ok=True)
-    objs = []
-    jobs = []
-    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
-        for s in SOURCES:
-            src = CSRC / s
-            obj = BUILD / (s + ".o")
-            objs.append(obj)
-            jobs.append(ex.submit(_compile, src, obj))
-        for j in jobs:
-            j.result()
-    tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
+def _link(objs, lib: Path) -> None:
+    tmp = lib.with_suffix(f".so.tmp{os.getpid()}")
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", str(tmp),
            *map(str, objs)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> Path:
+    BUILD.mkdir(exist_ok=True)
+    objs, pobjs = [], []
+    jobs = []
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
+        for names, out in ((SOURCES, objs), (PROBE_SOURCES, pobjs)):
+            for s in names:
+                src = CSRC / s
+                obj = BUILD / (s + ".o")
+                out.append(obj)
+                jobs.append(ex.submit(_compile, src, obj))
+        for j in jobs:
+            j.result()
+    _link(objs, LIB)
+    _link(pobjs, PROBE)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE}")
     return LIB
 
 
