@@ -185,6 +185,12 @@ typedef struct {
      * steps run in full. Results are unchanged. */
     uint32_t cand_steps;     /* seed steps whose argmax ran over the list */
     uint32_t cand_halts;     /* selections that halted and finished in full */
+    uint32_t spec_rounds;    /* imm_run, LT: rounds whose compaction, index and
+                                selection ran speculatively beside the round
+                                before (its ids drawn ahead in that round's
+                                launch) and were kept because that round
+                                failed its test; IMM_SPEC=0 in the environment
+                                turns this off. Results are unchanged. */
 } imm_stats;
 
 /* Thread-local description of the last error of this thread. */

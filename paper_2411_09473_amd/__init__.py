@@ -68,7 +68,8 @@ class imm_stats(C.Structure):
                 ("walk_lanes", C.c_uint32), ("select_graphs", C.c_uint32),
                 ("select_captures", C.c_uint32), ("dense_sets", C.c_uint32),
                 ("sample_graphs", C.c_uint32), ("sample_captures", C.c_uint32),
-                ("cand_steps", C.c_uint32), ("cand_halts", C.c_uint32)]
+                ("cand_steps", C.c_uint32), ("cand_halts", C.c_uint32),
+                ("spec_rounds", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}

@@ -174,6 +174,32 @@ struct SampleGraph {
     ~SampleGraph();
 };
 
+// The buffers of one greedy selection. A workspace holds the active ones in
+// its own fields; a second set lets the next round's selection run
+// speculatively beside the current one (swap_sel exchanges them).
+struct SelBufs {
+    uint32_t* counts_work = nullptr;
+    uint32_t* heavy = nullptr;
+    uint32_t* covered = nullptr;
+    uint64_t cap_cov = 0;
+    unsigned long long* slots = nullptr;
+    uint32_t* chunk_n = nullptr;
+    unsigned long long* cov_entries = nullptr;
+    Chunk* chunks = nullptr;
+    uint64_t cap_chunks = 0;
+    uint32_t* seeds_d = nullptr;
+    uint32_t* gains_d = nullptr;
+    uint64_t cap_k = 0;
+    uint32_t* gains_h = nullptr;  // pinned
+    SelectDesc* desc_d = nullptr;
+    SelectDesc desc_h{};
+    uint32_t* cand = nullptr;
+    uint32_t* cand_bits = nullptr;
+    uint32_t* cand_state = nullptr;
+    uint32_t* cand_h = nullptr;  // pinned
+    SelectDesc desc_last{};
+};
+
 struct Workspace {
     int device = 0;
     uint32_t n = 0;
@@ -246,6 +272,20 @@ struct Workspace {
     uint32_t* cand_h = nullptr;
     SelectDesc desc_last{};
     uint64_t cand_steps = 0, cand_halts = 0;
+    // A speculative round (LT, ids drawn ahead and counted apart): while the
+    // current round's selection runs, the next round's sets [spec_lo,
+    // spec_hi) are compacted after the pool, indexed as segment nseg and
+    // selected over, on the side stream, with the second selection buffers (sel2)
+    // and counts_spec (the pool's counts with those sets). Kept if the
+    // current round fails its test, dropped otherwise; the workspace's host
+    // state changes only when it is kept.
+    SelBufs sel2;
+    uint32_t* counts_spec = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev = nullptr;
+    bool spec = false;
+    uint64_t spec_lo = 0, spec_hi = 0;
+    uint64_t spec_rounds = 0;  // speculative rounds kept since the last reset
     uint32_t* big = nullptr;   // giant-set slots: bitmap + bounded queue each
     uint32_t big_slots = 0;
     uint32_t big_qcap = 0;
@@ -384,6 +424,22 @@ imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uin
 IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap);
 imm_status ws_after_multi(Workspace& w);
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);
+// Speculative rounds. ws_spec_possible: the last pass drew the next round's
+// ids ahead and counted them apart. ws_spec_reserve (after ws_select_prepare,
+// before the round's selection is launched, on the workspace's stream): every
+// buffer the speculative round writes is grown now, as a grow waits for the
+// stream and frees the old buffer. ws_spec_launch (after the round's
+// selection is queued): the next round's compaction, index segment and
+// selection of k seeds on the side stream, ordered after the work queued on
+// the workspace's stream before `after`. ws_spec_commit: the speculation
+// becomes the workspace's next round (its sets, index segment and
+// selection, as ws_extend_launch and ws_select_prepare would have left
+// them); ws_spec_drop: it is discarded (both wait for the side stream).
+bool ws_spec_possible(const Workspace& w);
+imm_status ws_spec_reserve(Workspace& w, uint32_t k);
+imm_status ws_spec_launch(Workspace& w, uint32_t k, hipEvent_t after);
+imm_status ws_spec_commit(Workspace& w);
+imm_status ws_spec_drop(Workspace& w);
 // Both halves and the synchronisation in between.
 imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
                      uint64_t count);

@@ -459,11 +459,28 @@ bool BatchRunner::step() {
         }
     }
     std::vector<Query*> ready;
+    // a lone LT query whose round drew the next round's ids ahead runs that
+    // round speculatively beside this one's selection (its own stream, its
+    // own selection buffers): kept if this round fails its test
+    Query* spec_q = nullptr;
     for (auto* q : live) {
         imm_status s = finish_sampling(*q);
+        if (s == IMM_OK && live.size() == 1 && active_.size() == 1 && q->st == main_ &&
+            q->sched == kSchedImm && !q->final && q->i < q->i_max && q->g->model == IMM_LT &&
+            ws_spec_possible(*q->w)) {
+            const char* e = std::getenv("IMM_SPEC");
+            if (!(e && std::strcmp(e, "0") == 0)) {
+                s = ws_spec_reserve(*q->w, q->p.k);
+                if (s == IMM_OK) spec_q = q;
+            }
+        }
         if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
-        if (s != IMM_OK) finish_err(q, s);
-        else ready.push_back(q);
+        if (s != IMM_OK) {
+            finish_err(q, s);
+            if (q == spec_q) spec_q = nullptr;
+        } else {
+            ready.push_back(q);
+        }
     }
     // the selections of all queries together, on the main stream
     if (!ready.empty()) {
@@ -521,6 +538,9 @@ bool BatchRunner::step() {
                                 hipMemcpyHostToDevice, main_) == hipSuccess;
             bool graph = false;
             for (auto* q : ready) graph |= (q->p.flags & IMM_GRAPH_SELECT) != 0;
+            // the speculative round starts after everything this round's
+            // selection needs, and runs beside the selection
+            if (spec_q && ok) ok = hipEventRecord(spec_q->w->side_ev, main_) == hipSuccess;
             if (timing) (void)hipEventRecord(ev_a_, main_);
             int launched = 0;
             if (graph && ok) {
@@ -539,6 +559,7 @@ bool BatchRunner::step() {
                                             sel_total, dense_total, main_) == hipSuccess;
             }
             if (timing) (void)hipEventRecord(ev_b_, main_);
+            if (spec_q && ok) ok = ws_spec_launch(*spec_q->w, spec_q->p.k, spec_q->w->side_ev) == IMM_OK;
             for (auto* q : ready)
                 if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main_) == IMM_OK;
             if (ok) ok = hipStreamSynchronize(main_) == hipSuccess;
@@ -553,6 +574,23 @@ bool BatchRunner::step() {
             const imm_status s = ok ? end_iteration(*q)
                                     : fail(IMM_EDEVICE, "batched selection failed");
             if (s != IMM_OK) finish_err(q, s);
+        }
+        if (spec_q && spec_q->w->spec) {
+            Query* q = spec_q;
+            Workspace& w = *q->w;
+            if (!q->done && !q->final) {
+                // this round failed its test: the next round is the one run
+                // speculatively; its θ decision is taken now
+                imm_status s = ws_spec_commit(w);
+                if (s == IMM_OK) s = begin_iteration(*q);
+                if (s == IMM_OK) {
+                    q->before = w.spec_lo;
+                    s = end_iteration(*q);
+                }
+                if (s != IMM_OK) finish_err(q, s);
+            } else {
+                (void)ws_spec_drop(w);
+            }
         }
     }
     std::vector<Query*> next;

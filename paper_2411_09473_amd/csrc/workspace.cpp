@@ -126,6 +126,10 @@ Workspace::~Workspace() {
     if (herr) (void)hipHostFree(herr);
     if (gains_h) (void)hipHostFree(gains_h);
     if (cand_h) (void)hipHostFree(cand_h);
+    if (sel2.gains_h) (void)hipHostFree(sel2.gains_h);
+    if (sel2.cand_h) (void)hipHostFree(sel2.cand_h);
+    if (side_ev) (void)hipEventDestroy(side_ev);
+    if (side) (void)hipStreamDestroy(side);
 }
 
 IcGraphDev ic_view(const imm_graph* g) {
@@ -177,6 +181,8 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.list_only = false;
     w.cand_steps = 0;
     w.cand_halts = 0;
+    w.spec = false;
+    w.spec_rounds = 0;
     if (w.dense_counts) HIP_TRY(hipMemsetAsync(w.dense_counts, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), st));
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
@@ -736,10 +742,15 @@ imm_status ws_index_update(Workspace& w) {
 
 }  // namespace
 
-imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
-    hipStream_t st = w.st;
-    IMM_TRY(ws_index_update(w));
-    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, w.n_sets / 32 + 1, 0, st, "covered"));
+namespace {
+
+// The selection state of a pool of n_sets sets (entries bounded by p_ub,
+// indexed in nseg segments, cacc[v] the length of v's index lists): the
+// workspace's selection buffers grown and cleared, the working counts, the
+// candidate list, and the descriptor, on stream st.
+imm_status ws_select_state(Workspace& w, uint32_t k, SelectDesc* d, const uint32_t* cacc,
+                           uint64_t n_sets, uint32_t nseg, uint64_t p_ub, hipStream_t st) {
+    IMM_TRY(grow(w.arena, &w.covered, &w.cap_cov, n_sets / 32 + 1, 0, st, "covered"));
     if (w.cap_k < k) {
         if (w.seeds_d) {
             HIP_TRY(hipStreamSynchronize(st));
@@ -761,12 +772,12 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
         w.cap_k = k;
     }
     // a seed's queue entries: at most one per started 64 members of every set
-    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, w.n_sets + w.p_ub / 64 + 1, 0, st,
+    IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, n_sets + p_ub / 64 + 1, 0, st,
                  "chunk queue"));
     // working counts, and the list of vertices whose index lists are long
     HIP_TRY(hipMemsetAsync(w.heavy + w.n, 0, 4, st));
-    HIP_TRY(launch_select_init2(w.counts_acc, w.n_dense ? w.dense_counts : nullptr,
-                                w.counts_work, w.n, w.heavy, w.heavy + w.n, st));
+    HIP_TRY(launch_select_init2(cacc, w.n_dense ? w.dense_counts : nullptr, w.counts_work, w.n,
+                                w.heavy, w.heavy + w.n, st));
     // dense claims: per-step marks, then the claim cursor
     if (w.n_dense) {
         if (w.cap_mark_k < k) {
@@ -780,10 +791,10 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
         }
         HIP_TRY(hipMemsetAsync(w.dense_mark, 0, (w.cap_mark_k + 2) * 4, st));
     }
-    HIP_TRY(hipMemsetAsync(w.covered, 0, (w.n_sets / 32 + 1) * 4, st));
+    HIP_TRY(hipMemsetAsync(w.covered, 0, (n_sets / 32 + 1) * 4, st));
     // the whole block: its layout follows the capacity cap_k, not this k
     HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
-    if (w.nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
+    if (nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
     // the candidate list from the working counts (steps 1 .. k-1 may use it);
     // IMM_CAND_MAX bounds it (0: every step in full)
     uint32_t cand_max = kCandMax;
@@ -795,10 +806,10 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
         HIP_TRY(launch_cand_build(w.counts_work, w.n, cand_max, w.cand, w.cand_bits,
                                   w.cand_state, st));
     }
-    *d = SelectDesc{w.counts_work, w.counts_acc, w.heavy,     w.heavy + w.n, w.inv_offs,
+    *d = SelectDesc{w.counts_work, cacc,         w.heavy,     w.heavy + w.n, w.inv_offs,
                     w.inv_set,     w.set_off,    w.set_vtx,   w.covered,     w.slots,
                     w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
-                    w.cov_entries, w.n,          k,           w.nseg,        (uint32_t)w.n_sets,
+                    w.cov_entries, w.n,          k,           nseg,          (uint32_t)n_sets,
                     0,             0,            0,           0,             w.update_mode};
     if (w.n_dense) {
         d->dense_bits = w.dense_bits;
@@ -818,6 +829,13 @@ imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
     }
     w.desc_last = *d;
     return IMM_OK;
+}
+
+}  // namespace
+
+imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d) {
+    IMM_TRY(ws_index_update(w));
+    return ws_select_state(w, k, d, w.counts_acc, w.n_sets, w.nseg, w.p_ub, w.st);
 }
 
 imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st) {
@@ -1117,6 +1135,206 @@ imm_status ws_export_pool(Workspace& w, std::vector<uint64_t>* so, std::vector<u
     return IMM_OK;
 }
 
+// ---------------------------------------------------------- speculation --
+
+namespace {
+
+void swap_sel(Workspace& w, SelBufs& b) {
+    std::swap(w.counts_work, b.counts_work);
+    std::swap(w.heavy, b.heavy);
+    std::swap(w.covered, b.covered);
+    std::swap(w.cap_cov, b.cap_cov);
+    std::swap(w.slots, b.slots);
+    std::swap(w.chunk_n, b.chunk_n);
+    std::swap(w.cov_entries, b.cov_entries);
+    std::swap(w.chunks, b.chunks);
+    std::swap(w.cap_chunks, b.cap_chunks);
+    std::swap(w.seeds_d, b.seeds_d);
+    std::swap(w.gains_d, b.gains_d);
+    std::swap(w.cap_k, b.cap_k);
+    std::swap(w.gains_h, b.gains_h);
+    std::swap(w.desc_d, b.desc_d);
+    std::swap(w.desc_h, b.desc_h);
+    std::swap(w.cand, b.cand);
+    std::swap(w.cand_bits, b.cand_bits);
+    std::swap(w.cand_state, b.cand_state);
+    std::swap(w.cand_h, b.cand_h);
+    std::swap(w.desc_last, b.desc_last);
+}
+
+// Whether a segment of at most seg_ub entries is indexed by the partition
+// (as ws_index_update decides), given the pair buffer's capacity then.
+bool index_by_partition(const Workspace& w, uint64_t seg_ub) {
+    if (index_bucket_shift(w.n) >= 32 || std::getenv("IMM_INDEX_ATOMIC")) return false;
+    uint64_t pair_room = kIndexPairsBytes;
+    if (w.arena.budget)
+        pair_room = std::min(pair_room, (w.arena.budget - std::min(w.arena.budget, w.arena.used)) / 4);
+    const bool fits = w.cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
+    return fits && (seg_ub >= kIndexPartitionMin || std::getenv("IMM_INDEX_PARTITION"));
+}
+
+}  // namespace
+
+bool ws_spec_possible(const Workspace& w) {
+    return w.ahead_next > 0 && w.ahead_n >= w.ahead_next && w.counts_next && w.n_dense == 0 &&
+           w.n_sets + w.ahead_next <= 0xFFFFFFFFull;
+}
+
+imm_status ws_spec_reserve(Workspace& w, uint32_t k) {
+    hipStream_t st = w.st;
+    const uint64_t kk = w.ahead_next;
+    const uint64_t lo = w.n_sets, hi = lo + kk;
+    const uint64_t p_hi = w.p_ub + w.ahead_bound;
+    const uint64_t stride = (uint64_t)w.n + 1;
+    // the index segment this round's selection builds first, then the
+    // speculative one
+    const uint32_t nseg = w.nseg + (w.indexed_sets < w.n_sets ? 1u : 0u);
+    if (nseg + 1 > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
+    IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, hi + 1, lo + 1, st, "set_off"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan,
+                 std::max(scan_tmp_entries(kk), scan_tmp_entries(w.n)), 0, st, "scan tmp"));
+    IMM_TRY(grow(w.arena, &w.inv_offs, &w.cap_offs, ((uint64_t)nseg + 1) * stride,
+                 (uint64_t)w.nseg * stride, st, "index offsets"));
+    IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, p_hi + 1, std::min(w.p_ub, w.cap_inv), st,
+                 "inv_set"));
+    const uint64_t cur_ub = w.p_ub - std::min(w.p_indexed, w.p_ub);
+    uint64_t pairs = 0;
+    if (w.indexed_sets < w.n_sets && index_by_partition(w, cur_ub)) pairs = cur_ub + 1;
+    if (index_by_partition(w, w.ahead_bound)) pairs = std::max(pairs, w.ahead_bound + 1);
+    if (pairs) {
+        IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, pairs, 0, st, "index pairs"));
+        if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
+    }
+    if (!w.counts_spec)
+        IMM_TRY(w.arena.alloc((void**)&w.counts_spec, (uint64_t)w.n * 4, "counts (speculative)"));
+    // the second selection buffers, at the sizes ws_select_state will ask for
+    SelBufs& b = w.sel2;
+    if (!b.counts_work) {
+        IMM_TRY(w.arena.alloc((void**)&b.counts_work, (uint64_t)w.n * 4 + 16, "counts_work"));
+        IMM_TRY(w.arena.alloc((void**)&b.heavy, (uint64_t)w.n * 4 + 16, "heavy vertex list"));
+        IMM_TRY(w.arena.alloc((void**)&b.desc_d, sizeof(SelectDesc), "select descriptor"));
+        IMM_TRY(w.arena.alloc((void**)&b.cand, (uint64_t)kCandMax * 4, "candidate list"));
+        IMM_TRY(w.arena.alloc((void**)&b.cand_bits, ((uint64_t)w.n + 31) / 32 * 4 + 16,
+                              "candidate bitmap"));
+        IMM_TRY(w.arena.alloc((void**)&b.cand_state, (kCandHead + kCandBins) * 4,
+                              "candidate state"));
+        HIP_TRY(hipHostMalloc((void**)&b.cand_h, kCandHead * 4, hipHostMallocDefault));
+    }
+    IMM_TRY(grow(w.arena, &b.covered, &b.cap_cov, hi / 32 + 1, 0, st, "covered"));
+    IMM_TRY(grow(w.arena, &b.chunks, &b.cap_chunks, hi + p_hi / 64 + 1, 0, st, "chunk queue"));
+    if (b.cap_k < k) {
+        if (b.seeds_d) {
+            HIP_TRY(hipStreamSynchronize(st));
+            w.arena.release(b.seeds_d);
+            w.arena.release(b.gains_d);
+            w.arena.release(b.slots);
+            (void)hipHostFree(b.gains_h);
+            b.gains_h = nullptr;
+        }
+        IMM_TRY(w.arena.alloc((void**)&b.seeds_d, (uint64_t)k * 4, "seeds"));
+        IMM_TRY(w.arena.alloc((void**)&b.gains_d, (uint64_t)k * 4, "gains"));
+        IMM_TRY(w.arena.alloc((void**)&b.slots, (uint64_t)k * (kArgSlots * 8 + 16),
+                              "seed-step state"));
+        b.chunk_n = reinterpret_cast<uint32_t*>(b.slots + (uint64_t)k * kArgSlots);
+        b.cov_entries = reinterpret_cast<unsigned long long*>(b.chunk_n + 2ull * k);
+        HIP_TRY(hipHostMalloc((void**)&b.gains_h, (uint64_t)k * 4, hipHostMallocDefault));
+        b.cap_k = k;
+    }
+    if (!w.side) HIP_TRY(hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking));
+    if (!w.side_ev) HIP_TRY(hipEventCreateWithFlags(&w.side_ev, hipEventDisableTiming));
+    return IMM_OK;
+}
+
+imm_status ws_spec_launch(Workspace& w, uint32_t k, hipEvent_t after) {
+    hipStream_t S = w.side;
+    HIP_TRY(hipStreamWaitEvent(S, after, 0));
+    const uint64_t kk = w.ahead_next, lo = w.n_sets, hi = lo + kk, split = w.ahead_split;
+    const uint64_t stride = (uint64_t)w.n + 1;
+    // the sets' offsets and members, after the pool's (as ws_take_ahead)
+    HIP_TRY(launch_scan_u32(w.sizes + split, nullptr, w.set_off + lo, kk, 0, w.set_off + lo,
+                            w.scan_tmp, S));
+    HIP_TRY(launch_compact(w.stage, w.stage_off + split, w.set_off, lo, (uint32_t)kk, w.set_vtx, S));
+    // the pool's counts with them
+    HIP_TRY(hipMemcpyAsync(w.counts_spec, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice,
+                           S));
+    HIP_TRY(launch_add_counts(w.counts_next, w.counts_spec, w.n, S));
+    // their index segment, numbered nseg: offsets from the scan of their
+    // counts (as ws_index_update, with those counts as the increase)
+    uint64_t* io = w.inv_offs + (uint64_t)w.nseg * stride;
+    HIP_TRY(launch_scan_u32(w.counts_next, nullptr, io, w.n, 0, w.set_off + lo, w.scan_tmp, S));
+    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, S));
+    const uint32_t shift = index_bucket_shift(w.n);
+    if (index_by_partition(w, w.ahead_bound)) {
+        const double mean = std::max(1.0, (double)w.ahead_bound / (double)kk);
+        const uint32_t groups =
+            (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
+        HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, lo, (uint32_t)kk, groups, w.n, shift,
+                                       io, w.iplan, w.inv_pairs, w.cap_pairs, w.inv_cursor,
+                                       w.inv_set, &w.sc->err, w.device, S));
+    } else {
+        HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, lo, (uint32_t)kk, io, w.inv_cursor,
+                                   w.inv_set, &w.sc->err, S));
+    }
+    // the selection over the pool with them, in the second buffers
+    swap_sel(w, w.sel2);
+    SelectDesc d{};
+    imm_status s = ws_select_state(w, k, &d, w.counts_spec, hi, w.nseg + 1,
+                                   w.p_ub + w.ahead_bound, S);
+    hipError_t e = hipSuccess;
+    if (s == IMM_OK) {
+        d.arg_cnt = argmax_blocks(w.n);
+        d.sel_cnt = select_blocks(w.device, hi, 1);
+        w.desc_h = d;
+        e = hipMemcpyAsync(w.desc_d, &w.desc_h, sizeof(d), hipMemcpyHostToDevice, S);
+        for (uint32_t t = 0; e == hipSuccess && t < k; ++t)
+            e = launch_select_step(w.desc_d, 1, t, d.arg_cnt, d.sel_cnt, 0, S);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w.gains_h, w.gains_d, (uint64_t)k * 4, hipMemcpyDeviceToHost, S);
+        if (e == hipSuccess && d.cand_state)
+            e = hipMemcpyAsync(w.cand_h, w.cand_state, kCandHead * 4, hipMemcpyDeviceToHost, S);
+    }
+    swap_sel(w, w.sel2);
+    IMM_TRY(s);
+    HIP_TRY(e);
+    w.spec = true;
+    w.spec_lo = lo;
+    w.spec_hi = hi;
+    return IMM_OK;
+}
+
+imm_status ws_spec_commit(Workspace& w) {
+    HIP_TRY(hipStreamSynchronize(w.side));
+    const uint64_t kk = w.spec_hi - w.spec_lo;
+    // the host state the next round's ws_extend_launch and ws_select_prepare
+    // would have left
+    w.ahead_n -= kk;
+    w.ahead_split += kk;
+    w.ahead_next = 0;
+    w.n_sets = w.spec_hi;
+    w.p_ub += w.ahead_bound;
+    ++w.nseg;
+    w.indexed_sets = w.n_sets;
+    hipStream_t st = w.st;
+    HIP_TRY(hipMemcpyAsync(w.counts_acc, w.counts_spec, (uint64_t)w.n * 4,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.counts_prev, w.counts_spec, (uint64_t)w.n * 4,
+                           hipMemcpyDeviceToDevice, st));
+    // the pool size and error flag, as the selection's copy-out leaves them
+    HIP_TRY(hipMemcpyAsync(w.hp, w.set_off + w.n_sets, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(w.herr, &w.sc->err, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    swap_sel(w, w.sel2);
+    w.spec = false;
+    ++w.spec_rounds;
+    return IMM_OK;
+}
+
+imm_status ws_spec_drop(Workspace& w) {
+    w.spec = false;
+    HIP_TRY(hipStreamSynchronize(w.side));
+    return IMM_OK;
+}
+
 void fill_stats(Workspace& w, imm_stats* s) {
     double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t launches[4] = {0, 0, 0, 0};
@@ -1146,6 +1364,7 @@ void fill_stats(Workspace& w, imm_stats* s) {
     s->dense_sets = (uint32_t)std::min<uint64_t>(w.n_dense, 0xFFFFFFFFu);
     s->cand_steps = (uint32_t)std::min<uint64_t>(w.cand_steps, 0xFFFFFFFFu);
     s->cand_halts = (uint32_t)std::min<uint64_t>(w.cand_halts, 0xFFFFFFFFu);
+    s->spec_rounds = (uint32_t)std::min<uint64_t>(w.spec_rounds, 0xFFFFFFFFu);
 }
 
 }  // namespace imm
