@@ -643,8 +643,6 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     }
 }
 
-// cw = cacc; vertices with long index lists are appended to heavy (one
-// atomic per wave).
 // The dense sets' part of seed step t's counter update, after the list part
 // (decrement_kernel): when the step recounts, every count gains the bitmap
 // sum of the uncovered dense sets; otherwise it loses that of the dense sets
@@ -780,6 +778,8 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
     }
 }
 
+// cw = cacc (+ dc, the dense sets' counts); vertices with long index lists
+// are appended to heavy (one atomic per wave).
 __global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, const uint32_t* dc,
                                                           uint32_t* cw, uint32_t n,
                                                           uint32_t* heavy, uint32_t* n_heavy) {
