@@ -252,8 +252,9 @@ __global__ __launch_bounds__(64) void inv_scatter_kernel(const uint64_t* set_off
 //     vertex's list.
 // Ranks within a list depend on timing, as with the atomic scatter: the
 // selection only counts and tests a list's members, never its order.
-constexpr uint32_t kPartBS = 256;
-constexpr uint32_t kPlaceBS = 256;
+constexpr uint32_t kPartBS = 1024;
+constexpr uint32_t kPartTile = 256;  // sets per tile group
+constexpr uint32_t kPlaceBS = 1024;
 constexpr uint32_t kPlaceBatch = 4;
 
 __global__ __launch_bounds__(1024) void inv_plan_kernel(const uint64_t* io, uint32_t n,
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(1024) void inv_plan_kernel(const uint64_t* io, uint
     }
 }
 
-// The members of the sets [j0, j0 + kPartBS) of [.., jend), walked by the
+// The members of the sets [j0, min(j0 + kPartBS, jend)), walked by the
 // whole workgroup: f(u, j) for each member u of set j, up to eight loads per
 // thread in flight.
 template <class F>
@@ -341,8 +342,8 @@ __global__ __launch_bounds__(kPartBS) void inv_part_kernel(const uint64_t* set_o
     for (uint32_t b = threadIdx.x; b < nb; b += kPartBS) s_cnt[b] = 0;
     __syncthreads();
     const uint64_t jend = lo + count;
-    const uint64_t g0 = lo + (uint64_t)blockIdx.x * tile_groups * kPartBS;
-    const uint64_t g1 = min(g0 + (uint64_t)tile_groups * kPartBS, jend);
+    const uint64_t g0 = lo + (uint64_t)blockIdx.x * tile_groups * kPartTile;
+    const uint64_t g1 = min(g0 + (uint64_t)tile_groups * kPartTile, jend);
     // the tile's members are one contiguous range of the pool: the histogram
     // reads it flat, eight coalesced loads per thread in flight
     {
@@ -364,26 +365,40 @@ __global__ __launch_bounds__(kPartBS) void inv_part_kernel(const uint64_t* set_o
         }
     }
     __syncthreads();
-    // one reservation per bucket; a bucket whose range would overflow keeps
-    // its pairs out and raises *err
+    // one reservation per bucket, a thread's all in flight together; a
+    // bucket whose range would overflow keeps its pairs out and raises *err
+    static_assert(kBktMax % kPartBS == 0, "buckets per thread");
+    constexpr uint32_t kResPer = kBktMax / kPartBS;
+    unsigned long long got[kResPer];
+#pragma unroll
+    for (uint32_t x = 0; x < kResPer; ++x) {
+        const uint32_t b = threadIdx.x + x * kPartBS;
+        const uint32_t c = b < nb ? s_cnt[b] : 0u;
+        got[x] = 0ull;
+        if (c) got[x] = atomicAdd(&pl->cur[b], (unsigned long long)c);
+    }
     bool bad = false;
-    for (uint32_t b = threadIdx.x; b < nb; b += kPartBS) {
-        const uint32_t c = s_cnt[b];
-        uint64_t at = ~0ull;
-        if (c) {
-            at = pl->off[b] + atomicAdd(&pl->cur[b], (unsigned long long)c);
-            if (at + c > pl->off[b + 1]) {
-                at = ~0ull;
-                bad = true;
+#pragma unroll
+    for (uint32_t x = 0; x < kResPer; ++x) {
+        const uint32_t b = threadIdx.x + x * kPartBS;
+        if (b < nb) {
+            const uint32_t c = s_cnt[b];
+            uint64_t at = ~0ull;
+            if (c) {
+                at = pl->off[b] + got[x];
+                if (at + c > pl->off[b + 1]) {
+                    at = ~0ull;
+                    bad = true;
+                }
             }
+            s_base[b] = at;
+            s_res[b] = c;
+            s_cnt[b] = 0;
         }
-        s_base[b] = at;
-        s_res[b] = c;
-        s_cnt[b] = 0;
     }
     __syncthreads();
     for (uint64_t j0 = g0; j0 < g1; j0 += kPartBS)
-        block_members(set_off, set_vtx, j0, jend, s_sb, s_sa, s_w, [&](uint32_t u, uint64_t j) {
+        block_members(set_off, set_vtx, j0, g1, s_sb, s_sa, s_w, [&](uint32_t u, uint64_t j) {
             const uint32_t b = u >> shift;
             if (b >= nb) {  // not a vertex: the pool is corrupt
                 bad = true;
@@ -407,8 +422,11 @@ __global__ __launch_bounds__(kPlaceBS) void inv_place_kernel(const unsigned long
                                                              uint32_t* inv_set, uint32_t* err) {
     __shared__ uint32_t s_cnt[kBktVtxMax];
     __shared__ uint32_t s_base[kBktVtxMax];
+    __shared__ uint32_t s_pre[kBktMax + 1];  // the plan's first slice per bucket
     __shared__ uint32_t s_b;
-    const uint32_t nsl = pl->sl_pre[nb];
+    for (uint32_t b = threadIdx.x; b <= nb; b += kPlaceBS) s_pre[b] = pl->sl_pre[b];
+    __syncthreads();
+    const uint32_t nsl = s_pre[nb];
     // Workgroups go to the eight XCDs in turn (workgroup i to XCD i mod 8),
     // each with its own L2. With a grid of a multiple of eight, the slices
     // (in bucket order) are cut into eight ranges, one per XCD, so that the
@@ -426,14 +444,14 @@ __global__ __launch_bounds__(kPlaceBS) void inv_place_kernel(const unsigned long
             uint32_t a = 0, z = nb;
             while (z - a > 1) {
                 const uint32_t mid = (a + z) >> 1;
-                if (pl->sl_pre[mid] <= t) a = mid; else z = mid;
+                if (s_pre[mid] <= t) a = mid; else z = mid;
             }
             s_b = a;
         }
         __syncthreads();
         const uint32_t b = s_b;
         const uint64_t bo = pl->off[b], be = pl->off[b + 1];
-        const uint64_t e0 = bo + (uint64_t)(t - pl->sl_pre[b]) * kSlice;
+        const uint64_t e0 = bo + (uint64_t)(t - s_pre[b]) * kSlice;
         const uint64_t e1 = min(be, e0 + kSlice);
         const bool whole = be - bo <= kSlice;
         const uint32_t v0 = b << shift;
@@ -749,7 +767,7 @@ hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_v
     const uint32_t nb = (uint32_t)(((uint64_t)n + (1ull << shift) - 1) >> shift);
     hipLaunchKernelGGL(inv_plan_kernel, dim3(1), dim3(1024), 0, st, inv_off, n, shift, nb, cap, pl,
                        err);
-    const uint64_t tile = (uint64_t)tile_groups * kPartBS;
+    const uint64_t tile = (uint64_t)tile_groups * kPartTile;
     const uint64_t tiles = (count + tile - 1) / tile;
     hipLaunchKernelGGL(inv_part_kernel, dim3((uint32_t)tiles), dim3(kPartBS), 0, st, set_off,
                        set_vtx, lo, count, tile_groups, shift, nb, pl, tmp, err);
