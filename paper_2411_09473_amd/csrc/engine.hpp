@@ -273,16 +273,26 @@ struct Workspace {
     SelectDesc desc_last{};
     uint64_t cand_steps = 0, cand_halts = 0;
     // A speculative round (LT, ids drawn ahead and counted apart): while the
-    // current round's selection runs, the next round's sets [spec_lo,
-    // spec_hi) are compacted after the pool, indexed as segment nseg and
-    // selected over, on the side stream, with the second selection buffers (sel2)
-    // and counts_spec (the pool's counts with those sets). Kept if the
-    // current round fails its test, dropped otherwise; the workspace's host
-    // state changes only when it is kept.
+    // current round's index update, selection state and selection run, the
+    // next round's sets [spec_lo, spec_hi) are compacted after the pool,
+    // indexed as segment spec_seg and selected over, on the side stream, with
+    // scratch of their own (scan_tmp2, inv_cursor2, inv_pairs2, iplan2), the
+    // second selection buffers (sel2) and counts_spec (the pool's counts with
+    // those sets). Kept if the current round fails its test, dropped
+    // otherwise; the workspace's host state changes only when it is kept.
+    // side_ev orders the side stream after the pool's compaction, side_ev2
+    // after the current round's index update.
     SelBufs sel2;
     uint32_t* counts_spec = nullptr;
+    uint64_t* scan_tmp2 = nullptr;
+    uint64_t cap_scan2 = 0;
+    uint32_t* inv_cursor2 = nullptr;
+    unsigned long long* inv_pairs2 = nullptr;
+    uint64_t cap_pairs2 = 0;
+    IndexPlan* iplan2 = nullptr;
+    uint32_t spec_seg = 0;
     hipStream_t side = nullptr;
-    hipEvent_t side_ev = nullptr;
+    hipEvent_t side_ev = nullptr, side_ev2 = nullptr;
     bool spec = false;
     uint64_t spec_lo = 0, spec_hi = 0;
     uint64_t spec_rounds = 0;  // speculative rounds kept since the last reset
@@ -425,19 +435,24 @@ IcTask ws_ic_task(Workspace& w, const imm_graph* g, uint64_t seed, uint32_t qcap
 imm_status ws_after_multi(Workspace& w);
 imm_status ws_extend_finish(Workspace& w, const imm_graph* g, uint64_t seed);
 // Speculative rounds. ws_spec_possible: the last pass drew the next round's
-// ids ahead and counted them apart. ws_spec_reserve (after ws_select_prepare,
-// before the round's selection is launched, on the workspace's stream): every
-// buffer the speculative round writes is grown now, as a grow waits for the
-// stream and frees the old buffer. ws_spec_launch (after the round's
-// selection is queued): the next round's compaction, index segment and
-// selection of k seeds on the side stream, ordered after the work queued on
-// the workspace's stream before `after`. ws_spec_commit: the speculation
-// becomes the workspace's next round (its sets, index segment and
-// selection, as ws_extend_launch and ws_select_prepare would have left
-// them); ws_spec_drop: it is discarded (both wait for the side stream).
+// ids ahead and counted them apart. ws_spec_reserve (after the pool's
+// compaction, before ws_select_prepare, on the workspace's stream): every
+// buffer that this round's index update or the speculative round writes is
+// grown now, as a grow waits for the workspace's stream alone before it
+// frees the old buffer. ws_spec_launch_index (then): the next round's
+// compaction, counts and index segment on the side stream, ordered after the
+// work queued on the workspace's stream before `after`, so that they run
+// beside this round's index update and selection. ws_spec_launch_select
+// (after ws_select_prepare): their selection of k seeds, ordered after
+// `after`, which must follow this round's index update (the selection reads
+// every segment). ws_spec_commit: the speculation becomes the workspace's
+// next round (its sets, index segment and selection, as ws_extend_launch and
+// ws_select_prepare would have left them); ws_spec_drop: it is discarded
+// (both wait for the side stream).
 bool ws_spec_possible(const Workspace& w);
 imm_status ws_spec_reserve(Workspace& w, uint32_t k);
-imm_status ws_spec_launch(Workspace& w, uint32_t k, hipEvent_t after);
+imm_status ws_spec_launch_index(Workspace& w, hipEvent_t after);
+imm_status ws_spec_launch_select(Workspace& w, uint32_t k, hipEvent_t after);
 imm_status ws_spec_commit(Workspace& w);
 imm_status ws_spec_drop(Workspace& w);
 // Both halves and the synchronisation in between.
@@ -446,6 +461,9 @@ imm_status ws_extend(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t i
 // Selection: index update and per-instance state for k seeds (on w.st);
 // returns the descriptor with its block ranges left for the caller.
 imm_status ws_select_prepare(Workspace& w, uint32_t k, SelectDesc* d);
+// The index update alone (the new sets' segment, on w.st; nothing when every
+// set is indexed), as ws_select_prepare begins.
+imm_status ws_index_update(Workspace& w);
 // Queue the copy-out of gains, pool size and error flag on stream st.
 imm_status ws_select_copy_out(Workspace& w, uint32_t k, hipStream_t st);
 // After st is synchronised: error check, exact pool size, coverage.

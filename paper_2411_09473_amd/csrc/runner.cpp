@@ -460,8 +460,9 @@ bool BatchRunner::step() {
     }
     std::vector<Query*> ready;
     // a lone LT query whose round drew the next round's ids ahead runs that
-    // round speculatively beside this one's selection (its own stream, its
-    // own selection buffers): kept if this round fails its test
+    // round speculatively beside this one's index update and selection (its
+    // own stream, scratch and selection buffers): kept if this round fails
+    // its test
     Query* spec_q = nullptr;
     for (auto* q : live) {
         imm_status s = finish_sampling(*q);
@@ -469,15 +470,26 @@ bool BatchRunner::step() {
             q->sched == kSchedImm && !q->final && q->i < q->i_max && q->g->model == IMM_LT &&
             ws_spec_possible(*q->w)) {
             const char* e = std::getenv("IMM_SPEC");
-            if (!(e && std::strcmp(e, "0") == 0)) {
-                s = ws_spec_reserve(*q->w, q->p.k);
-                if (s == IMM_OK) spec_q = q;
+            // without the memory for it the round runs alone
+            if (!(e && std::strcmp(e, "0") == 0) && ws_spec_reserve(*q->w, q->p.k) == IMM_OK) {
+                spec_q = q;
+                // its compaction and index segment, once the pool's compaction is queued
+                s = hipEventRecord(q->w->side_ev, q->st) == hipSuccess
+                        ? ws_spec_launch_index(*q->w, q->w->side_ev)
+                        : fail(IMM_EDEVICE, "speculative round: event record failed");
+                // its selection reads every segment: it waits for this round's
+                if (s == IMM_OK) s = ws_index_update(*q->w);
+                if (s == IMM_OK && hipEventRecord(q->w->side_ev2, q->st) != hipSuccess)
+                    s = fail(IMM_EDEVICE, "speculative round: event record failed");
             }
         }
         if (s == IMM_OK) s = ws_select_prepare(*q->w, q->p.k, &q->desc);
         if (s != IMM_OK) {
             finish_err(q, s);
-            if (q == spec_q) spec_q = nullptr;
+            if (q == spec_q) {
+                (void)ws_spec_drop(*q->w);  // waits for what it queued
+                spec_q = nullptr;
+            }
         } else {
             ready.push_back(q);
         }
@@ -538,9 +550,6 @@ bool BatchRunner::step() {
                                 hipMemcpyHostToDevice, main_) == hipSuccess;
             bool graph = false;
             for (auto* q : ready) graph |= (q->p.flags & IMM_GRAPH_SELECT) != 0;
-            // the speculative round starts after everything this round's
-            // selection needs, and runs beside the selection
-            if (spec_q && ok) ok = hipEventRecord(spec_q->w->side_ev, main_) == hipSuccess;
             if (timing) (void)hipEventRecord(ev_a_, main_);
             int launched = 0;
             if (graph && ok) {
@@ -559,7 +568,8 @@ bool BatchRunner::step() {
                                             sel_total, dense_total, main_) == hipSuccess;
             }
             if (timing) (void)hipEventRecord(ev_b_, main_);
-            if (spec_q && ok) ok = ws_spec_launch(*spec_q->w, spec_q->p.k, spec_q->w->side_ev) == IMM_OK;
+            if (spec_q && ok)
+                ok = ws_spec_launch_select(*spec_q->w, spec_q->p.k, spec_q->w->side_ev2) == IMM_OK;
             for (auto* q : ready)
                 if (ok) ok = ws_select_copy_out(*q->w, q->p.k, main_) == IMM_OK;
             if (ok) ok = hipStreamSynchronize(main_) == hipSuccess;
@@ -575,10 +585,10 @@ bool BatchRunner::step() {
                                     : fail(IMM_EDEVICE, "batched selection failed");
             if (s != IMM_OK) finish_err(q, s);
         }
-        if (spec_q && spec_q->w->spec) {
+        if (spec_q) {
             Query* q = spec_q;
             Workspace& w = *q->w;
-            if (!q->done && !q->final) {
+            if (w.spec && !q->done && !q->final) {
                 // this round failed its test: the next round is the one run
                 // speculatively; its θ decision is taken now
                 imm_status s = ws_spec_commit(w);

@@ -129,6 +129,7 @@ Workspace::~Workspace() {
     if (sel2.gains_h) (void)hipHostFree(sel2.gains_h);
     if (sel2.cand_h) (void)hipHostFree(sel2.cand_h);
     if (side_ev) (void)hipEventDestroy(side_ev);
+    if (side_ev2) (void)hipEventDestroy(side_ev2);
     if (side) (void)hipStreamDestroy(side);
 }
 
@@ -680,8 +681,6 @@ void ws_note_pool(Workspace& w, uint64_t sets_before) {
     if (w.indexed_sets == w.n_sets) w.p_indexed = p;
 }
 
-namespace {
-
 // Index the sets added since the last call as a new segment: its offsets are
 // the scan of the count increase since then, based at the pool position of
 // its first set.
@@ -739,8 +738,6 @@ imm_status ws_index_update(Workspace& w) {
     w.indexed_sets = w.n_sets;
     return IMM_OK;
 }
-
-}  // namespace
 
 namespace {
 
@@ -1163,13 +1160,14 @@ void swap_sel(Workspace& w, SelBufs& b) {
 }
 
 // Whether a segment of at most seg_ub entries is indexed by the partition
-// (as ws_index_update decides), given the pair buffer's capacity then.
-bool index_by_partition(const Workspace& w, uint64_t seg_ub) {
+// (as ws_index_update decides), given the capacity of the pair buffer it
+// would use.
+bool index_by_partition(const Workspace& w, uint64_t seg_ub, uint64_t cap_pairs) {
     if (index_bucket_shift(w.n) >= 32 || std::getenv("IMM_INDEX_ATOMIC")) return false;
     uint64_t pair_room = kIndexPairsBytes;
     if (w.arena.budget)
         pair_room = std::min(pair_room, (w.arena.budget - std::min(w.arena.budget, w.arena.used)) / 4);
-    const bool fits = w.cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
+    const bool fits = cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
     return fits && (seg_ub >= kIndexPartitionMin || std::getenv("IMM_INDEX_PARTITION"));
 }
 
@@ -1191,19 +1189,27 @@ imm_status ws_spec_reserve(Workspace& w, uint32_t k) {
     const uint32_t nseg = w.nseg + (w.indexed_sets < w.n_sets ? 1u : 0u);
     if (nseg + 1 > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
     IMM_TRY(grow(w.arena, &w.set_off, &w.cap_sets, hi + 1, lo + 1, st, "set_off"));
-    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan,
-                 std::max(scan_tmp_entries(kk), scan_tmp_entries(w.n)), 0, st, "scan tmp"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
+    IMM_TRY(grow(w.arena, &w.scan_tmp2, &w.cap_scan2,
+                 std::max(scan_tmp_entries(kk), scan_tmp_entries(w.n)), 0, st,
+                 "scan tmp (speculative)"));
+    if (!w.inv_cursor2)
+        IMM_TRY(w.arena.alloc((void**)&w.inv_cursor2, (uint64_t)w.n * 4,
+                              "inv_cursor (speculative)"));
     IMM_TRY(grow(w.arena, &w.inv_offs, &w.cap_offs, ((uint64_t)nseg + 1) * stride,
                  (uint64_t)w.nseg * stride, st, "index offsets"));
     IMM_TRY(grow(w.arena, &w.inv_set, &w.cap_inv, p_hi + 1, std::min(w.p_ub, w.cap_inv), st,
                  "inv_set"));
     const uint64_t cur_ub = w.p_ub - std::min(w.p_indexed, w.p_ub);
-    uint64_t pairs = 0;
-    if (w.indexed_sets < w.n_sets && index_by_partition(w, cur_ub)) pairs = cur_ub + 1;
-    if (index_by_partition(w, w.ahead_bound)) pairs = std::max(pairs, w.ahead_bound + 1);
-    if (pairs) {
-        IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, pairs, 0, st, "index pairs"));
+    if (w.indexed_sets < w.n_sets && index_by_partition(w, cur_ub, w.cap_pairs)) {
+        IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, cur_ub + 1, 0, st, "index pairs"));
         if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
+    }
+    if (index_by_partition(w, w.ahead_bound, w.cap_pairs2)) {
+        IMM_TRY(grow(w.arena, &w.inv_pairs2, &w.cap_pairs2, w.ahead_bound + 1, 0, st,
+                     "index pairs (speculative)"));
+        if (!w.iplan2)
+            IMM_TRY(w.arena.alloc((void**)&w.iplan2, sizeof(IndexPlan), "index plan (speculative)"));
     }
     if (!w.counts_spec)
         IMM_TRY(w.arena.alloc((void**)&w.counts_spec, (uint64_t)w.n * 4, "counts (speculative)"));
@@ -1242,43 +1248,56 @@ imm_status ws_spec_reserve(Workspace& w, uint32_t k) {
     }
     if (!w.side) HIP_TRY(hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking));
     if (!w.side_ev) HIP_TRY(hipEventCreateWithFlags(&w.side_ev, hipEventDisableTiming));
+    if (!w.side_ev2) HIP_TRY(hipEventCreateWithFlags(&w.side_ev2, hipEventDisableTiming));
     return IMM_OK;
 }
 
-imm_status ws_spec_launch(Workspace& w, uint32_t k, hipEvent_t after) {
+imm_status ws_spec_launch_index(Workspace& w, hipEvent_t after) {
     hipStream_t S = w.side;
     HIP_TRY(hipStreamWaitEvent(S, after, 0));
     const uint64_t kk = w.ahead_next, lo = w.n_sets, hi = lo + kk, split = w.ahead_split;
     const uint64_t stride = (uint64_t)w.n + 1;
+    // the segment after the one this round's index update adds
+    w.spec_seg = w.nseg + (w.indexed_sets < w.n_sets ? 1u : 0u);
     // the sets' offsets and members, after the pool's (as ws_take_ahead)
     HIP_TRY(launch_scan_u32(w.sizes + split, nullptr, w.set_off + lo, kk, 0, w.set_off + lo,
-                            w.scan_tmp, S));
+                            w.scan_tmp2, S));
     HIP_TRY(launch_compact(w.stage, w.stage_off + split, w.set_off, lo, (uint32_t)kk, w.set_vtx, S));
     // the pool's counts with them
     HIP_TRY(hipMemcpyAsync(w.counts_spec, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice,
                            S));
     HIP_TRY(launch_add_counts(w.counts_next, w.counts_spec, w.n, S));
-    // their index segment, numbered nseg: offsets from the scan of their
-    // counts (as ws_index_update, with those counts as the increase)
-    uint64_t* io = w.inv_offs + (uint64_t)w.nseg * stride;
-    HIP_TRY(launch_scan_u32(w.counts_next, nullptr, io, w.n, 0, w.set_off + lo, w.scan_tmp, S));
-    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, S));
+    // their index segment: offsets from the scan of their counts (as
+    // ws_index_update, with those counts as the increase)
+    uint64_t* io = w.inv_offs + (uint64_t)w.spec_seg * stride;
+    HIP_TRY(launch_scan_u32(w.counts_next, nullptr, io, w.n, 0, w.set_off + lo, w.scan_tmp2, S));
+    HIP_TRY(hipMemsetAsync(w.inv_cursor2, 0, (uint64_t)w.n * 4, S));
     const uint32_t shift = index_bucket_shift(w.n);
-    if (index_by_partition(w, w.ahead_bound)) {
+    if (index_by_partition(w, w.ahead_bound, w.cap_pairs2)) {
         const double mean = std::max(1.0, (double)w.ahead_bound / (double)kk);
         const uint32_t groups =
             (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
         HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, lo, (uint32_t)kk, groups, w.n, shift,
-                                       io, w.iplan, w.inv_pairs, w.cap_pairs, w.inv_cursor,
+                                       io, w.iplan2, w.inv_pairs2, w.cap_pairs2, w.inv_cursor2,
                                        w.inv_set, &w.sc->err, w.device, S));
     } else {
-        HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, lo, (uint32_t)kk, io, w.inv_cursor,
+        HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, lo, (uint32_t)kk, io, w.inv_cursor2,
                                    w.inv_set, &w.sc->err, S));
     }
+    w.spec_lo = lo;
+    w.spec_hi = hi;
+    return IMM_OK;
+}
+
+imm_status ws_spec_launch_select(Workspace& w, uint32_t k, hipEvent_t after) {
+    hipStream_t S = w.side;
+    if (w.nseg != w.spec_seg) return fail(IMM_EDEVICE, "internal error: speculative segment");
+    HIP_TRY(hipStreamWaitEvent(S, after, 0));
+    const uint64_t hi = w.spec_hi;
     // the selection over the pool with them, in the second buffers
     swap_sel(w, w.sel2);
     SelectDesc d{};
-    imm_status s = ws_select_state(w, k, &d, w.counts_spec, hi, w.nseg + 1,
+    imm_status s = ws_select_state(w, k, &d, w.counts_spec, hi, w.spec_seg + 1,
                                    w.p_ub + w.ahead_bound, S);
     hipError_t e = hipSuccess;
     if (s == IMM_OK) {
@@ -1297,8 +1316,6 @@ imm_status ws_spec_launch(Workspace& w, uint32_t k, hipEvent_t after) {
     IMM_TRY(s);
     HIP_TRY(e);
     w.spec = true;
-    w.spec_lo = lo;
-    w.spec_hi = hi;
     return IMM_OK;
 }
 
