@@ -247,6 +247,10 @@ struct Workspace {
     unsigned long long* inv_pairs = nullptr;  // ... and its (set, vertex) pairs
     uint64_t cap_pairs = 0;
     uint64_t p_indexed = 0;  // entries of the indexed sets (a lower bound)
+    // sets [pend_lo, pend_hi) of the pool whose members counts_acc does not
+    // hold yet (taken from the ids drawn ahead): the next index update counts
+    // them, building its segment from the sets alone when it can
+    uint64_t pend_lo = 0, pend_hi = 0;
     // one allocation: k * kArgSlots partial maxima, then 2k queue lengths,
     // then k covered-member totals
     unsigned long long* slots = nullptr;

@@ -221,6 +221,7 @@ struct IndexPlan {
     uint64_t off[kBktMax + 1];          // bucket ranges in the segment
     unsigned long long cur[kBktMax];    // partition cursors
     uint32_t sl_pre[kBktMax + 1];       // first slice of each bucket
+    uint32_t tot[kBktMax];              // the counting build's bucket totals
 };
 uint32_t index_bucket_shift(uint32_t n);  // 32 when n is too large for the partition
 hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
@@ -228,6 +229,19 @@ hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_v
                                   uint32_t shift, const uint64_t* inv_off, IndexPlan* pl,
                                   unsigned long long* tmp, uint64_t cap, uint32_t* cursor,
                                   uint32_t* inv_set, uint32_t* err, int device, hipStream_t st);
+// The same segment built from the sets alone, when the counts of some of
+// them are not known yet: the entries per bucket are counted first (one
+// pass, LDS histograms), the partition follows, and each bucket's workgroup
+// counts its vertices' entries, scans them into the segment's list offsets
+// inv_off (n + 1 of them, based at set_off[lo]), places the lists, and sets
+// counts[v] = base[v] + v's entries in the segment for every vertex. One
+// workgroup per bucket: meant for segments whose buckets hold a modest
+// number of entries each.
+hipError_t launch_inv_counting(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                               uint32_t count, uint32_t tile_groups, uint32_t n, uint32_t shift,
+                               uint64_t* inv_off, const uint32_t* base, uint32_t* counts,
+                               IndexPlan* pl, unsigned long long* tmp, uint64_t cap,
+                               uint32_t* inv_set, uint32_t* err, int device, hipStream_t st);
 // counts[v] += occurrences of v in set_vtx[0..P).
 hipError_t launch_count_entries(const uint32_t* set_vtx, uint64_t P, uint32_t* counts,
                                 hipStream_t st);

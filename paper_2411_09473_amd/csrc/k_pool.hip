@@ -506,6 +506,168 @@ __global__ __launch_bounds__(kPlaceBS) void inv_place_kernel(const unsigned long
     if (bad) atomicOr(err, 1u);
 }
 
+// ---- index build from the sets alone (the counting build)
+//
+// For a segment whose sets' counts are not all known, the bucket ranges come
+// from a histogram of the entries instead of the scanned offsets, and every
+// bucket is one slice: its workgroup sees all the entries of its vertices,
+// counts them, scans them into list offsets, writes the offsets and counts
+// of its vertices and places their lists (ranks from LDS counters, no
+// global atomic per entry).
+constexpr uint32_t kHistBS = 1024;
+
+__global__ __launch_bounds__(kHistBS) void inv_hist_kernel(const uint64_t* set_off, uint64_t lo,
+                                                           uint64_t hi, const uint32_t* set_vtx,
+                                                           uint32_t shift, uint32_t nb,
+                                                           IndexPlan* pl) {
+    __shared__ uint32_t s_h[kBktMax];
+    for (uint32_t b = threadIdx.x; b < nb; b += kHistBS) s_h[b] = 0u;
+    __syncthreads();
+    const uint64_t a0 = set_off[lo], a1 = set_off[hi];
+    const uint64_t stride = (uint64_t)gridDim.x * kHistBS;
+    constexpr uint32_t kB = 8;
+    for (uint64_t e0 = a0 + (uint64_t)blockIdx.x * kHistBS + threadIdx.x; e0 < a1;
+         e0 += stride * kB) {
+        uint32_t u[kB];
+#pragma unroll
+        for (uint32_t x = 0; x < kB; ++x) {
+            const uint64_t e = e0 + x * stride;
+            u[x] = set_vtx[e < a1 ? e : e0];
+        }
+#pragma unroll
+        for (uint32_t x = 0; x < kB; ++x) {
+            const uint32_t b = u[x] >> shift;
+            if (e0 + x * stride < a1 && b < nb) atomicAdd(&s_h[b], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += kHistBS)
+        if (s_h[b]) atomicAdd(&pl->tot[b], s_h[b]);
+}
+
+// Bucket ranges as the exclusive scan of the totals, one slice per bucket
+// (empty ones too: their vertices still get offsets). A segment beyond the
+// pair buffer gets empty buckets and raises *err, as in inv_plan_kernel.
+__global__ __launch_bounds__(1024) void inv_plan_counts_kernel(uint32_t nb, uint64_t cap,
+                                                               IndexPlan* pl, uint32_t* err) {
+    __shared__ uint64_t s_w[1024 / kWave];
+    __shared__ uint64_t s_carry;
+    uint64_t part = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += 1024) part += pl->tot[b];
+    uint64_t excl;
+    const uint64_t total = block_excl_scan64(part, &excl, s_w);
+    const bool fits = total <= cap;
+    if (threadIdx.x == 0) {
+        s_carry = 0;
+        if (!fits) atomicOr(err, 1u);
+    }
+    __syncthreads();
+    for (uint32_t c = 0; c <= nb; c += 1024) {
+        const uint32_t b = c + threadIdx.x;
+        const uint64_t t = b < nb && fits ? pl->tot[b] : 0;
+        const uint64_t tot = block_excl_scan64(t, &excl, s_w);
+        const uint64_t carry = s_carry;
+        if (b <= nb) {
+            pl->off[b] = carry + excl;
+            pl->sl_pre[b] = b;
+        }
+        if (b < nb) pl->cur[b] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kPlaceBS) void inv_place_counts_kernel(
+    const unsigned long long* tmp, const IndexPlan* pl, uint32_t nb, uint32_t shift, uint32_t n,
+    const uint64_t* seg_base, uint64_t* io, const uint32_t* base, uint32_t* counts,
+    uint32_t* inv_set, uint32_t* err) {
+    static_assert(kBktVtxMax == 4 * kPlaceBS, "four vertices per thread");
+    __shared__ uint32_t s_cnt[kBktVtxMax];  // counts, then ranks
+    __shared__ uint32_t s_ex[kBktVtxMax];   // list offsets within the bucket
+    __shared__ uint64_t s_w[kPlaceBS / kWave];
+    const uint64_t sb = *seg_base;
+    // buckets in eight ranges, one per XCD, as in inv_place_kernel
+    uint32_t t0 = blockIdx.x, tstep = gridDim.x, tend = nb;
+    if ((gridDim.x & 7u) == 0) {
+        const uint32_t x = blockIdx.x & 7u;
+        t0 = (uint32_t)((uint64_t)nb * x / 8) + (blockIdx.x >> 3);
+        tend = (uint32_t)((uint64_t)nb * (x + 1) / 8);
+        tstep = gridDim.x >> 3;
+    }
+    bool bad = false;
+    for (uint32_t b = t0; b < tend; b += tstep) {
+        const uint64_t bo = pl->off[b], be = pl->off[b + 1];
+        const uint32_t v0 = b << shift;
+        const uint32_t wn = min(1u << shift, n - v0);
+        for (uint32_t i = threadIdx.x; i < kBktVtxMax; i += kPlaceBS) s_cnt[i] = 0u;
+        __syncthreads();
+        constexpr uint64_t kRound = (uint64_t)kPlaceBS * kPlaceBatch;
+        for (uint64_t r0 = bo; r0 < be; r0 += kRound) {
+            uint32_t u[kPlaceBatch];
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint64_t e = r0 + (uint64_t)x * kPlaceBS + threadIdx.x;
+                u[x] = (uint32_t)tmp[e < be ? e : be - 1];
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint32_t ul = u[x] - v0;
+                if (r0 + (uint64_t)x * kPlaceBS + threadIdx.x < be) {
+                    if (ul < wn) atomicAdd(&s_cnt[ul], 1u);
+                    else bad = true;
+                }
+            }
+        }
+        __syncthreads();
+        // the counts' exclusive scan, four vertices per thread
+        const uint32_t i0 = 4u * threadIdx.x;
+        uint32_t c[4], sum = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            c[j] = i0 + j < wn ? s_cnt[i0 + j] : 0u;
+            sum += c[j];
+        }
+        uint64_t excl;
+        (void)block_excl_scan64(sum, &excl, s_w);
+        uint32_t run = (uint32_t)excl;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + j;
+            if (i < wn) {
+                s_ex[i] = run;
+                io[v0 + i] = sb + bo + run;
+                counts[v0 + i] = base[v0 + i] + c[j];
+            }
+            run += c[j];
+        }
+        if (b == nb - 1 && threadIdx.x == 0) io[n] = sb + be;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) s_cnt[i0 + j] = 0u;
+        __syncthreads();
+        // the lists: rank within the vertex's list from the LDS counters
+        for (uint64_t r0 = bo; r0 < be; r0 += kRound) {
+            unsigned long long p[kPlaceBatch];
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint64_t e = r0 + (uint64_t)x * kPlaceBS + threadIdx.x;
+                p[x] = tmp[e < be ? e : be - 1];
+            }
+#pragma unroll
+            for (uint32_t x = 0; x < kPlaceBatch; ++x) {
+                const uint32_t ul = (uint32_t)p[x] - v0;
+                if (r0 + (uint64_t)x * kPlaceBS + threadIdx.x < be && ul < wn) {
+                    const uint64_t at = bo + s_ex[ul] + atomicAdd(&s_cnt[ul], 1u);
+                    if (at < be) inv_set[sb + at] = (uint32_t)(p[x] >> 32);
+                    else bad = true;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(err, 1u);
+}
+
 __global__ __launch_bounds__(256) void count_entries_kernel(const uint32_t* set_vtx, uint64_t P,
                                                             uint32_t* counts) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -780,6 +942,33 @@ hipError_t launch_inv_partitioned(const uint64_t* set_off, const uint32_t* set_v
     hipLaunchKernelGGL(inv_place_kernel, dim3((uint32_t)std::max<uint64_t>(grid, 1)),
                        dim3(kPlaceBS), 0, st, tmp, pl, nb, shift, n, inv_off, cursor, inv_set,
                        err);
+    return hipGetLastError();
+}
+
+hipError_t launch_inv_counting(const uint64_t* set_off, const uint32_t* set_vtx, uint64_t lo,
+                               uint32_t count, uint32_t tile_groups, uint32_t n, uint32_t shift,
+                               uint64_t* inv_off, const uint32_t* base, uint32_t* counts,
+                               IndexPlan* pl, unsigned long long* tmp, uint64_t cap,
+                               uint32_t* inv_set, uint32_t* err, int device, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (shift >= 32 || tile_groups == 0) return hipErrorInvalidValue;
+    const uint32_t nb = (uint32_t)(((uint64_t)n + (1ull << shift) - 1) >> shift);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    hipError_t e = hipMemsetAsync(pl->tot, 0, (uint64_t)nb * 4, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(inv_hist_kernel, dim3((uint32_t)cus * 2), dim3(kHistBS), 0, st, set_off,
+                       lo, lo + count, set_vtx, shift, nb, pl);
+    hipLaunchKernelGGL(inv_plan_counts_kernel, dim3(1), dim3(1024), 0, st, nb, cap, pl, err);
+    const uint64_t tile = (uint64_t)tile_groups * kPartTile;
+    const uint64_t tiles = (count + tile - 1) / tile;
+    hipLaunchKernelGGL(inv_part_kernel, dim3((uint32_t)tiles), dim3(kPartBS), 0, st, set_off,
+                       set_vtx, lo, count, tile_groups, shift, nb, pl, tmp, err);
+    uint64_t grid = std::min<uint64_t>(nb, (uint64_t)cus * 8);
+    if (grid >= 8) grid &= ~7ull;  // a multiple of the XCD count
+    hipLaunchKernelGGL(inv_place_counts_kernel, dim3((uint32_t)std::max<uint64_t>(grid, 1)),
+                       dim3(kPlaceBS), 0, st, tmp, pl, nb, shift, n, set_off + lo, inv_off, base,
+                       counts, inv_set, err);
     return hipGetLastError();
 }
 

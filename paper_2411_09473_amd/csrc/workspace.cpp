@@ -175,6 +175,7 @@ imm_status ws_reset(Workspace& w, hipStream_t st, bool timing) {
     w.nseg = 0;
     w.indexed_sets = 0;
     w.p_indexed = 0;
+    w.pend_lo = w.pend_hi = 0;
     w.n_dense = 0;
     w.dense_entries = 0;
     w.ahead_n = 0;
@@ -397,6 +398,11 @@ imm_status ws_take_ahead(Workspace& w, uint64_t k) {
     if (w.ahead_next && k == w.ahead_next) {
         // exactly the ids the pass counted apart
         HIP_TRY(launch_add_counts(w.counts_next, w.counts_acc, w.n, st));
+    } else if (w.n_dense == 0 && w.indexed_sets <= w.n_sets &&
+               (w.pend_hi == w.pend_lo || w.pend_hi == w.n_sets)) {
+        // counted by the next index update, from the sets themselves
+        if (w.pend_hi == w.pend_lo) w.pend_lo = w.n_sets;
+        w.pend_hi = w.n_sets + k;
     } else {
         HIP_TRY(launch_count_sets(w.set_off, w.n_sets, w.n_sets + k, w.set_vtx, w.counts_acc,
                                   st));
@@ -643,6 +649,7 @@ imm_status ws_restart_pool(Workspace& w) {
     w.nseg = 0;
     w.indexed_sets = 0;
     w.p_indexed = 0;
+    w.pend_lo = w.pend_hi = 0;
     HIP_TRY(hipMemsetAsync(w.counts_acc, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.counts_prev, 0, (uint64_t)w.n * 4, st));
     HIP_TRY(hipMemsetAsync(w.set_off, 0, 8, st));
@@ -696,11 +703,12 @@ imm_status ws_index_update(Workspace& w) {
     IMM_TRY(grow(w.arena, &w.scan_tmp, &w.cap_scan, scan_tmp_entries(w.n), 0, st, "scan tmp"));
     uint64_t* io = w.inv_offs + w.nseg * stride;
     const int ti = w.timer.open(2, st);
-    HIP_TRY(launch_scan_u32(w.counts_acc, w.counts_prev, io, w.n, 0, w.set_off + w.indexed_sets,
-                            w.scan_tmp, st));
-    HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
     const uint32_t count = (uint32_t)(w.n_sets - w.indexed_sets);
     const uint32_t shift = index_bucket_shift(w.n);
+    // sets whose members are not counted yet
+    const uint64_t pend_lo = w.pend_lo, pend_hi = w.pend_hi;
+    const bool pending = pend_hi > pend_lo;
+    w.pend_lo = w.pend_hi = 0;
     // IMM_INDEX_ATOMIC / IMM_INDEX_PARTITION force either build (comparisons
     // and tests); results do not depend on it
     const bool atomic_scatter = std::getenv("IMM_INDEX_ATOMIC") != nullptr;
@@ -716,20 +724,34 @@ imm_status ws_index_update(Workspace& w) {
     const bool pairs_fit = w.cap_pairs > seg_ub || (seg_ub + 1) * 8 <= pair_room;
     // a small segment costs the scatter less than the partition's two extra
     // launches
-    if (shift < 32 && !atomic_scatter && pairs_fit &&
-        (seg_ub >= kIndexPartitionMin || force_partition)) {
+    const bool partition = shift < 32 && !atomic_scatter && pairs_fit &&
+                           (seg_ub >= kIndexPartitionMin || force_partition);
+    // partition tiles of about 32 K entries (64 K ones were slower)
+    const double mean = std::max(1.0, (double)seg_ub / (double)count);
+    const uint32_t groups = (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
+    if (partition) {
         IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, seg_ub + 1, 0, st, "index pairs"));
         if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
-        // partition tiles of about 32 K entries (64 K ones were slower)
-        const double mean = std::max(1.0, (double)seg_ub / (double)count);
-        const uint32_t groups =
-            (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
-        HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, w.indexed_sets, count, groups, w.n,
-                                       shift, io, w.iplan, w.inv_pairs, w.cap_pairs,
-                                       w.inv_cursor, w.inv_set, &w.sc->err, w.device, st));
+    }
+    if (partition && pending && w.n_dense == 0) {
+        // the segment and the counts from the sets themselves: no count pass
+        // over the uncounted sets, no scan of the count increase
+        HIP_TRY(launch_inv_counting(w.set_off, w.set_vtx, w.indexed_sets, count, groups, w.n,
+                                    shift, io, w.counts_prev, w.counts_acc, w.iplan, w.inv_pairs,
+                                    w.cap_pairs, w.inv_set, &w.sc->err, w.device, st));
     } else {
-        HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets, count, io, w.inv_cursor,
-                                   w.inv_set, &w.sc->err, st));
+        if (pending)
+            HIP_TRY(launch_count_sets(w.set_off, pend_lo, pend_hi, w.set_vtx, w.counts_acc, st));
+        HIP_TRY(launch_scan_u32(w.counts_acc, w.counts_prev, io, w.n, 0,
+                                w.set_off + w.indexed_sets, w.scan_tmp, st));
+        HIP_TRY(hipMemsetAsync(w.inv_cursor, 0, (uint64_t)w.n * 4, st));
+        if (partition)
+            HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, w.indexed_sets, count, groups,
+                                           w.n, shift, io, w.iplan, w.inv_pairs, w.cap_pairs,
+                                           w.inv_cursor, w.inv_set, &w.sc->err, w.device, st));
+        else
+            HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, w.indexed_sets, count, io,
+                                       w.inv_cursor, w.inv_set, &w.sc->err, st));
     }
     HIP_TRY(hipMemcpyAsync(w.counts_prev, w.counts_acc, (uint64_t)w.n * 4,
                            hipMemcpyDeviceToDevice, st));
@@ -1174,8 +1196,9 @@ bool index_by_partition(const Workspace& w, uint64_t seg_ub, uint64_t cap_pairs)
 }  // namespace
 
 bool ws_spec_possible(const Workspace& w) {
+    // (its counts start from the pool's, which must hold every set's members)
     return w.ahead_next > 0 && w.ahead_n >= w.ahead_next && w.counts_next && w.n_dense == 0 &&
-           w.n_sets + w.ahead_next <= 0xFFFFFFFFull;
+           w.pend_hi == w.pend_lo && w.n_sets + w.ahead_next <= 0xFFFFFFFFull;
 }
 
 imm_status ws_spec_reserve(Workspace& w, uint32_t k) {

@@ -68,6 +68,27 @@ def test_index_vertex_counts(imm, orc, stream, build, n):
 
 
 @pytest.mark.parametrize("build", BUILDS, indirect=True)
+@pytest.mark.parametrize("n", [2, 7, 2047, 2049, 5000])
+def test_index_vertex_counts_lt(imm, orc, stream, build, n):
+    """The same rings as LT graphs (in-weights 1/3 for the ring edge, 1/5
+    per chord): their later rounds and final selections take ids drawn
+    ahead, whose segments the partition builds from the sets alone."""
+    rng = np.random.default_rng(n + 1)
+    edges, wq = [], []
+    for v in range(n):
+        if n > 1:
+            edges.append(((v + 1) % n, v))
+            wq.append(T32 // 3)
+        for u in rng.choice(n, size=min(n, 3), replace=False):
+            if int(u) != v and int(u) != (v + 1) % n:
+                edges.append((int(u), v))
+                wq.append(T32 // 5)
+    g = synth.tiny_graph(n, edges, "lt", wq)
+    say(f"{build} index, LT ring of {n}")
+    _run(imm, orc, g, min(3, n), 0.3, 9, stream)
+
+
+@pytest.mark.parametrize("build", BUILDS, indirect=True)
 def test_index_no_edges(imm, orc, stream, build):
     g = synth.tiny_graph(3000, [], "ic", [])
     say(f"{build} index, no edges")
