@@ -251,6 +251,7 @@ struct Workspace {
     // hold yet (taken from the ids drawn ahead): the next index update counts
     // them, building its segment from the sets alone when it can
     uint64_t pend_lo = 0, pend_hi = 0;
+    bool lt = false;  // the pool holds LT sets (set by each sampling call)
     // one allocation: k * kArgSlots partial maxima, then 2k queue lengths,
     // then k covered-member totals
     unsigned long long* slots = nullptr;

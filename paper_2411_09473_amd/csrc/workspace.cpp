@@ -420,6 +420,7 @@ imm_status ws_take_ahead(Workspace& w, uint64_t k) {
 
 imm_status ws_extend_launch(Workspace& w, const imm_graph* g, uint64_t seed, uint64_t id_lo,
                             uint64_t count64, bool multi, uint64_t ahead, uint64_t next) {
+    w.lt = g->model == IMM_LT;
     w.pending_count = 0;
     w.pending_multi = false;
     w.pending_split = 0;
@@ -733,9 +734,11 @@ imm_status ws_index_update(Workspace& w) {
         IMM_TRY(grow(w.arena, &w.inv_pairs, &w.cap_pairs, seg_ub + 1, 0, st, "index pairs"));
         if (!w.iplan) IMM_TRY(w.arena.alloc((void**)&w.iplan, sizeof(IndexPlan), "index plan"));
     }
-    if (partition && pending && w.n_dense == 0) {
+    if (partition && (pending || w.lt) && w.n_dense == 0) {
         // the segment and the counts from the sets themselves: no count pass
-        // over the uncounted sets, no scan of the count increase
+        // over the uncounted sets, no scan of the count increase. It takes
+        // one workgroup per bucket, so it serves LT pools (walks spread
+        // their members over the buckets) and segments with uncounted sets
         HIP_TRY(launch_inv_counting(w.set_off, w.set_vtx, w.indexed_sets, count, groups, w.n,
                                     shift, io, w.counts_prev, w.counts_acc, w.iplan, w.inv_pairs,
                                     w.cap_pairs, w.inv_set, &w.sc->err, w.device, st));
@@ -1286,24 +1289,26 @@ imm_status ws_spec_launch_index(Workspace& w, hipEvent_t after) {
     HIP_TRY(launch_scan_u32(w.sizes + split, nullptr, w.set_off + lo, kk, 0, w.set_off + lo,
                             w.scan_tmp2, S));
     HIP_TRY(launch_compact(w.stage, w.stage_off + split, w.set_off, lo, (uint32_t)kk, w.set_vtx, S));
-    // the pool's counts with them
-    HIP_TRY(hipMemcpyAsync(w.counts_spec, w.counts_acc, (uint64_t)w.n * 4, hipMemcpyDeviceToDevice,
-                           S));
-    HIP_TRY(launch_add_counts(w.counts_next, w.counts_spec, w.n, S));
-    // their index segment: offsets from the scan of their counts (as
-    // ws_index_update, with those counts as the increase)
+    // their index segment, and the pool's counts with them
     uint64_t* io = w.inv_offs + (uint64_t)w.spec_seg * stride;
-    HIP_TRY(launch_scan_u32(w.counts_next, nullptr, io, w.n, 0, w.set_off + lo, w.scan_tmp2, S));
-    HIP_TRY(hipMemsetAsync(w.inv_cursor2, 0, (uint64_t)w.n * 4, S));
     const uint32_t shift = index_bucket_shift(w.n);
     if (index_by_partition(w, w.ahead_bound, w.cap_pairs2)) {
+        // from the sets themselves, as ws_index_update's counting build
         const double mean = std::max(1.0, (double)w.ahead_bound / (double)kk);
         const uint32_t groups =
             (uint32_t)std::min(64.0, std::max(1.0, 32768.0 / (256.0 * mean)));
-        HIP_TRY(launch_inv_partitioned(w.set_off, w.set_vtx, lo, (uint32_t)kk, groups, w.n, shift,
-                                       io, w.iplan2, w.inv_pairs2, w.cap_pairs2, w.inv_cursor2,
-                                       w.inv_set, &w.sc->err, w.device, S));
+        HIP_TRY(launch_inv_counting(w.set_off, w.set_vtx, lo, (uint32_t)kk, groups, w.n, shift,
+                                    io, w.counts_acc, w.counts_spec, w.iplan2, w.inv_pairs2,
+                                    w.cap_pairs2, w.inv_set, &w.sc->err, w.device, S));
     } else {
+        // offsets from the scan of the counts kept apart (as ws_index_update,
+        // with those counts as the increase)
+        HIP_TRY(hipMemcpyAsync(w.counts_spec, w.counts_acc, (uint64_t)w.n * 4,
+                               hipMemcpyDeviceToDevice, S));
+        HIP_TRY(launch_add_counts(w.counts_next, w.counts_spec, w.n, S));
+        HIP_TRY(launch_scan_u32(w.counts_next, nullptr, io, w.n, 0, w.set_off + lo, w.scan_tmp2,
+                                S));
+        HIP_TRY(hipMemsetAsync(w.inv_cursor2, 0, (uint64_t)w.n * 4, S));
         HIP_TRY(launch_inv_scatter(w.set_off, w.set_vtx, lo, (uint32_t)kk, io, w.inv_cursor2,
                                    w.inv_set, &w.sc->err, S));
     }
