@@ -120,6 +120,12 @@ __device__ __forceinline__ bool step_halted(const SelView& d, uint32_t t) {
     const uint32_t h = d.cand_state[1];
     return h != 0u && t >= h;
 }
+// The first four state words (mode, halting step, tau, list length) as one
+// load; zeros without a list.
+__device__ __forceinline__ uint4 cand_head(const SelView& d) {
+    return d.cand_state ? load_u4(reinterpret_cast<const IMM_GLOBAL uint4*>(d.cand_state))
+                        : make_uint4(0u, 0u, 0u, 0u);
+}
 // Whether step t >= 1 takes its argmax over the list and filters its
 // decrements (decided by step 1's argmax).
 __device__ __forceinline__ bool cand_step(const SelView& d, uint32_t t) {
@@ -192,23 +198,32 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
     const uint32_t blk = blockIdx.x - d.arg_lo;
     const uint32_t tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     if (d.cand_state && t >= 1) {
-        if (step_halted(d, t)) return;
+        // the state words and this workgroup's first list entries load
+        // together (the list buffer holds kCandMax entries; the ones past the
+        // list's length are not used)
+        const uint32_t first = blk * kArgBS * 4u;
+        uint32_t v0[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t i = first + u * kArgBS + tid;
+            v0[u] = d.cand[i < kCandMax ? i : kCandMax - 1];
+        }
+        const uint4 cs = cand_head(d);
+        if (cs.y != 0u && t >= cs.y) return;  // halted
         bool use;
         if (t == 1) {
             // the list serves steps 1.. unless it is empty, the update is
             // fixed, or step 0 recounted (its seed covered much of the pool)
             const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
-            use = d.cand_state[3] != 0u && d.update == kUpdateAdaptive &&
-                  d.cov_entries[0] * 4ull <= pool;
+            use = cs.w != 0u && d.update == kUpdateAdaptive && d.cov_entries[0] * 4ull <= pool;
             if (blk == 0 && tid == 0) d.cand_state[0] = use ? 1u : 2u;
         } else {
-            use = d.cand_state[0] == 1u;
+            use = cs.x == 1u;
         }
         if (use) {
             // the list's counts, four per thread per round, spread over the
             // instance's workgroups (a small graph has one)
-            const uint32_t nc = d.cand_state[3];
-            const uint32_t first = blk * kArgBS * 4u;
+            const uint32_t nc = cs.w;
             if (first >= nc) {
                 if (blk == 0 && tid == 0 && d.n_dense) d.dense_mark[t] = *d.dense_list_n;
                 return;
@@ -219,7 +234,9 @@ __global__ __launch_bounds__(kArgBS) void argmax_kernel(const SelectDesc* descs,
 #pragma unroll
                 for (uint32_t u = 0; u < 4; ++u) {
                     const uint32_t i = base + u * kArgBS + tid;
-                    v[u] = d.cand[i < nc ? i : nc - 1];
+                    // entries past the length repeat the last one (a repeated
+                    // vertex changes no maximum)
+                    v[u] = base == first && i < nc ? v0[u] : d.cand[i < nc ? i : nc - 1];
                 }
                 uint32_t c[4];
 #pragma unroll
@@ -296,10 +313,12 @@ __global__ __launch_bounds__(kClaimBS) void claim_kernel(const SelectDesc* descs
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
-    if (step_halted(d, t)) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
+    // the step's partial maxima and the state words load together
     const uint64_t m = slots_max(d.slots + (uint64_t)t * kArgSlots);
-    if (cand_step(d, t) && (uint32_t)(m >> 32) < d.cand_state[2]) {
+    const uint4 cs = cand_head(d);
+    if (cs.y != 0u && t >= cs.y) return;  // halted
+    if (t >= 1 && cs.x == 1u && (uint32_t)(m >> 32) < cs.z) {
         // no listed vertex reaches tau: an unlisted one might now be the
         // argmax, so the selection halts here (every workgroup agrees)
         if (blk == 0 && threadIdx.x == 0) d.cand_state[1] = t;
@@ -577,21 +596,24 @@ __global__ __launch_bounds__(kDecBS) void decrement_kernel(const SelectDesc* des
     if (q == nq) return;
     const SelView d = view_of(descs[q]);
     if (t >= d.k) return;
-    if (step_halted(d, t)) return;
     const uint32_t blk = blockIdx.x - d.sel_lo;
+    // the state words, the pool size, the step's covered total and its queue
+    // lengths load together
+    const uint4 cs = cand_head(d);
     const uint64_t pool = d.set_off[d.n_sets] + d.dense_entries;
-    if (d.update == kUpdateRecount ||
-        (d.update == kUpdateAdaptive && d.cov_entries[t] * 4ull > pool)) {
+    const uint64_t cov = d.cov_entries[t];
+    const uint32_t ns = d.chunk_n[2ull * t], nb = d.chunk_n[2ull * t + 1];
+    if (cs.y != 0u && t >= cs.y) return;  // halted
+    if (d.update == kUpdateRecount || (d.update == kUpdateAdaptive && cov * 4ull > pool)) {
         recount_all(d, blk, h_key, h_cnt);
         return;
     }
-    const uint32_t ns = d.chunk_n[2ull * t], nb = d.chunk_n[2ull * t + 1];
     const uint32_t wpb = kDecBS / kWave;
     if (blk * kDecBS >= ns && blk * wpb >= nb) return;
     IMM_GLOBAL uint32_t* cw = d.cw;
     const uint32_t v = d.seeds[t];
     // a candidate step decrements only the listed vertices
-    const bool filt = cand_step(d, t);
+    const bool filt = t >= 1 && cs.x == 1u;
     const uint32_t lane = threadIdx.x % kWave;
     const uint32_t threads = d.sel_cnt * kDecBS;
     const uint32_t nw = d.sel_cnt * wpb;
