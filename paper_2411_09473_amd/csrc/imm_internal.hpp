@@ -386,8 +386,16 @@ hipError_t launch_cand_build(const uint32_t* cw, uint32_t n, uint32_t cand_max, 
 // seed step does; chosen seeds keep their sentinel.
 hipError_t launch_select_recount(const SelectDesc* descs, uint32_t t, uint32_t sel_blocks,
                                  uint32_t dense_blocks, hipStream_t st);
+// Word ranges zeroed by launch_select_init2 on the way (the selection's
+// covered bits, seed-step block and candidate state; empty ones skipped).
+struct ZeroSpans {
+    static constexpr uint32_t kCount = 3;
+    uint32_t* p[kCount] = {nullptr, nullptr, nullptr};
+    uint64_t words[kCount] = {0, 0, 0};
+};
 hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_t* cw,
-                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st);
+                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st,
+                               const ZeroSpans& z = ZeroSpans{});
 
 // ---- misc
 hipError_t launch_philox(const uint32_t* ctr, uint64_t count, uint64_t key, uint32_t* out,

@@ -742,8 +742,9 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint32_t* cw, uint
 
 // tau, the lowest bin edge with at most cand_max vertices counting that much
 // or more (never below 1; no list when even the top bin holds more), then
-// one bitmap word (32 vertices) per thread and the list, one reservation
-// per wave.
+// the bitmap and the list. A wave takes 64 bitmap words (2048 vertices) as
+// eight coalesced rows of 64 16-byte loads; the eight lanes of a word OR its
+// 32 bits together, and the wave reserves its list entries with one atomic.
 __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint32_t n,
                                                         uint32_t cand_max, uint32_t* cand,
                                                         uint32_t* cand_bits, uint32_t* state) {
@@ -763,40 +764,57 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
     __syncthreads();
     const uint32_t tau = s_tau;
     const uint32_t words = (n + 31) / 32;
-    const uint32_t wd = blockIdx.x * 256 + threadIdx.x;
-    uint32_t bits = 0;
-    if (wd < words) {
-        const uint32_t v0 = wd * 32u;
-        if (v0 + 32u <= n) {
-            const uint4* p = reinterpret_cast<const uint4*>(cw + v0);
-            uint4 c[8];
+    const uint32_t lane = lane_id();
+    const uint32_t w0 = (blockIdx.x * (256u / kWave) + threadIdx.x / kWave) * kWave;
+    if (w0 >= words) return;
+    const uint32_t n4 = n / 4;
+    const uint4* cw4 = reinterpret_cast<const uint4*>(cw);
+    uint4 c[8];
 #pragma unroll
-            for (uint32_t j = 0; j < 8; ++j) c[j] = p[j];
-#pragma unroll
-            for (uint32_t j = 0; j < 8; ++j) {
-                bits |= (uint32_t)(c[j].x >= tau) << (4 * j);
-                bits |= (uint32_t)(c[j].y >= tau) << (4 * j + 1);
-                bits |= (uint32_t)(c[j].z >= tau) << (4 * j + 2);
-                bits |= (uint32_t)(c[j].w >= tau) << (4 * j + 3);
-            }
+    for (uint32_t r = 0; r < 8; ++r) {
+        // row r, lane l: the four counts of 16-byte group 8 w0 + 64 r + l
+        const uint32_t g = 8u * w0 + 64u * r + lane;
+        if (g < n4) {
+            c[r] = cw4[g];
         } else {
-            for (uint32_t j = 0; v0 + j < n; ++j) bits |= (uint32_t)(cw[v0 + j] >= tau) << j;
+            const uint32_t v = 4u * g;
+            c[r] = make_uint4(v < n ? cw[v] : 0u, v + 1 < n ? cw[v + 1] : 0u,
+                              v + 2 < n ? cw[v + 2] : 0u, v + 3 < n ? cw[v + 3] : 0u);
         }
-        cand_bits[wd] = bits;
     }
-    const uint32_t cnt = (uint32_t)__popc(bits);
+    uint32_t bits[8], cnt = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < 8; ++r) {
+        uint32_t b = (uint32_t)(c[r].x >= tau) | ((uint32_t)(c[r].y >= tau) << 1) |
+                     ((uint32_t)(c[r].z >= tau) << 2) | ((uint32_t)(c[r].w >= tau) << 3);
+        b <<= 4u * (lane & 7u);
+        b |= __shfl_xor(b, 1, kWave);
+        b |= __shfl_xor(b, 2, kWave);
+        b |= __shfl_xor(b, 4, kWave);
+        // word w0 + 8 r + lane / 8, held by the first lane of its eight
+        const uint32_t wd = w0 + 8u * r + lane / 8u;
+        const bool own = (lane & 7u) == 0u && wd < words;
+        bits[r] = own ? b : 0u;
+        if (own) cand_bits[wd] = b;
+        cnt += (uint32_t)__popc(bits[r]);
+    }
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t tot = __shfl(incl, kWave - 1, kWave);
     if (tot == 0) return;
     uint32_t base = 0;
-    if (lane_id() == kWave - 1) base = atomicAdd(&state[3], tot);
+    if (lane == kWave - 1) base = atomicAdd(&state[3], tot);
     base = __shfl(base, kWave - 1, kWave);
     uint32_t pos = base + incl - cnt;
-    while (bits) {
-        const uint32_t j = (uint32_t)__ffs(bits) - 1u;
-        bits &= bits - 1u;
-        if (pos < kCandMax) cand[pos] = wd * 32u + j;
-        ++pos;
+#pragma unroll
+    for (uint32_t r = 0; r < 8; ++r) {
+        uint32_t b = bits[r];
+        const uint32_t wd = w0 + 8u * r + lane / 8u;
+        while (b) {
+            const uint32_t j = (uint32_t)__ffs(b) - 1u;
+            b &= b - 1u;
+            if (pos < kCandMax) cand[pos] = wd * 32u + j;
+            ++pos;
+        }
     }
 }
 
@@ -804,7 +822,16 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
 // are appended to heavy (one atomic per wave).
 __global__ __launch_bounds__(256) void select_init_kernel(const uint32_t* cacc, const uint32_t* dc,
                                                           uint32_t* cw, uint32_t n,
-                                                          uint32_t* heavy, uint32_t* n_heavy) {
+                                                          uint32_t* heavy, uint32_t* n_heavy,
+                                                          ZeroSpans z) {
+    // the selection's state blocks cleared on the way (no fill launches)
+    {
+        const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+        const uint64_t stride = (uint64_t)gridDim.x * 256;
+#pragma unroll
+        for (uint32_t k = 0; k < ZeroSpans::kCount; ++k)
+            for (uint64_t x = g; x < z.words[k]; x += stride) z.p[k][x] = 0u;
+    }
     const uint32_t u = blockIdx.x * 256 + threadIdx.x;
     const uint32_t c = u < n ? cacc[u] : 0u;
     if (u < n) cw[u] = c + (dc ? dc[u] : 0u);
@@ -842,10 +869,16 @@ hipError_t launch_select_init(const uint32_t* cacc, uint32_t* cw, uint32_t n, ui
 }
 
 hipError_t launch_select_init2(const uint32_t* cacc, const uint32_t* dc, uint32_t* cw,
-                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(select_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cacc, dc, cw,
-                       n, heavy, n_heavy);
+                               uint32_t n, uint32_t* heavy, uint32_t* n_heavy, hipStream_t st,
+                               const ZeroSpans& z) {
+    uint64_t zw = 0;
+    for (uint32_t k = 0; k < ZeroSpans::kCount; ++k) zw += z.p[k] ? z.words[k] : 0;
+    if (n == 0 && zw == 0) return hipSuccess;
+    ZeroSpans zz = z;
+    for (uint32_t k = 0; k < ZeroSpans::kCount; ++k)
+        if (!zz.p[k]) zz.words[k] = 0;
+    hipLaunchKernelGGL(select_init_kernel, dim3(std::max(1u, (n + 255) / 256)), dim3(256), 0, st,
+                       cacc, dc, cw, n, heavy, n_heavy, zz);
     return hipGetLastError();
 }
 
@@ -857,6 +890,7 @@ hipError_t launch_cand_build(const uint32_t* cw, uint32_t n, uint32_t cand_max, 
     hipLaunchKernelGGL(cand_hist_kernel, dim3(hb), dim3(256), 0, st, cw, n,
                        cand_state + kCandHead);
     const uint32_t words = (n + 31) / 32;
+    // four waves of 64 words each per workgroup
     hipLaunchKernelGGL(cand_list_kernel, dim3((words + 255) / 256), dim3(256), 0, st, cw, n,
                        cand_max, cand, cand_bits, cand_state);
     return hipGetLastError();

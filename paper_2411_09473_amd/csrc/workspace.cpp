@@ -796,10 +796,28 @@ imm_status ws_select_state(Workspace& w, uint32_t k, SelectDesc* d, const uint32
     // a seed's queue entries: at most one per started 64 members of every set
     IMM_TRY(grow(w.arena, &w.chunks, &w.cap_chunks, n_sets + p_ub / 64 + 1, 0, st,
                  "chunk queue"));
-    // working counts, and the list of vertices whose index lists are long
+    if (nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
+    // the candidate list from the working counts (steps 1 .. k-1 may use it);
+    // IMM_CAND_MAX bounds it (0: every step in full)
+    uint32_t cand_max = kCandMax;
+    if (const char* e = std::getenv("IMM_CAND_MAX"))
+        cand_max = (uint32_t)std::min<long>(std::max<long>(std::atol(e), 0), (long)kCandMax);
+    const bool cand = cand_max > 0 && k >= 2;
+    // working counts, and the list of vertices whose index lists are long;
+    // the same launch clears the covered bits, the seed-step block (its
+    // layout follows the capacity cap_k, not this k) and the candidate state
     HIP_TRY(hipMemsetAsync(w.heavy + w.n, 0, 4, st));
+    ZeroSpans z;
+    z.p[0] = w.covered;
+    z.words[0] = n_sets / 32 + 1;
+    z.p[1] = reinterpret_cast<uint32_t*>(w.slots);
+    z.words[1] = w.cap_k * (kArgSlots * 8 + 16) / 4;
+    if (cand) {
+        z.p[2] = w.cand_state;
+        z.words[2] = kCandHead + kCandBins;
+    }
     HIP_TRY(launch_select_init2(cacc, w.n_dense ? w.dense_counts : nullptr, w.counts_work, w.n,
-                                w.heavy, w.heavy + w.n, st));
+                                w.heavy, w.heavy + w.n, st, z));
     // dense claims: per-step marks, then the claim cursor
     if (w.n_dense) {
         if (w.cap_mark_k < k) {
@@ -813,21 +831,9 @@ imm_status ws_select_state(Workspace& w, uint32_t k, SelectDesc* d, const uint32
         }
         HIP_TRY(hipMemsetAsync(w.dense_mark, 0, (w.cap_mark_k + 2) * 4, st));
     }
-    HIP_TRY(hipMemsetAsync(w.covered, 0, (n_sets / 32 + 1) * 4, st));
-    // the whole block: its layout follows the capacity cap_k, not this k
-    HIP_TRY(hipMemsetAsync(w.slots, 0, w.cap_k * (kArgSlots * 8 + 16), st));
-    if (nseg > kMaxSegments) return fail(IMM_EOVERFLOW, "too many index segments");
-    // the candidate list from the working counts (steps 1 .. k-1 may use it);
-    // IMM_CAND_MAX bounds it (0: every step in full)
-    uint32_t cand_max = kCandMax;
-    if (const char* e = std::getenv("IMM_CAND_MAX"))
-        cand_max = (uint32_t)std::min<long>(std::max<long>(std::atol(e), 0), (long)kCandMax);
-    const bool cand = cand_max > 0 && k >= 2;
-    if (cand) {
-        HIP_TRY(hipMemsetAsync(w.cand_state, 0, (kCandHead + kCandBins) * 4, st));
+    if (cand)
         HIP_TRY(launch_cand_build(w.counts_work, w.n, cand_max, w.cand, w.cand_bits,
                                   w.cand_state, st));
-    }
     *d = SelectDesc{w.counts_work, cacc,         w.heavy,     w.heavy + w.n, w.inv_offs,
                     w.inv_set,     w.set_off,    w.set_vtx,   w.covered,     w.slots,
                     w.seeds_d,     w.gains_d,    w.chunks,    w.chunk_n,     w.cap_chunks,
