@@ -723,12 +723,24 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint32_t* cw, uint
     const uint32_t stride = gridDim.x * 256;
     const uint32_t n4 = n >> 2;
     const uint4* cw4 = reinterpret_cast<const uint4*>(cw);
-    for (uint32_t x = blockIdx.x * 256 + threadIdx.x; x < n4; x += stride) {
-        const uint4 c = cw4[x];
-        if (c.x) atomicAdd(&s_h[cand_bin(c.x)], 1u);
-        if (c.y) atomicAdd(&s_h[cand_bin(c.y)], 1u);
-        if (c.z) atomicAdd(&s_h[cand_bin(c.z)], 1u);
-        if (c.w) atomicAdd(&s_h[cand_bin(c.w)], 1u);
+    // four 16-byte loads per thread in flight (clamped; a repeated group
+    // is not counted)
+    for (uint32_t x0 = blockIdx.x * 256 + threadIdx.x; x0 < n4; x0 += 4 * stride) {
+        uint4 cc[4];
+#pragma unroll
+        for (uint32_t y = 0; y < 4; ++y) {
+            const uint32_t x = x0 + y * stride;
+            cc[y] = cw4[x < n4 ? x : x0];
+        }
+#pragma unroll
+        for (uint32_t y = 0; y < 4; ++y) {
+            if (x0 + y * stride >= n4) continue;
+            const uint4 c = cc[y];
+            if (c.x) atomicAdd(&s_h[cand_bin(c.x)], 1u);
+            if (c.y) atomicAdd(&s_h[cand_bin(c.y)], 1u);
+            if (c.z) atomicAdd(&s_h[cand_bin(c.z)], 1u);
+            if (c.w) atomicAdd(&s_h[cand_bin(c.w)], 1u);
+        }
     }
     const uint32_t tail = (n4 << 2) + blockIdx.x * 256 + threadIdx.x;
     if (tail < n && blockIdx.x * 256 + threadIdx.x < 4u) {
@@ -744,13 +756,24 @@ __global__ __launch_bounds__(256) void cand_hist_kernel(const uint32_t* cw, uint
 // or more (never below 1; no list when even the top bin holds more), then
 // the bitmap and the list. A wave takes 64 bitmap words (2048 vertices) as
 // eight coalesced rows of 64 16-byte loads; the eight lanes of a word OR its
-// 32 bits together, and the wave reserves its list entries with one atomic.
-__global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint32_t n,
-                                                        uint32_t cand_max, uint32_t* cand,
-                                                        uint32_t* cand_bits, uint32_t* state) {
+// 32 bits together. The workgroup reserves its list entries with one atomic
+// (the list length is one counter for the whole launch: an atomic per wave
+// would queue up on it).
+constexpr uint32_t kListBS = 1024;
+__global__ __launch_bounds__(kListBS) void cand_list_kernel(const uint32_t* cw, uint32_t n,
+                                                            uint32_t cand_max, uint32_t* cand,
+                                                            uint32_t* cand_bits,
+                                                            uint32_t* state) {
     __shared__ uint32_t s_tau;
+    __shared__ uint32_t s_wt[kListBS / kWave];
+    __shared__ uint32_t s_base;
+    __shared__ uint32_t s_hist[kCandBins];
+    // the histogram staged in LDS by all threads at once (a walk down it
+    // through global memory would be one dependent load per bin)
+    for (uint32_t x = threadIdx.x; x < kCandBins; x += kListBS) s_hist[x] = state[kCandHead + x];
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t* hist = state + kCandHead;
+        const uint32_t* hist = s_hist;
         uint32_t acc = 0, b = kCandBins;
         for (uint32_t x = kCandBins; x-- > 1;) {
             acc += hist[x];
@@ -764,9 +787,9 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
     __syncthreads();
     const uint32_t tau = s_tau;
     const uint32_t words = (n + 31) / 32;
-    const uint32_t lane = lane_id();
-    const uint32_t w0 = (blockIdx.x * (256u / kWave) + threadIdx.x / kWave) * kWave;
-    if (w0 >= words) return;
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t w0 = (blockIdx.x * (kListBS / kWave) + wv) * kWave;
+    const bool live = w0 < words;  // (the whole wave alike)
     const uint32_t n4 = n / 4;
     const uint4* cw4 = reinterpret_cast<const uint4*>(cw);
     uint4 c[8];
@@ -774,7 +797,9 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
     for (uint32_t r = 0; r < 8; ++r) {
         // row r, lane l: the four counts of 16-byte group 8 w0 + 64 r + l
         const uint32_t g = 8u * w0 + 64u * r + lane;
-        if (g < n4) {
+        if (!live) {
+            c[r] = make_uint4(0u, 0u, 0u, 0u);
+        } else if (g < n4) {
             c[r] = cw4[g];
         } else {
             const uint32_t v = 4u * g;
@@ -793,18 +818,26 @@ __global__ __launch_bounds__(256) void cand_list_kernel(const uint32_t* cw, uint
         b |= __shfl_xor(b, 4, kWave);
         // word w0 + 8 r + lane / 8, held by the first lane of its eight
         const uint32_t wd = w0 + 8u * r + lane / 8u;
-        const bool own = (lane & 7u) == 0u && wd < words;
+        const bool own = live && (lane & 7u) == 0u && wd < words;
         bits[r] = own ? b : 0u;
         if (own) cand_bits[wd] = b;
         cnt += (uint32_t)__popc(bits[r]);
     }
     const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-    if (tot == 0) return;
-    uint32_t base = 0;
-    if (lane == kWave - 1) base = atomicAdd(&state[3], tot);
-    base = __shfl(base, kWave - 1, kWave);
-    uint32_t pos = base + incl - cnt;
+    if (lane == kWave - 1) s_wt[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (uint32_t x = 0; x < kListBS / kWave; ++x) {
+            const uint32_t t = s_wt[x];
+            s_wt[x] = tot;  // the waves' offsets within the workgroup
+            tot += t;
+        }
+        s_base = tot ? atomicAdd(&state[3], tot) : 0u;
+    }
+    __syncthreads();
+    if (cnt == 0) return;
+    uint32_t pos = s_base + s_wt[wv] + incl - cnt;
 #pragma unroll
     for (uint32_t r = 0; r < 8; ++r) {
         uint32_t b = bits[r];
@@ -890,9 +923,10 @@ hipError_t launch_cand_build(const uint32_t* cw, uint32_t n, uint32_t cand_max, 
     hipLaunchKernelGGL(cand_hist_kernel, dim3(hb), dim3(256), 0, st, cw, n,
                        cand_state + kCandHead);
     const uint32_t words = (n + 31) / 32;
-    // four waves of 64 words each per workgroup
-    hipLaunchKernelGGL(cand_list_kernel, dim3((words + 255) / 256), dim3(256), 0, st, cw, n,
-                       cand_max, cand, cand_bits, cand_state);
+    // sixteen waves of 64 words each per workgroup
+    constexpr uint32_t kWordsPerBlock = kListBS / kWave * kWave;
+    hipLaunchKernelGGL(cand_list_kernel, dim3((words + kWordsPerBlock - 1) / kWordsPerBlock),
+                       dim3(kListBS), 0, st, cw, n, cand_max, cand, cand_bits, cand_state);
     return hipGetLastError();
 }
 
