@@ -89,6 +89,28 @@ def test_index_vertex_counts_lt(imm, orc, stream, build, n):
 
 
 @pytest.mark.parametrize("build", BUILDS, indirect=True)
+def test_index_lt_hub(imm, orc, stream, build):
+    """An LT graph whose walks nearly all pass through vertex 0 (in-weight
+    0.9 from it at every other vertex): vertex 0's bucket holds most of a
+    segment's entries, far more than one placement slice, and the counting
+    build gives that bucket to one workgroup."""
+    n = 20000
+    rng = np.random.default_rng(77)
+    edges, wq = [], []
+    for v in range(1, n):
+        edges.append((0, v))
+        wq.append(int(0.9 * T32))
+        edges.append(((v + 1) % n if (v + 1) % n != 0 else 1, v))
+        wq.append(T32 // 20)
+    for u in rng.choice(np.arange(1, n), 3, replace=False):
+        edges.append((int(u), 0))
+        wq.append(T32 // 4)
+    g = synth.tiny_graph(n, edges, "lt", wq)
+    say(f"{build} index, LT hub")
+    _run(imm, orc, g, 5, 0.05, 3, stream)
+
+
+@pytest.mark.parametrize("build", BUILDS, indirect=True)
 def test_index_no_edges(imm, orc, stream, build):
     g = synth.tiny_graph(3000, [], "ic", [])
     say(f"{build} index, no edges")
