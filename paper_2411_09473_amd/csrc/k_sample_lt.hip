@@ -280,7 +280,8 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
     const bool first = sub == 0;
     uint32_t* mb = bloom + (lane / P) * kBloomWords;  // this walk's filter
     // the wave's reservoir of sample positions [res_pos, res_end), claimed
-    // from the ticket 64 at a time (uniform across the wave)
+    // from the ticket 64 at a time, and one per walk slot for the last
+    // round of claims (uniform across the wave)
     uint32_t res_pos = 0, res_end = 0;
 
     constexpr uint32_t R = kWin / P;
@@ -313,12 +314,19 @@ __global__ __launch_bounds__(64, 5) void lt_small_kernel(LtGraphDev g, SampleRan
                 pos = res_pos + rank;
                 res_pos += want;
             } else {
+                // near the end of the positions (within one round of 64-wide
+                // claims by every wave, judged by this wave's last claim) a
+                // claim covers one walk per slot: a last wide claim would
+                // leave a few waves with several walks per slot to run while
+                // the rest of the GPU idles (want <= walk slots <= claim)
+                const uint32_t claim =
+                    (uint64_t)res_end + (uint64_t)gridDim.x * kWave >= total ? kWave / P : kWave;
                 uint32_t nb = 0;
-                if (lane == 0) nb = atomicAdd(ticket, kWave);
+                if (lane == 0) nb = atomicAdd(ticket, claim);
                 nb = __shfl(nb, 0, kWave);
                 pos = rank < have ? res_pos + rank : nb + (rank - have);
                 res_pos = nb + (want - have);
-                res_end = nb + kWave;
+                res_end = nb + claim;
             }
             bool start = false;
             if (need) {
