@@ -45,6 +45,7 @@ PHILOX_OPS = 60
 # kernel changed since its counters were taken has no entry.
 MEASURED_TRAFFIC = {
     ("lj_lt", "lt_small_kernel"): 4.200e9,
+    ("lj_lt:sample16777216", "lt_small_kernel"): 292.52e9,
     ("youtube_ic", "ic_large_kernel"): 8.162e9,
     ("youtube_ic:sample16777216", "ic_large_kernel"): 63.37e9,
 }
